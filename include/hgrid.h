@@ -1,0 +1,226 @@
+/*
+ * hgrid.h -- C ABI of the MI355X (gfx950) hierarchical-grid library.
+ *
+ * Octree and k-d tree dust grids for Monte Carlo radiative transfer
+ * (Saftly, Baes & Camps 2014, "Hierarchical octree and k-d tree grids for 3D
+ * radiative transfer simulations"): grid construction with per-node density
+ * sampling (Sect. 2.2, Eq. 1-3 of Sect. 4), straight-path traversal that
+ * returns the ordered crossed leaves, the length ds in each and the optical
+ * depth tau = sum kappa rho ds (Sect. 2.3), and point location (Sect. 2.3).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns int: HG_OK (0) or a negative HG_E_* code.  No call
+ *    aborts, throws or prints.  grid_strerror() names a code.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on that stream; calls that must report a data-dependent
+ *    status (record counts, direction checks, node counts) synchronise it
+ *    before returning, as documented per call.
+ *  - Array arguments are DEVICE pointers owned by the caller unless stated
+ *    otherwise; the library never frees them.  Grids are owned by the library
+ *    and released by grid_free().
+ *  - Points and directions are double[n][3] (x, y, z interleaved).
+ *  - The domain is a cube [lo, lo+side]^3 with side a power of two and each
+ *    lo a multiple of side/2 (e.g. [-1,1]^3), so that every cell boundary is
+ *    an exact binary fraction.
+ *  - Leaf ids are ranks among the leaves in the breadth-first node list
+ *    (the order in which the construction loop of Sect. 2.2 creates them).
+ */
+#ifndef HGRID_H
+#define HGRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HG_OK          0
+#define HG_E_INVAL    -1  /* null pointer, negative count, unknown enum, bad level range */
+#define HG_E_DOMAIN   -2  /* domain not a cube of power-of-two side with lo on a half-side multiple */
+#define HG_E_DIR      -3  /* a direction is not finite or | |k| - 1 | > 1e-6 */
+#define HG_E_CAPACITY -4  /* crossing records do not fit; tau, count, offsets and needed are valid */
+#define HG_E_OOM      -5  /* device allocation failed */
+#define HG_E_LIMIT    -6  /* tree exceeds 2^25 leaves or 2^25 internal nodes, or max_nodes */
+#define HG_E_HIP      -7  /* HIP runtime error; grid_last_hip_error() gives the hipError_t */
+#define HG_E_STEP     -8  /* a path exceeded the step guard (never expected for valid input) */
+#define HG_E_FORMAT   -9  /* imported arrays are not a valid breadth-first tree */
+
+/* ---- enums ------------------------------------------------------------- */
+#define HG_OCTREE 0        /* regular 8-way split at the node centre (Sect. 2.1) */
+#define HG_KDTREE 1        /* 2-way split at the midpoint, axis cycling x,y,z (Sect. 2.2) */
+
+#define HG_FP64         0  /* every step of the walk in FP64 */
+#define HG_FP32_RECHECK 1  /* FP32 exit decision with FP64 re-anchoring and near-tie recheck */
+
+#define HG_TAU_ONLY 0      /* per path: tau and crossing count */
+#define HG_RECORDS  1      /* also the ordered (leaf id, ds) records, CSR by path */
+
+#define HG_FLAG_TIMING   1 /* grid_trace: time the walk kernels with HIP events */
+#define HG_FLAG_RECHECKS 2 /* grid_trace: count FP64 rechecks (HG_FP32_RECHECK) */
+
+#define HG_MAX_CLUMPS (1 << 24)
+
+/* ---- density field ----------------------------------------------------- */
+/* The true density rho_t(x) of Sect. 3.2, given as a sum of parametric
+ * components (a C ABI cannot take a device callback).  Components are added in
+ * the order box, disk, clumps (ascending index), torus:
+ *   box    rho = box_rho inside the closed box [box_lo, box_hi], else 0
+ *   disk   rho = disk_rho0 exp(-R/disk_hR - |z|/disk_hz), R = sqrt(x^2+y^2)
+ *   clumps rho = amp_i exp(-r^2 / (2 sigma_i^2)) for r <= clump_trunc sigma_i
+ *   torus  rho = torus_rho where (R - torus_R0)^2 + z^2 <= torus_a^2
+ * The clump arrays are HOST pointers (clump_c is double[n][3]); they are
+ * copied during grid_build and may be freed afterwards. */
+typedef struct {
+    double lo[3];
+    double side;
+    int32_t has_box;
+    double box_lo[3], box_hi[3], box_rho;
+    int32_t has_disk;
+    double disk_rho0, disk_hR, disk_hz;
+    int32_t has_torus;
+    double torus_R0, torus_a, torus_rho;
+    int64_t n_clumps;
+    const double *clump_c;
+    const double *clump_sigma;
+    const double *clump_amp;
+    double clump_trunc;
+} hg_density;
+
+/* ---- stopping criteria (Sect. 2.2, 4.1, 4.2) ---------------------------- */
+/* A node at level l (root = 0) is split when l < min_level, or when
+ * l < max_level and any of  delta = M/total_mass > delta_max  (Sect. 2.2),
+ * tau = kappa M sqrt(a^2+b^2+c^2)/(abc) > tau_max  (Eq. 2),
+ * q = (rho_max - rho_min)/rho_max > q_max  (Eq. 3; q = 0 when rho_max = 0)
+ * holds.  M = V/n_samples * sum of rho_t at n_samples random positions in the
+ * node (Eq. 1), drawn by a counter-based SplitMix64 generator keyed by seed
+ * and the node's level and cell coordinates.  Use tau_max = +inf and
+ * q_max >= 1 to switch those criteria off.  max_level <= 19 (octree) or
+ * <= 57 (k-d tree).  max_nodes > 0 bounds the node count (else HG_E_LIMIT). */
+typedef struct {
+    double total_mass, delta_max, tau_max, q_max, kappa;
+    int32_t min_level, max_level, n_samples, reserved;
+    uint64_t seed;
+    int64_t max_nodes;
+} hg_criteria;
+
+/* ---- trace options and outputs ----------------------------------------- */
+typedef struct {
+    int32_t precision;  /* HG_FP64 or HG_FP32_RECHECK */
+    int32_t mode;       /* HG_TAU_ONLY or HG_RECORDS */
+    double kappa;       /* opacity in tau = sum kappa rho ds */
+    int32_t flags;      /* HG_FLAG_* */
+    int32_t block;      /* threads per block, 0 = library choice */
+    int32_t persistent; /* 1 = persistent lane-refill walk, 0 = one thread per path, -1 = library choice */
+    int32_t reserved;
+} hg_trace_opts;
+
+/* Outputs of grid_trace; every array is a caller-owned device buffer.
+ *   tau[n]       double, sum of kappa rho ds along the path
+ *   count[n]     int32, number of leaves crossed with ds > 0
+ *   offsets[n+1] int64, exclusive prefix sum of count (HG_RECORDS only)
+ *   leaf[cap]    int32 leaf ids in path order (HG_RECORDS only)
+ *   ds[cap]      double (HG_FP64) or float (HG_FP32_RECHECK) lengths
+ * Set by the call: needed (= offsets[n], the total crossings), rechecks
+ * (with HG_FLAG_RECHECKS) and kernel_ms[] (with HG_FLAG_TIMING: [0] count or
+ * tau-only walk, [1] prefix sum, [2] record-filling walk, [3] whole call). */
+typedef struct {
+    double *tau;
+    int32_t *count;
+    int64_t *offsets;
+    int32_t *leaf;
+    void *ds;
+    int64_t capacity;
+    int64_t needed;
+    int64_t rechecks;
+    float kernel_ms[4];
+} hg_trace_out;
+
+/* ---- flat grid arrays (the data exchanged with the oracle and the tests) -- */
+/* Node arrays follow the breadth-first node list of Sect. 2.2: node 0 is the
+ * root; the children of a split node are contiguous (2 for a k-d tree, lower
+ * then upper half; 8 for an octree, octant index bx + 2 by + 4 bz) and appear
+ * in the order their parents do.  coord[3] is the cell index of the node
+ * along each axis at that axis' depth (octree: level; k-d: floor((level+2-d)/3)).
+ * rope[6] per leaf, faces -x,+x,-y,+y,-z,+z: the node index of the smallest
+ * node containing the whole region just across that face (-1 on the domain
+ * boundary); its subtree holds the face's neighbor list of Sect. 2.3.
+ * For grid_import only tree_type, lo, side, n_nodes, first_child and rho are
+ * read (device pointers); the rest is ignored.  For grid_export every pointer
+ * is a borrowed device pointer into the grid, valid until grid_free. */
+typedef struct {
+    int32_t tree_type;
+    int32_t max_level;
+    double lo[3];
+    double side;
+    int64_t n_nodes, n_leaves;
+    const int32_t *first_child; /* [n_nodes], -1 for a leaf */
+    const double *rho;          /* [n_leaves], grid density of each leaf */
+    const uint8_t *level;       /* [n_nodes] */
+    const uint32_t *coord;      /* [n_nodes][3] */
+    const double *S;            /* [n_nodes] sum of the sampled densities */
+    const double *rho_min;      /* [n_nodes] */
+    const double *rho_max;      /* [n_nodes] */
+    const int32_t *leaf_of;     /* [n_nodes] leaf id or -1 */
+    const int32_t *node_of;     /* [n_leaves] */
+    const int32_t *rope;        /* [n_leaves][6] */
+} hg_grid_arrays;
+
+typedef struct hg_grid *hg_grid_t;
+
+/* Build a grid (Sect. 2.2: the node list grows breadth-first; each node's mass
+ * is the Monte Carlo estimate of Eq. 1 and it is split by the criteria above;
+ * leaves are the unsplit nodes).  The construction runs level by level on the
+ * GPU and synchronises the stream once per level to size the next one.  Leaf
+ * density rho = S/n_samples = M/V (Sect. 3.2).  On success *out owns the grid.
+ * Errors: HG_E_INVAL, HG_E_DOMAIN, HG_E_LIMIT, HG_E_OOM, HG_E_HIP. */
+int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_type,
+               void *stream, hg_grid_t *out);
+
+/* Trace n straight paths (Sect. 2.3).  origins and dirs are device double[n][3];
+ * each direction must be a unit vector.  A path starts at its origin, or at
+ * its entry point into the domain when the origin lies outside; a path that
+ * misses the domain has count 0 and tau 0.  The walk visits, in order, every
+ * leaf the path crosses with positive length and stops where the path leaves
+ * the domain.  Records mode runs a counting walk, a prefix sum into offsets
+ * and a record-filling walk; if capacity < needed it returns HG_E_CAPACITY
+ * after the first two with tau, count, offsets and needed valid.  The call
+ * synchronises the stream before returning.  Errors: HG_E_INVAL, HG_E_DIR,
+ * HG_E_CAPACITY, HG_E_STEP, HG_E_HIP. */
+int grid_trace(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
+               const hg_trace_opts *opts, hg_trace_out *out, void *stream);
+
+/* Leaf containing each point (Sect. 2.3, top-down search).  points is device
+ * double[n][3]; leaf_out device int32[n].  Cells are half-open [lo, hi) along
+ * each axis except that the domain's upper faces belong to the last cells;
+ * points outside the closed domain (or with a NaN coordinate) give -1.
+ * Asynchronous.  Errors: HG_E_INVAL, HG_E_HIP. */
+int grid_locate(hg_grid_t grid, const double *points, int64_t n, int32_t *leaf_out,
+                void *stream);
+
+/* Copy a tree given by its breadth-first first-child array and leaf densities
+ * into a new grid (deep copy; levels, cell coordinates and ropes are derived
+ * on the GPU).  Used to trace a grid built elsewhere, e.g. by a CPU reference.
+ * Synchronises the stream.  Errors: HG_E_INVAL, HG_E_DOMAIN, HG_E_FORMAT,
+ * HG_E_LIMIT, HG_E_OOM, HG_E_HIP. */
+int grid_import(const hg_grid_arrays *arrays, void *stream, hg_grid_t *out);
+
+/* Fill *out with the grid's counts and borrowed device pointers (see
+ * hg_grid_arrays).  Errors: HG_E_INVAL. */
+int grid_export(hg_grid_t grid, hg_grid_arrays *out);
+
+/* Release a grid and its device memory (NULL is ignored).  The caller must
+ * make sure no work using the grid is still queued. */
+void grid_free(hg_grid_t grid);
+
+/* Static description of a status code. */
+const char *grid_strerror(int code);
+
+/* hipError_t of the last HG_E_HIP returned on this thread (0 if none). */
+int grid_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HGRID_H */

@@ -1,0 +1,376 @@
+"""Python binding of libhgrid.so, the gfx950 hierarchical-grid library.
+
+Thin ctypes marshalling over the C ABI in include/hgrid.h: every step of grid
+construction, traversal and location runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and the stream.  If the library has
+not been built this module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhgrid.so")
+
+OCTREE = 0
+KDTREE = 1
+FP64 = 0
+FP32_RECHECK = 1
+TAU_ONLY = 0
+RECORDS = 1
+FLAG_TIMING = 1
+FLAG_RECHECKS = 2
+
+HG_OK = 0
+HG_E_INVAL = -1
+HG_E_DOMAIN = -2
+HG_E_DIR = -3
+HG_E_CAPACITY = -4
+HG_E_OOM = -5
+HG_E_LIMIT = -6
+HG_E_HIP = -7
+HG_E_STEP = -8
+HG_E_FORMAT = -9
+
+
+class HGError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+
+
+class Density(C.Structure):
+    _fields_ = [
+        ("lo", C.c_double * 3), ("side", C.c_double),
+        ("has_box", C.c_int32), ("box_lo", C.c_double * 3), ("box_hi", C.c_double * 3),
+        ("box_rho", C.c_double),
+        ("has_disk", C.c_int32), ("disk_rho0", C.c_double), ("disk_hR", C.c_double),
+        ("disk_hz", C.c_double),
+        ("has_torus", C.c_int32), ("torus_R0", C.c_double), ("torus_a", C.c_double),
+        ("torus_rho", C.c_double),
+        ("n_clumps", C.c_int64), ("clump_c", C.c_void_p), ("clump_sigma", C.c_void_p),
+        ("clump_amp", C.c_void_p), ("clump_trunc", C.c_double),
+    ]
+
+
+class Criteria(C.Structure):
+    _fields_ = [
+        ("total_mass", C.c_double), ("delta_max", C.c_double), ("tau_max", C.c_double),
+        ("q_max", C.c_double), ("kappa", C.c_double),
+        ("min_level", C.c_int32), ("max_level", C.c_int32), ("n_samples", C.c_int32),
+        ("reserved", C.c_int32), ("seed", C.c_uint64), ("max_nodes", C.c_int64),
+    ]
+
+
+class TraceOpts(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int32), ("mode", C.c_int32), ("kappa", C.c_double),
+        ("flags", C.c_int32), ("block", C.c_int32), ("persistent", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
+class TraceOut(C.Structure):
+    _fields_ = [
+        ("tau", C.c_void_p), ("count", C.c_void_p), ("offsets", C.c_void_p),
+        ("leaf", C.c_void_p), ("ds", C.c_void_p), ("capacity", C.c_int64),
+        ("needed", C.c_int64), ("rechecks", C.c_int64), ("kernel_ms", C.c_float * 4),
+    ]
+
+
+class GridArrays(C.Structure):
+    _fields_ = [
+        ("tree_type", C.c_int32), ("max_level", C.c_int32), ("lo", C.c_double * 3),
+        ("side", C.c_double), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64),
+        ("first_child", C.c_void_p), ("rho", C.c_void_p), ("level", C.c_void_p),
+        ("coord", C.c_void_p), ("S", C.c_void_p), ("rho_min", C.c_void_p),
+        ("rho_max", C.c_void_p), ("leaf_of", C.c_void_p), ("node_of", C.c_void_p),
+        ("rope", C.c_void_p),
+    ]
+
+
+_lib = None
+_hip_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_SIGS = [
+    ("grid_build", C.c_int, [C.POINTER(Density), C.POINTER(Criteria), C.c_int, C.c_void_p,
+                             C.POINTER(C.c_void_p)]),
+    ("grid_trace", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                             C.POINTER(TraceOpts), C.POINTER(TraceOut), C.c_void_p]),
+    ("grid_locate", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    ("grid_import", C.c_int, [C.POINTER(GridArrays), C.c_void_p, C.POINTER(C.c_void_p)]),
+    ("grid_export", C.c_int, [C.c_void_p, C.POINTER(GridArrays)]),
+    ("grid_free", None, [C.c_void_p]),
+    ("grid_strerror", C.c_char_p, [C.c_int]),
+    ("grid_last_hip_error", C.c_int, []),
+]
+
+
+def lib():
+    """Load libhgrid.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                "g.build()'` (hipcc, gfx950); there is no CPU fallback")
+        L = C.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().grid_strerror(code).decode()
+    except Exception:  # pragma: no cover - library missing
+        return "?"
+
+
+def _check(rc: int, what: str):
+    if rc != HG_OK:
+        raise HGError(rc, what)
+
+
+def _hip():
+    global _hip_lib
+    if _hip_lib is None:
+        h = C.CDLL("libamdhip64.so")
+        h.hipMemcpy.restype = C.c_int
+        h.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip_lib = h
+    return _hip_lib
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f64x3(a, device) -> torch.Tensor:
+    t = torch.as_tensor(a, dtype=torch.float64)
+    t = t.reshape(-1, 3).to(device).contiguous()
+    return t
+
+
+def _density_struct(d):
+    """Marshal a density description (attributes lo, side, box, disk, torus,
+    clump_c, clump_sigma, clump_amp, clump_trunc) into the C struct."""
+    s = Density()
+    keep = []
+    for i in range(3):
+        s.lo[i] = float(d.lo[i])
+    s.side = float(d.side)
+    if getattr(d, "box", None) is not None:
+        s.has_box = 1
+        for i in range(3):
+            s.box_lo[i] = d.box[i]
+            s.box_hi[i] = d.box[3 + i]
+        s.box_rho = d.box[6]
+    if getattr(d, "disk", None) is not None:
+        s.has_disk = 1
+        s.disk_rho0, s.disk_hR, s.disk_hz = d.disk
+    if getattr(d, "torus", None) is not None:
+        s.has_torus = 1
+        s.torus_R0, s.torus_a, s.torus_rho = d.torus
+    cc = getattr(d, "clump_c", None)
+    if cc is not None and len(cc):
+        c = np.ascontiguousarray(cc, dtype=np.float64).reshape(-1, 3)
+        sg = np.ascontiguousarray(d.clump_sigma, dtype=np.float64)
+        am = np.ascontiguousarray(d.clump_amp, dtype=np.float64)
+        keep += [c, sg, am]
+        s.n_clumps = c.shape[0]
+        s.clump_c = c.ctypes.data
+        s.clump_sigma = sg.ctypes.data
+        s.clump_amp = am.ctypes.data
+    s.clump_trunc = float(getattr(d, "clump_trunc", 3.0))
+    return s, keep
+
+
+def _criteria_struct(cr, max_nodes: int = 0):
+    c = Criteria()
+    c.total_mass = cr.total_mass
+    c.delta_max = cr.delta_max
+    c.tau_max = cr.tau_max
+    c.q_max = cr.q_max
+    c.kappa = cr.kappa
+    c.min_level = cr.min_level
+    c.max_level = cr.max_level
+    c.n_samples = cr.n_samples
+    c.seed = cr.seed & ((1 << 64) - 1)
+    c.max_nodes = max_nodes
+    return c
+
+
+class Grid:
+    """A grid owned by the library (device memory)."""
+
+    def __init__(self, handle: C.c_void_p, device):
+        self._h = handle
+        self.device = device
+        a = GridArrays()
+        _check(lib().grid_export(self._h, C.byref(a)), "grid_export")
+        self.tree_type = a.tree_type
+        self.max_level = a.max_level
+        self.n_nodes = a.n_nodes
+        self.n_leaves = a.n_leaves
+        self.lo = tuple(a.lo)
+        self.side = a.side
+
+    # -- construction ------------------------------------------------------
+    @classmethod
+    def build(cls, density, criteria, tree_type: int, stream=None, device="cuda",
+              max_nodes: int = 0):
+        s, keep = _density_struct(density)
+        c = _criteria_struct(criteria, max_nodes)
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            rc = lib().grid_build(C.byref(s), C.byref(c), tree_type, _stream(stream), C.byref(h))
+        del keep
+        _check(rc, "grid_build")
+        return cls(h, device)
+
+    @classmethod
+    def from_arrays(cls, tree_type: int, first_child, rho, lo=(-1.0, -1.0, -1.0), side=2.0,
+                    stream=None, device="cuda"):
+        fc = torch.as_tensor(first_child, dtype=torch.int32).to(device).contiguous()
+        r = torch.as_tensor(rho, dtype=torch.float64).to(device).contiguous()
+        a = GridArrays()
+        a.tree_type = tree_type
+        for i in range(3):
+            a.lo[i] = lo[i]
+        a.side = side
+        a.n_nodes = fc.numel()
+        a.n_leaves = r.numel()
+        a.first_child = fc.data_ptr()
+        a.rho = r.data_ptr()
+        h = C.c_void_p()
+        rc = lib().grid_import(C.byref(a), _stream(stream), C.byref(h))
+        _check(rc, "grid_import")
+        return cls(h, device)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().grid_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- queries -------------------------------------------------------------
+    def locate(self, points, stream=None) -> torch.Tensor:
+        p = _dev_f64x3(points, self.device)
+        out = torch.empty(p.shape[0], dtype=torch.int32, device=self.device)
+        _check(lib().grid_locate(self._h, _ptr(p), p.shape[0], _ptr(out), _stream(stream)),
+               "grid_locate")
+        return out
+
+    def trace(self, origins, dirs, precision: int = FP64, mode: int = RECORDS,
+              kappa: float = 1.0, capacity: Optional[int] = None, timing: bool = False,
+              count_rechecks: bool = False, stream=None, out: Optional[dict] = None,
+              block: int = 0, persistent: int = -1) -> dict:
+        """Trace paths; returns tau, count (and offsets, leaf, ds in records
+        mode) as device tensors plus needed / rechecks / kernel_ms."""
+        o = _dev_f64x3(origins, self.device)
+        k = _dev_f64x3(dirs, self.device)
+        n = o.shape[0]
+        res = out if out is not None else {}
+        if "tau" not in res or res["tau"].numel() != n:
+            res["tau"] = torch.empty(n, dtype=torch.float64, device=self.device)
+            res["count"] = torch.empty(n, dtype=torch.int32, device=self.device)
+        if mode == RECORDS and ("offsets" not in res or res["offsets"].numel() != n + 1):
+            res["offsets"] = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        opts = TraceOpts()
+        opts.precision = precision
+        opts.mode = mode
+        opts.kappa = kappa
+        opts.flags = (FLAG_TIMING if timing else 0) | (FLAG_RECHECKS if count_rechecks else 0)
+        opts.block = block
+        opts.persistent = persistent
+        dsdt = torch.float64 if precision == FP64 else torch.float32
+        for attempt in range(2):
+            to = TraceOut()
+            to.tau = res["tau"].data_ptr()
+            to.count = res["count"].data_ptr()
+            if mode == RECORDS:
+                cap = capacity if capacity is not None else (
+                    res["leaf"].numel() if "leaf" in res else 64 * max(n, 1))
+                if "leaf" not in res or res["leaf"].numel() < cap or res["ds"].dtype != dsdt:
+                    res["leaf"] = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+                    res["ds"] = torch.empty(max(cap, 1), dtype=dsdt, device=self.device)
+                to.offsets = res["offsets"].data_ptr()
+                to.leaf = res["leaf"].data_ptr()
+                to.ds = res["ds"].data_ptr()
+                to.capacity = res["leaf"].numel()
+            rc = lib().grid_trace(self._h, _ptr(o), _ptr(k), n, C.byref(opts), C.byref(to),
+                                  _stream(stream))
+            if rc == HG_E_CAPACITY and attempt == 0 and capacity is None:
+                capacity = int(to.needed)
+                res.pop("leaf", None)
+                res.pop("ds", None)
+                continue
+            _check(rc, "grid_trace")
+            break
+        res["needed"] = int(to.needed)
+        res["rechecks"] = int(to.rechecks)
+        res["kernel_ms"] = list(to.kernel_ms)
+        return res
+
+    # -- arrays ----------------------------------------------------------------
+    def export(self) -> dict:
+        """Copies of the grid's flat arrays as device tensors."""
+        a = GridArrays()
+        _check(lib().grid_export(self._h, C.byref(a)), "grid_export")
+        N, L = a.n_nodes, a.n_leaves
+        torch.cuda.synchronize(self.device)
+
+        def cp(ptr, shape, dt):
+            t = torch.empty(shape, dtype=dt, device=self.device)
+            if t.numel():
+                rc = _hip().hipMemcpy(C.c_void_p(t.data_ptr()), C.c_void_p(ptr),
+                                      t.numel() * t.element_size(), 3)
+                if rc != 0:
+                    raise RuntimeError(f"hipMemcpy failed ({rc})")
+            return t
+
+        return dict(
+            tree_type=a.tree_type, max_level=a.max_level, lo=tuple(a.lo), side=a.side,
+            n_nodes=N, n_leaves=L,
+            first_child=cp(a.first_child, (N,), torch.int32),
+            rho=cp(a.rho, (L,), torch.float64),
+            level=cp(a.level, (N,), torch.uint8),
+            coord=cp(a.coord, (N, 3), torch.int32),
+            S=cp(a.S, (N,), torch.float64),
+            rho_min=cp(a.rho_min, (N,), torch.float64),
+            rho_max=cp(a.rho_max, (N,), torch.float64),
+            leaf_of=cp(a.leaf_of, (N,), torch.int32),
+            node_of=cp(a.node_of, (L,), torch.int32),
+            rope=cp(a.rope, (N, 6), torch.int32),
+        )
+
+
+def build(density, criteria, tree_type, stream=None, device="cuda", max_nodes=0) -> Grid:
+    return Grid.build(density, criteria, tree_type, stream, device, max_nodes)
+
+
+def import_grid(tree_type, first_child, rho, lo=(-1.0, -1.0, -1.0), side=2.0, stream=None,
+                device="cuda") -> Grid:
+    return Grid.from_arrays(tree_type, first_child, rho, lo, side, stream, device)

@@ -1,0 +1,336 @@
+// C ABI entry points (include/hgrid.h): validation, ownership and dispatch.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace hg {
+
+int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s, hg_grid *g);
+int import_structure(int tree, const std::vector<int32_t> &fc, std::vector<uint8_t> &level,
+                     std::vector<uint32_t> &coord, int64_t level_begin[64], int *max_level);
+
+static thread_local int g_last_hip = 0;
+
+int set_hip_error(hipError_t e)
+{
+    g_last_hip = int(e);
+    return HG_E_HIP;
+}
+
+// Side a power of two; each lower corner an integer multiple of side/2.
+int check_domain(const double lo[3], double side)
+{
+    if (!(side > 0.0) || !isfinite(side)) return HG_E_DOMAIN;
+    int e = 0;
+    if (frexp(side, &e) != 0.5) return HG_E_DOMAIN;
+    if (e < -900 || e > 900) return HG_E_DOMAIN;
+    for (int d = 0; d < 3; d++) {
+        if (!isfinite(lo[d])) return HG_E_DOMAIN;
+        double m = lo[d] / (0.5 * side);
+        if (m != floor(m) || fabs(m) > 1e12) return HG_E_DOMAIN;
+    }
+    return HG_OK;
+}
+
+void free_grid_arrays(hg_grid *g)
+{
+    void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
+                    g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->child,
+                    g->status};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+namespace {
+
+__global__ void k_reset_status(TraceStatus *st)
+{
+    st->rechecks = 0;
+    st->bad_dir = 0;
+    st->step_guard = 0;
+    st->bad_ref = 0;
+    st->next_ray = 0;
+    st->done_waves = 0;
+}
+
+hg_grid *new_grid(int tree, const double lo[3], double side)
+{
+    hg_grid *g = (hg_grid *)calloc(1, sizeof(hg_grid));
+    if (!g) return nullptr;
+    g->tree = tree;
+    for (int d = 0; d < 3; d++) g->lo[d] = lo[d];
+    g->side = side;
+    if (hipMalloc((void **)&g->status, sizeof(TraceStatus)) != hipSuccess) {
+        free(g);
+        return nullptr;
+    }
+    return g;
+}
+
+void destroy(hg_grid *g)
+{
+    if (!g) return;
+    free_grid_arrays(g);
+    free(g);
+}
+
+bool finite_nonneg(double x) { return x >= 0.0 && !isnan(x); }
+
+}  // namespace
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" {
+
+const char *grid_strerror(int code)
+{
+    switch (code) {
+    case HG_OK: return "success";
+    case HG_E_INVAL: return "invalid argument";
+    case HG_E_DOMAIN: return "domain must be a cube of power-of-two side with corners on half-side multiples";
+    case HG_E_DIR: return "direction not a finite unit vector";
+    case HG_E_CAPACITY: return "record capacity too small (see needed)";
+    case HG_E_OOM: return "device allocation failed";
+    case HG_E_LIMIT: return "tree exceeds the library's node limits";
+    case HG_E_HIP: return "HIP runtime error";
+    case HG_E_STEP: return "path step guard exceeded";
+    case HG_E_FORMAT: return "arrays are not a valid breadth-first tree";
+    default: return "unknown status";
+    }
+}
+
+int grid_last_hip_error(void) { return g_last_hip; }
+
+int grid_build(const hg_density *dn, const hg_criteria *cr, int tree_type, void *stream,
+               hg_grid_t *out)
+{
+    if (!dn || !cr || !out) return HG_E_INVAL;
+    *out = nullptr;
+    if (tree_type != HG_OCTREE && tree_type != HG_KDTREE) return HG_E_INVAL;
+    int rc = check_domain(dn->lo, dn->side);
+    if (rc) return rc;
+    const int maxlv = tree_type == HG_OCTREE ? 19 : 57;
+    if (cr->max_level < 0 || cr->max_level > maxlv || cr->min_level < 0) return HG_E_INVAL;
+    if (cr->n_samples <= 0 || cr->n_samples > (1 << 20)) return HG_E_INVAL;
+    if (!(cr->total_mass > 0.0) || !isfinite(cr->total_mass)) return HG_E_INVAL;
+    if (isnan(cr->delta_max) || isnan(cr->tau_max) || isnan(cr->q_max)) return HG_E_INVAL;
+    if (!finite_nonneg(cr->kappa) || !isfinite(cr->kappa)) return HG_E_INVAL;
+    if (dn->n_clumps < 0 || dn->n_clumps > HG_MAX_CLUMPS) return HG_E_INVAL;
+    if (dn->n_clumps > 0) {
+        if (!dn->clump_c || !dn->clump_sigma || !dn->clump_amp) return HG_E_INVAL;
+        if (!(dn->clump_trunc > 0.0) || !isfinite(dn->clump_trunc)) return HG_E_INVAL;
+        for (int64_t i = 0; i < dn->n_clumps; i++)
+            if (!(dn->clump_sigma[i] > 0.0) || !isfinite(dn->clump_sigma[i])) return HG_E_INVAL;
+    }
+    if (dn->has_disk && (!(dn->disk_hR > 0.0) || !(dn->disk_hz > 0.0))) return HG_E_INVAL;
+    hg_grid *g = new_grid(tree_type, dn->lo, dn->side);
+    if (!g) return HG_E_OOM;
+    hipStream_t s = (hipStream_t)stream;
+    rc = build_grid(dn, cr, tree_type, s, g);
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        destroy(g);
+        return rc;
+    }
+    *out = g;
+    return HG_OK;
+}
+
+int grid_import(const hg_grid_arrays *a, void *stream, hg_grid_t *out)
+{
+    if (!a || !out) return HG_E_INVAL;
+    *out = nullptr;
+    if (a->tree_type != HG_OCTREE && a->tree_type != HG_KDTREE) return HG_E_INVAL;
+    if (a->n_nodes < 1 || a->n_nodes >= (int64_t(1) << 31) || !a->first_child || !a->rho)
+        return HG_E_INVAL;
+    int rc = check_domain(a->lo, a->side);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = a->n_nodes;
+    std::vector<int32_t> fc((size_t)n);
+    HG_CHECK(hipMemcpyAsync(fc.data(), a->first_child, size_t(n) * 4, hipMemcpyDeviceToHost, s));
+    HG_CHECK(hipStreamSynchronize(s));
+    std::vector<uint8_t> level;
+    std::vector<uint32_t> coord;
+    hg_grid *g = new_grid(a->tree_type, a->lo, a->side);
+    if (!g) return HG_E_OOM;
+    rc = import_structure(a->tree_type, fc, level, coord, g->level_begin, &g->max_level);
+    int64_t nl = 0;
+    for (int32_t f : fc) nl += f < 0;
+    if (!rc && nl != a->n_leaves) rc = HG_E_FORMAT;
+    if (rc) {
+        destroy(g);
+        return rc;
+    }
+    g->n_nodes = n;
+    const size_t N = size_t(n);
+    if (hipMalloc((void **)&g->first_child, N * 4) != hipSuccess ||
+        hipMalloc((void **)&g->level, N) != hipSuccess ||
+        hipMalloc((void **)&g->coord, N * 12) != hipSuccess ||
+        hipMalloc((void **)&g->S, N * 8) != hipSuccess ||
+        hipMalloc((void **)&g->rmin, N * 8) != hipSuccess ||
+        hipMalloc((void **)&g->rmax, N * 8) != hipSuccess ||
+        hipMalloc((void **)&g->rope, N * 24) != hipSuccess) {
+        destroy(g);
+        return HG_E_OOM;
+    }
+    hipError_t e = hipSuccess;
+    if (!e) e = hipMemcpyAsync(g->first_child, fc.data(), N * 4, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemcpyAsync(g->level, level.data(), N, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemcpyAsync(g->coord, coord.data(), N * 12, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemsetAsync(g->S, 0, N * 8, s);
+    if (!e) e = hipMemsetAsync(g->rmin, 0, N * 8, s);
+    if (!e) e = hipMemsetAsync(g->rmax, 0, N * 8, s);
+    if (e) {
+        destroy(g);
+        return set_hip_error(e);
+    }
+    rc = finalize_layout(g, a->rho, 1, s);
+    if (!rc) {
+        e = hipStreamSynchronize(s);
+        if (e) rc = set_hip_error(e);
+    }
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        destroy(g);
+        return rc;
+    }
+    *out = g;
+    return HG_OK;
+}
+
+int grid_export(hg_grid_t g, hg_grid_arrays *out)
+{
+    if (!g || !out) return HG_E_INVAL;
+    memset(out, 0, sizeof *out);
+    out->tree_type = g->tree;
+    out->max_level = g->max_level;
+    for (int d = 0; d < 3; d++) out->lo[d] = g->lo[d];
+    out->side = g->side;
+    out->n_nodes = g->n_nodes;
+    out->n_leaves = g->n_leaves;
+    out->first_child = g->first_child;
+    out->rho = g->rho;
+    out->level = g->level;
+    out->coord = g->coord;
+    out->S = g->S;
+    out->rho_min = g->rmin;
+    out->rho_max = g->rmax;
+    out->leaf_of = g->leaf_of;
+    out->node_of = g->node_of;
+    out->rope = g->rope;
+    return HG_OK;
+}
+
+void grid_free(hg_grid_t g) { destroy(g); }
+
+int grid_locate(hg_grid_t g, const double *points, int64_t n, int32_t *leaf_out, void *stream)
+{
+    if (!g || n < 0) return HG_E_INVAL;
+    if (n == 0) return HG_OK;
+    if (!points || !leaf_out) return HG_E_INVAL;
+    return launch_locate(g, points, n, leaf_out, (hipStream_t)stream);
+}
+
+int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
+               const hg_trace_opts *opts, hg_trace_out *out, void *stream)
+{
+    if (!g || !opts || !out || n < 0) return HG_E_INVAL;
+    if (opts->precision != HG_FP64 && opts->precision != HG_FP32_RECHECK) return HG_E_INVAL;
+    if (opts->mode != HG_TAU_ONLY && opts->mode != HG_RECORDS) return HG_E_INVAL;
+    if (!isfinite(opts->kappa)) return HG_E_INVAL;
+    const bool records = opts->mode == HG_RECORDS;
+    if (n > 0 && (!origins || !dirs || !out->tau || !out->count)) return HG_E_INVAL;
+    if (records && !out->offsets) return HG_E_INVAL;
+    if (records && out->capacity > 0 && (!out->leaf || !out->ds)) return HG_E_INVAL;
+    if (records && out->capacity < 0) return HG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const bool timing = (opts->flags & HG_FLAG_TIMING) != 0;
+    hipEvent_t ev[5] = {};
+    for (int i = 0; i < 4; i++) out->kernel_ms[i] = 0.f;
+    if (timing)
+        for (int i = 0; i < 5; i++) HG_CHECK(hipEventCreate(&ev[i]));
+    auto cleanup = [&]() {
+        if (timing)
+            for (int i = 0; i < 5; i++)
+                if (ev[i]) (void)hipEventDestroy(ev[i]);
+    };
+    int rc = HG_OK;
+    out->needed = 0;
+    out->rechecks = 0;
+    k_reset_status<<<1, 1, 0, s>>>(g->status);
+    if (timing) (void)hipEventRecord(ev[0], s);
+    rc = launch_walk(g, origins, dirs, n, opts, out, false, s, nullptr);
+    if (timing) (void)hipEventRecord(ev[1], s);
+    TraceStatus st;
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(&st, g->status, sizeof st, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) rc = set_hip_error(e);
+    }
+    if (!rc) {
+        out->rechecks = int64_t(st.rechecks);
+        if (st.bad_ref) rc = HG_E_FORMAT;
+        else if (st.bad_dir) rc = HG_E_DIR;
+        else if (st.step_guard) rc = HG_E_STEP;
+    }
+    int64_t *tmp = nullptr;
+    if (!rc && records) {
+        if (hipMallocAsync((void **)&tmp, scan_tmp_elems(n) * 8, s) != hipSuccess) rc = HG_E_OOM;
+        if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
+        if (timing) (void)hipEventRecord(ev[2], s);
+        int64_t needed = 0;
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(&needed, out->offsets + n, 8, hipMemcpyDeviceToHost, s);
+            if (!e) e = hipStreamSynchronize(s);
+            if (e) rc = set_hip_error(e);
+        }
+        if (!rc) {
+            out->needed = needed;
+            if (needed > out->capacity) rc = HG_E_CAPACITY;
+        }
+        if (!rc && needed > 0) {
+            if (timing) (void)hipEventRecord(ev[3], s);
+            rc = launch_walk(g, origins, dirs, n, opts, out, true, s, nullptr);
+            if (timing) (void)hipEventRecord(ev[4], s);
+        }
+        if (tmp) (void)hipFreeAsync(tmp, s);
+        if (!rc) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e) rc = set_hip_error(e);
+        }
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(&st, g->status, sizeof st, hipMemcpyDeviceToHost, s);
+            if (!e) e = hipStreamSynchronize(s);
+            if (e) rc = set_hip_error(e);
+            else if (st.bad_ref) rc = HG_E_FORMAT;
+            else if (st.step_guard) rc = HG_E_STEP;
+        }
+    }
+    if (timing && (rc == HG_OK || rc == HG_E_CAPACITY)) {
+        (void)hipEventSynchronize(ev[1]);
+        (void)hipEventElapsedTime(&out->kernel_ms[0], ev[0], ev[1]);
+        if (records) {
+            (void)hipEventSynchronize(ev[2]);
+            (void)hipEventElapsedTime(&out->kernel_ms[1], ev[1], ev[2]);
+            if (rc == HG_OK && out->needed > 0) {
+                (void)hipEventSynchronize(ev[4]);
+                (void)hipEventElapsedTime(&out->kernel_ms[2], ev[3], ev[4]);
+                (void)hipEventElapsedTime(&out->kernel_ms[3], ev[0], ev[4]);
+            } else {
+                (void)hipEventElapsedTime(&out->kernel_ms[3], ev[0], ev[2]);
+            }
+        } else {
+            out->kernel_ms[3] = out->kernel_ms[0];
+        }
+    }
+    cleanup();
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,503 @@
+// Grid construction on the GPU (Sect. 2.2, Eq. 1-3 of Sect. 4).
+//
+// The construction loop of the paper walks a growing node list once, deciding
+// each node and appending the children of split nodes.  Breadth-first order
+// makes that list level-synchronous: the nodes of level l are a contiguous
+// slice, and an exclusive prefix sum of their split flags gives every child its
+// slot in level l+1 in exactly the order the sequential loop would append it.
+// Per level:  k_sample_decide (one wavefront per node, one Monte Carlo sample
+// per lane: node mass of Eq. 1, criteria delta, tau of Eq. 2, q of Eq. 3),
+// prefix sum of split flags, k_append (children's level and cell coordinates).
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace hg {
+
+namespace {
+
+constexpr int BT = 256;
+constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64 output for state x (Steele, Lea & Flood 2014): advance by the
+// golden gamma, then the published mixing function.
+__device__ inline uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + GAMMA;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Node code: level in bits 57.., cell coordinates in 19-bit fields.
+__device__ inline uint64_t node_key(uint64_t seed, int level, uint32_t c0, uint32_t c1, uint32_t c2)
+{
+    uint64_t code = (uint64_t(level) << 57) | (uint64_t(c0) << 38) | (uint64_t(c1) << 19) | uint64_t(c2);
+    return splitmix64(seed ^ splitmix64(code));
+}
+
+// Uniform double in [0,1) for sample j, axis d.
+__device__ inline double sample_unit(uint64_t key, int j, int d)
+{
+    uint64_t r = splitmix64(key ^ (uint64_t(3 * j + d + 1) * GAMMA));
+    return double(r >> 11) * 0x1.0p-53;
+}
+
+__device__ inline int bin_of(const Dens &D, double x, int d)
+{
+    int b = int(floor((x - D.lo[d]) * D.bin_scale));
+    return b < 0 ? 0 : (b >= D.B ? D.B - 1 : b);
+}
+
+// rho_t(x): box, disk, clumps in ascending index, torus -- added in that order.
+__device__ double density_at(const Dens &D, double x0, double x1, double x2,
+                             const int64_t *__restrict__ bin_start)
+{
+    double rho = 0.0;
+    if (D.has_box) {
+        if (x0 >= D.box_lo[0] && x0 <= D.box_hi[0] && x1 >= D.box_lo[1] && x1 <= D.box_hi[1] &&
+            x2 >= D.box_lo[2] && x2 <= D.box_hi[2])
+            rho = rho + D.box_rho;
+    }
+    if (D.has_disk) {
+        double R = sqrt(x0 * x0 + x1 * x1);
+        double arg = -(R / D.disk_hR) - fabs(x2) / D.disk_hz;
+        rho = rho + D.disk_rho0 * exp(arg);
+    }
+    if (D.n_clumps > 0) {
+        int b = (bin_of(D, x0, 0) * D.B + bin_of(D, x1, 1)) * D.B + bin_of(D, x2, 2);
+        int64_t e = bin_start[b + 1];
+        for (int64_t j = bin_start[b]; j < e; j++) {
+            uint32_t i = D.bin_items[j];
+            double s = D.cs[i];
+            double lim = D.trunc * s;
+            double dx = x0 - D.cc[3 * i + 0];
+            double dy = x1 - D.cc[3 * i + 1];
+            double dz = x2 - D.cc[3 * i + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 <= lim * lim) {
+                double ee = r2 / (2.0 * s * s);
+                rho = rho + D.ca[i] * exp(-ee);
+            }
+        }
+    }
+    if (D.has_torus) {
+        double R = sqrt(x0 * x0 + x1 * x1);
+        double dR = R - D.torus_R0;
+        if (dR * dR + x2 * x2 <= D.torus_a * D.torus_a) rho = rho + D.torus_rho;
+    }
+    return rho;
+}
+
+// ---- clump binning --------------------------------------------------------
+
+__device__ inline bool clump_bin_range(const Dens &D, uint32_t i, int lo[3], int hi[3])
+{
+    double R = D.trunc * D.cs[i];
+    for (int d = 0; d < 3; d++) {
+        double c = D.cc[3 * i + d];
+        int a = int(floor((c - R - D.lo[d]) * D.bin_scale)) - 1;
+        int b = int(floor((c + R - D.lo[d]) * D.bin_scale)) + 1;
+        if (b < 0 || a > D.B - 1) return false;
+        lo[d] = a < 0 ? 0 : a;
+        hi[d] = b > D.B - 1 ? D.B - 1 : b;
+    }
+    return true;
+}
+
+__global__ void __launch_bounds__(BT) k_bin_count(Dens D, int32_t *__restrict__ cnt)
+{
+    uint32_t i = blockIdx.x * BT + threadIdx.x;
+    if (int(i) >= D.n_clumps) return;
+    int lo[3], hi[3];
+    if (!clump_bin_range(D, i, lo, hi)) return;
+    for (int x = lo[0]; x <= hi[0]; x++)
+        for (int y = lo[1]; y <= hi[1]; y++)
+            for (int z = lo[2]; z <= hi[2]; z++) atomicAdd(&cnt[(x * D.B + y) * D.B + z], 1);
+}
+
+__global__ void __launch_bounds__(BT) k_bin_fill(Dens D, const int64_t *__restrict__ start,
+                                                 int32_t *__restrict__ cursor,
+                                                 uint32_t *__restrict__ items)
+{
+    uint32_t i = blockIdx.x * BT + threadIdx.x;
+    if (int(i) >= D.n_clumps) return;
+    int lo[3], hi[3];
+    if (!clump_bin_range(D, i, lo, hi)) return;
+    for (int x = lo[0]; x <= hi[0]; x++)
+        for (int y = lo[1]; y <= hi[1]; y++)
+            for (int z = lo[2]; z <= hi[2]; z++) {
+                int b = (x * D.B + y) * D.B + z;
+                int p = atomicAdd(&cursor[b], 1);
+                items[start[b] + p] = i;
+            }
+}
+
+// Sort each bin's clump list ascending (insertion sort; lists are short).
+__global__ void __launch_bounds__(BT) k_bin_sort(int n_bins, const int64_t *__restrict__ start,
+                                                 uint32_t *__restrict__ items)
+{
+    int b = blockIdx.x * BT + threadIdx.x;
+    if (b >= n_bins) return;
+    int64_t s = start[b], e = start[b + 1];
+    for (int64_t i = s + 1; i < e; i++) {
+        uint32_t v = items[i];
+        int64_t j = i - 1;
+        while (j >= s && items[j] > v) {
+            items[j + 1] = items[j];
+            j--;
+        }
+        items[j + 1] = v;
+    }
+}
+
+// ---- per-level kernels ------------------------------------------------------
+
+struct CritDev {
+    double total_mass, delta_max, tau_max, q_max, kappa;
+    int min_level, max_level, n_samples;
+    uint64_t seed;
+};
+
+__device__ inline double read_lane_f64(double v, int lane)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
+}
+
+// One 64-lane wavefront per node of the level slice [begin, begin+count).
+// Lane j draws samples j, j+64, ...; the sum S runs in sample order (an ordered
+// reduction through readlane), min and max are order-free.
+__global__ void __launch_bounds__(BT)
+    k_sample_decide(int tree, Dens D, CritDev C, int64_t begin, int64_t count,
+                    const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
+                    const int64_t *__restrict__ bin_start, double *__restrict__ S_out,
+                    double *__restrict__ mn_out, double *__restrict__ mx_out,
+                    uint8_t *__restrict__ split)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t(blockIdx.x) * BT + threadIdx.x) >> 6;
+    if (t >= count) return;  // whole wavefront leaves together
+    const int64_t i = begin + t;
+    const int lv = level[i];
+    const uint32_t c0 = coord[3 * i], c1 = coord[3 * i + 1], c2 = coord[3 * i + 2];
+    double w[3], lo[3];
+    const uint32_t c[3] = {c0, c1, c2};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        w[d] = ldexp(D.side, -axis_depth(tree, lv, d));
+        lo[d] = D.lo[d] + double(c[d]) * w[d];
+    }
+    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
+    double S = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int base = 0; base < C.n_samples; base += 64) {
+        const int j = base + lane;
+        double r = 0.0;
+        if (j < C.n_samples) {
+            double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
+            double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
+            double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
+            r = density_at(D, x0, x1, x2, bin_start);
+            mn = fmin(mn, r);
+            mx = fmax(mx, r);
+        }
+        const int m = min(64, C.n_samples - base);
+        for (int jj = 0; jj < m; jj++) S = S + read_lane_f64(r, jj);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    if (lane != 0) return;
+    // Eq. (1): M = V/N sum rho; delta = M/M_tot; Eq. (2); Eq. (3).
+    double V = w[0] * w[1] * w[2];
+    double M = S * (V / double(C.n_samples));
+    double delta = M / C.total_mass;
+    double diag = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double tau = C.kappa * M * diag / (w[0] * w[1] * w[2]);
+    double q = mx > 0.0 ? (mx - mn) / mx : 0.0;
+    bool sp;
+    if (lv < C.min_level) sp = true;
+    else if (lv >= C.max_level) sp = false;
+    else sp = delta > C.delta_max || tau > C.tau_max || q > C.q_max;
+    S_out[i] = S;
+    mn_out[i] = mn;
+    mx_out[i] = mx;
+    split[t] = sp ? 1 : 0;
+}
+
+// Children of the split nodes of the level slice, in list order.
+__global__ void __launch_bounds__(BT)
+    k_append(int tree, int64_t begin, int64_t count, int64_t next, const uint8_t *__restrict__ split,
+             const int64_t *__restrict__ off, int32_t *__restrict__ fc, uint8_t *__restrict__ level,
+             uint32_t *__restrict__ coord)
+{
+    int64_t t = int64_t(blockIdx.x) * BT + threadIdx.x;
+    if (t >= count) return;
+    int64_t i = begin + t;
+    if (!split[t]) {
+        fc[i] = -1;
+        return;
+    }
+    const int nc = tree == OCT ? 8 : 2;
+    int64_t f = next + off[t] * nc;
+    fc[i] = int32_t(f);
+    int lv = level[i];
+    uint32_t c[3] = {coord[3 * i], coord[3 * i + 1], coord[3 * i + 2]};
+    for (int k = 0; k < nc; k++) {
+        uint32_t cc[3] = {c[0], c[1], c[2]};
+        if (tree == KD) {
+            int a = lv % 3;
+            cc[a] = 2u * c[a] + uint32_t(k);
+        } else {
+            for (int d = 0; d < 3; d++) cc[d] = 2u * c[d] + uint32_t((k >> d) & 1);
+        }
+        int64_t ch = f + k;
+        level[ch] = uint8_t(lv + 1);
+        coord[3 * ch] = cc[0];
+        coord[3 * ch + 1] = cc[1];
+        coord[3 * ch + 2] = cc[2];
+        fc[ch] = -1;
+    }
+}
+
+__global__ void k_init_root(int32_t *fc, uint8_t *level, uint32_t *coord)
+{
+    fc[0] = -1;
+    level[0] = 0;
+    coord[0] = coord[1] = coord[2] = 0;
+}
+
+inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+template <typename T>
+int grow_array(T **p, int64_t old_n, int64_t new_cap, size_t per, hipStream_t s)
+{
+    T *q = nullptr;
+    if (hipMalloc((void **)&q, size_t(new_cap) * per * sizeof(T)) != hipSuccess) return HG_E_OOM;
+    if (*p && old_n > 0)
+        HG_CHECK(hipMemcpyAsync(q, *p, size_t(old_n) * per * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HG_CHECK(hipStreamSynchronize(s));
+    if (*p) (void)hipFree(*p);
+    *p = q;
+    return HG_OK;
+}
+
+int grow_nodes(hg_grid *g, int64_t used, int64_t *cap, int64_t need, hipStream_t s)
+{
+    if (need <= *cap) return HG_OK;
+    int64_t c = *cap ? *cap : 4096;
+    while (c < need) c *= 2;
+    int rc;
+    if ((rc = grow_array(&g->first_child, used, c, 1, s))) return rc;
+    if ((rc = grow_array(&g->level, used, c, 1, s))) return rc;
+    if ((rc = grow_array(&g->coord, used, c, 3, s))) return rc;
+    if ((rc = grow_array(&g->S, used, c, 1, s))) return rc;
+    if ((rc = grow_array(&g->rmin, used, c, 1, s))) return rc;
+    if ((rc = grow_array(&g->rmax, used, c, 1, s))) return rc;
+    *cap = c;
+    return HG_OK;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s, hg_grid *g)
+{
+    const int nc = tree == OCT ? 8 : 2;
+    // ---- density on the device ----
+    Dens D;
+    memset(&D, 0, sizeof D);
+    for (int d = 0; d < 3; d++) D.lo[d] = dn->lo[d];
+    D.side = dn->side;
+    D.has_box = dn->has_box != 0;
+    for (int d = 0; d < 3; d++) {
+        D.box_lo[d] = dn->box_lo[d];
+        D.box_hi[d] = dn->box_hi[d];
+    }
+    D.box_rho = dn->box_rho;
+    D.has_disk = dn->has_disk != 0;
+    D.disk_rho0 = dn->disk_rho0;
+    D.disk_hR = dn->disk_hR;
+    D.disk_hz = dn->disk_hz;
+    D.has_torus = dn->has_torus != 0;
+    D.torus_R0 = dn->torus_R0;
+    D.torus_a = dn->torus_a;
+    D.torus_rho = dn->torus_rho;
+    D.trunc = dn->clump_trunc;
+    D.n_clumps = int(dn->n_clumps);
+    DevBuf cc, cs, ca, bstart, bitems, bcnt;
+    D.B = 1;
+    D.bin_scale = 1.0 / dn->side;
+    if (D.n_clumps > 0) {
+        const size_t n = size_t(D.n_clumps);
+        if (hipMalloc(&cc.p, n * 24) != hipSuccess || hipMalloc(&cs.p, n * 8) != hipSuccess ||
+            hipMalloc(&ca.p, n * 8) != hipSuccess)
+            return HG_E_OOM;
+        HG_CHECK(hipMemcpyAsync(cc.p, dn->clump_c, n * 24, hipMemcpyHostToDevice, s));
+        HG_CHECK(hipMemcpyAsync(cs.p, dn->clump_sigma, n * 8, hipMemcpyHostToDevice, s));
+        HG_CHECK(hipMemcpyAsync(ca.p, dn->clump_amp, n * 8, hipMemcpyHostToDevice, s));
+        D.cc = (const double *)cc.p;
+        D.cs = (const double *)cs.p;
+        D.ca = (const double *)ca.p;
+        // bin width about twice the mean truncation radius, at most 128 bins per axis
+        double rsum = 0.0;
+        for (size_t i = 0; i < n; i++) rsum += dn->clump_trunc * fabs(dn->clump_sigma[i]);
+        double rmean = rsum / double(n);
+        int B = rmean > 0.0 ? int(dn->side / (2.0 * rmean)) : 1;
+        B = std::max(1, std::min(128, B));
+        D.B = B;
+        D.bin_scale = double(B) / dn->side;
+        const int64_t nb = int64_t(B) * B * B;
+        DevBuf tmp;
+        if (hipMalloc(&bcnt.p, size_t(nb) * 4) != hipSuccess ||
+            hipMalloc(&bstart.p, size_t(nb + 1) * 8) != hipSuccess ||
+            hipMalloc(&tmp.p, scan_tmp_elems(nb) * 8) != hipSuccess)
+            return HG_E_OOM;
+        HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
+        k_bin_count<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (int32_t *)bcnt.p);
+        HG_CHECK(hipGetLastError());
+        int rc = scan_i32_to_i64((const int32_t *)bcnt.p, (int64_t *)bstart.p, nb, (int64_t *)tmp.p, s);
+        if (rc) return rc;
+        int64_t items = 0;
+        HG_CHECK(hipMemcpyAsync(&items, (int64_t *)bstart.p + nb, 8, hipMemcpyDeviceToHost, s));
+        HG_CHECK(hipStreamSynchronize(s));
+        if (hipMalloc(&bitems.p, size_t(items > 0 ? items : 1) * 4) != hipSuccess) return HG_E_OOM;
+        HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
+        k_bin_fill<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (const int64_t *)bstart.p,
+                                                          (int32_t *)bcnt.p, (uint32_t *)bitems.p);
+        HG_CHECK(hipGetLastError());
+        k_bin_sort<<<nblocks(nb, BT), BT, 0, s>>>(int(nb), (const int64_t *)bstart.p,
+                                                  (uint32_t *)bitems.p);
+        HG_CHECK(hipGetLastError());
+        D.bin_items = (const uint32_t *)bitems.p;
+    }
+    const int64_t *bin_start = (const int64_t *)bstart.p;
+
+    CritDev C;
+    C.total_mass = cr->total_mass;
+    C.delta_max = cr->delta_max;
+    C.tau_max = cr->tau_max;
+    C.q_max = cr->q_max;
+    C.kappa = cr->kappa;
+    C.min_level = cr->min_level;
+    C.max_level = cr->max_level;
+    C.n_samples = cr->n_samples;
+    C.seed = cr->seed;
+
+    // ---- level loop ----
+    int64_t cap = 0;
+    int rc = grow_nodes(g, 0, &cap, 4096, s);
+    if (rc) return rc;
+    k_init_root<<<1, 1, 0, s>>>(g->first_child, g->level, g->coord);
+    HG_CHECK(hipGetLastError());
+    DevBuf split, off, tmp;
+    int64_t scap = 0;
+    int64_t begin = 0, end = 1;
+    int lv = 0;
+    g->level_begin[0] = 0;
+    const int64_t max_nodes = cr->max_nodes > 0 ? cr->max_nodes : (int64_t(1) << 31) - 16;
+    for (;;) {
+        const int64_t cnt = end - begin;
+        if (cnt > scap) {
+            int64_t c = std::max<int64_t>(cnt, 4096);
+            if (split.p) (void)hipFree(split.p);
+            if (off.p) (void)hipFree(off.p);
+            if (tmp.p) (void)hipFree(tmp.p);
+            split.p = off.p = tmp.p = nullptr;
+            if (hipMalloc(&split.p, size_t(c)) != hipSuccess ||
+                hipMalloc(&off.p, size_t(c + 1) * 8) != hipSuccess ||
+                hipMalloc(&tmp.p, scan_tmp_elems(c) * 8) != hipSuccess)
+                return HG_E_OOM;
+            scap = c;
+        }
+        k_sample_decide<<<nblocks(cnt * 64, BT), BT, 0, s>>>(tree, D, C, begin, cnt, g->level,
+                                                              g->coord, bin_start, g->S, g->rmin,
+                                                              g->rmax, (uint8_t *)split.p);
+        HG_CHECK(hipGetLastError());
+        rc = scan_u8_to_i64((const uint8_t *)split.p, (int64_t *)off.p, cnt, (int64_t *)tmp.p, s);
+        if (rc) return rc;
+        int64_t n_split = 0;
+        HG_CHECK(hipMemcpyAsync(&n_split, (int64_t *)off.p + cnt, 8, hipMemcpyDeviceToHost, s));
+        HG_CHECK(hipStreamSynchronize(s));
+        const int64_t n_next = n_split * nc;
+        if (n_next == 0) break;
+        if (end + n_next > max_nodes) return HG_E_LIMIT;
+        if ((rc = grow_nodes(g, end, &cap, end + n_next, s))) return rc;
+        k_append<<<nblocks(cnt, BT), BT, 0, s>>>(tree, begin, cnt, end, (const uint8_t *)split.p,
+                                                 (const int64_t *)off.p, g->first_child, g->level,
+                                                 g->coord);
+        HG_CHECK(hipGetLastError());
+        lv++;
+        g->level_begin[lv] = end;
+        begin = end;
+        end += n_next;
+        if (lv > 62) return HG_E_LIMIT;
+    }
+    g->n_nodes = end;
+    g->max_level = lv;
+    g->level_begin[lv + 1] = end;
+    if (hipMalloc((void **)&g->rope, size_t(end) * 6 * 4) != hipSuccess) return HG_E_OOM;
+    return finalize_layout(g, nullptr, cr->n_samples, s);
+}
+
+// Levels and cell coordinates of an imported breadth-first tree, on the host,
+// with the structural checks the node list must satisfy.
+int import_structure(int tree, const std::vector<int32_t> &fc, std::vector<uint8_t> &level,
+                     std::vector<uint32_t> &coord, int64_t level_begin[64], int *max_level)
+{
+    const int64_t n = int64_t(fc.size());
+    const int nc = tree == OCT ? 8 : 2;
+    const int maxlv = tree == OCT ? 19 : 57;
+    level.assign(size_t(n), 0);
+    coord.assign(size_t(n) * 3, 0);
+    int64_t expect = 1;
+    for (int64_t i = 0; i < n; i++) {
+        int32_t f = fc[size_t(i)];
+        if (f < 0) continue;
+        if (f != expect || int64_t(f) + nc > n || level[size_t(i)] >= maxlv) return HG_E_FORMAT;
+        expect += nc;
+        int lv = level[size_t(i)];
+        for (int k = 0; k < nc; k++) {
+            uint32_t c[3] = {coord[3 * size_t(i)], coord[3 * size_t(i) + 1], coord[3 * size_t(i) + 2]};
+            if (tree == KD) {
+                int a = lv % 3;
+                c[a] = 2u * c[a] + uint32_t(k);
+            } else {
+                for (int d = 0; d < 3; d++) c[d] = 2u * c[d] + uint32_t((k >> d) & 1);
+            }
+            size_t ch = size_t(f) + size_t(k);
+            level[ch] = uint8_t(lv + 1);
+            for (int d = 0; d < 3; d++) coord[3 * ch + d] = c[d];
+        }
+    }
+    if (expect != n) return HG_E_FORMAT;
+    int ml = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int l = level[size_t(i)];
+        if (i > 0 && l < level[size_t(i - 1)]) return HG_E_FORMAT;
+        if (l > ml) {
+            for (int k = ml + 1; k <= l; k++) level_begin[k] = i;
+            ml = l;
+        }
+    }
+    level_begin[0] = 0;
+    level_begin[ml + 1] = n;
+    *max_level = ml;
+    return HG_OK;
+}
+
+}  // namespace hg
