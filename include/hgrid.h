@@ -110,9 +110,12 @@ typedef struct {
     int32_t mode;       /* HG_TAU_ONLY or HG_RECORDS */
     double kappa;       /* opacity in tau = sum kappa rho ds */
     int32_t flags;      /* HG_FLAG_* */
-    int32_t block;      /* threads per block, 0 = library choice */
-    int32_t persistent; /* 1 = persistent lane-refill walk, 0 = one thread per path, -1 = library choice */
-    int32_t reserved;
+    int32_t block;      /* reserved, 0 */
+    int32_t persistent; /* persistent lane-refill walk for: bit 0 the counting / tau-only walk,
+                           bit 1 the record-filling walk (else one thread per path);
+                           -1 = library choice */
+    int32_t chunk;      /* persistent walk: paths a wavefront takes per atomic, 0 = library choice */
+    int32_t refill_min; /* persistent walk: idle lanes that trigger a refill (1..64), 0 = library choice */
 } hg_trace_opts;
 
 /* Outputs of grid_trace; every array is a caller-owned device buffer.
@@ -121,6 +124,7 @@ typedef struct {
  *   offsets[n+1] int64, exclusive prefix sum of count (HG_RECORDS only)
  *   leaf[cap]    int32 leaf ids in path order (HG_RECORDS only)
  *   ds[cap]      double (HG_FP64) or float (HG_FP32_RECHECK) lengths
+ *   (leaf and ds must be 16-byte aligned; HG_E_INVAL otherwise)
  * Set by the call: needed (= offsets[n], the total crossings), rechecks
  * (with HG_FLAG_RECHECKS) and kernel_ms[] (with HG_FLAG_TIMING: [0] count or
  * tau-only walk, [1] prefix sum, [2] record-filling walk, [3] whole call). */

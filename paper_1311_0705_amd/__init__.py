@@ -71,7 +71,7 @@ class TraceOpts(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("mode", C.c_int32), ("kappa", C.c_double),
         ("flags", C.c_int32), ("block", C.c_int32), ("persistent", C.c_int32),
-        ("reserved", C.c_int32),
+        ("chunk", C.c_int32), ("refill_min", C.c_int32),
     ]
 
 
@@ -286,7 +286,7 @@ class Grid:
     def trace(self, origins, dirs, precision: int = FP64, mode: int = RECORDS,
               kappa: float = 1.0, capacity: Optional[int] = None, timing: bool = False,
               count_rechecks: bool = False, stream=None, out: Optional[dict] = None,
-              block: int = 0, persistent: int = -1) -> dict:
+              block: int = 0, persistent: int = -1, chunk: int = 0, refill_min: int = 0) -> dict:
         """Trace paths; returns tau, count (and offsets, leaf, ds in records
         mode) as device tensors plus needed / rechecks / kernel_ms."""
         o = _dev_f64x3(origins, self.device)
@@ -305,6 +305,8 @@ class Grid:
         opts.flags = (FLAG_TIMING if timing else 0) | (FLAG_RECHECKS if count_rechecks else 0)
         opts.block = block
         opts.persistent = persistent
+        opts.chunk = chunk
+        opts.refill_min = refill_min
         dsdt = torch.float64 if precision == FP64 else torch.float32
         for attempt in range(2):
             to = TraceOut()

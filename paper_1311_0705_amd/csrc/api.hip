@@ -36,13 +36,37 @@ int check_domain(const double lo[3], double side)
     return HG_OK;
 }
 
+int dalloc(void **p, size_t bytes, hipStream_t s)
+{
+    static bool pool_ready = false;
+    if (!pool_ready) {
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+        pool_ready = true;
+    }
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMallocAsync(p, bytes, s);
+    if (e == hipErrorOutOfMemory) return HG_E_OOM;
+    if (e != hipSuccess) return set_hip_error(e);
+    return HG_OK;
+}
+
+void dfree(void *p, hipStream_t s)
+{
+    if (p) (void)hipFreeAsync(p, s);
+}
+
 void free_grid_arrays(hg_grid *g)
 {
     void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
                     g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->child,
                     g->status};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void *p : ptrs) dfree(p, nullptr);
 }
 
 namespace {
@@ -64,7 +88,7 @@ hg_grid *new_grid(int tree, const double lo[3], double side)
     g->tree = tree;
     for (int d = 0; d < 3; d++) g->lo[d] = lo[d];
     g->side = side;
-    if (hipMalloc((void **)&g->status, sizeof(TraceStatus)) != hipSuccess) {
+    if (dalloc((void **)&g->status, sizeof(TraceStatus), nullptr) != HG_OK) {
         free(g);
         return nullptr;
     }
@@ -169,13 +193,10 @@ int grid_import(const hg_grid_arrays *a, void *stream, hg_grid_t *out)
     }
     g->n_nodes = n;
     const size_t N = size_t(n);
-    if (hipMalloc((void **)&g->first_child, N * 4) != hipSuccess ||
-        hipMalloc((void **)&g->level, N) != hipSuccess ||
-        hipMalloc((void **)&g->coord, N * 12) != hipSuccess ||
-        hipMalloc((void **)&g->S, N * 8) != hipSuccess ||
-        hipMalloc((void **)&g->rmin, N * 8) != hipSuccess ||
-        hipMalloc((void **)&g->rmax, N * 8) != hipSuccess ||
-        hipMalloc((void **)&g->rope, N * 24) != hipSuccess) {
+    if (dalloc_n(&g->first_child, N, s) || dalloc_n(&g->level, N, s) ||
+        dalloc_n(&g->coord, N * 3, s) || dalloc_n(&g->S, N, s) || dalloc_n(&g->rmin, N, s) ||
+        dalloc_n(&g->rmax, N, s) || dalloc_n(&g->rope, N * 6, s)) {
+        (void)hipStreamSynchronize(s);
         destroy(g);
         return HG_E_OOM;
     }
@@ -249,6 +270,7 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     if (records && !out->offsets) return HG_E_INVAL;
     if (records && out->capacity > 0 && (!out->leaf || !out->ds)) return HG_E_INVAL;
     if (records && out->capacity < 0) return HG_E_INVAL;
+    if (records && ((uintptr_t(out->leaf) | uintptr_t(out->ds)) & 15u)) return HG_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
     const bool timing = (opts->flags & HG_FLAG_TIMING) != 0;
     hipEvent_t ev[5] = {};
@@ -281,7 +303,7 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     }
     int64_t *tmp = nullptr;
     if (!rc && records) {
-        if (hipMallocAsync((void **)&tmp, scan_tmp_elems(n) * 8, s) != hipSuccess) rc = HG_E_OOM;
+        rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
         if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
         if (timing) (void)hipEventRecord(ev[2], s);
         int64_t needed = 0;
@@ -299,7 +321,7 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
             rc = launch_walk(g, origins, dirs, n, opts, out, true, s, nullptr);
             if (timing) (void)hipEventRecord(ev[4], s);
         }
-        if (tmp) (void)hipFreeAsync(tmp, s);
+        dfree(tmp, s);
         if (!rc) {
             hipError_t e = hipStreamSynchronize(s);
             if (e) rc = set_hip_error(e);

@@ -280,11 +280,11 @@ template <typename T>
 int grow_array(T **p, int64_t old_n, int64_t new_cap, size_t per, hipStream_t s)
 {
     T *q = nullptr;
-    if (hipMalloc((void **)&q, size_t(new_cap) * per * sizeof(T)) != hipSuccess) return HG_E_OOM;
+    int rc = dalloc_n(&q, size_t(new_cap) * per, s);
+    if (rc) return rc;
     if (*p && old_n > 0)
         HG_CHECK(hipMemcpyAsync(q, *p, size_t(old_n) * per * sizeof(T), hipMemcpyDeviceToDevice, s));
-    HG_CHECK(hipStreamSynchronize(s));
-    if (*p) (void)hipFree(*p);
+    dfree(*p, s);
     *p = q;
     return HG_OK;
 }
@@ -305,12 +305,18 @@ int grow_nodes(hg_grid *g, int64_t used, int64_t *cap, int64_t need, hipStream_t
     return HG_OK;
 }
 
+// Scratch buffer released on the stream when it goes out of scope.
 struct DevBuf {
     void *p = nullptr;
-    ~DevBuf()
+    hipStream_t s = nullptr;
+    explicit DevBuf(hipStream_t st) : s(st) {}
+    int alloc(size_t bytes)
     {
-        if (p) (void)hipFree(p);
+        dfree(p, s);
+        p = nullptr;
+        return dalloc(&p, bytes, s);
     }
+    ~DevBuf() { dfree(p, s); }
 };
 
 }  // namespace
@@ -339,14 +345,15 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
     D.torus_rho = dn->torus_rho;
     D.trunc = dn->clump_trunc;
     D.n_clumps = int(dn->n_clumps);
-    DevBuf cc, cs, ca, bstart, bitems, bcnt;
+    DevBuf cc(s), cs(s), ca(s), bstart(s), bitems(s), bcnt(s), btmp(s);
     D.B = 1;
     D.bin_scale = 1.0 / dn->side;
     if (D.n_clumps > 0) {
         const size_t n = size_t(D.n_clumps);
-        if (hipMalloc(&cc.p, n * 24) != hipSuccess || hipMalloc(&cs.p, n * 8) != hipSuccess ||
-            hipMalloc(&ca.p, n * 8) != hipSuccess)
-            return HG_E_OOM;
+        int rc0 = cc.alloc(n * 24);
+        if (!rc0) rc0 = cs.alloc(n * 8);
+        if (!rc0) rc0 = ca.alloc(n * 8);
+        if (rc0) return rc0;
         HG_CHECK(hipMemcpyAsync(cc.p, dn->clump_c, n * 24, hipMemcpyHostToDevice, s));
         HG_CHECK(hipMemcpyAsync(cs.p, dn->clump_sigma, n * 8, hipMemcpyHostToDevice, s));
         HG_CHECK(hipMemcpyAsync(ca.p, dn->clump_amp, n * 8, hipMemcpyHostToDevice, s));
@@ -362,20 +369,20 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
         D.B = B;
         D.bin_scale = double(B) / dn->side;
         const int64_t nb = int64_t(B) * B * B;
-        DevBuf tmp;
-        if (hipMalloc(&bcnt.p, size_t(nb) * 4) != hipSuccess ||
-            hipMalloc(&bstart.p, size_t(nb + 1) * 8) != hipSuccess ||
-            hipMalloc(&tmp.p, scan_tmp_elems(nb) * 8) != hipSuccess)
-            return HG_E_OOM;
+        rc0 = bcnt.alloc(size_t(nb) * 4);
+        if (!rc0) rc0 = bstart.alloc(size_t(nb + 1) * 8);
+        if (!rc0) rc0 = btmp.alloc(scan_tmp_elems(nb) * 8);
+        if (rc0) return rc0;
         HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
         k_bin_count<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (int32_t *)bcnt.p);
         HG_CHECK(hipGetLastError());
-        int rc = scan_i32_to_i64((const int32_t *)bcnt.p, (int64_t *)bstart.p, nb, (int64_t *)tmp.p, s);
+        int rc = scan_i32_to_i64((const int32_t *)bcnt.p, (int64_t *)bstart.p, nb,
+                                 (int64_t *)btmp.p, s);
         if (rc) return rc;
         int64_t items = 0;
         HG_CHECK(hipMemcpyAsync(&items, (int64_t *)bstart.p + nb, 8, hipMemcpyDeviceToHost, s));
         HG_CHECK(hipStreamSynchronize(s));
-        if (hipMalloc(&bitems.p, size_t(items > 0 ? items : 1) * 4) != hipSuccess) return HG_E_OOM;
+        if ((rc = bitems.alloc(size_t(items > 0 ? items : 1) * 4))) return rc;
         HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
         k_bin_fill<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (const int64_t *)bstart.p,
                                                           (int32_t *)bcnt.p, (uint32_t *)bitems.p);
@@ -404,7 +411,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
     if (rc) return rc;
     k_init_root<<<1, 1, 0, s>>>(g->first_child, g->level, g->coord);
     HG_CHECK(hipGetLastError());
-    DevBuf split, off, tmp;
+    DevBuf split(s), off(s), tmp(s);
     int64_t scap = 0;
     int64_t begin = 0, end = 1;
     int lv = 0;
@@ -414,14 +421,10 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
         const int64_t cnt = end - begin;
         if (cnt > scap) {
             int64_t c = std::max<int64_t>(cnt, 4096);
-            if (split.p) (void)hipFree(split.p);
-            if (off.p) (void)hipFree(off.p);
-            if (tmp.p) (void)hipFree(tmp.p);
-            split.p = off.p = tmp.p = nullptr;
-            if (hipMalloc(&split.p, size_t(c)) != hipSuccess ||
-                hipMalloc(&off.p, size_t(c + 1) * 8) != hipSuccess ||
-                hipMalloc(&tmp.p, scan_tmp_elems(c) * 8) != hipSuccess)
-                return HG_E_OOM;
+            while (c < 2 * cnt) c *= 2;
+            if ((rc = split.alloc(size_t(c)))) return rc;
+            if ((rc = off.alloc(size_t(c + 1) * 8))) return rc;
+            if ((rc = tmp.alloc(scan_tmp_elems(c) * 8))) return rc;
             scap = c;
         }
         k_sample_decide<<<nblocks(cnt * 64, BT), BT, 0, s>>>(tree, D, C, begin, cnt, g->level,
@@ -450,7 +453,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
     g->n_nodes = end;
     g->max_level = lv;
     g->level_begin[lv + 1] = end;
-    if (hipMalloc((void **)&g->rope, size_t(end) * 6 * 4) != hipSuccess) return HG_E_OOM;
+    if ((rc = dalloc_n(&g->rope, size_t(end) * 6, s))) return rc;
     return finalize_layout(g, nullptr, cr->n_samples, s);
 }
 

@@ -142,6 +142,16 @@ int set_hip_error(hipError_t e);
 int check_domain(const double lo[3], double side);
 void free_grid_arrays(hg_grid *g);
 
+// Stream-ordered device memory from the device's default pool (kept by the
+// pool between calls, so repeated builds do not go back to the driver).
+int dalloc(void **p, size_t bytes, hipStream_t s);
+void dfree(void *p, hipStream_t s);
+template <typename T>
+inline int dalloc_n(T **p, size_t n, hipStream_t s)
+{
+    return dalloc(reinterpret_cast<void **>(p), n * sizeof(T), s);
+}
+
 // ---- prefix sums (scan.hip) --------------------------------------------------
 // out[0..n] = exclusive prefix sum of in[0..n-1] (out[n] = total).  tmp must
 // hold scan_tmp_elems(n) int64 values.

@@ -211,12 +211,16 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     // numbering
     uint8_t *flag = nullptr;
     int64_t *rank = nullptr, *tmp = nullptr;
-    HG_CHECK(hipMallocAsync((void **)&flag, size_t(N), s));
-    HG_CHECK(hipMallocAsync((void **)&rank, size_t(N + 1) * sizeof(int64_t), s));
-    HG_CHECK(hipMallocAsync((void **)&tmp, scan_tmp_elems(N) * sizeof(int64_t), s));
+    int rc = dalloc_n(&flag, size_t(N), s);
+    if (!rc) rc = dalloc_n(&rank, size_t(N + 1), s);
+    if (!rc) rc = dalloc_n(&tmp, scan_tmp_elems(N), s);
+    if (rc) {
+        dfree(flag, s); dfree(rank, s); dfree(tmp, s);
+        return rc;
+    }
     k_flag_leaves<<<blocks_for(N), LT, 0, s>>>(g->first_child, N, flag);
     HG_CHECK(hipGetLastError());
-    int rc = scan_u8_to_i64(flag, rank, N, tmp, s);
+    rc = scan_u8_to_i64(flag, rank, N, tmp, s);
     if (rc) return rc;
     int64_t n_leaves = 0;
     HG_CHECK(hipMemcpyAsync(&n_leaves, rank + N, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -224,18 +228,15 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     g->n_leaves = n_leaves;
     g->n_internal = N - n_leaves;
     if (n_leaves > MAX_IDS || g->n_internal > MAX_IDS) {
-        (void)hipFreeAsync(flag, s); (void)hipFreeAsync(rank, s); (void)hipFreeAsync(tmp, s);
+        dfree(flag, s); dfree(rank, s); dfree(tmp, s);
         return HG_E_LIMIT;
     }
     const int64_t L = n_leaves, I = g->n_internal;
-    if (hipMalloc((void **)&g->leaf_of, size_t(N) * 4) != hipSuccess ||
-        hipMalloc((void **)&g->int_of, size_t(N) * 4) != hipSuccess ||
-        hipMalloc((void **)&g->node_of, size_t(L) * 4) != hipSuccess ||
-        hipMalloc((void **)&g->rho, size_t(L) * 8) != hipSuccess ||
-        hipMalloc((void **)&g->rec32, size_t(L) * sizeof(LeafRec32)) != hipSuccess ||
-        hipMalloc((void **)&g->rec64, size_t(L) * sizeof(LeafRec64)) != hipSuccess ||
-        hipMalloc((void **)&g->child, size_t(I > 0 ? I : 1) * nc * 4) != hipSuccess) {
-        (void)hipFreeAsync(flag, s); (void)hipFreeAsync(rank, s); (void)hipFreeAsync(tmp, s);
+    if (dalloc_n(&g->leaf_of, size_t(N), s) || dalloc_n(&g->int_of, size_t(N), s) ||
+        dalloc_n(&g->node_of, size_t(L), s) || dalloc_n(&g->rho, size_t(L), s) ||
+        dalloc_n(&g->rec32, size_t(L), s) || dalloc_n(&g->rec64, size_t(L), s) ||
+        dalloc_n(&g->child, size_t(I > 0 ? I : 1) * nc, s)) {
+        dfree(flag, s); dfree(rank, s); dfree(tmp, s);
         return HG_E_OOM;
     }
     k_number<<<blocks_for(N), LT, 0, s>>>(g->first_child, rank, N, g->leaf_of, g->int_of, g->node_of);
@@ -251,9 +252,9 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
         HG_CHECK(hipGetLastError());
     }
     g->root_ref = I > 0 ? make_ref(false, 0, 0) : make_ref(true, 0, 0);
-    HG_CHECK(hipFreeAsync(flag, s));
-    HG_CHECK(hipFreeAsync(rank, s));
-    HG_CHECK(hipFreeAsync(tmp, s));
+    dfree(flag, s);
+    dfree(rank, s);
+    dfree(tmp, s);
     HG_CHECK(hipStreamSynchronize(s));
     return HG_OK;
 }

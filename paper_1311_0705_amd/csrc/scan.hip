@@ -100,12 +100,38 @@ __global__ void __launch_bounds__(SCAN_THREADS)
     if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tile_sum[n_tiles];
 }
 
+// Inputs of at most one tile: one block does everything.
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS) k_scan_one_tile(const T *in, int64_t n, int64_t *out)
+{
+    const int64_t base = int64_t(threadIdx.x) * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        v[j] = load_val(in, base + j, n);
+        s += v[j];
+    }
+    int64_t total;
+    int64_t run = block_excl_scan(s, &total);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+        if (base + j < n) out[base + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) out[n] = total;
+}
+
 template <typename T>
 int scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s)
 {
     if (n < 0) return HG_E_INVAL;
+    if (n <= SCAN_TILE) {
+        k_scan_one_tile<T><<<1, SCAN_THREADS, 0, s>>>(in, n, out);
+        HG_CHECK(hipGetLastError());
+        return HG_OK;
+    }
     int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (tiles == 0) tiles = 1;
     if (tiles > 0x7fffffff) return HG_E_LIMIT;
     k_tile_sums<T><<<dim3(unsigned(tiles)), dim3(SCAN_THREADS), 0, s>>>(in, n, tmp);
     HG_CHECK(hipGetLastError());

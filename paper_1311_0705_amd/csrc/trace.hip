@@ -21,6 +21,9 @@
 // walk.  tau is then a Kahan-compensated FP32 sum of kappa rho32 ds32.
 #include <math.h>
 
+#include <algorithm>
+#include <type_traits>
+
 #include "common.h"
 
 namespace hg {
@@ -30,76 +33,110 @@ namespace {
 constexpr int TB = 256;
 constexpr int64_t STEP_GUARD = int64_t(1) << 26;
 
+// Keeps a value in registers: selecting among values passed through this stays
+// a register select instead of being folded into an indexed stack access.
+__device__ __forceinline__ double in_reg(double x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // 2^e for a normal exponent.
-__device__ inline double pow2(int e) { return __hiloint2double((e + 1023) << 20, 0); }
+__device__ __forceinline__ double pow2(int e) { return __hiloint2double((e + 1023) << 20, 0); }
+
+// Tie context of a descent, packed in one register: bits 0-1 the axis of the
+// face just crossed (3 = none), bits 2-4 "point on the low face of the leaf
+// just left" per axis, bits 5-7 "on its high face".
+constexpr int TIE_NONE = 3;
+
+// Direction signs of a path, packed: bit d set if k_d > 0, bit 3+d if k_d < 0.
+__device__ __forceinline__ int dir_bits(const double k[3])
+{
+    int b = 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) b |= (int(k[d] > 0.0) << d) | (int(k[d] < 0.0) << (3 + d));
+    return b;
+}
 
 // Side of a split plane c on axis d that holds the point whose coordinate is
 // x.  Off the plane the comparison decides.  On it: the axis of the face just
 // crossed goes to the side the path moves to; a plane on the boundary of the
 // leaf just left keeps the point inside that leaf's slab; otherwise the
-// direction decides, a zero component going to the upper side.  With no face
-// crossed (first leaf of a path, point location) olo/ohi are NaN and a = -1.
-__device__ inline int upper_side(double x, double c, int d, int a, double kd, double olo,
-                                 double ohi)
+// direction decides, a zero component going to the upper side.
+__device__ __forceinline__ int upper_side(double x, double c, int d, int dirb, int tie)
 {
-    if (x > c) return 1;
-    if (x < c) return 0;
-    if (d == a) return kd > 0.0;
-    if (c == ohi) return 0;
-    if (c == olo) return 1;
-    return !(kd < 0.0);
+    const int kpos = (dirb >> d) & 1;
+    const int kneg = (dirb >> (3 + d)) & 1;
+    const int onlo = (tie >> (2 + d)) & 1;
+    const int onhi = (tie >> (5 + d)) & 1;
+    const int on_plane = d == (tie & 3) ? kpos : (onhi ? 0 : (onlo ? 1 : kneg ^ 1));
+    return x > c ? 1 : (x < c ? 0 : on_plane);
 }
 
 // True when ref may be dereferenced: a leaf or internal id inside the arrays.
-__device__ inline bool ref_ok(const WalkGrid &G, uint32_t ref)
+__device__ __forceinline__ bool ref_ok(const WalkGrid &G, uint32_t ref)
 {
     return ref != NULL_REF && ref_id(ref) < (ref_is_leaf(ref) ? G.n_leaves : G.n_internal);
 }
 
-// Descend from the internal node `ref` (level lv, cell coordinates c) to the
-// leaf holding q.  Returns NULL_REF if a reference is out of range or the
-// depth exceeds the format's limit (never for a valid layout).
+// One descent step from the internal node ref (level lv, lower corner lo)
+// toward the point q: returns the child's reference and moves lo to the
+// child's corner.  Split planes are lo + half the node's width (exact: every
+// plane is a binary fraction).  Child references of the first lds_n internal
+// nodes are read from LDS.
 template <int TREE>
-__device__ inline uint32_t descend(const WalkGrid &G, uint32_t ref, int &lv, uint32_t c[3],
-                                   const double q[3], int a, const double k[3],
-                                   const double olo[3], const double ohi[3])
+__device__ __forceinline__ uint32_t child_of(const WalkGrid &G, const uint32_t *lds, uint32_t lds_n,
+                                             uint32_t ref, int &lv, double lo[3], const double q[3],
+                                             int dirb, int tie)
+{
+    const uint32_t id = ref_id(ref);
+    uint32_t slot;
+    if (TREE == KD) {
+        const int q3 = (lv * 43691) >> 17;  // lv / 3: the split axis b = lv mod 3 has depth lv / 3
+        const int b = lv - 3 * q3;
+        const double l0 = in_reg(lo[0]), l1 = in_reg(lo[1]), l2 = in_reg(lo[2]);
+        const double q0 = in_reg(q[0]), q1 = in_reg(q[1]), q2 = in_reg(q[2]);
+        const double lob = b == 0 ? l0 : (b == 1 ? l1 : l2);
+        const double qb = b == 0 ? q0 : (b == 1 ? q1 : q2);
+        const double mid = lob + pow2(G.lg - q3 - 1);
+        const int up = upper_side(qb, mid, b, dirb, tie);
+        slot = 2u * id + uint32_t(up);
+        const double nlo = up ? mid : lob;
+        lo[0] = b == 0 ? nlo : l0;
+        lo[1] = b == 1 ? nlo : l1;
+        lo[2] = b == 2 ? nlo : l2;
+    } else {
+        const double wh = pow2(G.lg - lv - 1);
+        uint32_t idx = 0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const double mid = lo[d] + wh;
+            const int up = upper_side(q[d], mid, d, dirb, tie);
+            idx |= uint32_t(up) << d;
+            lo[d] = up ? mid : lo[d];
+        }
+        slot = 8u * id + idx;
+    }
+    lv++;
+    return id < lds_n ? lds[slot] : G.child[slot];
+}
+
+// Descend from ref to the leaf holding q.  Returns NULL_REF if a reference is
+// out of range or the depth exceeds the format's limit (never for a valid
+// layout).
+template <int TREE>
+__device__ __forceinline__ uint32_t descend(const WalkGrid &G, const uint32_t *lds, uint32_t lds_n,
+                                            uint32_t ref, int &lv, double lo[3], const double q[3],
+                                            int dirb, int tie)
 {
     while (!ref_is_leaf(ref)) {
         if (!ref_ok(G, ref) || lv >= 62) return NULL_REF;
-        const uint32_t id = ref_id(ref);
-        if (TREE == KD) {
-            const int b = lv % 3;
-            uint32_t cb = 0;
-            double qb = 0, kb = 0, lob = 0, hib = 0, dlo = 0;
-#pragma unroll
-            for (int d = 0; d < 3; d++)
-                if (d == b) {
-                    cb = c[d]; qb = q[d]; kb = k[d]; lob = olo[d]; hib = ohi[d]; dlo = G.lo[d];
-                }
-            const double mid = dlo + double(2u * cb + 1u) * pow2(G.lg - lv / 3 - 1);
-            const int up = upper_side(qb, mid, b, a, kb, lob, hib);
-            ref = G.child[2u * id + uint32_t(up)];
-#pragma unroll
-            for (int d = 0; d < 3; d++)
-                if (d == b) c[d] = 2u * cb + uint32_t(up);
-        } else {
-            const double w = pow2(G.lg - lv - 1);
-            int idx = 0;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                const double mid = G.lo[d] + double(2u * c[d] + 1u) * w;
-                const int up = upper_side(q[d], mid, d, a, k[d], olo[d], ohi[d]);
-                idx |= up << d;
-                c[d] = 2u * c[d] + uint32_t(up);
-            }
-            ref = G.child[8u * id + uint32_t(idx)];
-        }
-        lv++;
+        ref = child_of<TREE>(G, lds, lds_n, ref, lv, lo, q, dirb, tie);
     }
     return ref_ok(G, ref) ? ref : NULL_REF;
 }
 
-__device__ inline bool inside_closed(const WalkGrid &G, const double x[3])
+__device__ __forceinline__ bool inside_closed(const WalkGrid &G, const double x[3])
 {
     bool in = true;
 #pragma unroll
@@ -109,7 +146,7 @@ __device__ inline bool inside_closed(const WalkGrid &G, const double x[3])
 
 // Start of the path inside the closed domain: the origin itself, or the entry
 // point found by the slab test, placed exactly on the entry face.
-__device__ inline bool clip_ray(const WalkGrid &G, const double p0[3], const double k[3],
+__device__ __forceinline__ bool clip_ray(const WalkGrid &G, const double p0[3], const double k[3],
                                 const double inv[3], double &s, double p[3])
 {
     if (inside_closed(G, p0)) {
@@ -153,34 +190,6 @@ __device__ inline bool clip_ray(const WalkGrid &G, const double p0[3], const dou
     return true;
 }
 
-struct LeafData {
-    uint32_t rope[6];
-    double rho64;
-    float rho32;
-};
-
-template <int PREC>
-__device__ inline LeafData load_leaf(const WalkGrid &G, uint32_t id)
-{
-    LeafData L;
-    if (PREC == HG_FP64) {
-        const uint4 *r = reinterpret_cast<const uint4 *>(G.rec64 + id);
-        const uint4 a = r[0], b = r[1];
-        L.rope[0] = a.x; L.rope[1] = a.y; L.rope[2] = a.z; L.rope[3] = a.w;
-        L.rope[4] = b.x; L.rope[5] = b.y;
-        L.rho64 = __hiloint2double(int(b.w), int(b.z));
-        L.rho32 = 0.f;
-    } else {
-        const uint4 *r = reinterpret_cast<const uint4 *>(G.rec32 + id);
-        const uint4 a = r[0], b = r[1];
-        L.rope[0] = a.x; L.rope[1] = a.y; L.rope[2] = a.z; L.rope[3] = a.w;
-        L.rope[4] = b.x; L.rope[5] = b.y;
-        L.rho32 = __uint_as_float(b.z);
-        L.rho64 = 0.0;
-    }
-    return L;
-}
-
 struct WalkArgs {
     const double *O;
     const double *K;
@@ -195,248 +204,479 @@ struct WalkArgs {
     int count_rechecks;
 };
 
-template <int TREE, int PREC, bool FILL>
-__device__ void walk_ray(const WalkGrid &G, const WalkArgs &A, int64_t i)
-{
-    double p0[3], k[3], inv[3], ainv[3];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        p0[d] = A.O[3 * i + d];
-        k[d] = A.K[3 * i + d];
-    }
-    const double nn = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-    const bool finite = isfinite(k[0]) && isfinite(k[1]) && isfinite(k[2]);
-    if (!finite || !(fabs(sqrt(nn) - 1.0) <= 1e-6)) {
-        if (!FILL) {
-            A.tau[i] = __longlong_as_double(0x7ff8000000000000ll);
-            A.count[i] = 0;
-            A.st->bad_dir = 1;
-        }
-        return;
-    }
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        inv[d] = 1.0 / k[d];
-        ainv[d] = fabs(inv[d]);
-    }
-    double s, p[3];
-    if (!clip_ray(G, p0, k, inv, s, p)) {
-        if (!FILL) {
-            A.tau[i] = 0.0;
-            A.count[i] = 0;
-        }
-        return;
-    }
-    // FP32 exit decision is used only where its error bound holds.
-    float ainv32[3];
-    bool force64 = false;
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        ainv32[d] = float(ainv[d]);
-        if (k[d] != 0.0 && !(fabs(k[d]) >= 1e-30)) force64 = true;
-    }
-    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
-    double olo[3] = {nanv, nanv, nanv}, ohi[3] = {nanv, nanv, nanv};
-    uint32_t c[3] = {0u, 0u, 0u};
-    int lv = 0;
-    uint32_t ref = descend<TREE>(G, G.root, lv, c, p, -1, k, olo, ohi);
-    if (ref == NULL_REF) {
-        A.st->bad_ref = 1;
-        if (!FILL) {
-            A.tau[i] = 0.0;
-            A.count[i] = 0;
-        }
-        return;
-    }
+// Everything a lane carries for one path.
+template <int PREC>
+struct Path {
+    using DsT = typename std::conditional<PREC == HG_FP64, double, float>::type;
+    double p0[3], k[3], ainv[3];
+    double s, p[3];          // path length so far and the current entry point
+    double lo[3];            // lower corner of the current node
+    uint32_t ref;            // current node (leaf once the descent ends)
+    int lv;                  // its level
+    int tie;                 // tie context of the pending descent
+    int dirb;                // direction signs (dir_bits)
+    int32_t cnt;             // leaves crossed with ds > 0
+    int steps;
+    double tau64;
+    float tau32, comp32;
+    bool force64;
+    int64_t base, room;      // record slice of this path (fill walk)
+    uint32_t sl[4];          // fill walk: last four records, staged for
+    DsT sd[4];               // 16-byte aligned vector stores
+};
 
-    double tau64 = 0.0;
-    float tau32 = 0.f, comp32 = 0.f;
-    const float kappa32 = float(A.kappa);
-    int32_t cnt = 0;
-    const int64_t base = FILL ? A.offsets[i] : 0;
-    const int64_t room = FILL ? A.offsets[i + 1] - base : 0;
-    unsigned long long rechecks = 0;
-    for (int64_t step = 0;; step++) {
-        if (step >= STEP_GUARD) {
-            A.st->step_guard = 1;
-            break;
-        }
-        const uint32_t id = ref_id(ref);
-        const LeafData L = load_leaf<PREC>(G, id);
-        double lo[3], hi[3], D[3];
-        int dep[3];
+enum { PATH_WALK = 0, PATH_MISS = 1, PATH_BAD_DIR = 2 };
+
+template <int PREC, bool FILL>
+__device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Path<PREC> &P)
+{
+    double inv[3];
 #pragma unroll
-        for (int d = 0; d < 3; d++) {
-            dep[d] = axis_depth(TREE, lv, d);
-            const double w = pow2(G.lg - dep[d]);
-            lo[d] = G.lo[d] + double(c[d]) * w;
-            hi[d] = G.lo[d] + double(c[d] + 1u) * w;
-            D[d] = k[d] > 0.0 ? hi[d] - p[d] : p[d] - lo[d];
-        }
-        int a = -1;
-        if (PREC == HG_FP32_RECHECK) {
-            float m1 = INFINITY, m2 = INFINITY;
-            int i1 = -1;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                float t = k[d] == 0.0 ? INFINITY : float(D[d]) * ainv32[d];
-                if (t < m1) {
-                    m2 = m1;
-                    m1 = t;
-                    i1 = d;
-                } else if (t < m2) {
-                    m2 = t;
-                }
-            }
-            const float hmin = float(pow2(G.lg - dep[0]));
-            if (force64 || !(m2 - m1 >= 1e-5f * hmin)) {
-                rechecks++;
-                i1 = -1;
-            }
-            a = i1;
-        }
-        if (a < 0) {
-            double tmin = INFINITY;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                double t = k[d] == 0.0 ? INFINITY : D[d] * ainv[d];
-                if (t != t) t = INFINITY;
-                if (t < tmin) {
-                    tmin = t;
-                    a = d;
-                }
-            }
-        }
-        if (a < 0) {
-            A.st->step_guard = 1;
-            break;
-        }
-        double Da = 0, ka = 0, aia = 0, loa = 0, hia = 0;
-        uint32_t ca = 0;
-        int depa = 0;
-#pragma unroll
-        for (int d = 0; d < 3; d++)
-            if (d == a) {
-                Da = D[d]; ka = k[d]; aia = ainv[d]; loa = lo[d]; hia = hi[d]; ca = c[d]; depa = dep[d];
-            }
-        double ds = Da * aia;
-        if (ds != ds) ds = INFINITY;
-        if (ds > 0.0) {
-            if (FILL) {
-                if (cnt >= room) {
-                    A.st->step_guard = 1;  // the fill walk must repeat the counting walk
-                    break;
-                }
-                const int64_t pos = base + cnt;
-                A.leaf[pos] = int32_t(id);
-                if (PREC == HG_FP64) reinterpret_cast<double *>(A.ds)[pos] = ds;
-                else reinterpret_cast<float *>(A.ds)[pos] = float(ds);
-            } else {
-                if (PREC == HG_FP64) {
-                    tau64 = tau64 + A.kappa * L.rho64 * ds;
-                } else {
-                    const float y = kappa32 * L.rho32 * float(ds) - comp32;
-                    const float t = tau32 + y;
-                    comp32 = (t - tau32) - y;
-                    tau32 = t;
-                }
-            }
-            cnt++;
-        }
-        const bool up = ka > 0.0;
-        if (up ? (ca + 1u == (1u << depa)) : (ca == 0u)) break;
-        // re-anchor the exit point on the crossed face
-        s = s + ds;
-        double q[3];
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (d == a) {
-                q[d] = up ? hia : loa;
-            } else {
-                const double v = p0[d] + s * k[d];
-                q[d] = v < lo[d] ? lo[d] : (v > hi[d] ? hi[d] : v);
-            }
-        }
-        // rope of the exit face, then descend to the leaf holding the exit point
-        const int face = 2 * a + (up ? 1 : 0);
-        uint32_t nref = L.rope[0];
-#pragma unroll
-        for (int f = 1; f < 6; f++)
-            if (f == face) nref = L.rope[f];
-        // Cell coordinates of the rope target.  It is never finer than the
-        // leaf across the face; along the exit axis a k-d target may be one
-        // level finer (the half of a same-size neighbour touching the face).
-        const int nlv = ref_level(nref);
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const int dn = axis_depth(TREE, nlv, d);
-            uint32_t cd = c[d];
-            if (d == a) {
-                if (dn >= dep[d]) cd = up ? (cd + 1u) << (dn - dep[d]) : (cd << (dn - dep[d])) - 1u;
-                else cd = (up ? cd + 1u : cd - 1u) >> (dep[d] - dn);
-            } else {
-                cd = cd >> (dep[d] - dn);
-            }
-            c[d] = cd;
-        }
-        if (nref == NULL_REF) {
-            A.st->bad_ref = 1;
-            break;
-        }
-        lv = nlv;
-        ref = descend<TREE>(G, nref, lv, c, q, a, k, lo, hi);
-        if (ref == NULL_REF) {
-            A.st->bad_ref = 1;
-            break;
-        }
-#pragma unroll
-        for (int d = 0; d < 3; d++) p[d] = q[d];
+    for (int d = 0; d < 3; d++) {
+        P.p0[d] = A.O[3 * i + d];
+        P.k[d] = A.K[3 * i + d];
     }
-    if (!FILL) {
-        A.count[i] = cnt;
-        if (PREC == HG_FP64) A.tau[i] = tau64;
-        else A.tau[i] = double(tau32) - double(comp32);
+    const double nn = P.k[0] * P.k[0] + P.k[1] * P.k[1] + P.k[2] * P.k[2];
+    const bool finite = isfinite(P.k[0]) && isfinite(P.k[1]) && isfinite(P.k[2]);
+    if (!finite || !(fabs(sqrt(nn) - 1.0) <= 1e-6)) return PATH_BAD_DIR;
+    P.force64 = false;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        inv[d] = 1.0 / P.k[d];
+        P.ainv[d] = fabs(inv[d]);
+        // The FP32 exit decision is used only where its error bound holds.
+        if (P.k[d] != 0.0 && !(fabs(P.k[d]) >= 1e-30)) P.force64 = true;
     }
-    if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
+    if (!clip_ray(G, P.p0, P.k, inv, P.s, P.p)) return PATH_MISS;
+#pragma unroll
+    for (int d = 0; d < 3; d++) P.lo[d] = G.lo[d];
+    P.lv = 0;
+    P.ref = G.root;
+    P.tie = TIE_NONE;
+    P.dirb = dir_bits(P.k);
+    P.cnt = 0;
+    P.steps = 0;
+    P.tau64 = 0.0;
+    P.tau32 = 0.f;
+    P.comp32 = 0.f;
+    if (FILL) {
+        P.base = A.offsets[i];
+        P.room = A.offsets[i + 1] - P.base;
+    }
+    return PATH_WALK;
 }
 
+enum { STEP_GO = 0, STEP_END = 1, STEP_ERR = 2 };
+
+// Fill walk: records are staged four at a time and written as aligned 16-byte
+// vectors once a group of four positions (pos = 4m .. 4m+3 of the record
+// arrays, which must be 16-byte aligned) is complete; the partial groups at
+// the two ends of a path's slice are written element by element.
+template <int PREC>
+__device__ __forceinline__ void store_one(const WalkArgs &A, int64_t pos, uint32_t id, double ds)
+{
+    A.leaf[pos] = int32_t(id);
+    if (PREC == HG_FP64) reinterpret_cast<double *>(A.ds)[pos] = ds;
+    else reinterpret_cast<float *>(A.ds)[pos] = float(ds);
+}
+
+template <int PREC>
+__device__ __forceinline__ void stage_record(const WalkArgs &A, Path<PREC> &P, int64_t pos, uint32_t id,
+                                             double ds)
+{
+    P.sl[0] = P.sl[1]; P.sl[1] = P.sl[2]; P.sl[2] = P.sl[3]; P.sl[3] = id;
+    P.sd[0] = P.sd[1]; P.sd[1] = P.sd[2]; P.sd[2] = P.sd[3];
+    P.sd[3] = typename Path<PREC>::DsT(ds);
+    if ((pos & 3) != 3) return;
+    const int64_t g = pos - 3;
+    if (g >= P.base) {
+        *reinterpret_cast<uint4 *>(A.leaf + g) = make_uint4(P.sl[0], P.sl[1], P.sl[2], P.sl[3]);
+        if (PREC == HG_FP64) {
+            double2 *d = reinterpret_cast<double2 *>(reinterpret_cast<double *>(A.ds) + g);
+            d[0] = make_double2(P.sd[0], P.sd[1]);
+            d[1] = make_double2(P.sd[2], P.sd[3]);
+        } else {
+            *reinterpret_cast<float4 *>(reinterpret_cast<float *>(A.ds) + g) =
+                make_float4(P.sd[0], P.sd[1], P.sd[2], P.sd[3]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            if (g + j >= P.base) store_one<PREC>(A, g + j, P.sl[j], P.sd[j]);
+    }
+}
+
+// Write the staged records of an unfinished group at the end of a path.
+template <int PREC>
+__device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC> &P)
+{
+    if (P.cnt == 0) return;
+    const int64_t last = P.base + P.cnt - 1;
+    const int ph = int(last & 3);
+    if (ph == 3) return;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const int64_t pos = last - j;
+        if (j <= ph && pos >= P.base) store_one<PREC>(A, pos, P.sl[3 - j], P.sd[3 - j]);
+    }
+}
+
+// Per-axis depth and cell width of a node at level lv.
+template <int TREE>
+__device__ __forceinline__ void level_geom(int lg, int lv, int dep[3], double w[3])
+{
+    if (TREE == OCT) {
+        const double ww = pow2(lg - lv);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            dep[d] = lv;
+            w[d] = ww;
+        }
+    } else {
+        const int q = (lv * 43691) >> 17;  // lv / 3 for 0 <= lv < 64
+        const int r = lv - 3 * q;
+        dep[0] = q + (r >= 1);
+        dep[1] = q + (r >= 2);
+        dep[2] = q;
+#pragma unroll
+        for (int d = 0; d < 3; d++) w[d] = pow2(lg - dep[d]);
+    }
+}
+
+// One crossing of the leaf P.ref: exit face, record / tau, re-anchoring, and
+// the rope target of the exit face (left in P.ref for the next descent).  The
+// exit face depends only on the cell and the entry point, so it is decided
+// before the leaf's record is read; then only the rope of that face and the
+// density are loaded.
+template <int TREE, int PREC, bool FILL>
+__device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC> &P,
+                                     unsigned long long &rechecks)
+{
+    if (!ref_ok(G, P.ref)) return STEP_ERR;
+    const uint32_t id = ref_id(P.ref);
+    int dep[3];
+    double w[3], hi[3], E[3], t[3];
+    int edge = 0;
+    const double *lo = P.lo;
+    level_geom<TREE>(G.lg, P.lv, dep, w);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        hi[d] = lo[d] + w[d];
+        E[d] = P.k[d] > 0.0 ? hi[d] : lo[d];  // the face the path moves toward
+        // that face lies on the domain boundary
+        edge |= int(E[d] == (P.k[d] > 0.0 ? G.lo[d] + G.side : G.lo[d])) << d;
+        // t = Delta |1/k|; a zero direction component gives +inf or NaN, and
+        // neither ever wins the strict comparisons below
+        t[d] = fabs(E[d] - P.p[d]) * P.ainv[d];
+    }
+    int a = -1;
+    if (PREC == HG_FP32_RECHECK) {
+        float m1 = INFINITY, m2 = INFINITY;
+        int i1 = -1;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const float t32 = float(fabs(E[d] - P.p[d])) * float(P.ainv[d]);
+            if (t32 < m1) {
+                m2 = m1;
+                m1 = t32;
+                i1 = d;
+            } else if (t32 < m2) {
+                m2 = t32;
+            }
+        }
+        const float hmin = float(w[0]);  // axis 0 is never coarser than the others
+        if (P.force64 || !(m2 - m1 >= 1e-5f * hmin)) {
+            rechecks++;
+            i1 = -1;
+        }
+        a = i1;
+    }
+    if (a < 0) {
+        double tmin = INFINITY;
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+            if (t[d] < tmin) {
+                tmin = t[d];
+                a = d;
+            }
+    }
+    if (a < 0) return STEP_ERR;
+    const double t0 = in_reg(t[0]), t1 = in_reg(t[1]), t2 = in_reg(t[2]);
+    const double ds = a == 0 ? t0 : (a == 1 ? t1 : t2);
+    const bool up = (P.dirb >> a) & 1;
+    const int face = 2 * a + (up ? 1 : 0);
+    // the leaf record: rope of the exit face, density
+    const uint32_t *rec = PREC == HG_FP64 ? reinterpret_cast<const uint32_t *>(G.rec64 + id)
+                                          : reinterpret_cast<const uint32_t *>(G.rec32 + id);
+    const uint32_t nref = rec[face];
+    if (ds > 0.0) {
+        if (FILL) {
+            if (P.cnt >= P.room) return STEP_ERR;  // the fill walk must repeat the counting walk
+            stage_record<PREC>(A, P, P.base + P.cnt, id, ds);
+        } else if (PREC == HG_FP64) {
+            const double rho64 = *reinterpret_cast<const double *>(rec + 6);
+            P.tau64 = P.tau64 + A.kappa * rho64 * ds;
+        } else {
+            const float rho32 = __uint_as_float(rec[6]);
+            const float y = float(A.kappa) * rho32 * float(ds) - P.comp32;
+            const float tt = P.tau32 + y;
+            P.comp32 = (tt - P.tau32) - y;
+            P.tau32 = tt;
+        }
+        P.cnt++;
+    }
+    // exit face on the domain boundary: the path ends
+    if ((edge >> a) & 1) return STEP_END;
+    // re-anchor the exit point on the crossed face
+    P.s = P.s + ds;
+    int onlo = 0, onhi = 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const double v = P.p0[d] + P.s * P.k[d];
+        const double q = d == a ? E[d] : fmin(fmax(v, lo[d]), hi[d]);
+        onlo |= int(q == lo[d]) << d;
+        onhi |= int(q == hi[d]) << d;
+        P.p[d] = q;
+    }
+    P.tie = a | (onlo << 2) | (onhi << 5);
+    if (nref == NULL_REF) return STEP_ERR;
+    // Lower corner of the rope target: the corner of the leaf, moved across
+    // the exit face and aligned down to the target's cell size (exact).  The
+    // target is never finer than the leaf across the face; along the exit axis
+    // a k-d target may be one level finer (the half of a same-size neighbour
+    // touching the face).
+    const int nlv = ref_level(nref);
+    int dn[3];
+    double wn[3];
+    level_geom<TREE>(G.lg, nlv, dn, wn);
+    double nlo[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const double x = d != a ? lo[d] : (up ? hi[d] : lo[d] - fmin(w[d], wn[d]));
+        const double inv = pow2(dn[d] - G.lg);
+        nlo[d] = G.lo[d] + floor((x - G.lo[d]) * inv) * wn[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) P.lo[d] = nlo[d];
+    P.lv = nlv;
+    P.ref = nref;
+    return STEP_GO;
+}
+
+template <int PREC, bool FILL>
+__device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Path<PREC> &P)
+{
+    if (FILL) {
+        flush_records<PREC>(A, P);
+        if (P.cnt != P.room) A.st->step_guard = 1;
+        return;
+    }
+    A.count[i] = P.cnt;
+    if (PREC == HG_FP64) A.tau[i] = P.tau64;
+    else A.tau[i] = double(P.tau32) - double(P.comp32);
+}
+
+template <int PREC, bool FILL>
+__device__ __forceinline__ void finish_unwalked(const WalkArgs &A, int64_t i, int why)
+{
+    if (FILL) return;
+    A.count[i] = 0;
+    if (why == PATH_BAD_DIR) {
+        A.tau[i] = __longlong_as_double(0x7ff8000000000000ll);
+        A.st->bad_dir = 1;
+    } else {
+        A.tau[i] = 0.0;
+    }
+}
+
+// One lane per path, the whole walk in one loop.
 template <int TREE, int PREC, bool FILL>
 __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 {
     const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
-    if (i < A.n) walk_ray<TREE, PREC, FILL>(G, A, i);
+    if (i >= A.n) return;
+    Path<PREC> P;
+    const int why = init_path<PREC, FILL>(G, A, i, P);
+    if (why != PATH_WALK) {
+        finish_unwalked<PREC, FILL>(A, i, why);
+        return;
+    }
+    unsigned long long rechecks = 0;
+    for (;;) {
+        P.ref = descend<TREE>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+        if (P.ref == NULL_REF) {
+            A.st->bad_ref = 1;
+            break;
+        }
+        const int r = cross<TREE, PREC, FILL>(G, A, P, rechecks);
+        if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
+            A.st->step_guard = 1;
+            break;
+        }
+        if (r == STEP_END) break;
+    }
+    finish_path<PREC, FILL>(A, i, P);
+    if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
+}
+
+// Persistent walk: each wavefront keeps its lanes busy by handing new paths
+// to lanes whose path ended.  Refills happen in batches (once at least
+// refill_min lanes are idle, or none is busy) from a wavefront-local chunk of
+// paths taken with one atomic on the global path counter, so the divergent
+// path set-up and the atomic round trip are amortised over many paths.  Each
+// iteration a busy lane performs one dependent global access: a descent step
+// (the first levels of every descent come from LDS) or a crossing.
+template <int TREE, int PREC, bool FILL>
+__global__ void __launch_bounds__(TB)
+    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min)
+{
+    extern __shared__ uint32_t lds[];
+    const int nc = TREE == OCT ? 8 : 2;
+    for (uint32_t j = threadIdx.x; j < lds_n * nc; j += TB) lds[j] = G.child[j];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    Path<PREC> P;
+    int64_t ray = -1;
+    bool done = false;
+    uint32_t cnext = 0, cend = 0;   // wavefront-local chunk [cnext, cend)
+    bool drained = false;           // the global counter is exhausted
+    unsigned long long rechecks = 0;
+    for (;;) {
+        const bool want = ray < 0 && !done;
+        const uint64_t wmask = __ballot(want);
+        const uint64_t amask = __ballot(ray >= 0);
+        const int nwant = __popcll(wmask);
+        if (nwant && (nwant >= refill_min || !amask)) {
+            if (cnext >= cend && !drained) {
+                uint32_t b = 0;
+                if (lane == 0) b = atomicAdd(&A.st->next_ray, chunk);
+                b = __shfl(b, 0, 64);
+                if (int64_t(b) >= A.n) {
+                    drained = true;
+                    cnext = cend = 0;
+                } else {
+                    cnext = b;
+                    cend = uint32_t(std::min<int64_t>(int64_t(b) + chunk, A.n));
+                }
+            }
+            const uint32_t avail = cend - cnext;
+            if (want) {
+                const uint32_t rank = uint32_t(__popcll(wmask & below));
+                if (rank < avail) {
+                    const int64_t r = int64_t(cnext) + rank;
+                    const int why = init_path<PREC, FILL>(G, A, r, P);
+                    if (why == PATH_WALK) ray = r;
+                    else finish_unwalked<PREC, FILL>(A, r, why);
+                } else if (drained) {
+                    done = true;
+                }
+            }
+            cnext += std::min<uint32_t>(avail, uint32_t(nwant));
+        }
+        if (!amask && !__ballot(ray >= 0)) {
+            if (!__ballot(!done)) break;
+            continue;
+        }
+        if (ray < 0) continue;
+        if (!ref_is_leaf(P.ref)) {
+            // LDS levels, then at most one global level this iteration
+            for (;;) {
+                if (!ref_ok(G, P.ref) || P.lv >= 62) {
+                    P.ref = NULL_REF;
+                    break;
+                }
+                const bool global = ref_id(P.ref) >= lds_n;
+                P.ref = child_of<TREE>(G, lds, lds_n, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+                if (global || ref_is_leaf(P.ref)) break;
+            }
+            if (P.ref == NULL_REF || (ref_is_leaf(P.ref) && !ref_ok(G, P.ref))) {
+                A.st->bad_ref = 1;
+                finish_path<PREC, FILL>(A, ray, P);
+                ray = -1;
+                continue;
+            }
+        }
+        if (ref_is_leaf(P.ref)) {
+            const int r = cross<TREE, PREC, FILL>(G, A, P, rechecks);
+            if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
+                A.st->step_guard = 1;
+                finish_path<PREC, FILL>(A, ray, P);
+                ray = -1;
+            } else if (r == STEP_END) {
+                finish_path<PREC, FILL>(A, ray, P);
+                ray = -1;
+            }
+        }
+    }
+    if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
 template <int TREE>
-__global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restrict__ P, int64_t n,
+__global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restrict__ X, int64_t n,
                                                int32_t *__restrict__ out)
 {
     const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (i >= n) return;
     double x[3];
 #pragma unroll
-    for (int d = 0; d < 3; d++) x[d] = P[3 * i + d];
+    for (int d = 0; d < 3; d++) x[d] = X[3 * i + d];
     if (!inside_closed(G, x)) {
         out[i] = -1;
         return;
     }
-    const double nanv = __longlong_as_double(0x7ff8000000000000ll);
-    const double z[3] = {0.0, 0.0, 0.0};
-    const double nn[3] = {nanv, nanv, nanv};
-    uint32_t c[3] = {0u, 0u, 0u};
+    double lo[3] = {G.lo[0], G.lo[1], G.lo[2]};
     int lv = 0;
-    const uint32_t r = descend<TREE>(G, G.root, lv, c, x, -1, z, nn, nn);
+    const uint32_t r = descend<TREE>(G, nullptr, 0u, G.root, lv, lo, x, 0, TIE_NONE);
     out[i] = r == NULL_REF ? -2 : int32_t(ref_id(r));
 }
 
+__global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
+
+constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
+constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
+
 template <int TREE, int PREC, bool FILL>
-int launch_t(const WalkGrid &G, const WalkArgs &A, int block, hipStream_t s)
+int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trace_opts *o,
+             hipStream_t s)
 {
-    (void)block;
-    const int64_t nb = (A.n + TB - 1) / TB;
-    if (nb == 0) return HG_OK;
-    k_walk<TREE, PREC, FILL><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, A);
-    HG_CHECK(hipGetLastError());
+    if (A.n == 0) return HG_OK;
+    if (!persistent) {
+        const int64_t nb = (A.n + TB - 1) / TB;
+        k_walk<TREE, PREC, FILL><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, A);
+        HG_CHECK(hipGetLastError());
+        return HG_OK;
+    }
+    const int nc = TREE == OCT ? 8 : 2;
+    const uint32_t lds_n = uint32_t(std::min<uint64_t>(G.n_internal, LDS_BYTES / (4u * nc)));
+    const size_t lds = size_t(lds_n) * nc * 4u;
+    static int occ = -1, cus = 0;
+    static size_t occ_lds = 0;
+    if (occ < 0 || occ_lds != lds) {
+        int dev = 0;
+        HG_CHECK(hipGetDevice(&dev));
+        HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, FILL>), TB, lds));
+        occ_lds = lds;
+    }
+    const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
+    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 512u;
+    const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : 16;
+    for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
+        WalkArgs B = A;
+        B.n = std::min(PERSIST_CHUNK, A.n - start);
+        B.O = A.O + 3 * start;
+        B.K = A.K + 3 * start;
+        B.tau = A.tau ? A.tau + start : nullptr;
+        B.count = A.count ? A.count + start : nullptr;
+        B.offsets = A.offsets ? A.offsets + start : nullptr;
+        k_reset_counter<<<1, 1, 0, s>>>(A.st);
+        HG_CHECK(hipGetLastError());
+        k_walk_persistent<TREE, PREC, FILL><<<dim3(blocks), dim3(TB), lds, s>>>(G, B, lds_n, chunk,
+                                                                                  refill_min);
+        HG_CHECK(hipGetLastError());
+    }
     return HG_OK;
 }
 
@@ -464,6 +704,9 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
                 const hg_trace_opts *opts, hg_trace_out *out, bool fill, hipStream_t s, float *ms)
 {
     (void)ms;
+    // bit 0: persistent counting / tau-only walk, bit 1: persistent fill walk
+    const int mode = opts->persistent < 0 ? 3 : opts->persistent;
+    const int persistent = fill ? (mode >> 1) & 1 : mode & 1;
     const WalkGrid G = walk_grid(g);
     WalkArgs A;
     A.O = o;
@@ -480,16 +723,16 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
     const int prec = opts->precision;
     if (g->tree == KD) {
         if (prec == HG_FP64)
-            return fill ? launch_t<KD, HG_FP64, true>(G, A, opts->block, s)
-                        : launch_t<KD, HG_FP64, false>(G, A, opts->block, s);
-        return fill ? launch_t<KD, HG_FP32_RECHECK, true>(G, A, opts->block, s)
-                    : launch_t<KD, HG_FP32_RECHECK, false>(G, A, opts->block, s);
+            return fill ? launch_t<KD, HG_FP64, true>(G, A, persistent, opts, s)
+                        : launch_t<KD, HG_FP64, false>(G, A, persistent, opts, s);
+        return fill ? launch_t<KD, HG_FP32_RECHECK, true>(G, A, persistent, opts, s)
+                    : launch_t<KD, HG_FP32_RECHECK, false>(G, A, persistent, opts, s);
     }
     if (prec == HG_FP64)
-        return fill ? launch_t<OCT, HG_FP64, true>(G, A, opts->block, s)
-                    : launch_t<OCT, HG_FP64, false>(G, A, opts->block, s);
-    return fill ? launch_t<OCT, HG_FP32_RECHECK, true>(G, A, opts->block, s)
-                : launch_t<OCT, HG_FP32_RECHECK, false>(G, A, opts->block, s);
+        return fill ? launch_t<OCT, HG_FP64, true>(G, A, persistent, opts, s)
+                    : launch_t<OCT, HG_FP64, false>(G, A, persistent, opts, s);
+    return fill ? launch_t<OCT, HG_FP32_RECHECK, true>(G, A, persistent, opts, s)
+                : launch_t<OCT, HG_FP32_RECHECK, false>(G, A, persistent, opts, s);
 }
 
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s)

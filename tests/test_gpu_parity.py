@@ -61,9 +61,16 @@ def random_rays(n, seed, lo=-1.0, hi=1.0):
 
 
 def check_trace(og, g, o, k, kappa=1.0):
+    out = None
+    for persistent in (0, 3):
+        out = _check_trace(og, g, o, k, kappa, persistent)
+    return out
+
+
+def _check_trace(og, g, o, k, kappa, persistent):
     ref = og.trace(o, k, kappa=kappa)
     n = o.shape[0]
-    r = g.trace(o, k, precision=hg.FP64, mode=hg.RECORDS, kappa=kappa)
+    r = g.trace(o, k, precision=hg.FP64, mode=hg.RECORDS, kappa=kappa, persistent=persistent)
     tot = r["needed"]
     assert tot == int(ref["offsets"][-1])
     assert np.array_equal(r["count"].cpu().numpy(), ref["count"])
@@ -71,11 +78,11 @@ def check_trace(og, g, o, k, kappa=1.0):
     assert np.array_equal(r["leaf"][:tot].cpu().numpy(), ref["leaf"])
     assert np.array_equal(r["ds"][:tot].cpu().numpy(), ref["ds"])            # bitwise
     assert np.array_equal(r["tau"].cpu().numpy(), ref["tau"])                # same order, same ops
-    t = g.trace(o, k, precision=hg.FP64, mode=hg.TAU_ONLY, kappa=kappa)
+    t = g.trace(o, k, precision=hg.FP64, mode=hg.TAU_ONLY, kappa=kappa, persistent=persistent)
     assert np.array_equal(t["tau"].cpu().numpy(), ref["tau"])
     assert np.array_equal(t["count"].cpu().numpy(), ref["count"])
     f = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, kappa=kappa,
-                count_rechecks=True)
+                count_rechecks=True, persistent=persistent)
     assert f["needed"] == tot
     assert np.array_equal(f["count"].cpu().numpy(), ref["count"])
     assert np.array_equal(f["leaf"][:tot].cpu().numpy(), ref["leaf"])
