@@ -37,6 +37,14 @@ HBM_PEAK_GBS = 8000.0
 #   The record-filling walk also reads the path (48 B) and its offset (8 B).
 #   The counting (tau-only) walk reads 24 B per crossing, the path (48 B), and
 #   writes tau + count (12 B).
+# HBM traffic of the dominant kernel from rocprofv3 --pmc runs (FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch), scaled by what the same counters read for a
+# 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE 1.0 GiB).
+# Valid only for the walk source it was measured on (sha256 of trace.hip).
+TRAFFIC = {"trace_sha256": "b4f12bc0c7bd9e93626cc32a1a383fe05fb3af5f38fc8354b4810373c542185b",
+           "fetch_kib": 32660382.3, "write_kib": 10795357.5,
+           "fetch_scale": 2.0, "write_scale": 1.0}
+
 B_X_FILL32 = 32
 B_RAY_FILL = 48 + 8
 B_X_COUNT32 = 24
@@ -194,9 +202,10 @@ def main():
     alg_fill = crossings * B_X_FILL32 + n * B_RAY_FILL
     achieved = alg_fill / (fill_avg * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_walk<kd,fp32_recheck,fill>" if w.tree_type == W.KDTREE
-                else "k_walk<octree,fp32_recheck,fill>",
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(a.workload),
+                "kernel": "k_walk_persistent<kd,fp32_recheck,fill>" if w.tree_type == W.KDTREE
+                else "k_walk_persistent<octree,fp32_recheck,fill>",
                 "kernel_ms": round(fill_avg, 3),
                 "alg_bytes_per_launch": int(alg_fill)}
 
@@ -240,6 +249,20 @@ def main():
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, o_np, k_np, crossings, a.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel, if the counters were taken
+    on the current walk source; else None."""
+    import hashlib
+    if workload != 2 or TRAFFIC["trace_sha256"] is None:
+        return None
+    src = os.path.join(ROOT, "paper_1311_0705_amd", "csrc", "trace.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["trace_sha256"]:
+            return None
+    return int(TRAFFIC["fetch_kib"] * 1024 * TRAFFIC["fetch_scale"]
+               + TRAFFIC["write_kib"] * 1024 * TRAFFIC["write_scale"])
 
 
 def cpu_baseline(w, o_np, k_np, crossings_total, budget_s):
