@@ -24,6 +24,10 @@
  *    an exact binary fraction.
  *  - Leaf ids are ranks among the leaves in the breadth-first node list
  *    (the order in which the construction loop of Sect. 2.2 creates them).
+ *  - Trees of up to 2^25 leaves and 2^25 internal nodes use a compact walk
+ *    layout (32-bit references, 32-byte leaf records); larger trees switch to
+ *    64-bit references and 64-byte records automatically.  The environment
+ *    variable HGRID_WIDE_REFS=1 forces the wide layout (for testing).
  */
 #ifndef HGRID_H
 #define HGRID_H
@@ -41,7 +45,7 @@ extern "C" {
 #define HG_E_DIR      -3  /* a direction is not finite or | |k| - 1 | > 1e-6 */
 #define HG_E_CAPACITY -4  /* crossing records do not fit; tau, count, offsets and needed are valid */
 #define HG_E_OOM      -5  /* device allocation failed */
-#define HG_E_LIMIT    -6  /* tree exceeds 2^25 leaves or 2^25 internal nodes, or max_nodes */
+#define HG_E_LIMIT    -6  /* tree exceeds 2^31 nodes or criteria.max_nodes */
 #define HG_E_HIP      -7  /* HIP runtime error; grid_last_hip_error() gives the hipError_t */
 #define HG_E_STEP     -8  /* a path exceeded the step guard (never expected for valid input) */
 #define HG_E_FORMAT   -9  /* imported arrays are not a valid breadth-first tree */

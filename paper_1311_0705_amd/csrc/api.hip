@@ -64,8 +64,8 @@ void dfree(void *p, hipStream_t s)
 void free_grid_arrays(hg_grid *g)
 {
     void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
-                    g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->child,
-                    g->status};
+                    g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->recw,
+                    g->child, g->status};
     for (void *p : ptrs) dfree(p, nullptr);
 }
 

@@ -4,15 +4,16 @@
 //   node arrays   first_child i32, level u8, coord u32[3], S/rho_min/rho_max f64,
 //                 rope i32[6] (node index of each face's rope target),
 //                 leaf_of i32, int_of i32 (internal-node rank or -1)
-//   walk arrays   rec32 / rec64: one 32-byte record per leaf holding the six
-//                 encoded rope targets and the leaf density (f32 or f64), so
-//                 one crossing reads one 32-byte sector;
-//                 child u32: per internal node the encoded references of its
+//   walk arrays   per-leaf walk records holding the six encoded rope targets
+//                 and the leaf density, so one crossing reads one sector;
+//                 child: per internal node the encoded references of its
 //                 2 (k-d) or 8 (octree) children, read one per descent step.
-// An encoded reference packs  leaf flag (bit 31) | level (bits 25..30) | id
-// (bits 0..24), id being the leaf rank or the internal-node rank.  It is all
-// the walk needs: the cell box of the target follows from the level and from
-// the coordinates of the leaf being left.
+// An encoded reference packs  leaf flag (top bit) | level (6 bits) | id, id
+// being the leaf rank or the internal-node rank.  Compact layout: 32-bit
+// references (ids < 2^25) and 32-byte records, one f32 and one f64 record
+// array; wide layout (larger trees): 64-bit references and one 64-byte record
+// holding both densities.  The cell box of a reference's target follows from
+// its level and the corner of the node the walk comes from.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,11 +27,7 @@ namespace hg {
 constexpr int OCT = HG_OCTREE;
 constexpr int KD = HG_KDTREE;
 
-constexpr uint32_t NULL_REF = 0xFFFFFFFFu;
-constexpr uint32_t LEAF_BIT = 0x80000000u;
-constexpr int LEVEL_SHIFT = 25;
-constexpr uint32_t ID_MASK = (1u << 25) - 1u;
-constexpr int64_t MAX_IDS = int64_t(1) << 25;
+constexpr int64_t MAX_IDS = int64_t(1) << 25;       // compact-layout id limit
 constexpr int DEPTH_BITS = 20;  // integer box resolution: per-axis depth <= 19
 
 __host__ __device__ inline int axis_depth(int tree, int level, int d)
@@ -38,13 +35,20 @@ __host__ __device__ inline int axis_depth(int tree, int level, int d)
     return tree == OCT ? level : (level + 2 - d) / 3;
 }
 
-__host__ __device__ inline uint32_t make_ref(bool leaf, int level, uint32_t id)
-{
-    return (leaf ? LEAF_BIT : 0u) | (uint32_t(level) << LEVEL_SHIFT) | id;
-}
-__host__ __device__ inline bool ref_is_leaf(uint32_t r) { return (r & LEAF_BIT) != 0u; }
-__host__ __device__ inline int ref_level(uint32_t r) { return int((r >> LEVEL_SHIFT) & 63u); }
-__host__ __device__ inline uint32_t ref_id(uint32_t r) { return r & ID_MASK; }
+// Reference encoding for R = uint32_t (compact) or uint64_t (wide).
+template <typename R>
+struct Ref {
+    static constexpr int BITS = int(sizeof(R) * 8);
+    static constexpr int LEVEL_SHIFT = BITS == 32 ? 25 : 56;
+    static constexpr R NUL = ~R(0);
+    __host__ __device__ static R make(bool leaf, int level, uint64_t id)
+    {
+        return (leaf ? R(R(1) << (BITS - 1)) : R(0)) | (R(level) << LEVEL_SHIFT) | R(id);
+    }
+    __host__ __device__ static bool leaf(R r) { return ((r >> (BITS - 1)) & R(1)) != R(0); }
+    __host__ __device__ static int level(R r) { return int((r >> LEVEL_SHIFT) & R(63)); }
+    __host__ __device__ static uint64_t id(R r) { return uint64_t(r & ((R(1) << LEVEL_SHIFT) - R(1))); }
+};
 
 struct alignas(32) LeafRec32 {
     uint32_t rope[6];
@@ -55,8 +59,15 @@ struct alignas(32) LeafRec64 {
     uint32_t rope[6];
     double rho;
 };
+struct alignas(64) LeafRecW {
+    uint64_t rope[6];
+    double rho64;
+    float rho32;
+    uint32_t pad;
+};
 static_assert(sizeof(LeafRec32) == 32, "record size");
 static_assert(sizeof(LeafRec64) == 32, "record size");
+static_assert(sizeof(LeafRecW) == 64, "record size");
 
 // Density field on the device.  Clumps are found through a uniform binning
 // grid whose per-bin lists are sorted by clump index, so the sum over clumps
@@ -83,11 +94,10 @@ struct WalkGrid {
     int lg;                        // log2 of the domain side
     double lo[3];
     double side;
-    uint32_t root;                 // encoded reference of the root
-    uint32_t n_leaves, n_internal; // bounds every reference is checked against
-    const LeafRec32 *rec32;
-    const LeafRec64 *rec64;
-    const uint32_t *child;         // [n_internal][2 or 8]
+    uint64_t root;                 // encoded reference of the root
+    uint64_t n_leaves, n_internal; // bounds every reference is checked against
+    const void *rec;               // walk records of the precision in use
+    const void *child;             // [n_internal][2 or 8] references
 };
 
 // Scratch for device-side status shared by the trace kernels.
@@ -121,10 +131,12 @@ struct hg_grid {
     int32_t *node_of;
     double *rho;
     // walk layout
-    hg::LeafRec32 *rec32;
-    hg::LeafRec64 *rec64;
-    uint32_t *child;
-    uint32_t root_ref;
+    int wide;                  // 64-bit references and 64-byte records
+    hg::LeafRec32 *rec32;      // compact layout
+    hg::LeafRec64 *rec64;      // compact layout
+    hg::LeafRecW *recw;        // wide layout
+    void *child;               // uint32_t or uint64_t references
+    uint64_t root_ref;
     hg::TraceStatus *status;   // device scratch
     int64_t level_begin[64];   // first node of each level; level_begin[max_level+1] = n_nodes
 };
@@ -166,7 +178,7 @@ int scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *tmp, hip
 int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream_t s);
 
 // ---- trace / locate (trace.hip) --------------------------------------------
-WalkGrid walk_grid(const hg_grid *g);
+WalkGrid walk_grid(const hg_grid *g, int precision);
 int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
                 const hg_trace_opts *opts, hg_trace_out *out, bool fill, hipStream_t s,
                 float *ms);

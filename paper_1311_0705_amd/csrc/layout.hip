@@ -10,6 +10,8 @@
 // points at its sibling across the new split plane, and every rope is then
 // pushed down while a single child of the target still contains the face
 // region.
+#include <stdlib.h>
+
 #include "common.h"
 
 namespace hg {
@@ -136,14 +138,20 @@ __global__ void __launch_bounds__(LT)
     }
 }
 
-__device__ inline uint32_t encode(int32_t n, const int32_t *__restrict__ fc,
-                                  const uint8_t *__restrict__ level,
-                                  const int32_t *__restrict__ leaf_of,
-                                  const int32_t *__restrict__ int_of)
+template <typename R>
+__device__ inline R encode(int32_t n, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+                           const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of)
 {
-    if (n < 0) return NULL_REF;
-    bool leaf = fc[n] < 0;
-    return make_ref(leaf, level[n], uint32_t(leaf ? leaf_of[n] : int_of[n]));
+    if (n < 0) return Ref<R>::NUL;
+    const bool leaf = fc[n] < 0;
+    return Ref<R>::make(leaf, level[n], uint64_t(uint32_t(leaf ? leaf_of[n] : int_of[n])));
+}
+
+// Grid density of a leaf = M/V = S/N (Sect. 3.2), or the imported value.
+__device__ inline double leaf_rho(int64_t l, int32_t n, const double *S, const double *rho_in,
+                                  double n_samples)
+{
+    return rho_in ? rho_in[l] : S[n] / n_samples;
 }
 
 __global__ void __launch_bounds__(LT)
@@ -151,22 +159,19 @@ __global__ void __launch_bounds__(LT)
                    const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                    const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
                    const int32_t *__restrict__ rope, const double *__restrict__ S,
-                   const double *__restrict__ rho_in, double inv_n, double n_samples,
-                   double *__restrict__ rho, LeafRec32 *__restrict__ rec32,
-                   LeafRec64 *__restrict__ rec64)
+                   const double *__restrict__ rho_in, double n_samples, double *__restrict__ rho,
+                   LeafRec32 *__restrict__ rec32, LeafRec64 *__restrict__ rec64)
 {
     int64_t l = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (l >= n_leaves) return;
-    int32_t n = node_of[l];
-    // Grid density of a leaf = M/V = S/N (Sect. 3.2).
-    double r = rho_in ? rho_in[l] : S[n] / n_samples;
-    (void)inv_n;
+    const int32_t n = node_of[l];
+    const double r = leaf_rho(l, n, S, rho_in, n_samples);
     rho[l] = r;
     LeafRec32 a;
     LeafRec64 b;
 #pragma unroll
     for (int j = 0; j < 6; j++) {
-        uint32_t e = encode(rope[6 * int64_t(n) + j], fc, level, leaf_of, int_of);
+        const uint32_t e = encode<uint32_t>(rope[6 * int64_t(n) + j], fc, level, leaf_of, int_of);
         a.rope[j] = e;
         b.rope[j] = e;
     }
@@ -178,9 +183,33 @@ __global__ void __launch_bounds__(LT)
 }
 
 __global__ void __launch_bounds__(LT)
+    k_leaf_records_wide(int64_t n_leaves, const int32_t *__restrict__ node_of,
+                        const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+                        const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
+                        const int32_t *__restrict__ rope, const double *__restrict__ S,
+                        const double *__restrict__ rho_in, double n_samples,
+                        double *__restrict__ rho, LeafRecW *__restrict__ recw)
+{
+    int64_t l = int64_t(blockIdx.x) * LT + threadIdx.x;
+    if (l >= n_leaves) return;
+    const int32_t n = node_of[l];
+    const double r = leaf_rho(l, n, S, rho_in, n_samples);
+    rho[l] = r;
+    LeafRecW a;
+#pragma unroll
+    for (int j = 0; j < 6; j++)
+        a.rope[j] = encode<uint64_t>(rope[6 * int64_t(n) + j], fc, level, leaf_of, int_of);
+    a.rho64 = r;
+    a.rho32 = float(r);
+    a.pad = 0;
+    recw[l] = a;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(LT)
     k_child_refs(int64_t n, int nc, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                  const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
-                 uint32_t *__restrict__ child)
+                 R *__restrict__ child)
 {
     int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (t >= n * nc) return;
@@ -188,7 +217,7 @@ __global__ void __launch_bounds__(LT)
     int k = int(t % nc);
     int32_t f = fc[i];
     if (f < 0) return;
-    child[int64_t(int_of[i]) * nc + k] = encode(f + k, fc, level, leaf_of, int_of);
+    child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, fc, level, leaf_of, int_of);
 }
 
 inline unsigned blocks_for(int64_t n) { return unsigned((n + LT - 1) / LT); }
@@ -227,31 +256,44 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     HG_CHECK(hipStreamSynchronize(s));
     g->n_leaves = n_leaves;
     g->n_internal = N - n_leaves;
-    if (n_leaves > MAX_IDS || g->n_internal > MAX_IDS) {
-        dfree(flag, s); dfree(rank, s); dfree(tmp, s);
-        return HG_E_LIMIT;
-    }
+    const char *force = getenv("HGRID_WIDE_REFS");
+    g->wide = (n_leaves > MAX_IDS || g->n_internal > MAX_IDS || (force && force[0] == '1')) ? 1 : 0;
     const int64_t L = n_leaves, I = g->n_internal;
-    if (dalloc_n(&g->leaf_of, size_t(N), s) || dalloc_n(&g->int_of, size_t(N), s) ||
-        dalloc_n(&g->node_of, size_t(L), s) || dalloc_n(&g->rho, size_t(L), s) ||
-        dalloc_n(&g->rec32, size_t(L), s) || dalloc_n(&g->rec64, size_t(L), s) ||
-        dalloc_n(&g->child, size_t(I > 0 ? I : 1) * nc, s)) {
+    const size_t rsz = g->wide ? 8 : 4;
+    int arc = dalloc_n(&g->leaf_of, size_t(N), s);
+    if (!arc) arc = dalloc_n(&g->int_of, size_t(N), s);
+    if (!arc) arc = dalloc_n(&g->node_of, size_t(L), s);
+    if (!arc) arc = dalloc_n(&g->rho, size_t(L), s);
+    if (!arc && g->wide) arc = dalloc_n(&g->recw, size_t(L), s);
+    if (!arc && !g->wide) arc = dalloc_n(&g->rec32, size_t(L), s);
+    if (!arc && !g->wide) arc = dalloc_n(&g->rec64, size_t(L), s);
+    if (!arc) arc = dalloc(&g->child, size_t(I > 0 ? I : 1) * nc * rsz, s);
+    if (arc) {
         dfree(flag, s); dfree(rank, s); dfree(tmp, s);
-        return HG_E_OOM;
+        return arc;
     }
     k_number<<<blocks_for(N), LT, 0, s>>>(g->first_child, rank, N, g->leaf_of, g->int_of, g->node_of);
     HG_CHECK(hipGetLastError());
-    k_leaf_records<<<blocks_for(L), LT, 0, s>>>(L, g->node_of, g->first_child, g->level, g->leaf_of,
-                                                g->int_of, g->rope, g->S, rho_leaf,
-                                                1.0 / double(n_samples), double(n_samples), g->rho,
-                                                g->rec32, g->rec64);
+    if (g->wide)
+        k_leaf_records_wide<<<blocks_for(L), LT, 0, s>>>(L, g->node_of, g->first_child, g->level,
+                                                         g->leaf_of, g->int_of, g->rope, g->S,
+                                                         rho_leaf, double(n_samples), g->rho,
+                                                         g->recw);
+    else
+        k_leaf_records<<<blocks_for(L), LT, 0, s>>>(L, g->node_of, g->first_child, g->level,
+                                                    g->leaf_of, g->int_of, g->rope, g->S, rho_leaf,
+                                                    double(n_samples), g->rho, g->rec32, g->rec64);
     HG_CHECK(hipGetLastError());
     if (I > 0) {
-        k_child_refs<<<blocks_for(N * nc), LT, 0, s>>>(N, nc, g->first_child, g->level, g->leaf_of,
-                                                       g->int_of, g->child);
+        if (g->wide)
+            k_child_refs<uint64_t><<<blocks_for(N * nc), LT, 0, s>>>(
+                N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->child);
+        else
+            k_child_refs<uint32_t><<<blocks_for(N * nc), LT, 0, s>>>(
+                N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->child);
         HG_CHECK(hipGetLastError());
     }
-    g->root_ref = I > 0 ? make_ref(false, 0, 0) : make_ref(true, 0, 0);
+    g->root_ref = g->wide ? Ref<uint64_t>::make(I == 0, 0, 0) : Ref<uint32_t>::make(I == 0, 0, 0);
     dfree(flag, s);
     dfree(rank, s);
     dfree(tmp, s);

@@ -74,23 +74,32 @@ __device__ __forceinline__ int upper_side(double x, double c, int d, int dirb, i
 }
 
 // True when ref may be dereferenced: a leaf or internal id inside the arrays.
-__device__ __forceinline__ bool ref_ok(const WalkGrid &G, uint32_t ref)
+template <typename R>
+__device__ __forceinline__ bool ref_ok(const WalkGrid &G, R ref)
 {
-    return ref != NULL_REF && ref_id(ref) < (ref_is_leaf(ref) ? G.n_leaves : G.n_internal);
+    return ref != Ref<R>::NUL && Ref<R>::id(ref) < (Ref<R>::leaf(ref) ? G.n_leaves : G.n_internal);
 }
+
+// Walk-record layout: compact (32-bit references, 32-byte records, separate
+// f32 and f64 record arrays) or wide (64-bit references, one 64-byte record).
+template <typename R, int PREC>
+struct Rec {
+    static constexpr int STRIDE = sizeof(R) == 8 ? 64 : 32;
+    static constexpr int RHO64 = sizeof(R) == 8 ? 48 : 24;
+    static constexpr int RHO32 = sizeof(R) == 8 ? 56 : 24;
+};
 
 // One descent step from the internal node ref (level lv, lower corner lo)
 // toward the point q: returns the child's reference and moves lo to the
 // child's corner.  Split planes are lo + half the node's width (exact: every
 // plane is a binary fraction).  Child references of the first lds_n internal
 // nodes are read from LDS.
-template <int TREE>
-__device__ __forceinline__ uint32_t child_of(const WalkGrid &G, const uint32_t *lds, uint32_t lds_n,
-                                             uint32_t ref, int &lv, double lo[3], const double q[3],
-                                             int dirb, int tie)
+template <int TREE, typename R>
+__device__ __forceinline__ R child_of(const WalkGrid &G, const R *lds, uint32_t lds_n, R ref, int &lv,
+                                      double lo[3], const double q[3], int dirb, int tie)
 {
-    const uint32_t id = ref_id(ref);
-    uint32_t slot;
+    const uint64_t id = Ref<R>::id(ref);
+    uint64_t slot;
     if (TREE == KD) {
         const int q3 = (lv * 43691) >> 17;  // lv / 3: the split axis b = lv mod 3 has depth lv / 3
         const int b = lv - 3 * q3;
@@ -100,7 +109,7 @@ __device__ __forceinline__ uint32_t child_of(const WalkGrid &G, const uint32_t *
         const double qb = b == 0 ? q0 : (b == 1 ? q1 : q2);
         const double mid = lob + pow2(G.lg - q3 - 1);
         const int up = upper_side(qb, mid, b, dirb, tie);
-        slot = 2u * id + uint32_t(up);
+        slot = 2u * id + uint64_t(up);
         const double nlo = up ? mid : lob;
         lo[0] = b == 0 ? nlo : l0;
         lo[1] = b == 1 ? nlo : l1;
@@ -118,22 +127,21 @@ __device__ __forceinline__ uint32_t child_of(const WalkGrid &G, const uint32_t *
         slot = 8u * id + idx;
     }
     lv++;
-    return id < lds_n ? lds[slot] : G.child[slot];
+    return id < lds_n ? lds[slot] : static_cast<const R *>(G.child)[slot];
 }
 
-// Descend from ref to the leaf holding q.  Returns NULL_REF if a reference is
+// Descend from ref to the leaf holding q.  Returns the null reference if one is
 // out of range or the depth exceeds the format's limit (never for a valid
 // layout).
-template <int TREE>
-__device__ __forceinline__ uint32_t descend(const WalkGrid &G, const uint32_t *lds, uint32_t lds_n,
-                                            uint32_t ref, int &lv, double lo[3], const double q[3],
-                                            int dirb, int tie)
+template <int TREE, typename R>
+__device__ __forceinline__ R descend(const WalkGrid &G, const R *lds, uint32_t lds_n, R ref, int &lv,
+                                     double lo[3], const double q[3], int dirb, int tie)
 {
-    while (!ref_is_leaf(ref)) {
-        if (!ref_ok(G, ref) || lv >= 62) return NULL_REF;
-        ref = child_of<TREE>(G, lds, lds_n, ref, lv, lo, q, dirb, tie);
+    while (!Ref<R>::leaf(ref)) {
+        if (!ref_ok(G, ref) || lv >= 62) return Ref<R>::NUL;
+        ref = child_of<TREE, R>(G, lds, lds_n, ref, lv, lo, q, dirb, tie);
     }
-    return ref_ok(G, ref) ? ref : NULL_REF;
+    return ref_ok(G, ref) ? ref : Ref<R>::NUL;
 }
 
 __device__ __forceinline__ bool inside_closed(const WalkGrid &G, const double x[3])
@@ -205,13 +213,13 @@ struct WalkArgs {
 };
 
 // Everything a lane carries for one path.
-template <int PREC>
+template <int PREC, typename R>
 struct Path {
     using DsT = typename std::conditional<PREC == HG_FP64, double, float>::type;
     double p0[3], k[3], ainv[3];
     double s, p[3];          // path length so far and the current entry point
     double lo[3];            // lower corner of the current node
-    uint32_t ref;            // current node (leaf once the descent ends)
+    R ref;                   // current node (leaf once the descent ends)
     int lv;                  // its level
     int tie;                 // tie context of the pending descent
     int dirb;                // direction signs (dir_bits)
@@ -227,8 +235,8 @@ struct Path {
 
 enum { PATH_WALK = 0, PATH_MISS = 1, PATH_BAD_DIR = 2 };
 
-template <int PREC, bool FILL>
-__device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Path<PREC> &P)
+template <int PREC, bool FILL, typename R>
+__device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Path<PREC, R> &P)
 {
     double inv[3];
 #pragma unroll
@@ -251,7 +259,7 @@ __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, i
 #pragma unroll
     for (int d = 0; d < 3; d++) P.lo[d] = G.lo[d];
     P.lv = 0;
-    P.ref = G.root;
+    P.ref = R(G.root);
     P.tie = TIE_NONE;
     P.dirb = dir_bits(P.k);
     P.cnt = 0;
@@ -280,13 +288,13 @@ __device__ __forceinline__ void store_one(const WalkArgs &A, int64_t pos, uint32
     else reinterpret_cast<float *>(A.ds)[pos] = float(ds);
 }
 
-template <int PREC>
-__device__ __forceinline__ void stage_record(const WalkArgs &A, Path<PREC> &P, int64_t pos, uint32_t id,
+template <int PREC, typename R>
+__device__ __forceinline__ void stage_record(const WalkArgs &A, Path<PREC, R> &P, int64_t pos, uint32_t id,
                                              double ds)
 {
     P.sl[0] = P.sl[1]; P.sl[1] = P.sl[2]; P.sl[2] = P.sl[3]; P.sl[3] = id;
     P.sd[0] = P.sd[1]; P.sd[1] = P.sd[2]; P.sd[2] = P.sd[3];
-    P.sd[3] = typename Path<PREC>::DsT(ds);
+    P.sd[3] = typename Path<PREC, R>::DsT(ds);
     if ((pos & 3) != 3) return;
     const int64_t g = pos - 3;
     if (g >= P.base) {
@@ -307,8 +315,8 @@ __device__ __forceinline__ void stage_record(const WalkArgs &A, Path<PREC> &P, i
 }
 
 // Write the staged records of an unfinished group at the end of a path.
-template <int PREC>
-__device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC> &P)
+template <int PREC, typename R>
+__device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC, R> &P)
 {
     if (P.cnt == 0) return;
     const int64_t last = P.base + P.cnt - 1;
@@ -348,12 +356,12 @@ __device__ __forceinline__ void level_geom(int lg, int lv, int dep[3], double w[
 // exit face depends only on the cell and the entry point, so it is decided
 // before the leaf's record is read; then only the rope of that face and the
 // density are loaded.
-template <int TREE, int PREC, bool FILL>
-__device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC> &P,
+template <int TREE, int PREC, bool FILL, typename R>
+__device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC, R> &P,
                                      unsigned long long &rechecks)
 {
     if (!ref_ok(G, P.ref)) return STEP_ERR;
-    const uint32_t id = ref_id(P.ref);
+    const uint64_t id = Ref<R>::id(P.ref);
     int dep[3];
     double w[3], hi[3], E[3], t[3];
     int edge = 0;
@@ -406,18 +414,17 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     const bool up = (P.dirb >> a) & 1;
     const int face = 2 * a + (up ? 1 : 0);
     // the leaf record: rope of the exit face, density
-    const uint32_t *rec = PREC == HG_FP64 ? reinterpret_cast<const uint32_t *>(G.rec64 + id)
-                                          : reinterpret_cast<const uint32_t *>(G.rec32 + id);
-    const uint32_t nref = rec[face];
+    const char *rec = static_cast<const char *>(G.rec) + id * Rec<R, PREC>::STRIDE;
+    const R nref = reinterpret_cast<const R *>(rec)[face];
     if (ds > 0.0) {
         if (FILL) {
             if (P.cnt >= P.room) return STEP_ERR;  // the fill walk must repeat the counting walk
-            stage_record<PREC>(A, P, P.base + P.cnt, id, ds);
+            stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
         } else if (PREC == HG_FP64) {
-            const double rho64 = *reinterpret_cast<const double *>(rec + 6);
+            const double rho64 = *reinterpret_cast<const double *>(rec + Rec<R, PREC>::RHO64);
             P.tau64 = P.tau64 + A.kappa * rho64 * ds;
         } else {
-            const float rho32 = __uint_as_float(rec[6]);
+            const float rho32 = *reinterpret_cast<const float *>(rec + Rec<R, PREC>::RHO32);
             const float y = float(A.kappa) * rho32 * float(ds) - P.comp32;
             const float tt = P.tau32 + y;
             P.comp32 = (tt - P.tau32) - y;
@@ -439,13 +446,13 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
         P.p[d] = q;
     }
     P.tie = a | (onlo << 2) | (onhi << 5);
-    if (nref == NULL_REF) return STEP_ERR;
+    if (nref == Ref<R>::NUL) return STEP_ERR;
     // Lower corner of the rope target: the corner of the leaf, moved across
     // the exit face and aligned down to the target's cell size (exact).  The
     // target is never finer than the leaf across the face; along the exit axis
     // a k-d target may be one level finer (the half of a same-size neighbour
     // touching the face).
-    const int nlv = ref_level(nref);
+    const int nlv = Ref<R>::level(nref);
     int dn[3];
     double wn[3];
     level_geom<TREE>(G.lg, nlv, dn, wn);
@@ -463,11 +470,11 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     return STEP_GO;
 }
 
-template <int PREC, bool FILL>
-__device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Path<PREC> &P)
+template <int PREC, bool FILL, typename R>
+__device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Path<PREC, R> &P)
 {
     if (FILL) {
-        flush_records<PREC>(A, P);
+        flush_records<PREC, R>(A, P);
         if (P.cnt != P.room) A.st->step_guard = 1;
         return;
     }
@@ -490,32 +497,32 @@ __device__ __forceinline__ void finish_unwalked(const WalkArgs &A, int64_t i, in
 }
 
 // One lane per path, the whole walk in one loop.
-template <int TREE, int PREC, bool FILL>
+template <int TREE, int PREC, bool FILL, typename R>
 __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 {
     const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (i >= A.n) return;
-    Path<PREC> P;
-    const int why = init_path<PREC, FILL>(G, A, i, P);
+    Path<PREC, R> P;
+    const int why = init_path<PREC, FILL, R>(G, A, i, P);
     if (why != PATH_WALK) {
         finish_unwalked<PREC, FILL>(A, i, why);
         return;
     }
     unsigned long long rechecks = 0;
     for (;;) {
-        P.ref = descend<TREE>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
-        if (P.ref == NULL_REF) {
+        P.ref = descend<TREE, R>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+        if (P.ref == Ref<R>::NUL) {
             A.st->bad_ref = 1;
             break;
         }
-        const int r = cross<TREE, PREC, FILL>(G, A, P, rechecks);
+        const int r = cross<TREE, PREC, FILL, R>(G, A, P, rechecks);
         if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
             A.st->step_guard = 1;
             break;
         }
         if (r == STEP_END) break;
     }
-    finish_path<PREC, FILL>(A, i, P);
+    finish_path<PREC, FILL, R>(A, i, P);
     if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
@@ -526,17 +533,18 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 // path set-up and the atomic round trip are amortised over many paths.  Each
 // iteration a busy lane performs one dependent global access: a descent step
 // (the first levels of every descent come from LDS) or a crossing.
-template <int TREE, int PREC, bool FILL>
+template <int TREE, int PREC, bool FILL, typename R>
 __global__ void __launch_bounds__(TB)
     k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min)
 {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ uint64_t lds_raw[];
+    R *lds = reinterpret_cast<R *>(lds_raw);
     const int nc = TREE == OCT ? 8 : 2;
-    for (uint32_t j = threadIdx.x; j < lds_n * nc; j += TB) lds[j] = G.child[j];
+    for (uint32_t j = threadIdx.x; j < lds_n * nc; j += TB) lds[j] = static_cast<const R *>(G.child)[j];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    Path<PREC> P;
+    Path<PREC, R> P;
     int64_t ray = -1;
     bool done = false;
     uint32_t cnext = 0, cend = 0;   // wavefront-local chunk [cnext, cend)
@@ -565,7 +573,7 @@ __global__ void __launch_bounds__(TB)
                 const uint32_t rank = uint32_t(__popcll(wmask & below));
                 if (rank < avail) {
                     const int64_t r = int64_t(cnext) + rank;
-                    const int why = init_path<PREC, FILL>(G, A, r, P);
+                    const int why = init_path<PREC, FILL, R>(G, A, r, P);
                     if (why == PATH_WALK) ray = r;
                     else finish_unwalked<PREC, FILL>(A, r, why);
                 } else if (drained) {
@@ -579,32 +587,32 @@ __global__ void __launch_bounds__(TB)
             continue;
         }
         if (ray < 0) continue;
-        if (!ref_is_leaf(P.ref)) {
+        if (!Ref<R>::leaf(P.ref)) {
             // LDS levels, then at most one global level this iteration
             for (;;) {
                 if (!ref_ok(G, P.ref) || P.lv >= 62) {
-                    P.ref = NULL_REF;
+                    P.ref = Ref<R>::NUL;
                     break;
                 }
-                const bool global = ref_id(P.ref) >= lds_n;
-                P.ref = child_of<TREE>(G, lds, lds_n, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
-                if (global || ref_is_leaf(P.ref)) break;
+                const bool global = Ref<R>::id(P.ref) >= lds_n;
+                P.ref = child_of<TREE, R>(G, lds, lds_n, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+                if (global || Ref<R>::leaf(P.ref)) break;
             }
-            if (P.ref == NULL_REF || (ref_is_leaf(P.ref) && !ref_ok(G, P.ref))) {
+            if (P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref))) {
                 A.st->bad_ref = 1;
-                finish_path<PREC, FILL>(A, ray, P);
+                finish_path<PREC, FILL, R>(A, ray, P);
                 ray = -1;
                 continue;
             }
         }
-        if (ref_is_leaf(P.ref)) {
-            const int r = cross<TREE, PREC, FILL>(G, A, P, rechecks);
+        if (Ref<R>::leaf(P.ref)) {
+            const int r = cross<TREE, PREC, FILL, R>(G, A, P, rechecks);
             if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
                 A.st->step_guard = 1;
-                finish_path<PREC, FILL>(A, ray, P);
+                finish_path<PREC, FILL, R>(A, ray, P);
                 ray = -1;
             } else if (r == STEP_END) {
-                finish_path<PREC, FILL>(A, ray, P);
+                finish_path<PREC, FILL, R>(A, ray, P);
                 ray = -1;
             }
         }
@@ -612,7 +620,7 @@ __global__ void __launch_bounds__(TB)
     if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
-template <int TREE>
+template <int TREE, typename R>
 __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restrict__ X, int64_t n,
                                                int32_t *__restrict__ out)
 {
@@ -627,8 +635,8 @@ __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restr
     }
     double lo[3] = {G.lo[0], G.lo[1], G.lo[2]};
     int lv = 0;
-    const uint32_t r = descend<TREE>(G, nullptr, 0u, G.root, lv, lo, x, 0, TIE_NONE);
-    out[i] = r == NULL_REF ? -2 : int32_t(ref_id(r));
+    const R r = descend<TREE, R>(G, nullptr, 0u, R(G.root), lv, lo, x, 0, TIE_NONE);
+    out[i] = r == Ref<R>::NUL ? -2 : int32_t(Ref<R>::id(r));
 }
 
 __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
@@ -636,20 +644,10 @@ __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
 constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
 
-template <int TREE, int PREC, bool FILL>
-int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trace_opts *o,
-             hipStream_t s)
+// Occupancy-derived persistent grid size, cached per kernel instance.
+template <int TREE, int PREC, bool FILL, typename R>
+int persistent_blocks(size_t lds, unsigned *blocks)
 {
-    if (A.n == 0) return HG_OK;
-    if (!persistent) {
-        const int64_t nb = (A.n + TB - 1) / TB;
-        k_walk<TREE, PREC, FILL><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, A);
-        HG_CHECK(hipGetLastError());
-        return HG_OK;
-    }
-    const int nc = TREE == OCT ? 8 : 2;
-    const uint32_t lds_n = uint32_t(std::min<uint64_t>(G.n_internal, LDS_BYTES / (4u * nc)));
-    const size_t lds = size_t(lds_n) * nc * 4u;
     static int occ = -1, cus = 0;
     static size_t occ_lds = 0;
     if (occ < 0 || occ_lds != lds) {
@@ -657,11 +655,32 @@ int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trac
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, FILL>), TB, lds));
+            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, FILL, R>), TB, lds));
         occ_lds = lds;
     }
-    const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
-    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 512u;
+    *blocks = unsigned(std::max(1, cus) * std::max(1, occ));
+    return HG_OK;
+}
+
+template <int TREE, int PREC, bool FILL, typename R>
+int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trace_opts *o,
+             hipStream_t s)
+{
+    if (A.n == 0) return HG_OK;
+    if (!persistent) {
+        const int64_t nb = (A.n + TB - 1) / TB;
+        k_walk<TREE, PREC, FILL, R><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, A);
+        HG_CHECK(hipGetLastError());
+        return HG_OK;
+    }
+    const int nc = TREE == OCT ? 8 : 2;
+    const uint32_t lds_n =
+        uint32_t(std::min<uint64_t>(G.n_internal, LDS_BYTES / (sizeof(R) * size_t(nc))));
+    const size_t lds = size_t(lds_n) * nc * sizeof(R);
+    unsigned blocks = 0;
+    int rc = persistent_blocks<TREE, PREC, FILL, R>(lds, &blocks);
+    if (rc) return rc;
+    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 128u;
     const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : 16;
     for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
         WalkArgs B = A;
@@ -673,16 +692,27 @@ int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trac
         B.offsets = A.offsets ? A.offsets + start : nullptr;
         k_reset_counter<<<1, 1, 0, s>>>(A.st);
         HG_CHECK(hipGetLastError());
-        k_walk_persistent<TREE, PREC, FILL><<<dim3(blocks), dim3(TB), lds, s>>>(G, B, lds_n, chunk,
-                                                                                  refill_min);
+        k_walk_persistent<TREE, PREC, FILL, R><<<dim3(blocks), dim3(TB), lds, s>>>(G, B, lds_n, chunk,
+                                                                                     refill_min);
         HG_CHECK(hipGetLastError());
     }
     return HG_OK;
 }
 
+template <int TREE, typename R>
+int dispatch_walk(const WalkGrid &G, const WalkArgs &A, int prec, bool fill, int persistent,
+                  const hg_trace_opts *o, hipStream_t s)
+{
+    if (prec == HG_FP64)
+        return fill ? launch_t<TREE, HG_FP64, true, R>(G, A, persistent, o, s)
+                    : launch_t<TREE, HG_FP64, false, R>(G, A, persistent, o, s);
+    return fill ? launch_t<TREE, HG_FP32_RECHECK, true, R>(G, A, persistent, o, s)
+                : launch_t<TREE, HG_FP32_RECHECK, false, R>(G, A, persistent, o, s);
+}
+
 }  // namespace
 
-WalkGrid walk_grid(const hg_grid *g)
+WalkGrid walk_grid(const hg_grid *g, int precision)
 {
     WalkGrid G;
     G.tree = g->tree;
@@ -692,10 +722,11 @@ WalkGrid walk_grid(const hg_grid *g)
     frexp(g->side, &e);
     G.lg = e - 1;
     G.root = g->root_ref;
-    G.n_leaves = uint32_t(g->n_leaves);
-    G.n_internal = uint32_t(g->n_internal);
-    G.rec32 = g->rec32;
-    G.rec64 = g->rec64;
+    G.n_leaves = uint64_t(g->n_leaves);
+    G.n_internal = uint64_t(g->n_internal);
+    G.rec = g->wide ? static_cast<const void *>(g->recw)
+                    : (precision == HG_FP64 ? static_cast<const void *>(g->rec64)
+                                            : static_cast<const void *>(g->rec32));
     G.child = g->child;
     return G;
 }
@@ -707,7 +738,7 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
     // bit 0: persistent counting / tau-only walk, bit 1: persistent fill walk
     const int mode = opts->persistent < 0 ? 3 : opts->persistent;
     const int persistent = fill ? (mode >> 1) & 1 : mode & 1;
-    const WalkGrid G = walk_grid(g);
+    const WalkGrid G = walk_grid(g, opts->precision);
     WalkArgs A;
     A.O = o;
     A.K = k;
@@ -721,27 +752,26 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
     A.st = g->status;
     A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
     const int prec = opts->precision;
-    if (g->tree == KD) {
-        if (prec == HG_FP64)
-            return fill ? launch_t<KD, HG_FP64, true>(G, A, persistent, opts, s)
-                        : launch_t<KD, HG_FP64, false>(G, A, persistent, opts, s);
-        return fill ? launch_t<KD, HG_FP32_RECHECK, true>(G, A, persistent, opts, s)
-                    : launch_t<KD, HG_FP32_RECHECK, false>(G, A, persistent, opts, s);
-    }
-    if (prec == HG_FP64)
-        return fill ? launch_t<OCT, HG_FP64, true>(G, A, persistent, opts, s)
-                    : launch_t<OCT, HG_FP64, false>(G, A, persistent, opts, s);
-    return fill ? launch_t<OCT, HG_FP32_RECHECK, true>(G, A, persistent, opts, s)
-                : launch_t<OCT, HG_FP32_RECHECK, false>(G, A, persistent, opts, s);
+    if (g->tree == KD)
+        return g->wide ? dispatch_walk<KD, uint64_t>(G, A, prec, fill, persistent, opts, s)
+                       : dispatch_walk<KD, uint32_t>(G, A, prec, fill, persistent, opts, s);
+    return g->wide ? dispatch_walk<OCT, uint64_t>(G, A, prec, fill, persistent, opts, s)
+                   : dispatch_walk<OCT, uint32_t>(G, A, prec, fill, persistent, opts, s);
 }
 
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s)
 {
-    const WalkGrid G = walk_grid(g);
+    const WalkGrid G = walk_grid(g, HG_FP64);
     const int64_t nb = (n + TB - 1) / TB;
     if (nb == 0) return HG_OK;
-    if (g->tree == KD) k_locate<KD><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, p, n, leaf);
-    else k_locate<OCT><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, p, n, leaf);
+    const dim3 grid{unsigned(nb), 1u, 1u}, block{unsigned(TB), 1u, 1u};
+    if (g->tree == KD) {
+        if (g->wide) k_locate<KD, uint64_t><<<grid, block, 0, s>>>(G, p, n, leaf);
+        else k_locate<KD, uint32_t><<<grid, block, 0, s>>>(G, p, n, leaf);
+    } else {
+        if (g->wide) k_locate<OCT, uint64_t><<<grid, block, 0, s>>>(G, p, n, leaf);
+        else k_locate<OCT, uint32_t><<<grid, block, 0, s>>>(G, p, n, leaf);
+    }
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }

@@ -317,3 +317,30 @@ def test_deterministic_repeat():
     e1, e2 = g.export(), g2.export()
     for key in ("first_child", "S", "rope", "rho"):
         assert torch.equal(e1[key], e2[key])
+
+
+def test_wide_reference_layout(trees, monkeypatch):
+    # Trees beyond 2^25 leaves or internal nodes use 64-bit references and
+    # 64-byte records; HGRID_WIDE_REFS=1 forces that layout on small trees.
+    monkeypatch.setenv("HGRID_WIDE_REFS", "1")
+    for name, og in trees:
+        print(f"[gpu] wide layout {name}", flush=True)
+        g = to_gpu(og)
+        o1, k1 = random_rays(300, 15)
+        oa, ka = adversarial_rays()
+        check_trace(og, g, np.concatenate([o1, oa]), np.concatenate([k1, ka]), kappa=1.3)
+        pts = np.random.default_rng(2).uniform(-1.05, 1.05, size=(3000, 3))
+        assert np.array_equal(g.locate(pts).cpu().numpy(), og.locate(pts))
+    w = W.workload(1)
+    gw = hg.Grid.build(w.density, w.criteria, w.tree_type, device=DEV)
+    monkeypatch.delenv("HGRID_WIDE_REFS")
+    gc = hg.Grid.build(w.density, w.criteria, w.tree_type, device=DEV)
+    o, k = W.rays(w.ray_kind, 20_000, 8)
+    for prec in (hg.FP64, hg.FP32_RECHECK):
+        a = gw.trace(o, k, precision=prec, mode=hg.RECORDS)
+        b = gc.trace(o, k, precision=prec, mode=hg.RECORDS)
+        n = a["needed"]
+        assert n == b["needed"]
+        for key in ("tau", "count", "offsets"):
+            assert torch.equal(a[key], b[key])
+        assert torch.equal(a["leaf"][:n], b["leaf"][:n]) and torch.equal(a["ds"][:n], b["ds"][:n])
