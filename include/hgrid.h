@@ -198,6 +198,22 @@ int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_
 int grid_trace(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
                const hg_trace_opts *opts, hg_trace_out *out, void *stream);
 
+/* Trace several grids' path batches in one persistent launch per walk pass
+ * (Sect. 2.3, as grid_trace).  Entry g traces n[g] paths origins[g] / dirs[g]
+ * through grids[g] into outs[g] with the shared options opts.  The device
+ * work queue holds chunks of opts->chunk paths (0 = library choice) of one
+ * grid each; wavefronts take chunks with one atomic and mix octree and k-d
+ * grids freely.  Records mode: one counting launch for the whole batch, a
+ * prefix sum per grid, one record-filling launch; HG_E_CAPACITY if any
+ * outs[g].capacity < outs[g].needed (all needed are set).  Results equal
+ * those of n_grids separate grid_trace calls bit for bit.  The batch's
+ * rechecks and kernel times are reported in outs[0].  Grids that need the
+ * wide layout are traced one by one.  Synchronises the stream.  Errors as
+ * grid_trace. */
+int grid_trace_batched(int n_grids, const hg_grid_t *grids, const double *const *origins,
+                       const double *const *dirs, const int64_t *n, const hg_trace_opts *opts,
+                       hg_trace_out *outs, void *stream);
+
 /* Leaf containing each point (Sect. 2.3, top-down search).  points is device
  * double[n][3]; leaf_out device int32[n].  Cells are half-open [lo, hi) along
  * each axis except that the domain's upper faces belong to the last cells;

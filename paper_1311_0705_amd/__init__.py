@@ -103,6 +103,9 @@ _SIGS = [
                              C.POINTER(C.c_void_p)]),
     ("grid_trace", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                              C.POINTER(TraceOpts), C.POINTER(TraceOut), C.c_void_p]),
+    ("grid_trace_batched", C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                     C.POINTER(TraceOpts), C.POINTER(TraceOut), C.c_void_p]),
     ("grid_locate", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     ("grid_import", C.c_int, [C.POINTER(GridArrays), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("grid_export", C.c_int, [C.c_void_p, C.POINTER(GridArrays)]),
@@ -367,6 +370,70 @@ class Grid:
             node_of=cp(a.node_of, (L,), torch.int32),
             rope=cp(a.rope, (N, 6), torch.int32),
         )
+
+
+def trace_batched(grids, origins, dirs, precision: int = FP64, mode: int = RECORDS,
+                  kappa: float = 1.0, capacities=None, timing: bool = False,
+                  count_rechecks: bool = False, chunk: int = 0, refill_min: int = 0,
+                  stream=None, outs=None):
+    """Trace len(grids) path batches in one batched call; returns one result
+    dict per grid (as Grid.trace) and the batch's kernel_ms / rechecks in the
+    first."""
+    ng = len(grids)
+    dev = grids[0].device
+    os_ = [_dev_f64x3(o, dev) for o in origins]
+    ks_ = [_dev_f64x3(k, dev) for k in dirs]
+    ns = [o.shape[0] for o in os_]
+    res = outs if outs is not None else [dict() for _ in range(ng)]
+    dsdt = torch.float64 if precision == FP64 else torch.float32
+    opts = TraceOpts()
+    opts.precision = precision
+    opts.mode = mode
+    opts.kappa = kappa
+    opts.flags = (FLAG_TIMING if timing else 0) | (FLAG_RECHECKS if count_rechecks else 0)
+    opts.chunk = chunk
+    opts.refill_min = refill_min
+    for attempt in range(2):
+        tos = (TraceOut * ng)()
+        for i in range(ng):
+            r = res[i]
+            n = ns[i]
+            if "tau" not in r or r["tau"].numel() != n:
+                r["tau"] = torch.empty(n, dtype=torch.float64, device=dev)
+                r["count"] = torch.empty(n, dtype=torch.int32, device=dev)
+            to = tos[i]
+            to.tau = r["tau"].data_ptr()
+            to.count = r["count"].data_ptr()
+            if mode == RECORDS:
+                if "offsets" not in r or r["offsets"].numel() != n + 1:
+                    r["offsets"] = torch.empty(n + 1, dtype=torch.int64, device=dev)
+                cap = capacities[i] if capacities is not None else (
+                    r["leaf"].numel() if "leaf" in r else 64 * max(n, 1))
+                if "leaf" not in r or r["leaf"].numel() < cap or r["ds"].dtype != dsdt:
+                    r["leaf"] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+                    r["ds"] = torch.empty(max(cap, 1), dtype=dsdt, device=dev)
+                to.offsets = r["offsets"].data_ptr()
+                to.leaf = r["leaf"].data_ptr()
+                to.ds = r["ds"].data_ptr()
+                to.capacity = r["leaf"].numel()
+        gp = (C.c_void_p * ng)(*[g._h.value if isinstance(g._h, C.c_void_p) else g._h for g in grids])
+        op = (C.c_void_p * ng)(*[o.data_ptr() for o in os_])
+        kp = (C.c_void_p * ng)(*[k.data_ptr() for k in ks_])
+        np_ = (C.c_int64 * ng)(*ns)
+        rc = lib().grid_trace_batched(ng, gp, op, kp, np_, C.byref(opts), tos, _stream(stream))
+        if rc == HG_E_CAPACITY and attempt == 0 and capacities is None:
+            capacities = [int(tos[i].needed) for i in range(ng)]
+            for r in res:
+                r.pop("leaf", None)
+                r.pop("ds", None)
+            continue
+        _check(rc, "grid_trace_batched")
+        break
+    for i in range(ng):
+        res[i]["needed"] = int(tos[i].needed)
+        res[i]["rechecks"] = int(tos[i].rechecks)
+        res[i]["kernel_ms"] = list(tos[i].kernel_ms)
+    return res
 
 
 def build(density, criteria, tree_type, stream=None, device="cuda", max_nodes=0) -> Grid:

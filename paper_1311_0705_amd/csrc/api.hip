@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -258,8 +259,8 @@ int grid_locate(hg_grid_t g, const double *points, int64_t n, int32_t *leaf_out,
     return launch_locate(g, points, n, leaf_out, (hipStream_t)stream);
 }
 
-int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
-               const hg_trace_opts *opts, hg_trace_out *out, void *stream)
+static int check_trace_args(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
+                            const hg_trace_opts *opts, const hg_trace_out *out)
 {
     if (!g || !opts || !out || n < 0) return HG_E_INVAL;
     if (opts->precision != HG_FP64 && opts->precision != HG_FP32_RECHECK) return HG_E_INVAL;
@@ -271,6 +272,143 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     if (records && out->capacity > 0 && (!out->leaf || !out->ds)) return HG_E_INVAL;
     if (records && out->capacity < 0) return HG_E_INVAL;
     if (records && ((uintptr_t(out->leaf) | uintptr_t(out->ds)) & 15u)) return HG_E_INVAL;
+    return HG_OK;
+}
+
+static int read_status(hg_grid *g, TraceStatus *st, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(st, g->status, sizeof *st, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return set_hip_error(e);
+    if (st->bad_ref) return HG_E_FORMAT;
+    if (st->bad_dir) return HG_E_DIR;
+    if (st->step_guard) return HG_E_STEP;
+    return HG_OK;
+}
+
+int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *origins,
+                       const double *const *dirs, const int64_t *n, const hg_trace_opts *opts,
+                       hg_trace_out *outs, void *stream)
+{
+    if (ng < 1 || !grids || !origins || !dirs || !n || !opts || !outs) return HG_E_INVAL;
+    bool any_wide = false;
+    for (int i = 0; i < ng; i++) {
+        int rc = check_trace_args(grids[i], origins[i], dirs[i], n[i], opts, &outs[i]);
+        if (rc) return rc;
+        any_wide = any_wide || grids[i]->wide;
+    }
+    if (any_wide) {
+        int first = HG_OK;
+        for (int i = 0; i < ng; i++) {
+            int rc = grid_trace(grids[i], origins[i], dirs[i], n[i], opts, &outs[i], stream);
+            if (rc && !first) first = rc;
+        }
+        return first;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool records = opts->mode == HG_RECORDS;
+    const bool timing = (opts->flags & HG_FLAG_TIMING) != 0;
+    const int64_t chunk = opts->chunk > 0 ? opts->chunk : 1024;
+    hg_grid *g0 = grids[0];
+    std::vector<WalkGrid> hG((size_t)ng);
+    std::vector<WalkArgs> hA((size_t)ng);
+    std::vector<BatchChunk> hC;
+    int64_t nmax = 0;
+    for (int i = 0; i < ng; i++) {
+        hG[size_t(i)] = walk_grid(grids[i], opts->precision);
+        hA[size_t(i)] = walk_args(grids[i], origins[i], dirs[i], n[i], opts, &outs[i]);
+        hA[size_t(i)].st = g0->status;
+        for (int64_t a = 0; a < n[i]; a += chunk) hC.push_back(BatchChunk{i, 0, a, std::min(n[i], a + chunk)});
+        nmax = std::max(nmax, n[i]);
+        outs[i].needed = 0;
+        outs[i].rechecks = 0;
+        for (int t = 0; t < 4; t++) outs[i].kernel_ms[t] = 0.f;
+    }
+    if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
+    WalkGrid *dG = nullptr;
+    WalkArgs *dA = nullptr;
+    BatchChunk *dC = nullptr;
+    int64_t *tmp = nullptr;
+    int rc = dalloc_n(&dG, size_t(ng), s);
+    if (!rc) rc = dalloc_n(&dA, size_t(ng), s);
+    if (!rc) rc = dalloc_n(&dC, std::max<size_t>(hC.size(), 1), s);
+    if (!rc && records) rc = dalloc_n(&tmp, scan_tmp_elems(nmax), s);
+    hipEvent_t ev[4] = {};
+    if (!rc && timing)
+        for (int t = 0; t < 4; t++)
+            if (hipEventCreate(&ev[t]) != hipSuccess) rc = HG_E_HIP;
+    hipError_t e = hipSuccess;
+    if (!rc) e = hipMemcpyAsync(dG, hG.data(), sizeof(WalkGrid) * size_t(ng), hipMemcpyHostToDevice, s);
+    if (!rc && !e) e = hipMemcpyAsync(dA, hA.data(), sizeof(WalkArgs) * size_t(ng), hipMemcpyHostToDevice, s);
+    if (!rc && !e && !hC.empty())
+        e = hipMemcpyAsync(dC, hC.data(), sizeof(BatchChunk) * hC.size(), hipMemcpyHostToDevice, s);
+    if (!rc && e) rc = set_hip_error(e);
+    TraceStatus st;
+    if (!rc) {
+        k_reset_status<<<1, 1, 0, s>>>(g0->status);
+        if (timing) (void)hipEventRecord(ev[0], s);
+        rc = launch_batched(dG, dA, dC, int(hC.size()), opts, false, g0->status, s);
+        if (timing) (void)hipEventRecord(ev[1], s);
+    }
+    if (!rc) rc = read_status(g0, &st, s);
+    if (!rc) outs[0].rechecks = int64_t(st.rechecks);
+    if (!rc && records) {
+        for (int i = 0; i < ng && !rc; i++)
+            rc = scan_i32_to_i64(outs[i].count, outs[i].offsets, n[i], tmp, s);
+        std::vector<int64_t> tot((size_t)ng, 0);
+        for (int i = 0; i < ng && !rc; i++) {
+            e = hipMemcpyAsync(&tot[size_t(i)], outs[i].offsets + n[i], 8, hipMemcpyDeviceToHost, s);
+            if (e) rc = set_hip_error(e);
+        }
+        if (!rc) {
+            e = hipStreamSynchronize(s);
+            if (e) rc = set_hip_error(e);
+        }
+        bool fits = true;
+        for (int i = 0; i < ng && !rc; i++) {
+            outs[i].needed = tot[size_t(i)];
+            if (tot[size_t(i)] > outs[i].capacity) fits = false;
+        }
+        if (!rc && !fits) rc = HG_E_CAPACITY;
+        if (!rc) {
+            if (timing) (void)hipEventRecord(ev[2], s);
+            rc = launch_batched(dG, dA, dC, int(hC.size()), opts, true, g0->status, s);
+            if (timing) (void)hipEventRecord(ev[3], s);
+        }
+        if (!rc) rc = read_status(g0, &st, s);
+    }
+    if (!rc) {
+        e = hipStreamSynchronize(s);
+        if (e) rc = set_hip_error(e);
+    }
+    if (timing && (rc == HG_OK || rc == HG_E_CAPACITY)) {
+        (void)hipEventElapsedTime(&outs[0].kernel_ms[0], ev[0], ev[1]);
+        if (records && rc == HG_OK) {
+            (void)hipEventElapsedTime(&outs[0].kernel_ms[1], ev[1], ev[2]);
+            (void)hipEventElapsedTime(&outs[0].kernel_ms[2], ev[2], ev[3]);
+            (void)hipEventElapsedTime(&outs[0].kernel_ms[3], ev[0], ev[3]);
+        } else {
+            outs[0].kernel_ms[3] = outs[0].kernel_ms[0];
+        }
+    }
+    for (int t = 0; t < 4; t++)
+        if (ev[t]) (void)hipEventDestroy(ev[t]);
+    (void)hipStreamSynchronize(s);
+    dfree(dG, s);
+    dfree(dA, s);
+    dfree(dC, s);
+    dfree(tmp, s);
+    return rc;
+}
+
+int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
+               const hg_trace_opts *opts, hg_trace_out *out, void *stream)
+{
+    {
+        int rc0 = check_trace_args(g, origins, dirs, n, opts, out);
+        if (rc0) return rc0;
+    }
+    const bool records = opts->mode == HG_RECORDS;
     hipStream_t s = (hipStream_t)stream;
     const bool timing = (opts->flags & HG_FLAG_TIMING) != 0;
     hipEvent_t ev[5] = {};

@@ -110,6 +110,28 @@ struct TraceStatus {
     unsigned int done_waves;
 };
 
+// Per-grid arguments of a walk launch.
+struct WalkArgs {
+    const double *O;
+    const double *K;
+    int64_t n;
+    double kappa;
+    double *tau;
+    int32_t *count;
+    const int64_t *offsets;
+    int32_t *leaf;
+    void *ds;
+    TraceStatus *st;
+    int count_rechecks;
+};
+
+// One entry of the batched walk's work queue: paths [start, end) of a grid.
+struct BatchChunk {
+    int32_t grid;
+    int32_t pad;
+    int64_t start, end;
+};
+
 }  // namespace hg
 
 // The library's grid object.
@@ -183,5 +205,10 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
                 const hg_trace_opts *opts, hg_trace_out *out, bool fill, hipStream_t s,
                 float *ms);
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s);
+WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
+                   const hg_trace_opts *opts, hg_trace_out *out);
+int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
+                   int n_chunks, const hg_trace_opts *opts, bool fill, TraceStatus *st,
+                   hipStream_t s);
 
 }  // namespace hg

@@ -198,20 +198,6 @@ __device__ __forceinline__ bool clip_ray(const WalkGrid &G, const double p0[3], 
     return true;
 }
 
-struct WalkArgs {
-    const double *O;
-    const double *K;
-    int64_t n;
-    double kappa;
-    double *tau;
-    int32_t *count;
-    const int64_t *offsets;
-    int32_t *leaf;
-    void *ds;
-    TraceStatus *st;
-    int count_rechecks;
-};
-
 // Everything a lane carries for one path.
 template <int PREC, typename R>
 struct Path {
@@ -620,6 +606,118 @@ __global__ void __launch_bounds__(TB)
     if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
+// One step of a busy lane in the batched walk: at most one global descent
+// level, or one crossing.  Returns false when the path ended (or failed).
+template <int TREE, int PREC, bool FILL>
+__device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &A,
+                                             Path<PREC, uint32_t> &P, int64_t ray,
+                                             unsigned long long &rechecks)
+{
+    if (!Ref<uint32_t>::leaf(P.ref)) {
+        if (!ref_ok(G, P.ref) || P.lv >= 62) {
+            A.st->bad_ref = 1;
+            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            return false;
+        }
+        P.ref = child_of<TREE, uint32_t>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+        if (Ref<uint32_t>::leaf(P.ref) && !ref_ok(G, P.ref)) {
+            A.st->bad_ref = 1;
+            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            return false;
+        }
+    }
+    if (Ref<uint32_t>::leaf(P.ref)) {
+        const int r = cross<TREE, PREC, FILL, uint32_t>(G, A, P, rechecks);
+        if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
+            A.st->step_guard = 1;
+            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            return false;
+        }
+        if (r == STEP_END) {
+            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Batched walk over many grids in one persistent launch.  The device work
+// queue is a table of chunks (grid, path range); a wavefront takes one chunk
+// per atomic and keeps that grid's parameters uniform across its lanes,
+// refilling lanes from the chunk.  Before taking up a chunk of another grid it
+// lets its lanes finish their paths.  Octree and k-d grids mix freely: the
+// tree type is a wavefront-uniform branch.
+template <int PREC, bool FILL>
+__global__ void __launch_bounds__(TB)
+    k_walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
+                   const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min,
+                   TraceStatus *st)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    Path<PREC, uint32_t> P;
+    int64_t ray = -1;
+    bool done = false;
+    int gi = -1, pc = -1;
+    int64_t cnext = 0, cend = 0;
+    bool drained = false;
+    WalkGrid G;
+    WalkArgs A;
+    unsigned long long rechecks = 0;
+    for (;;) {
+        const bool want = ray < 0 && !done;
+        const uint64_t wmask = __ballot(want);
+        const uint64_t amask = __ballot(ray >= 0);
+        const int nwant = __popcll(wmask);
+        if (nwant && (nwant >= refill_min || !amask)) {
+            if (cnext >= cend) {
+                if (pc < 0 && !drained) {
+                    int c = 0;
+                    if (lane == 0) c = int(atomicAdd(&st->next_ray, 1u));
+                    c = __shfl(c, 0, 64);
+                    if (c >= n_chunks) drained = true;
+                    else pc = c;
+                }
+                if (pc >= 0) {
+                    const int cg = __builtin_amdgcn_readfirstlane(chunks[pc].grid);
+                    if (cg == gi || !amask) {
+                        if (cg != gi) {
+                            gi = cg;
+                            G = grids[gi];
+                            A = args[gi];
+                        }
+                        cnext = chunks[pc].start;
+                        cend = chunks[pc].end;
+                        pc = -1;
+                    }
+                }
+            }
+            const int64_t avail = cend - cnext;
+            if (want) {
+                const int64_t rank = __popcll(wmask & below);
+                if (rank < avail) {
+                    const int64_t r = cnext + rank;
+                    const int why = init_path<PREC, FILL, uint32_t>(G, A, r, P);
+                    if (why == PATH_WALK) ray = r;
+                    else finish_unwalked<PREC, FILL>(A, r, why);
+                } else if (drained && pc < 0) {
+                    done = true;
+                }
+            }
+            cnext += std::min<int64_t>(avail, nwant);
+        }
+        if (!amask && !__ballot(ray >= 0)) {
+            if (!__ballot(!done)) break;
+            continue;
+        }
+        if (ray < 0) continue;
+        const bool alive = G.tree == KD ? batched_step<KD, PREC, FILL>(G, A, P, ray, rechecks)
+                                        : batched_step<OCT, PREC, FILL>(G, A, P, ray, rechecks);
+        if (!alive) ray = -1;
+    }
+    if (!FILL && rechecks && A.count_rechecks) atomicAdd(&st->rechecks, rechecks);
+}
+
 template <int TREE, typename R>
 __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restrict__ X, int64_t n,
                                                int32_t *__restrict__ out)
@@ -710,6 +808,27 @@ int dispatch_walk(const WalkGrid &G, const WalkArgs &A, int prec, bool fill, int
                 : launch_t<TREE, HG_FP32_RECHECK, false, R>(G, A, persistent, o, s);
 }
 
+template <int PREC, bool FILL>
+int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
+                     int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
+{
+    static int occ = -1, cus = 0;
+    if (occ < 0) {
+        int dev = 0;
+        HG_CHECK(hipGetDevice(&dev));
+        HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, FILL>), TB, 0));
+    }
+    const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
+    k_reset_counter<<<1, 1, 0, s>>>(st);
+    HG_CHECK(hipGetLastError());
+    k_walk_batched<PREC, FILL><<<dim3(blocks), dim3(TB), 0, s>>>(grids, args, chunks, n_chunks,
+                                                                 refill_min, st);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
+}
+
 }  // namespace
 
 WalkGrid walk_grid(const hg_grid *g, int precision)
@@ -757,6 +876,36 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
                        : dispatch_walk<KD, uint32_t>(G, A, prec, fill, persistent, opts, s);
     return g->wide ? dispatch_walk<OCT, uint64_t>(G, A, prec, fill, persistent, opts, s)
                    : dispatch_walk<OCT, uint32_t>(G, A, prec, fill, persistent, opts, s);
+}
+
+WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
+                   const hg_trace_opts *opts, hg_trace_out *out)
+{
+    WalkArgs A;
+    A.O = o;
+    A.K = k;
+    A.n = n;
+    A.kappa = opts->kappa;
+    A.tau = out->tau;
+    A.count = out->count;
+    A.offsets = out->offsets;
+    A.leaf = out->leaf;
+    A.ds = out->ds;
+    A.st = g->status;
+    A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
+    return A;
+}
+
+int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
+                   int n_chunks, const hg_trace_opts *opts, bool fill, TraceStatus *st,
+                   hipStream_t s)
+{
+    const int refill_min = opts->refill_min > 0 ? std::min(opts->refill_min, 64) : 16;
+    if (opts->precision == HG_FP64)
+        return fill ? launch_batched_t<HG_FP64, true>(grids, args, chunks, n_chunks, refill_min, st, s)
+                    : launch_batched_t<HG_FP64, false>(grids, args, chunks, n_chunks, refill_min, st, s);
+    return fill ? launch_batched_t<HG_FP32_RECHECK, true>(grids, args, chunks, n_chunks, refill_min, st, s)
+                : launch_batched_t<HG_FP32_RECHECK, false>(grids, args, chunks, n_chunks, refill_min, st, s);
 }
 
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s)
