@@ -64,6 +64,11 @@ extern "C" {
 #define HG_FLAG_RECHECKS 2 /* grid_trace: count FP64 rechecks (HG_FP32_RECHECK) */
 
 #define HG_MAX_CLUMPS (1 << 24)
+#define HG_MAX_BATCH  (1 << 16) /* grids per batch (batch_create) */
+
+#define HG_STAGE_BUILD 1   /* batch_run / batch_capture: construct every grid */
+#define HG_STAGE_TRACE 2   /* batch_run / batch_capture: trace the bound path batches */
+#define HG_STAGE_ALL   3
 
 /* ---- density field ----------------------------------------------------- */
 /* The true density rho_t(x) of Sect. 3.2, given as a sum of parametric
@@ -236,6 +241,68 @@ int grid_export(hg_grid_t grid, hg_grid_arrays *out);
 /* Release a grid and its device memory (NULL is ignored).  The caller must
  * make sure no work using the grid is still queued. */
 void grid_free(hg_grid_t grid);
+
+/* ---- batches: many grids built and traced without host synchronisation -- */
+/* A batch holds n_grids grids whose construction (Sect. 2.2 with the
+ * criteria of Sect. 4, exactly as grid_build) and path tracing (Sect. 2.3,
+ * exactly as grid_trace_batched) are enqueued with launch shapes fixed in
+ * advance and every count kept on the device.  batch_run therefore neither
+ * allocates nor synchronises, and batch_capture records it into a HIP graph
+ * that batch_replay launches again (the build-then-trace pass of a batch with
+ * new contents of the bound input buffers, or simply again).  Grids use the
+ * compact layout only (node capacity at most 2^25). */
+typedef struct hg_batch *hg_batch_t;
+
+/* Reserve a batch: density dens[g] (copied; clumps binned here), criteria
+ * crit[g] and tree type tree_types[g] of every grid.  crit[g].max_nodes >= 1
+ * is grid g's node capacity: all its device arrays (about 160 bytes per node)
+ * are allocated now.  Synchronises the device.  Errors: HG_E_INVAL (as
+ * grid_build, or max_nodes < 1, or n_grids outside 1..HG_MAX_BATCH),
+ * HG_E_DOMAIN, HG_E_LIMIT (max_nodes > 2^25), HG_E_OOM, HG_E_HIP. */
+int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit,
+                 const int *tree_types, hg_batch_t *out);
+
+/* Bind the path batches every later trace stage reads: origins[g] / dirs[g]
+ * (device, n[g] paths) into outs[g] (caller-owned device buffers, as
+ * grid_trace; the pointers are kept, the buffers must outlive their use).
+ * opts as grid_trace_batched (chunk = paths per work-queue entry).  Replaces
+ * an earlier binding and drops a captured graph.  Synchronises the device.
+ * Errors: HG_E_INVAL, HG_E_LIMIT, HG_E_OOM, HG_E_HIP. */
+int batch_bind(hg_batch_t batch, const double *const *origins, const double *const *dirs,
+               const int64_t *n, const hg_trace_opts *opts, hg_trace_out *outs);
+
+/* Enqueue the stages (HG_STAGE_*) on stream: no allocation, no host
+ * synchronisation.  The trace stage reads the grids of the last build stage
+ * and needs a binding.  Records mode: a grid whose records exceed its
+ * capacity gets none written (batch_result reports it).  Errors: HG_E_INVAL,
+ * HG_E_HIP. */
+int batch_run(hg_batch_t batch, int stages, void *stream);
+
+/* Capture batch_run(batch, stages) on stream (not the legacy default stream)
+ * into a graph kept by the batch; batch_replay(batch, stream) launches it.
+ * Errors: HG_E_INVAL, HG_E_HIP. */
+int batch_capture(hg_batch_t batch, int stages, void *stream);
+int batch_replay(hg_batch_t batch, void *stream);
+
+/* Wait for the stream and read the results of the last run or replay:
+ * per-grid node and leaf counts (arrays of n_grids, may be NULL) and, for a
+ * bound batch, outs[g].needed (records mode) and the recheck count in
+ * outs[0].rechecks (with HG_FLAG_RECHECKS).  Returns HG_E_LIMIT if a grid
+ * exceeded its node capacity (its tree is incomplete), HG_E_CAPACITY if a
+ * grid's records did not fit, else the trace errors of grid_trace. */
+int batch_result(hg_batch_t batch, void *stream, int64_t *n_nodes, int64_t *n_leaves,
+                 hg_trace_out *outs);
+
+/* A grid handle on grid g of a built batch, for grid_trace, grid_locate and
+ * grid_export; it borrows the batch's arrays (valid until the next build
+ * stage or batch_free) and is released with grid_free.  Synchronises the
+ * device.  Errors: HG_E_INVAL, HG_E_LIMIT (the grid exceeded its capacity),
+ * HG_E_OOM, HG_E_HIP. */
+int batch_grid(hg_batch_t batch, int g, hg_grid_t *out);
+
+/* Release a batch and its device memory (NULL is ignored); synchronises the
+ * device.  Grid handles from batch_grid must be freed before. */
+void batch_free(hg_batch_t batch);
 
 /* Static description of a status code. */
 const char *grid_strerror(int code);

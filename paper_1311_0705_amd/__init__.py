@@ -25,6 +25,9 @@ TAU_ONLY = 0
 RECORDS = 1
 FLAG_TIMING = 1
 FLAG_RECHECKS = 2
+STAGE_BUILD = 1
+STAGE_TRACE = 2
+STAGE_ALL = 3
 
 HG_OK = 0
 HG_E_INVAL = -1
@@ -110,6 +113,17 @@ _SIGS = [
     ("grid_import", C.c_int, [C.POINTER(GridArrays), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("grid_export", C.c_int, [C.c_void_p, C.POINTER(GridArrays)]),
     ("grid_free", None, [C.c_void_p]),
+    ("batch_create", C.c_int, [C.c_int, C.POINTER(Density), C.POINTER(Criteria),
+                               C.POINTER(C.c_int), C.POINTER(C.c_void_p)]),
+    ("batch_bind", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                             C.POINTER(C.c_int64), C.POINTER(TraceOpts), C.POINTER(TraceOut)]),
+    ("batch_run", C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    ("batch_capture", C.c_int, [C.c_void_p, C.c_int, C.c_void_p]),
+    ("batch_replay", C.c_int, [C.c_void_p, C.c_void_p]),
+    ("batch_result", C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64),
+                               C.POINTER(C.c_int64), C.POINTER(TraceOut)]),
+    ("batch_grid", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
+    ("batch_free", None, [C.c_void_p]),
     ("grid_strerror", C.c_char_p, [C.c_int]),
     ("grid_last_hip_error", C.c_int, []),
 ]
@@ -443,3 +457,125 @@ def build(density, criteria, tree_type, stream=None, device="cuda", max_nodes=0)
 def import_grid(tree_type, first_child, rho, lo=(-1.0, -1.0, -1.0), side=2.0, stream=None,
                 device="cuda") -> Grid:
     return Grid.from_arrays(tree_type, first_child, rho, lo, side, stream, device)
+
+
+class Batch:
+    """Many grids built and traced with no host synchronisation (the batch_*
+    calls): construction of every grid level by level in shared launches,
+    then the batched walk over the bound path batches; run() enqueues it,
+    capture() records it into a HIP graph that replay() launches."""
+
+    def __init__(self, densities, criteria, tree_types, max_nodes, device="cuda"):
+        ng = len(densities)
+        ds = (Density * ng)()
+        keep = []
+        for i, d in enumerate(densities):
+            st, k = _density_struct(d)
+            ds[i] = st
+            keep += k
+        cs = (Criteria * ng)(*[_criteria_struct(c, int(m)) for c, m in zip(criteria, max_nodes)])
+        tt = (C.c_int * ng)(*[int(t) for t in tree_types])
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            rc = lib().batch_create(ng, ds, cs, tt, C.byref(h))
+        del keep
+        _check(rc, "batch_create")
+        self._h = h
+        self.ng = ng
+        self.device = device
+        self.tree_types = [int(t) for t in tree_types]
+        self.results = None
+        self._keep = None
+        self._outs = None
+        self._capture_stream = None
+
+    def bind(self, origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
+             kappa: float = 1.0, capacities=None, chunk: int = 0, refill_min: int = 0,
+             count_rechecks: bool = False):
+        """Bind path batches (one per grid) and allocate their outputs; the
+        returned result dicts are filled by each later run or replay."""
+        dev = self.device
+        os_ = [_dev_f64x3(o, dev) for o in origins]
+        ks_ = [_dev_f64x3(k, dev) for k in dirs]
+        ns = [o.shape[0] for o in os_]
+        dsdt = torch.float64 if precision == FP64 else torch.float32
+        res = []
+        tos = (TraceOut * self.ng)()
+        for i, n in enumerate(ns):
+            r = {"tau": torch.empty(n, dtype=torch.float64, device=dev),
+                 "count": torch.empty(n, dtype=torch.int32, device=dev)}
+            tos[i].tau = r["tau"].data_ptr()
+            tos[i].count = r["count"].data_ptr()
+            if mode == RECORDS:
+                cap = int(capacities[i]) if capacities is not None else 64 * max(n, 1)
+                r["offsets"] = torch.empty(n + 1, dtype=torch.int64, device=dev)
+                r["leaf"] = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+                r["ds"] = torch.empty(max(cap, 1), dtype=dsdt, device=dev)
+                tos[i].offsets = r["offsets"].data_ptr()
+                tos[i].leaf = r["leaf"].data_ptr()
+                tos[i].ds = r["ds"].data_ptr()
+                tos[i].capacity = r["leaf"].numel()
+            res.append(r)
+        opts = TraceOpts()
+        opts.precision = precision
+        opts.mode = mode
+        opts.kappa = kappa
+        opts.flags = FLAG_RECHECKS if count_rechecks else 0
+        opts.chunk = chunk
+        opts.refill_min = refill_min
+        op = (C.c_void_p * self.ng)(*[o.data_ptr() for o in os_])
+        kp = (C.c_void_p * self.ng)(*[k.data_ptr() for k in ks_])
+        np_ = (C.c_int64 * self.ng)(*ns)
+        with torch.cuda.device(dev):
+            _check(lib().batch_bind(self._h, op, kp, np_, C.byref(opts), tos), "batch_bind")
+        self._keep = (os_, ks_)
+        self._outs = tos
+        self.results = res
+        return res
+
+    def run(self, stages: int = STAGE_ALL, stream=None):
+        _check(lib().batch_run(self._h, stages, _stream(stream)), "batch_run")
+
+    def capture(self, stages: int = STAGE_ALL, stream=None):
+        """Record the stages into a graph (on a side stream unless one is
+        given: the legacy default stream cannot be captured)."""
+        if stream is None:
+            if self._capture_stream is None:
+                self._capture_stream = torch.cuda.Stream(self.device)
+            stream = self._capture_stream
+        torch.cuda.synchronize(self.device)
+        _check(lib().batch_capture(self._h, stages, _stream(stream)), "batch_capture")
+
+    def replay(self, stream=None):
+        _check(lib().batch_replay(self._h, _stream(stream)), "batch_replay")
+
+    def result(self, stream=None):
+        """Wait for the stream; per-grid node and leaf counts; sets needed and
+        rechecks in the bound result dicts.  Raises HGError on a failed grid."""
+        nn = (C.c_int64 * self.ng)()
+        nl = (C.c_int64 * self.ng)()
+        rc = lib().batch_result(self._h, _stream(stream), nn, nl, self._outs)
+        if self.results is not None:
+            for i, r in enumerate(self.results):
+                r["needed"] = int(self._outs[i].needed)
+                r["rechecks"] = int(self._outs[i].rechecks)
+        _check(rc, "batch_result")
+        return list(nn), list(nl)
+
+    def grid(self, i: int) -> Grid:
+        """Grid i as a Grid (borrowing the batch's arrays; free it first)."""
+        h = C.c_void_p()
+        _check(lib().batch_grid(self._h, int(i), C.byref(h)), "batch_grid")
+        return Grid(h, self.device)
+
+    def free(self):
+        if getattr(self, "_h", None):
+            torch.cuda.synchronize(self.device)
+            lib().batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -70,14 +70,13 @@ void free_grid_arrays(hg_grid *g)
     for (void *p : ptrs) dfree(p, nullptr);
 }
 
-namespace {
-
 __global__ void k_reset_status(TraceStatus *st)
 {
     st->rechecks = 0;
     st->bad_dir = 0;
     st->step_guard = 0;
     st->bad_ref = 0;
+    st->cap_overflow = 0;
     st->next_ray = 0;
     st->done_waves = 0;
 }
@@ -99,13 +98,37 @@ hg_grid *new_grid(int tree, const double lo[3], double side)
 void destroy(hg_grid *g)
 {
     if (!g) return;
-    free_grid_arrays(g);
+    if (g->borrowed) dfree(g->status, nullptr);
+    else free_grid_arrays(g);
     free(g);
 }
 
+namespace {
 bool finite_nonneg(double x) { return x >= 0.0 && !isnan(x); }
-
 }  // namespace
+
+int check_build_args(const hg_density *dn, const hg_criteria *cr, int tree_type)
+{
+    if (tree_type != HG_OCTREE && tree_type != HG_KDTREE) return HG_E_INVAL;
+    int rc = check_domain(dn->lo, dn->side);
+    if (rc) return rc;
+    const int maxlv = tree_type == HG_OCTREE ? 19 : 57;
+    if (cr->max_level < 0 || cr->max_level > maxlv || cr->min_level < 0) return HG_E_INVAL;
+    if (cr->n_samples <= 0 || cr->n_samples > (1 << 20)) return HG_E_INVAL;
+    if (!(cr->total_mass > 0.0) || !isfinite(cr->total_mass)) return HG_E_INVAL;
+    if (isnan(cr->delta_max) || isnan(cr->tau_max) || isnan(cr->q_max)) return HG_E_INVAL;
+    if (!finite_nonneg(cr->kappa) || !isfinite(cr->kappa)) return HG_E_INVAL;
+    if (dn->n_clumps < 0 || dn->n_clumps > HG_MAX_CLUMPS) return HG_E_INVAL;
+    if (dn->n_clumps > 0) {
+        if (!dn->clump_c || !dn->clump_sigma || !dn->clump_amp) return HG_E_INVAL;
+        if (!(dn->clump_trunc > 0.0) || !isfinite(dn->clump_trunc)) return HG_E_INVAL;
+        for (int64_t i = 0; i < dn->n_clumps; i++)
+            if (!(dn->clump_sigma[i] > 0.0) || !isfinite(dn->clump_sigma[i])) return HG_E_INVAL;
+    }
+    if (dn->has_disk && (!(dn->disk_hR > 0.0) || !(dn->disk_hz > 0.0))) return HG_E_INVAL;
+    return HG_OK;
+}
+
 }  // namespace hg
 
 using namespace hg;
@@ -136,23 +159,8 @@ int grid_build(const hg_density *dn, const hg_criteria *cr, int tree_type, void 
 {
     if (!dn || !cr || !out) return HG_E_INVAL;
     *out = nullptr;
-    if (tree_type != HG_OCTREE && tree_type != HG_KDTREE) return HG_E_INVAL;
-    int rc = check_domain(dn->lo, dn->side);
+    int rc = check_build_args(dn, cr, tree_type);
     if (rc) return rc;
-    const int maxlv = tree_type == HG_OCTREE ? 19 : 57;
-    if (cr->max_level < 0 || cr->max_level > maxlv || cr->min_level < 0) return HG_E_INVAL;
-    if (cr->n_samples <= 0 || cr->n_samples > (1 << 20)) return HG_E_INVAL;
-    if (!(cr->total_mass > 0.0) || !isfinite(cr->total_mass)) return HG_E_INVAL;
-    if (isnan(cr->delta_max) || isnan(cr->tau_max) || isnan(cr->q_max)) return HG_E_INVAL;
-    if (!finite_nonneg(cr->kappa) || !isfinite(cr->kappa)) return HG_E_INVAL;
-    if (dn->n_clumps < 0 || dn->n_clumps > HG_MAX_CLUMPS) return HG_E_INVAL;
-    if (dn->n_clumps > 0) {
-        if (!dn->clump_c || !dn->clump_sigma || !dn->clump_amp) return HG_E_INVAL;
-        if (!(dn->clump_trunc > 0.0) || !isfinite(dn->clump_trunc)) return HG_E_INVAL;
-        for (int64_t i = 0; i < dn->n_clumps; i++)
-            if (!(dn->clump_sigma[i] > 0.0) || !isfinite(dn->clump_sigma[i])) return HG_E_INVAL;
-    }
-    if (dn->has_disk && (!(dn->disk_hR > 0.0) || !(dn->disk_hz > 0.0))) return HG_E_INVAL;
     hg_grid *g = new_grid(tree_type, dn->lo, dn->side);
     if (!g) return HG_E_OOM;
     hipStream_t s = (hipStream_t)stream;
@@ -318,7 +326,8 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         hG[size_t(i)] = walk_grid(grids[i], opts->precision);
         hA[size_t(i)] = walk_args(grids[i], origins[i], dirs[i], n[i], opts, &outs[i]);
         hA[size_t(i)].st = g0->status;
-        for (int64_t a = 0; a < n[i]; a += chunk) hC.push_back(BatchChunk{i, 0, a, std::min(n[i], a + chunk)});
+        const int32_t head = int32_t(hC.size());
+        for (int64_t a = 0; a < n[i]; a += chunk) hC.push_back(BatchChunk{i, head, a, std::min(n[i], a + chunk)});
         nmax = std::max(nmax, n[i]);
         outs[i].needed = 0;
         outs[i].rechecks = 0;

@@ -16,84 +16,13 @@
 #include <vector>
 
 #include "common.h"
+#include "sampling.h"
 
 namespace hg {
 
 namespace {
 
 constexpr int BT = 256;
-constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ull;
-
-// SplitMix64 output for state x (Steele, Lea & Flood 2014): advance by the
-// golden gamma, then the published mixing function.
-__device__ inline uint64_t splitmix64(uint64_t x)
-{
-    uint64_t z = x + GAMMA;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-// Node code: level in bits 57.., cell coordinates in 19-bit fields.
-__device__ inline uint64_t node_key(uint64_t seed, int level, uint32_t c0, uint32_t c1, uint32_t c2)
-{
-    uint64_t code = (uint64_t(level) << 57) | (uint64_t(c0) << 38) | (uint64_t(c1) << 19) | uint64_t(c2);
-    return splitmix64(seed ^ splitmix64(code));
-}
-
-// Uniform double in [0,1) for sample j, axis d.
-__device__ inline double sample_unit(uint64_t key, int j, int d)
-{
-    uint64_t r = splitmix64(key ^ (uint64_t(3 * j + d + 1) * GAMMA));
-    return double(r >> 11) * 0x1.0p-53;
-}
-
-__device__ inline int bin_of(const Dens &D, double x, int d)
-{
-    int b = int(floor((x - D.lo[d]) * D.bin_scale));
-    return b < 0 ? 0 : (b >= D.B ? D.B - 1 : b);
-}
-
-// rho_t(x): box, disk, clumps in ascending index, torus -- added in that order.
-__device__ double density_at(const Dens &D, double x0, double x1, double x2,
-                             const int64_t *__restrict__ bin_start)
-{
-    double rho = 0.0;
-    if (D.has_box) {
-        if (x0 >= D.box_lo[0] && x0 <= D.box_hi[0] && x1 >= D.box_lo[1] && x1 <= D.box_hi[1] &&
-            x2 >= D.box_lo[2] && x2 <= D.box_hi[2])
-            rho = rho + D.box_rho;
-    }
-    if (D.has_disk) {
-        double R = sqrt(x0 * x0 + x1 * x1);
-        double arg = -(R / D.disk_hR) - fabs(x2) / D.disk_hz;
-        rho = rho + D.disk_rho0 * exp(arg);
-    }
-    if (D.n_clumps > 0) {
-        int b = (bin_of(D, x0, 0) * D.B + bin_of(D, x1, 1)) * D.B + bin_of(D, x2, 2);
-        int64_t e = bin_start[b + 1];
-        for (int64_t j = bin_start[b]; j < e; j++) {
-            uint32_t i = D.bin_items[j];
-            double s = D.cs[i];
-            double lim = D.trunc * s;
-            double dx = x0 - D.cc[3 * i + 0];
-            double dy = x1 - D.cc[3 * i + 1];
-            double dz = x2 - D.cc[3 * i + 2];
-            double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 <= lim * lim) {
-                double ee = r2 / (2.0 * s * s);
-                rho = rho + D.ca[i] * exp(-ee);
-            }
-        }
-    }
-    if (D.has_torus) {
-        double R = sqrt(x0 * x0 + x1 * x1);
-        double dR = R - D.torus_R0;
-        if (dR * dR + x2 * x2 <= D.torus_a * D.torus_a) rho = rho + D.torus_rho;
-    }
-    return rho;
-}
-
 // ---- clump binning --------------------------------------------------------
 
 __device__ inline bool clump_bin_range(const Dens &D, uint32_t i, int lo[3], int hi[3])
@@ -158,21 +87,7 @@ __global__ void __launch_bounds__(BT) k_bin_sort(int n_bins, const int64_t *__re
 
 // ---- per-level kernels ------------------------------------------------------
 
-struct CritDev {
-    double total_mass, delta_max, tau_max, q_max, kappa;
-    int min_level, max_level, n_samples;
-    uint64_t seed;
-};
-
-__device__ inline double read_lane_f64(double v, int lane)
-{
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
-}
-
 // One 64-lane wavefront per node of the level slice [begin, begin+count).
-// Lane j draws samples j, j+64, ...; the sum S runs in sample order (an ordered
-// reduction through readlane), min and max are order-free.
 __global__ void __launch_bounds__(BT)
     k_sample_decide(int tree, Dens D, CritDev C, int64_t begin, int64_t count,
                     const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
@@ -184,52 +99,13 @@ __global__ void __launch_bounds__(BT)
     const int64_t t = (int64_t(blockIdx.x) * BT + threadIdx.x) >> 6;
     if (t >= count) return;  // whole wavefront leaves together
     const int64_t i = begin + t;
-    const int lv = level[i];
-    const uint32_t c0 = coord[3 * i], c1 = coord[3 * i + 1], c2 = coord[3 * i + 2];
-    double w[3], lo[3];
-    const uint32_t c[3] = {c0, c1, c2};
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        w[d] = ldexp(D.side, -axis_depth(tree, lv, d));
-        lo[d] = D.lo[d] + double(c[d]) * w[d];
-    }
-    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
-    double S = 0.0, mn = INFINITY, mx = -INFINITY;
-    for (int base = 0; base < C.n_samples; base += 64) {
-        const int j = base + lane;
-        double r = 0.0;
-        if (j < C.n_samples) {
-            double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
-            double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
-            double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
-            r = density_at(D, x0, x1, x2, bin_start);
-            mn = fmin(mn, r);
-            mx = fmax(mx, r);
-        }
-        const int m = min(64, C.n_samples - base);
-        for (int jj = 0; jj < m; jj++) S = S + read_lane_f64(r, jj);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-    }
+    const NodeSample r = sample_node_wave(tree, D, C, level[i], coord[3 * i], coord[3 * i + 1],
+                                          coord[3 * i + 2], bin_start);
     if (lane != 0) return;
-    // Eq. (1): M = V/N sum rho; delta = M/M_tot; Eq. (2); Eq. (3).
-    double V = w[0] * w[1] * w[2];
-    double M = S * (V / double(C.n_samples));
-    double delta = M / C.total_mass;
-    double diag = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    double tau = C.kappa * M * diag / (w[0] * w[1] * w[2]);
-    double q = mx > 0.0 ? (mx - mn) / mx : 0.0;
-    bool sp;
-    if (lv < C.min_level) sp = true;
-    else if (lv >= C.max_level) sp = false;
-    else sp = delta > C.delta_max || tau > C.tau_max || q > C.q_max;
-    S_out[i] = S;
-    mn_out[i] = mn;
-    mx_out[i] = mx;
-    split[t] = sp ? 1 : 0;
+    S_out[i] = r.S;
+    mn_out[i] = r.mn;
+    mx_out[i] = r.mx;
+    split[t] = r.split ? 1 : 0;
 }
 
 // Children of the split nodes of the level slice, in list order.
@@ -251,13 +127,8 @@ __global__ void __launch_bounds__(BT)
     int lv = level[i];
     uint32_t c[3] = {coord[3 * i], coord[3 * i + 1], coord[3 * i + 2]};
     for (int k = 0; k < nc; k++) {
-        uint32_t cc[3] = {c[0], c[1], c[2]};
-        if (tree == KD) {
-            int a = lv % 3;
-            cc[a] = 2u * c[a] + uint32_t(k);
-        } else {
-            for (int d = 0; d < 3; d++) cc[d] = 2u * c[d] + uint32_t((k >> d) & 1);
-        }
+        uint32_t cc[3];
+        child_coord(tree, lv, c, k, cc);
         int64_t ch = f + k;
         level[ch] = uint8_t(lv + 1);
         coord[3 * ch] = cc[0];
@@ -321,12 +192,11 @@ struct DevBuf {
 
 }  // namespace
 
-int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s, hg_grid *g)
+int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *out)
 {
-    const int nc = tree == OCT ? 8 : 2;
-    // ---- density on the device ----
     Dens D;
     memset(&D, 0, sizeof D);
+    *st = DensStore{};
     for (int d = 0; d < 3; d++) D.lo[d] = dn->lo[d];
     D.side = dn->side;
     D.has_box = dn->has_box != 0;
@@ -345,54 +215,79 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
     D.torus_rho = dn->torus_rho;
     D.trunc = dn->clump_trunc;
     D.n_clumps = int(dn->n_clumps);
-    DevBuf cc(s), cs(s), ca(s), bstart(s), bitems(s), bcnt(s), btmp(s);
     D.B = 1;
     D.bin_scale = 1.0 / dn->side;
-    if (D.n_clumps > 0) {
-        const size_t n = size_t(D.n_clumps);
-        int rc0 = cc.alloc(n * 24);
-        if (!rc0) rc0 = cs.alloc(n * 8);
-        if (!rc0) rc0 = ca.alloc(n * 8);
-        if (rc0) return rc0;
-        HG_CHECK(hipMemcpyAsync(cc.p, dn->clump_c, n * 24, hipMemcpyHostToDevice, s));
-        HG_CHECK(hipMemcpyAsync(cs.p, dn->clump_sigma, n * 8, hipMemcpyHostToDevice, s));
-        HG_CHECK(hipMemcpyAsync(ca.p, dn->clump_amp, n * 8, hipMemcpyHostToDevice, s));
-        D.cc = (const double *)cc.p;
-        D.cs = (const double *)cs.p;
-        D.ca = (const double *)ca.p;
-        // bin width about twice the mean truncation radius, at most 128 bins per axis
-        double rsum = 0.0;
-        for (size_t i = 0; i < n; i++) rsum += dn->clump_trunc * fabs(dn->clump_sigma[i]);
-        double rmean = rsum / double(n);
-        int B = rmean > 0.0 ? int(dn->side / (2.0 * rmean)) : 1;
-        B = std::max(1, std::min(128, B));
-        D.B = B;
-        D.bin_scale = double(B) / dn->side;
-        const int64_t nb = int64_t(B) * B * B;
-        rc0 = bcnt.alloc(size_t(nb) * 4);
-        if (!rc0) rc0 = bstart.alloc(size_t(nb + 1) * 8);
-        if (!rc0) rc0 = btmp.alloc(scan_tmp_elems(nb) * 8);
-        if (rc0) return rc0;
-        HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
-        k_bin_count<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (int32_t *)bcnt.p);
-        HG_CHECK(hipGetLastError());
-        int rc = scan_i32_to_i64((const int32_t *)bcnt.p, (int64_t *)bstart.p, nb,
-                                 (int64_t *)btmp.p, s);
-        if (rc) return rc;
-        int64_t items = 0;
-        HG_CHECK(hipMemcpyAsync(&items, (int64_t *)bstart.p + nb, 8, hipMemcpyDeviceToHost, s));
-        HG_CHECK(hipStreamSynchronize(s));
-        if ((rc = bitems.alloc(size_t(items > 0 ? items : 1) * 4))) return rc;
-        HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
-        k_bin_fill<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (const int64_t *)bstart.p,
-                                                          (int32_t *)bcnt.p, (uint32_t *)bitems.p);
-        HG_CHECK(hipGetLastError());
-        k_bin_sort<<<nblocks(nb, BT), BT, 0, s>>>(int(nb), (const int64_t *)bstart.p,
-                                                  (uint32_t *)bitems.p);
-        HG_CHECK(hipGetLastError());
-        D.bin_items = (const uint32_t *)bitems.p;
-    }
-    const int64_t *bin_start = (const int64_t *)bstart.p;
+    *out = D;
+    if (D.n_clumps <= 0) return HG_OK;
+    const size_t n = size_t(D.n_clumps);
+    int rc = dalloc(&st->cc, n * 24, s);
+    if (!rc) rc = dalloc(&st->cs, n * 8, s);
+    if (!rc) rc = dalloc(&st->ca, n * 8, s);
+    if (rc) return rc;
+    HG_CHECK(hipMemcpyAsync(st->cc, dn->clump_c, n * 24, hipMemcpyHostToDevice, s));
+    HG_CHECK(hipMemcpyAsync(st->cs, dn->clump_sigma, n * 8, hipMemcpyHostToDevice, s));
+    HG_CHECK(hipMemcpyAsync(st->ca, dn->clump_amp, n * 8, hipMemcpyHostToDevice, s));
+    D.cc = (const double *)st->cc;
+    D.cs = (const double *)st->cs;
+    D.ca = (const double *)st->ca;
+    // bin width about twice the mean truncation radius, at most 128 bins per axis
+    double rsum = 0.0;
+    for (size_t i = 0; i < n; i++) rsum += dn->clump_trunc * fabs(dn->clump_sigma[i]);
+    double rmean = rsum / double(n);
+    int B = rmean > 0.0 ? int(dn->side / (2.0 * rmean)) : 1;
+    B = std::max(1, std::min(128, B));
+    D.B = B;
+    D.bin_scale = double(B) / dn->side;
+    const int64_t nb = int64_t(B) * B * B;
+    DevBuf bcnt(s), btmp(s);
+    rc = bcnt.alloc(size_t(nb) * 4);
+    if (!rc) rc = dalloc(&st->bin_start, size_t(nb + 1) * 8, s);
+    if (!rc) rc = btmp.alloc(scan_tmp_elems(nb) * 8);
+    if (rc) return rc;
+    HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
+    k_bin_count<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (int32_t *)bcnt.p);
+    HG_CHECK(hipGetLastError());
+    rc = scan_i32_to_i64((const int32_t *)bcnt.p, (int64_t *)st->bin_start, nb, (int64_t *)btmp.p, s);
+    if (rc) return rc;
+    int64_t items = 0;
+    HG_CHECK(hipMemcpyAsync(&items, (int64_t *)st->bin_start + nb, 8, hipMemcpyDeviceToHost, s));
+    HG_CHECK(hipStreamSynchronize(s));
+    if ((rc = dalloc(&st->bin_items, size_t(items > 0 ? items : 1) * 4, s))) return rc;
+    HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
+    k_bin_fill<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (const int64_t *)st->bin_start,
+                                                      (int32_t *)bcnt.p, (uint32_t *)st->bin_items);
+    HG_CHECK(hipGetLastError());
+    k_bin_sort<<<nblocks(nb, BT), BT, 0, s>>>(int(nb), (const int64_t *)st->bin_start,
+                                              (uint32_t *)st->bin_items);
+    HG_CHECK(hipGetLastError());
+    D.bin_items = (const uint32_t *)st->bin_items;
+    *out = D;
+    return HG_OK;
+}
+
+void release_density(DensStore *st, hipStream_t s)
+{
+    dfree(st->cc, s);
+    dfree(st->cs, s);
+    dfree(st->ca, s);
+    dfree(st->bin_start, s);
+    dfree(st->bin_items, s);
+    *st = DensStore{};
+}
+
+int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s, hg_grid *g)
+{
+    const int nc = tree == OCT ? 8 : 2;
+    Dens D;
+    DensStore store;
+    struct Release {
+        DensStore *st;
+        hipStream_t s;
+        ~Release() { release_density(st, s); }
+    } release{&store, s};
+    int rc = prepare_density(dn, s, &store, &D);
+    if (rc) return rc;
+    const int64_t *bin_start = (const int64_t *)store.bin_start;
 
     CritDev C;
     C.total_mass = cr->total_mass;
@@ -407,7 +302,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
 
     // ---- level loop ----
     int64_t cap = 0;
-    int rc = grow_nodes(g, 0, &cap, 4096, s);
+    rc = grow_nodes(g, 0, &cap, 4096, s);
     if (rc) return rc;
     k_init_root<<<1, 1, 0, s>>>(g->first_child, g->level, g->coord);
     HG_CHECK(hipGetLastError());

@@ -106,6 +106,7 @@ struct TraceStatus {
     int bad_dir;
     int step_guard;
     int bad_ref;                   // a reference out of range: the layout is corrupt
+    int cap_overflow;              // a grid's records did not fit (batched walk, device check)
     unsigned int next_ray;         // persistent-kernel work counter
     unsigned int done_waves;
 };
@@ -121,14 +122,18 @@ struct WalkArgs {
     const int64_t *offsets;
     int32_t *leaf;
     void *ds;
+    int64_t capacity;              // record slots behind leaf / ds
     TraceStatus *st;
     int count_rechecks;
 };
 
 // One entry of the batched walk's work queue: paths [start, end) of a grid.
+// One entry of the batched walk's work table: paths [start, end) of grid
+// `grid`; head is the table index of that grid's first chunk (the chunks of a
+// grid are contiguous and in path order).
 struct BatchChunk {
     int32_t grid;
-    int32_t pad;
+    int32_t head;
     int64_t start, end;
 };
 
@@ -161,6 +166,7 @@ struct hg_grid {
     uint64_t root_ref;
     hg::TraceStatus *status;   // device scratch
     int64_t level_begin[64];   // first node of each level; level_begin[max_level+1] = n_nodes
+    int borrowed;              // arrays belong to a batch (only status is the grid's own)
 };
 
 namespace hg {
@@ -174,6 +180,9 @@ int set_hip_error(hipError_t e);
     } while (0)
 
 int check_domain(const double lo[3], double side);
+int check_build_args(const hg_density *dn, const hg_criteria *cr, int tree_type);
+hg_grid *new_grid(int tree, const double lo[3], double side);
+void destroy(hg_grid *g);
 void free_grid_arrays(hg_grid *g);
 
 // Stream-ordered device memory from the device's default pool (kept by the
@@ -192,6 +201,28 @@ inline int dalloc_n(T **p, size_t n, hipStream_t s)
 size_t scan_tmp_elems(int64_t n);
 int scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
 int scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
+// The same with the element count read from the device at run time (a fixed
+// launch shape, so the call can be captured in a graph); tmp holds
+// scan_dev_tmp_elems() values.
+size_t scan_dev_tmp_elems();
+int scan_u8_to_i64_dev(const uint8_t *in, int64_t *out, const int64_t *n_dev, int64_t *tmp,
+                       hipStream_t s);
+// Offsets of every grid of a batched walk from its counts, one block per
+// chunk of the work table (device copies chunks and args); tmp holds
+// scan_chunks_tmp_elems(n_chunks) values.
+size_t scan_chunks_tmp_elems(int n_chunks);
+int scan_chunks(const BatchChunk *chunks, int n_chunks, const WalkArgs *args, int ng, int64_t *tmp,
+                hipStream_t s);
+
+// ---- density (build.hip) -------------------------------------------------------
+// Device copies of a density's clump arrays and its clump binning grid.
+struct DensStore {
+    void *cc = nullptr, *cs = nullptr, *ca = nullptr, *bin_start = nullptr, *bin_items = nullptr;
+};
+// Copies the density to the device and bins its clumps (synchronises s once
+// when there are clumps).  release_density frees what it allocated.
+int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *out);
+void release_density(DensStore *st, hipStream_t s);
 
 // ---- layout (layout.hip) -----------------------------------------------------
 // Given first_child, level and coord for every node (and level_begin), derive

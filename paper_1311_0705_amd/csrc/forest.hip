@@ -1,0 +1,746 @@
+// Batched construction and tracing of many grids ("a forest") with every
+// launch sized on the host in advance and every count kept on the device, so
+// a whole build-then-trace pass has no host synchronisation and can be
+// captured in a HIP graph and replayed.
+//
+// The construction is the same level-synchronous form of the node-list loop
+// of Sect. 2.2 as the single-grid builder, run for all grids of the batch at
+// once: per level one launch samples every node of that level of every grid
+// (Eq. 1-3), one prefix sum over the concatenated split flags gives every
+// child its slot in its own grid, one launch appends the children.  Grids are
+// told apart by a per-level prefix of their node counts (a binary search per
+// work item).  Node arrays are reserved up front from each grid's node
+// capacity (criteria.max_nodes); a grid that would exceed it stops growing and
+// is reported.  Results are identical to grid_build's, node for node.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "rope.h"
+#include "sampling.h"
+
+namespace hg {
+
+namespace {
+
+constexpr int FT = 256;
+constexpr int LB_N = 66;         // level-begin slots per grid
+constexpr int META = LB_N + 4;   // + n_nodes, n_leaves, depth, error
+constexpr int M_NODES = LB_N, M_LEAVES = LB_N + 1, M_DEPTH = LB_N + 2, M_ERR = LB_N + 3;
+constexpr unsigned FLAT_BLOCKS = 1024;    // grid-stride launches over device-sized ranges
+constexpr unsigned SAMPLE_BLOCKS = 2048;  // wavefront-per-node sampling (4 waves per block)
+
+struct ForestGrid {
+    int tree, nc, lg, pad;
+    Dens D;
+    CritDev C;
+    const int64_t *bin_start;
+    int64_t cap;
+    int32_t *fc;
+    uint8_t *level;
+    uint32_t *coord;
+    double *S, *rmin, *rmax;
+    int32_t *rope, *leaf_of, *int_of, *node_of;
+    double *rho;
+    LeafRec32 *rec32;
+    LeafRec64 *rec64;
+    uint32_t *child;
+    int64_t *meta;  // [META]: level begins, then n_nodes, n_leaves, depth, error
+};
+
+// Grid owning flat item t, given the prefix P[0..ng] of per-grid counts.
+__device__ inline int owner(const int64_t *__restrict__ P, int ng, int64_t t)
+{
+    int lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Exclusive prefix of per-grid values v(i) into P[0..ng] by one block.
+template <typename F>
+__device__ inline void block_prefix(int ng, int64_t *P, F v)
+{
+    __shared__ int64_t part[FT + 1];
+    const int per = (ng + FT - 1) / FT;
+    const int a = int(threadIdx.x) * per, b = min(ng, a + per);
+    int64_t s = 0;
+    for (int i = a; i < b; i++) s += v(i);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int j = 0; j < FT; j++) {
+            const int64_t x = part[j];
+            part[j] = run;
+            run += x;
+        }
+        part[FT] = run;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int i = a; i < b; i++) {
+        P[i] = run;
+        run += v(i);
+    }
+    if (threadIdx.x == 0) P[ng] = part[FT];
+}
+
+__global__ void __launch_bounds__(FT) k_f_init(const ForestGrid *__restrict__ F, int ng)
+{
+    const int i = int(blockIdx.x) * FT + threadIdx.x;
+    if (i >= ng) return;
+    const ForestGrid &G = F[i];
+    G.fc[0] = -1;
+    G.level[0] = 0;
+    G.coord[0] = G.coord[1] = G.coord[2] = 0;
+    for (int j = 0; j < 6; j++) G.rope[j] = -1;
+    G.meta[0] = 0;
+    for (int l = 1; l < LB_N; l++) G.meta[l] = 1;
+    G.meta[M_NODES] = 0;
+    G.meta[M_LEAVES] = 0;
+    G.meta[M_DEPTH] = 0;
+    G.meta[M_ERR] = 0;
+}
+
+__global__ void __launch_bounds__(FT) k_f_level_prefix(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                       int64_t *P)
+{
+    block_prefix(ng, P, [&](int i) { return F[i].meta[lv + 1] - F[i].meta[lv]; });
+}
+
+// One wavefront per node of level lv, over all grids.
+__global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                 const int64_t *__restrict__ P, uint8_t *__restrict__ flag)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t T = P[ng];
+    const int64_t nw = int64_t(gridDim.x) * (FT / 64);
+    for (int64_t t = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; t < T; t += nw) {
+        const int i = owner(P, ng, t);
+        const ForestGrid &G = F[i];
+        const int64_t n = G.meta[lv] + (t - P[i]);
+        const NodeSample r = sample_node_wave(G.tree, G.D, G.C, lv, G.coord[3 * n], G.coord[3 * n + 1],
+                                              G.coord[3 * n + 2], G.bin_start);
+        if (lane == 0) {
+            G.S[n] = r.S;
+            G.rmin[n] = r.mn;
+            G.rmax[n] = r.mx;
+            flag[t] = r.split ? 1 : 0;
+        }
+    }
+}
+
+// Per grid: the next level's extent, or an error if it would not fit.
+__global__ void __launch_bounds__(FT) k_f_close(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                const int64_t *__restrict__ P,
+                                                const int64_t *__restrict__ off)
+{
+    const int i = int(blockIdx.x) * FT + threadIdx.x;
+    if (i >= ng) return;
+    const ForestGrid &G = F[i];
+    int64_t nn = (off[P[i + 1]] - off[P[i]]) * G.nc;
+    const int64_t end = G.meta[lv + 1];
+    if (end + nn > G.cap) {
+        G.meta[M_ERR] = 1;
+        nn = 0;
+    }
+    for (int l = lv + 2; l < LB_N; l++) G.meta[l] = end + nn;
+}
+
+__global__ void __launch_bounds__(FT) k_f_append(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                 const int64_t *__restrict__ P,
+                                                 const uint8_t *__restrict__ flag,
+                                                 const int64_t *__restrict__ off)
+{
+    const int64_t T = P[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(P, ng, t);
+        const ForestGrid &G = F[i];
+        const int64_t n = G.meta[lv] + (t - P[i]);
+        if (!flag[t] || G.meta[lv + 2] == G.meta[lv + 1]) {
+            G.fc[n] = -1;
+            continue;
+        }
+        const int64_t f = G.meta[lv + 1] + (off[t] - off[P[i]]) * G.nc;
+        G.fc[n] = int32_t(f);
+        const uint32_t c[3] = {G.coord[3 * n], G.coord[3 * n + 1], G.coord[3 * n + 2]};
+        for (int k = 0; k < G.nc; k++) {
+            uint32_t cc[3];
+            child_coord(G.tree, lv, c, k, cc);
+            const int64_t ch = f + k;
+            G.level[ch] = uint8_t(lv + 1);
+            G.coord[3 * ch] = cc[0];
+            G.coord[3 * ch + 1] = cc[1];
+            G.coord[3 * ch + 2] = cc[2];
+            G.fc[ch] = -1;
+        }
+    }
+}
+
+// Ropes of the children of level lv's nodes.
+__global__ void __launch_bounds__(FT) k_f_ropes(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                const int64_t *__restrict__ P)
+{
+    const int64_t T = P[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(P, ng, t);
+        const ForestGrid &G = F[i];
+        const int64_t p = G.meta[lv] + (t - P[i]);
+        for (int k = 0; k < G.nc; k++) child_ropes(G.tree, p, k, G.fc, G.level, G.coord, G.rope);
+    }
+}
+
+__global__ void __launch_bounds__(FT) k_f_node_prefix(const ForestGrid *__restrict__ F, int ng,
+                                                      int lmax, int64_t *PN)
+{
+    block_prefix(ng, PN, [&](int i) { return F[i].meta[lmax + 1]; });
+    for (int i = threadIdx.x; i < ng; i += FT) {
+        const ForestGrid &G = F[i];
+        G.meta[M_NODES] = G.meta[lmax + 1];
+        int d = 0;
+        for (int l = 1; l <= lmax; l++)
+            if (G.meta[l + 1] > G.meta[l]) d = l;
+        G.meta[M_DEPTH] = d;
+    }
+}
+
+__global__ void __launch_bounds__(FT) k_f_flag(const ForestGrid *__restrict__ F, int ng,
+                                               const int64_t *__restrict__ PN, uint8_t *__restrict__ flag)
+{
+    const int64_t T = PN[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(PN, ng, t);
+        flag[t] = F[i].fc[t - PN[i]] < 0 ? 1 : 0;
+    }
+}
+
+// Leaf rank = leaves before the node in list order; internal rank = the rest.
+__global__ void __launch_bounds__(FT) k_f_number(const ForestGrid *__restrict__ F, int ng,
+                                                 const int64_t *__restrict__ PN,
+                                                 const int64_t *__restrict__ rank)
+{
+    const int64_t T = PN[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(PN, ng, t);
+        const ForestGrid &G = F[i];
+        const int64_t n = t - PN[i];
+        const int64_t lr = rank[t] - rank[PN[i]];
+        if (G.fc[n] < 0) {
+            G.leaf_of[n] = int32_t(lr);
+            G.int_of[n] = -1;
+            G.node_of[lr] = int32_t(n);
+        } else {
+            G.leaf_of[n] = -1;
+            G.int_of[n] = int32_t(n - lr);
+        }
+    }
+}
+
+// Leaf counts, the leaf prefix and each grid's walk parameters.
+__global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restrict__ F, int ng,
+                                                      const int64_t *__restrict__ PN,
+                                                      const int64_t *__restrict__ rank, int64_t *PL,
+                                                      WalkGrid *__restrict__ w32, WalkGrid *__restrict__ w64)
+{
+    block_prefix(ng, PL, [&](int i) { return rank[PN[i + 1]] - rank[PN[i]]; });
+    for (int i = threadIdx.x; i < ng; i += FT) {
+        const ForestGrid &G = F[i];
+        const int64_t L = rank[PN[i + 1]] - rank[PN[i]];
+        const int64_t I = G.meta[M_NODES] - L;
+        G.meta[M_LEAVES] = L;
+        WalkGrid W;
+        W.tree = G.tree;
+        W.lg = G.lg;
+        for (int d = 0; d < 3; d++) W.lo[d] = G.D.lo[d];
+        W.side = G.D.side;
+        W.root = Ref<uint32_t>::make(I == 0, 0, 0);
+        W.n_leaves = uint64_t(L);
+        W.n_internal = uint64_t(I);
+        W.child = G.child;
+        W.rec = G.rec32;
+        w32[i] = W;
+        W.rec = G.rec64;
+        w64[i] = W;
+    }
+}
+
+__global__ void __launch_bounds__(FT) k_f_records(const ForestGrid *__restrict__ F, int ng,
+                                                  const int64_t *__restrict__ PL)
+{
+    const int64_t T = PL[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(PL, ng, t);
+        const ForestGrid &G = F[i];
+        const int64_t l = t - PL[i];
+        const int32_t n = G.node_of[l];
+        const double r = leaf_rho(l, n, G.S, nullptr, double(G.C.n_samples));
+        G.rho[l] = r;
+        LeafRec32 a;
+        LeafRec64 b;
+#pragma unroll
+        for (int j = 0; j < 6; j++) {
+            const uint32_t e = encode<uint32_t>(G.rope[6 * int64_t(n) + j], G.fc, G.level, G.leaf_of, G.int_of);
+            a.rope[j] = e;
+            b.rope[j] = e;
+        }
+        a.rho = float(r);
+        a.pad = 0;
+        b.rho = r;
+        G.rec32[l] = a;
+        G.rec64[l] = b;
+    }
+}
+
+__global__ void __launch_bounds__(FT) k_f_child_refs(const ForestGrid *__restrict__ F, int ng,
+                                                     const int64_t *__restrict__ PN)
+{
+    const int64_t T = PN[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(PN, ng, t);
+        const ForestGrid &G = F[i];
+        const int64_t n = t - PN[i];
+        const int32_t f = G.fc[n];
+        if (f < 0) continue;
+        const int64_t base = int64_t(G.int_of[n]) * G.nc;
+        for (int k = 0; k < G.nc; k++)
+            G.child[base + k] = encode<uint32_t>(f + k, G.fc, G.level, G.leaf_of, G.int_of);
+    }
+}
+
+__global__ void k_f_reset_status(TraceStatus *st)
+{
+    st->rechecks = 0;
+    st->bad_dir = 0;
+    st->step_guard = 0;
+    st->bad_ref = 0;
+    st->cap_overflow = 0;
+    st->next_ray = 0;
+    st->done_waves = 0;
+}
+
+__global__ void __launch_bounds__(FT) k_f_totals(const WalkArgs *__restrict__ A, int ng, int64_t *out)
+{
+    const int i = int(blockIdx.x) * FT + threadIdx.x;
+    if (i < ng) out[i] = A[i].offsets[A[i].n];
+}
+
+}  // namespace
+}  // namespace hg
+
+using namespace hg;
+
+// The library's batch object.
+struct hg_batch {
+    int ng = 0;
+    int lmax = 0;
+    std::vector<DensStore> dens;
+    std::vector<ForestGrid> hF;
+    ForestGrid *dF = nullptr;
+    int64_t *meta = nullptr;        // [ng][META]
+    int64_t *P = nullptr;           // [(lmax+1)][ng+1]
+    int64_t *PN = nullptr, *PL = nullptr;
+    uint8_t *flag = nullptr;        // [sum of capacities]
+    int64_t *off = nullptr;         // [sum of capacities + 1]
+    int64_t *stmp = nullptr;
+    WalkGrid *w32 = nullptr, *w64 = nullptr;
+    TraceStatus *status = nullptr;
+    std::vector<void *> arrays;     // every per-grid allocation
+    // bound trace
+    bool bound = false;
+    hg_trace_opts opts{};
+    std::vector<int64_t> n;
+    std::vector<hg_trace_out> outs;
+    WalkArgs *dA = nullptr;
+    BatchChunk *dC = nullptr;
+    int n_chunks = 0;
+    int64_t *ctmp = nullptr;
+    int64_t *totals = nullptr;
+    // captured graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_bound(hg_batch *b)
+{
+    dfree(b->dA, nullptr);
+    dfree(b->dC, nullptr);
+    dfree(b->ctmp, nullptr);
+    dfree(b->totals, nullptr);
+    b->dA = nullptr;
+    b->dC = nullptr;
+    b->ctmp = nullptr;
+    b->totals = nullptr;
+    b->bound = false;
+}
+
+void free_batch(hg_batch *b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    free_bound(b);
+    for (auto &d : b->dens) release_density(&d, nullptr);
+    for (void *p : b->arrays) dfree(p, nullptr);
+    void *ptrs[] = {b->dF, b->meta, b->P, b->PN, b->PL, b->flag, b->off, b->stmp, b->w32, b->w64,
+                    b->status};
+    for (void *p : ptrs) dfree(p, nullptr);
+    (void)hipDeviceSynchronize();
+    delete b;
+}
+
+template <typename T>
+int grid_array(hg_batch *b, T **p, size_t n)
+{
+    int rc = dalloc_n(p, n, nullptr);
+    if (!rc) b->arrays.push_back(*p);
+    return rc;
+}
+
+int enqueue_build(hg_batch *b, hipStream_t s)
+{
+    const int ng = b->ng;
+    const unsigned gb = unsigned((ng + FT - 1) / FT);
+    k_f_init<<<gb, FT, 0, s>>>(b->dF, ng);
+    HG_CHECK(hipGetLastError());
+    for (int lv = 0; lv <= b->lmax; lv++) {
+        int64_t *P = b->P + size_t(lv) * size_t(ng + 1);
+        k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, lv, P);
+        HG_CHECK(hipGetLastError());
+        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag);
+        HG_CHECK(hipGetLastError());
+        int rc = scan_u8_to_i64_dev(b->flag, b->off, P + ng, b->stmp, s);
+        if (rc) return rc;
+        k_f_close<<<gb, FT, 0, s>>>(b->dF, ng, lv, P, b->off);
+        HG_CHECK(hipGetLastError());
+        k_f_append<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag, b->off);
+        HG_CHECK(hipGetLastError());
+    }
+    for (int lv = 0; lv < b->lmax; lv++) {
+        k_f_ropes<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, b->P + size_t(lv) * size_t(ng + 1));
+        HG_CHECK(hipGetLastError());
+    }
+    k_f_node_prefix<<<1, FT, 0, s>>>(b->dF, ng, b->lmax, b->PN);
+    HG_CHECK(hipGetLastError());
+    k_f_flag<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PN, b->flag);
+    HG_CHECK(hipGetLastError());
+    int rc = scan_u8_to_i64_dev(b->flag, b->off, b->PN + ng, b->stmp, s);
+    if (rc) return rc;
+    k_f_number<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PN, b->off);
+    HG_CHECK(hipGetLastError());
+    k_f_leaf_prefix<<<1, FT, 0, s>>>(b->dF, ng, b->PN, b->off, b->PL, b->w32, b->w64);
+    HG_CHECK(hipGetLastError());
+    k_f_records<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PL);
+    HG_CHECK(hipGetLastError());
+    k_f_child_refs<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PN);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
+}
+
+int enqueue_trace(hg_batch *b, hipStream_t s)
+{
+    if (!b->bound) return HG_E_INVAL;
+    const WalkGrid *G = b->opts.precision == HG_FP64 ? b->w64 : b->w32;
+    k_f_reset_status<<<1, 1, 0, s>>>(b->status);
+    HG_CHECK(hipGetLastError());
+    int rc = HG_OK;
+    if (b->n_chunks > 0) rc = launch_batched(G, b->dA, b->dC, b->n_chunks, &b->opts, false, b->status, s);
+    if (rc || b->opts.mode != HG_RECORDS) return rc;
+    rc = scan_chunks(b->dC, b->n_chunks, b->dA, b->ng, b->ctmp, s);
+    if (rc || b->n_chunks == 0) return rc;
+    return launch_batched(G, b->dA, b->dC, b->n_chunks, &b->opts, true, b->status, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, const int *tree_types,
+                 hg_batch_t *out)
+{
+    if (!out) return HG_E_INVAL;
+    *out = nullptr;
+    if (n_grids < 1 || n_grids > HG_MAX_BATCH || !dens || !crit || !tree_types) return HG_E_INVAL;
+    int lmax = 0;
+    int64_t total_cap = 0;
+    for (int i = 0; i < n_grids; i++) {
+        int rc = check_build_args(&dens[i], &crit[i], tree_types[i]);
+        if (rc) return rc;
+        if (crit[i].max_nodes < 1) return HG_E_INVAL;
+        if (crit[i].max_nodes > MAX_IDS) return HG_E_LIMIT;
+        lmax = std::max(lmax, int(crit[i].max_level));
+        total_cap += crit[i].max_nodes;
+    }
+    hg_batch *b = new hg_batch;
+    b->ng = n_grids;
+    b->lmax = lmax;
+    b->dens.resize(size_t(n_grids));
+    b->hF.resize(size_t(n_grids));
+    int rc = HG_OK;
+    for (int i = 0; i < n_grids && !rc; i++) {
+        ForestGrid &G = b->hF[size_t(i)];
+        memset(&G, 0, sizeof G);
+        const hg_criteria &c = crit[i];
+        G.tree = tree_types[i];
+        G.nc = G.tree == HG_OCTREE ? 8 : 2;
+        int e = 0;
+        frexp(dens[i].side, &e);
+        G.lg = e - 1;
+        rc = prepare_density(&dens[i], nullptr, &b->dens[size_t(i)], &G.D);
+        if (rc) break;
+        G.bin_start = (const int64_t *)b->dens[size_t(i)].bin_start;
+        G.C = CritDev{c.total_mass, c.delta_max, c.tau_max, c.q_max, c.kappa,
+                      c.min_level, c.max_level, c.n_samples, c.seed};
+        const size_t cap = size_t(c.max_nodes);
+        G.cap = int64_t(cap);
+        if (!rc) rc = grid_array(b, &G.fc, cap);
+        if (!rc) rc = grid_array(b, &G.level, cap);
+        if (!rc) rc = grid_array(b, &G.coord, 3 * cap);
+        if (!rc) rc = grid_array(b, &G.S, cap);
+        if (!rc) rc = grid_array(b, &G.rmin, cap);
+        if (!rc) rc = grid_array(b, &G.rmax, cap);
+        if (!rc) rc = grid_array(b, &G.rope, 6 * cap);
+        if (!rc) rc = grid_array(b, &G.leaf_of, cap);
+        if (!rc) rc = grid_array(b, &G.int_of, cap);
+        if (!rc) rc = grid_array(b, &G.node_of, cap);
+        if (!rc) rc = grid_array(b, &G.rho, cap);
+        if (!rc) rc = grid_array(b, &G.rec32, cap);
+        if (!rc) rc = grid_array(b, &G.rec64, cap);
+        if (!rc) rc = grid_array(b, &G.child, cap);
+    }
+    const size_t ng1 = size_t(n_grids) + 1;
+    if (!rc) rc = dalloc_n(&b->meta, size_t(n_grids) * META, nullptr);
+    for (int i = 0; i < n_grids && !rc; i++) b->hF[size_t(i)].meta = b->meta + size_t(i) * META;
+    if (!rc) rc = dalloc_n(&b->dF, size_t(n_grids), nullptr);
+    if (!rc) rc = dalloc_n(&b->P, size_t(lmax + 1) * ng1, nullptr);
+    if (!rc) rc = dalloc_n(&b->PN, ng1, nullptr);
+    if (!rc) rc = dalloc_n(&b->PL, ng1, nullptr);
+    if (!rc) rc = dalloc_n(&b->flag, size_t(total_cap), nullptr);
+    if (!rc) rc = dalloc_n(&b->off, size_t(total_cap) + 1, nullptr);
+    if (!rc) rc = dalloc_n(&b->stmp, scan_dev_tmp_elems(), nullptr);
+    if (!rc) rc = dalloc_n(&b->w32, size_t(n_grids), nullptr);
+    if (!rc) rc = dalloc_n(&b->w64, size_t(n_grids), nullptr);
+    if (!rc) rc = dalloc_n(&b->status, 1, nullptr);
+    if (!rc) {
+        hipError_t e = hipMemcpy(b->dF, b->hF.data(), sizeof(ForestGrid) * size_t(n_grids),
+                                 hipMemcpyHostToDevice);
+        if (!e) e = hipDeviceSynchronize();
+        if (e) rc = set_hip_error(e);
+    }
+    if (rc) {
+        free_batch(b);
+        return rc;
+    }
+    *out = b;
+    return HG_OK;
+}
+
+int batch_bind(hg_batch_t b, const double *const *origins, const double *const *dirs, const int64_t *n,
+               const hg_trace_opts *opts, hg_trace_out *outs)
+{
+    if (!b || !origins || !dirs || !n || !opts || !outs) return HG_E_INVAL;
+    if (opts->precision != HG_FP64 && opts->precision != HG_FP32_RECHECK) return HG_E_INVAL;
+    if (opts->mode != HG_TAU_ONLY && opts->mode != HG_RECORDS) return HG_E_INVAL;
+    if (!isfinite(opts->kappa)) return HG_E_INVAL;
+    const bool records = opts->mode == HG_RECORDS;
+    for (int i = 0; i < b->ng; i++) {
+        const hg_trace_out &o = outs[i];
+        if (n[i] < 0) return HG_E_INVAL;
+        if (n[i] > 0 && (!origins[i] || !dirs[i] || !o.tau || !o.count)) return HG_E_INVAL;
+        if (records && (!o.offsets || o.capacity < 0)) return HG_E_INVAL;
+        if (records && o.capacity > 0 && (!o.leaf || !o.ds)) return HG_E_INVAL;
+        if (records && ((uintptr_t(o.leaf) | uintptr_t(o.ds)) & 15u)) return HG_E_INVAL;
+    }
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    free_bound(b);
+    const int64_t chunk = opts->chunk > 0 ? opts->chunk : 1024;
+    std::vector<WalkArgs> hA(size_t(b->ng));
+    std::vector<BatchChunk> hC;
+    for (int i = 0; i < b->ng; i++) {
+        WalkArgs &A = hA[size_t(i)];
+        A.O = origins[i];
+        A.K = dirs[i];
+        A.n = n[i];
+        A.kappa = opts->kappa;
+        A.tau = outs[i].tau;
+        A.count = outs[i].count;
+        A.offsets = records ? outs[i].offsets : nullptr;
+        A.leaf = records ? outs[i].leaf : nullptr;
+        A.ds = records ? outs[i].ds : nullptr;
+        A.capacity = records ? outs[i].capacity : 0;
+        A.st = b->status;
+        A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
+        const int32_t head = int32_t(hC.size());
+        for (int64_t a = 0; a < n[i]; a += chunk)
+            hC.push_back(BatchChunk{i, head, a, std::min(n[i], a + chunk)});
+    }
+    if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
+    int rc = dalloc_n(&b->dA, size_t(b->ng), nullptr);
+    if (!rc) rc = dalloc_n(&b->dC, std::max<size_t>(hC.size(), 1), nullptr);
+    if (!rc) rc = dalloc_n(&b->ctmp, scan_chunks_tmp_elems(int(hC.size())), nullptr);
+    if (!rc) rc = dalloc_n(&b->totals, size_t(b->ng), nullptr);
+    if (!rc) {
+        hipError_t e = hipMemcpy(b->dA, hA.data(), sizeof(WalkArgs) * hA.size(), hipMemcpyHostToDevice);
+        if (!e && !hC.empty())
+            e = hipMemcpy(b->dC, hC.data(), sizeof(BatchChunk) * hC.size(), hipMemcpyHostToDevice);
+        if (!e) e = hipDeviceSynchronize();
+        if (e) rc = set_hip_error(e);
+    }
+    if (rc) {
+        free_bound(b);
+        return rc;
+    }
+    b->opts = *opts;
+    b->n.assign(n, n + b->ng);
+    b->outs.assign(outs, outs + b->ng);
+    b->n_chunks = int(hC.size());
+    b->bound = true;
+    return HG_OK;
+}
+
+int batch_run(hg_batch_t b, int stages, void *stream)
+{
+    if (!b || (stages & ~HG_STAGE_ALL) || !stages) return HG_E_INVAL;
+    if ((stages & HG_STAGE_TRACE) && !b->bound) return HG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = HG_OK;
+    if (stages & HG_STAGE_BUILD) rc = enqueue_build(b, s);
+    if (!rc && (stages & HG_STAGE_TRACE)) rc = enqueue_trace(b, s);
+    return rc;
+}
+
+int batch_capture(hg_batch_t b, int stages, void *stream)
+{
+    if (!b || (stages & ~HG_STAGE_ALL) || !stages) return HG_E_INVAL;
+    if ((stages & HG_STAGE_TRACE) && !b->bound) return HG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (!s) return HG_E_INVAL;  // the legacy default stream cannot be captured
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    HG_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = batch_run(b, stages, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e) return set_hip_error(e);
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e) {
+        (void)hipGraphDestroy(g);
+        return set_hip_error(e);
+    }
+    b->graph = g;
+    return HG_OK;
+}
+
+int batch_replay(hg_batch_t b, void *stream)
+{
+    if (!b || !b->exec) return HG_E_INVAL;
+    HG_CHECK(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return HG_OK;
+}
+
+int batch_result(hg_batch_t b, void *stream, int64_t *n_nodes, int64_t *n_leaves, hg_trace_out *outs)
+{
+    if (!b) return HG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> meta(size_t(b->ng) * META);
+    TraceStatus st;
+    memset(&st, 0, sizeof st);
+    std::vector<int64_t> tot(size_t(b->ng), 0);
+    const bool records = b->bound && b->opts.mode == HG_RECORDS;
+    if (records) {
+        k_f_totals<<<unsigned((b->ng + FT - 1) / FT), FT, 0, s>>>(b->dA, b->ng, b->totals);
+        HG_CHECK(hipGetLastError());
+    }
+    HG_CHECK(hipMemcpyAsync(meta.data(), b->meta, sizeof(int64_t) * meta.size(), hipMemcpyDeviceToHost, s));
+    HG_CHECK(hipMemcpyAsync(&st, b->status, sizeof st, hipMemcpyDeviceToHost, s));
+    if (records)
+        HG_CHECK(hipMemcpyAsync(tot.data(), b->totals, sizeof(int64_t) * tot.size(), hipMemcpyDeviceToHost, s));
+    HG_CHECK(hipStreamSynchronize(s));
+    int rc = HG_OK;
+    for (int i = 0; i < b->ng; i++) {
+        const int64_t *m = meta.data() + size_t(i) * META;
+        if (n_nodes) n_nodes[i] = m[M_NODES];
+        if (n_leaves) n_leaves[i] = m[M_LEAVES];
+        if (m[M_ERR]) rc = HG_E_LIMIT;
+        if (outs && b->bound) {
+            outs[i].needed = records ? tot[size_t(i)] : 0;
+            outs[i].rechecks = i == 0 ? int64_t(st.rechecks) : 0;
+            if (records && tot[size_t(i)] > b->outs[size_t(i)].capacity && !rc) rc = HG_E_CAPACITY;
+        }
+    }
+    if (!rc && b->bound) {
+        if (st.bad_ref) rc = HG_E_FORMAT;
+        else if (st.bad_dir) rc = HG_E_DIR;
+        else if (st.step_guard) rc = HG_E_STEP;
+        else if (st.cap_overflow) rc = HG_E_CAPACITY;
+    }
+    return rc;
+}
+
+int batch_grid(hg_batch_t b, int i, hg_grid_t *out)
+{
+    if (!out) return HG_E_INVAL;
+    *out = nullptr;
+    if (!b || i < 0 || i >= b->ng) return HG_E_INVAL;
+    const ForestGrid &F = b->hF[size_t(i)];
+    int64_t m[META];
+    HG_CHECK(hipDeviceSynchronize());
+    HG_CHECK(hipMemcpy(m, F.meta, sizeof m, hipMemcpyDeviceToHost));
+    if (m[M_ERR]) return HG_E_LIMIT;
+    hg_grid *g = new_grid(F.tree, F.D.lo, F.D.side);
+    if (!g) return HG_E_OOM;
+    g->borrowed = 1;
+    g->n_nodes = m[M_NODES];
+    g->n_leaves = m[M_LEAVES];
+    g->n_internal = g->n_nodes - g->n_leaves;
+    g->max_level = int(m[M_DEPTH]);
+    for (int l = 0; l < 64; l++) g->level_begin[l] = l <= g->max_level + 1 ? m[l] : g->n_nodes;
+    g->first_child = F.fc;
+    g->level = F.level;
+    g->coord = F.coord;
+    g->S = F.S;
+    g->rmin = F.rmin;
+    g->rmax = F.rmax;
+    g->rope = F.rope;
+    g->leaf_of = F.leaf_of;
+    g->int_of = F.int_of;
+    g->node_of = F.node_of;
+    g->rho = F.rho;
+    g->wide = 0;
+    g->rec32 = F.rec32;
+    g->rec64 = F.rec64;
+    g->child = F.child;
+    g->root_ref = Ref<uint32_t>::make(g->n_internal == 0, 0, 0);
+    *out = g;
+    return HG_OK;
+}
+
+void batch_free(hg_batch_t b) { free_batch(b); }
+
+}  // extern "C"

@@ -1,81 +1,20 @@
 // Walk layout of a finished tree: face ropes, leaf / internal numbering, the
 // 32-byte per-leaf walk records and the encoded child references.
 //
-// Ropes stand in for the per-wall neighbor lists of Sect. 2.3.  A leaf's rope
-// through face f is the smallest node that contains the whole region just
-// across f; the leaves of that node's subtree touching f are exactly the
-// face's neighbor list, and the walk reaches the right one by descending from
-// the rope target with the exit point.  Ropes are derived level by level: a
-// child inherits its parent's ropes on the faces it shares with the parent,
-// points at its sibling across the new split plane, and every rope is then
-// pushed down while a single child of the target still contains the face
-// region.
+// Ropes stand in for the per-wall neighbor lists of Sect. 2.3: the leaves of
+// a rope target's subtree touching the face are exactly that face's neighbor
+// list, and the walk reaches the right one by descending from the rope target
+// with the exit point.  Ropes are derived level by level from the root.
 #include <stdlib.h>
 
 #include "common.h"
+#include "rope.h"
 
 namespace hg {
 
 namespace {
 
 constexpr int LT = 256;
-
-// Integer extent of a node along each axis in units of 2^-DEPTH_BITS of the
-// domain side.
-__device__ inline void int_extent(int tree, int level, const uint32_t c[3], uint32_t lo[3],
-                                  uint32_t hi[3])
-{
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        int sh = DEPTH_BITS - axis_depth(tree, level, d);
-        lo[d] = c[d] << sh;
-        hi[d] = (c[d] + 1u) << sh;
-    }
-}
-
-// Push rope target n down while one child of it holds the whole region across
-// face (axis a, upper side `up`) of the node with extent [clo, chi).
-__device__ int32_t push_down(int tree, int32_t n, int a, int up, const uint32_t clo[3],
-                             const uint32_t chi[3], const int32_t *__restrict__ fc,
-                             const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord)
-{
-    if (n < 0) return n;
-    for (;;) {
-        int32_t f = fc[n];
-        if (f < 0) return n;
-        int lv = level[n];
-        if (tree == KD) {
-            int b = lv % 3;
-            int side;
-            if (b == a) {
-                side = up ? 0 : 1;   // the half of the target adjacent to the face
-            } else {
-                uint32_t mid = (2u * coord[3 * n + b] + 1u)
-                               << (DEPTH_BITS - axis_depth(KD, lv, b) - 1);
-                if (chi[b] <= mid) side = 0;
-                else if (clo[b] >= mid) side = 1;
-                else return n;
-            }
-            n = f + side;
-        } else {
-            int idx = 0;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                int bit;
-                if (d == a) {
-                    bit = up ? 0 : 1;
-                } else {
-                    uint32_t mid = (2u * coord[3 * n + d] + 1u) << (DEPTH_BITS - lv - 1);
-                    if (chi[d] <= mid) bit = 0;
-                    else if (clo[d] >= mid) bit = 1;
-                    else return n;
-                }
-                idx |= bit << d;
-            }
-            n = f + idx;
-        }
-    }
-}
 
 // One thread per (node of level l, child slot): the child's six ropes.
 __global__ void __launch_bounds__(LT)
@@ -85,32 +24,7 @@ __global__ void __launch_bounds__(LT)
 {
     int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (t >= count * nc) return;
-    int64_t p = begin + t / nc;
-    int k = int(t % nc);
-    int32_t f = fc[p];
-    if (f < 0) return;
-    int lv = level[p];
-    int32_t child = f + k;
-    int32_t r[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) r[j] = rope[6 * p + j];
-    if (tree == KD) {
-        int a = lv % 3;
-        if (k == 0) r[2 * a + 1] = f + 1;
-        else r[2 * a] = f;
-    } else {
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (((k >> d) & 1) == 0) r[2 * d + 1] = f + (k | (1 << d));
-            else r[2 * d] = f + (k & ~(1 << d));
-        }
-    }
-    uint32_t c[3] = {coord[3 * child], coord[3 * child + 1], coord[3 * child + 2]};
-    uint32_t clo[3], chi[3];
-    int_extent(tree, lv + 1, c, clo, chi);
-#pragma unroll
-    for (int j = 0; j < 6; j++)
-        rope[6 * int64_t(child) + j] = push_down(tree, r[j], j / 2, j % 2, clo, chi, fc, level, coord);
+    child_ropes(tree, begin + t / nc, int(t % nc), fc, level, coord, rope);
 }
 
 __global__ void __launch_bounds__(LT) k_flag_leaves(const int32_t *__restrict__ fc, int64_t n,
@@ -136,22 +50,6 @@ __global__ void __launch_bounds__(LT)
         leaf_of[i] = -1;
         int_of[i] = int32_t(i - lr);
     }
-}
-
-template <typename R>
-__device__ inline R encode(int32_t n, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
-                           const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of)
-{
-    if (n < 0) return Ref<R>::NUL;
-    const bool leaf = fc[n] < 0;
-    return Ref<R>::make(leaf, level[n], uint64_t(uint32_t(leaf ? leaf_of[n] : int_of[n])));
-}
-
-// Grid density of a leaf = M/V = S/N (Sect. 3.2), or the imported value.
-__device__ inline double leaf_rho(int64_t l, int32_t n, const double *S, const double *rho_in,
-                                  double n_samples)
-{
-    return rho_in ? rho_in[l] : S[n] / n_samples;
 }
 
 __global__ void __launch_bounds__(LT)

@@ -1,0 +1,166 @@
+// Device side of the per-node Monte Carlo sampling (Sect. 2.2 and 4): the
+// counter-based sample positions, the density models and the criteria of
+// Eq. 1-3, shared by the single-grid and the batched builders.
+#pragma once
+
+#include "common.h"
+
+namespace hg {
+
+constexpr uint64_t SPLITMIX_GAMMA = 0x9E3779B97F4A7C15ull;
+
+// Criteria as the kernels read them.
+struct CritDev {
+    double total_mass, delta_max, tau_max, q_max, kappa;
+    int min_level, max_level, n_samples;
+    uint64_t seed;
+};
+
+// SplitMix64 output for state x (Steele, Lea & Flood 2014): advance by the
+// golden gamma, then the published mixing function.
+__device__ inline uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + SPLITMIX_GAMMA;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Node code: level in bits 57.., cell coordinates in 19-bit fields.
+__device__ inline uint64_t node_key(uint64_t seed, int level, uint32_t c0, uint32_t c1, uint32_t c2)
+{
+    uint64_t code = (uint64_t(level) << 57) | (uint64_t(c0) << 38) | (uint64_t(c1) << 19) | uint64_t(c2);
+    return splitmix64(seed ^ splitmix64(code));
+}
+
+// Uniform double in [0,1) for sample j, axis d.
+__device__ inline double sample_unit(uint64_t key, int j, int d)
+{
+    uint64_t r = splitmix64(key ^ (uint64_t(3 * j + d + 1) * SPLITMIX_GAMMA));
+    return double(r >> 11) * 0x1.0p-53;
+}
+
+__device__ inline int bin_of(const Dens &D, double x, int d)
+{
+    int b = int(floor((x - D.lo[d]) * D.bin_scale));
+    return b < 0 ? 0 : (b >= D.B ? D.B - 1 : b);
+}
+
+// rho_t(x): box, disk, clumps in ascending index, torus -- added in that order.
+__device__ inline double density_at(const Dens &D, double x0, double x1, double x2,
+                                    const int64_t *__restrict__ bin_start)
+{
+    double rho = 0.0;
+    if (D.has_box) {
+        if (x0 >= D.box_lo[0] && x0 <= D.box_hi[0] && x1 >= D.box_lo[1] && x1 <= D.box_hi[1] &&
+            x2 >= D.box_lo[2] && x2 <= D.box_hi[2])
+            rho = rho + D.box_rho;
+    }
+    if (D.has_disk) {
+        double R = sqrt(x0 * x0 + x1 * x1);
+        double arg = -(R / D.disk_hR) - fabs(x2) / D.disk_hz;
+        rho = rho + D.disk_rho0 * exp(arg);
+    }
+    if (D.n_clumps > 0) {
+        int b = (bin_of(D, x0, 0) * D.B + bin_of(D, x1, 1)) * D.B + bin_of(D, x2, 2);
+        int64_t e = bin_start[b + 1];
+        for (int64_t j = bin_start[b]; j < e; j++) {
+            uint32_t i = D.bin_items[j];
+            double s = D.cs[i];
+            double lim = D.trunc * s;
+            double dx = x0 - D.cc[3 * i + 0];
+            double dy = x1 - D.cc[3 * i + 1];
+            double dz = x2 - D.cc[3 * i + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 <= lim * lim) {
+                double ee = r2 / (2.0 * s * s);
+                rho = rho + D.ca[i] * exp(-ee);
+            }
+        }
+    }
+    if (D.has_torus) {
+        double R = sqrt(x0 * x0 + x1 * x1);
+        double dR = R - D.torus_R0;
+        if (dR * dR + x2 * x2 <= D.torus_a * D.torus_a) rho = rho + D.torus_rho;
+    }
+    return rho;
+}
+
+__device__ inline double read_lane_f64(double v, int lane)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
+}
+
+struct NodeSample {
+    double S, mn, mx;
+    bool split;
+};
+
+// Sampling and decision for one node by one whole 64-lane wavefront (every
+// lane must call it with the same node).  Lane j draws samples j, j+64, ...;
+// the sum S runs in sample order (an ordered reduction through readlane), min
+// and max are order-free.  Eq. (1): M = V/N sum rho, delta = M/M_tot;
+// Eq. (2): tau = kappa M sqrt(a^2+b^2+c^2)/(abc); Eq. (3): q = (max-min)/max.
+__device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const CritDev &C, int lv,
+                                              uint32_t c0, uint32_t c1, uint32_t c2,
+                                              const int64_t *__restrict__ bin_start)
+{
+    const int lane = threadIdx.x & 63;
+    double w[3], lo[3];
+    const uint32_t c[3] = {c0, c1, c2};
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        w[d] = ldexp(D.side, -axis_depth(tree, lv, d));
+        lo[d] = D.lo[d] + double(c[d]) * w[d];
+    }
+    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
+    double S = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int base = 0; base < C.n_samples; base += 64) {
+        const int j = base + lane;
+        double r = 0.0;
+        if (j < C.n_samples) {
+            double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
+            double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
+            double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
+            r = density_at(D, x0, x1, x2, bin_start);
+            mn = fmin(mn, r);
+            mx = fmax(mx, r);
+        }
+        const int m = min(64, C.n_samples - base);
+        for (int jj = 0; jj < m; jj++) S = S + read_lane_f64(r, jj);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    double V = w[0] * w[1] * w[2];
+    double M = S * (V / double(C.n_samples));
+    double delta = M / C.total_mass;
+    double diag = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double tau = C.kappa * M * diag / (w[0] * w[1] * w[2]);
+    double q = mx > 0.0 ? (mx - mn) / mx : 0.0;
+    bool sp;
+    if (lv < C.min_level) sp = true;
+    else if (lv >= C.max_level) sp = false;
+    else sp = delta > C.delta_max || tau > C.tau_max || q > C.q_max;
+    return NodeSample{S, mn, mx, sp};
+}
+
+// Level and cell coordinates of child k of a node (k-d: split axis level mod
+// 3, lower half first; octree: octant k = bx + 2 by + 4 bz).
+__host__ __device__ inline void child_coord(int tree, int lv, const uint32_t c[3], int k, uint32_t cc[3])
+{
+    cc[0] = c[0];
+    cc[1] = c[1];
+    cc[2] = c[2];
+    if (tree == KD) {
+        const int a = lv % 3;
+        cc[a] = 2u * c[a] + uint32_t(k);
+    } else {
+        for (int d = 0; d < 3; d++) cc[d] = 2u * c[d] + uint32_t((k >> d) & 1);
+    }
+}
+
+}  // namespace hg

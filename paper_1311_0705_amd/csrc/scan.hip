@@ -142,7 +142,160 @@ int scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s)
     return HG_OK;
 }
 
+// ---- element count on the device ---------------------------------------------
+// A fixed grid of DSCAN_BLOCKS blocks; block b scans the contiguous range
+// [b*per, (b+1)*per) with per = ceil(n / DSCAN_BLOCKS) rounded up to a tile.
+constexpr int DSCAN_BLOCKS = 256;
+
+__device__ inline int64_t dscan_per(int64_t n)
+{
+    const int64_t per = (n + DSCAN_BLOCKS - 1) / DSCAN_BLOCKS;
+    return (per + SCAN_TILE - 1) / SCAN_TILE * SCAN_TILE;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_dscan_sums(const T *in, const int64_t *n_dev, int64_t *bsum)
+{
+    const int64_t n = *n_dev;
+    const int64_t per = dscan_per(n);
+    const int64_t b0 = int64_t(blockIdx.x) * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    int64_t s = 0;
+    for (int64_t base = b0 + int64_t(threadIdx.x) * SCAN_ITEMS; base < b1; base += SCAN_TILE) {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; j++) s += load_val(in, base + j, b1);
+    }
+    int64_t total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_dscan_apply(const T *in, const int64_t *n_dev, const int64_t *bsum, int64_t *out)
+{
+    const int64_t n = *n_dev;
+    const int64_t per = dscan_per(n);
+    const int64_t b0 = int64_t(blockIdx.x) * per;
+    const int64_t b1 = b0 + per < n ? b0 + per : n;
+    int64_t carry = bsum[blockIdx.x];
+    for (int64_t tile = b0; tile < b1; tile += SCAN_TILE) {
+        const int64_t base = tile + int64_t(threadIdx.x) * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS];
+        int64_t s = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; j++) {
+            v[j] = load_val(in, base + j, b1);
+            s += v[j];
+        }
+        int64_t total;
+        int64_t run = carry + block_excl_scan(s, &total);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; j++) {
+            if (base + j < b1) out[base + j] = run;
+            run += v[j];
+        }
+        carry += total;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[DSCAN_BLOCKS];
+}
+
+// ---- per-chunk segmented scan of the batched walk's counts --------------------
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_chunk_sums(const BatchChunk *__restrict__ chunks, const WalkArgs *__restrict__ args,
+                 int64_t *csum)
+{
+    const BatchChunk c = chunks[blockIdx.x];
+    const int32_t *cnt = args[c.grid].count;
+    int64_t s = 0;
+    for (int64_t base = c.start + int64_t(threadIdx.x) * SCAN_ITEMS; base < c.end; base += SCAN_TILE) {
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; j++) s += load_val(cnt, base + j, c.end);
+    }
+    int64_t total;
+    block_excl_scan(s, &total);
+    if (threadIdx.x == 0) csum[blockIdx.x] = total;
+}
+
+// cex = exclusive scan of the chunk sums over the whole table; a chunk's base
+// within its grid is cex[c] - cex[head].
+__global__ void __launch_bounds__(SCAN_THREADS)
+    k_chunk_apply(const BatchChunk *__restrict__ chunks, const WalkArgs *__restrict__ args,
+                  const int64_t *cex)
+{
+    const BatchChunk c = chunks[blockIdx.x];
+    const WalkArgs &A = args[c.grid];
+    const int32_t *cnt = A.count;
+    int64_t *out = const_cast<int64_t *>(A.offsets);
+    int64_t carry = cex[blockIdx.x] - cex[c.head];
+    for (int64_t tile = c.start; tile < c.end; tile += SCAN_TILE) {
+        const int64_t base = tile + int64_t(threadIdx.x) * SCAN_ITEMS;
+        int64_t v[SCAN_ITEMS];
+        int64_t s = 0;
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; j++) {
+            v[j] = load_val(cnt, base + j, c.end);
+            s += v[j];
+        }
+        int64_t total;
+        int64_t run = carry + block_excl_scan(s, &total);
+#pragma unroll
+        for (int j = 0; j < SCAN_ITEMS; j++) {
+            if (base + j < c.end) out[base + j] = run;
+            run += v[j];
+        }
+        carry += total;
+    }
+    if (c.end == A.n && threadIdx.x == 0) out[A.n] = carry;
+}
+
+__global__ void k_chunk_empty(const WalkArgs *__restrict__ args, int ng)
+{
+    const int g = int(blockIdx.x) * SCAN_THREADS + threadIdx.x;
+    if (g < ng && args[g].n == 0) const_cast<int64_t *>(args[g].offsets)[0] = 0;
+}
+
 }  // namespace
+
+size_t scan_dev_tmp_elems() { return size_t(DSCAN_BLOCKS) + 1; }
+
+int scan_u8_to_i64_dev(const uint8_t *in, int64_t *out, const int64_t *n_dev, int64_t *tmp,
+                       hipStream_t s)
+{
+    k_dscan_sums<uint8_t><<<DSCAN_BLOCKS, SCAN_THREADS, 0, s>>>(in, n_dev, tmp);
+    HG_CHECK(hipGetLastError());
+    k_scan_tile_sums<<<1, SCAN_THREADS, 0, s>>>(tmp, DSCAN_BLOCKS);
+    HG_CHECK(hipGetLastError());
+    k_dscan_apply<uint8_t><<<DSCAN_BLOCKS, SCAN_THREADS, 0, s>>>(in, n_dev, tmp, out);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
+}
+
+size_t scan_chunks_tmp_elems(int n_chunks)
+{
+    return 2 * (size_t(n_chunks) + 1) + scan_tmp_elems(n_chunks);
+}
+
+int scan_chunks(const BatchChunk *chunks, int n_chunks, const WalkArgs *args, int ng, int64_t *tmp,
+                hipStream_t s)
+{
+    if (ng > 0) {
+        k_chunk_empty<<<unsigned((ng + SCAN_THREADS - 1) / SCAN_THREADS), SCAN_THREADS, 0, s>>>(args, ng);
+        HG_CHECK(hipGetLastError());
+    }
+    if (n_chunks <= 0) return HG_OK;
+    int64_t *csum = tmp;
+    int64_t *cex = tmp + (n_chunks + 1);
+    int64_t *stmp = tmp + 2 * (size_t(n_chunks) + 1);
+    k_chunk_sums<<<unsigned(n_chunks), SCAN_THREADS, 0, s>>>(chunks, args, csum);
+    HG_CHECK(hipGetLastError());
+    int rc = scan_impl<int64_t>(csum, cex, n_chunks, stmp, s);
+    if (rc) return rc;
+    k_chunk_apply<<<unsigned(n_chunks), SCAN_THREADS, 0, s>>>(chunks, args, cex);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
+}
 
 size_t scan_tmp_elems(int64_t n)
 {

@@ -689,6 +689,11 @@ __global__ void __launch_bounds__(TB)
                         cnext = chunks[pc].start;
                         cend = chunks[pc].end;
                         pc = -1;
+                        // records of a grid that does not fit are not written
+                        if (FILL && A.offsets[A.n] > A.capacity) {
+                            if (lane == 0) st->cap_overflow = 1;
+                            cnext = cend;
+                        }
                     }
                 }
             }
@@ -868,6 +873,7 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
     A.offsets = out->offsets;
     A.leaf = out->leaf;
     A.ds = out->ds;
+    A.capacity = out->capacity;
     A.st = g->status;
     A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
     const int prec = opts->precision;
@@ -891,6 +897,7 @@ WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n
     A.offsets = out->offsets;
     A.leaf = out->leaf;
     A.ds = out->ds;
+    A.capacity = out->capacity;
     A.st = g->status;
     A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
     return A;

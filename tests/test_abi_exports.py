@@ -11,7 +11,7 @@ HEADER = os.path.join(ROOT, "include", "hgrid.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(grid_\w+)\s*\(", src, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:grid|batch)_\w+)\s*\(", src, flags=re.M)
     return sorted(set(names))
 
 
