@@ -1,21 +1,37 @@
 """Benchmark of the hierarchical-grid hot path on one MI355X.
 
-One step = the whole path over one batch: grid_build (GPU construction with
-per-node density sampling and the mass criterion) followed by grid_trace of
-every path of the batch with the FP32-with-FP64-recheck walk in records mode
-(counting walk, prefix sum, record-filling walk).  Inputs (ray origins and
-directions) are resident in HBM before the timed region.
+One step = the whole path over one batch of synthetic input: grid_build (GPU
+construction with per-node density sampling and the stopping criteria)
+followed by grid_trace of every path of the batch with the
+FP32-with-FP64-recheck walk.  Inputs (ray origins and directions) are
+resident in HBM before the timed region.
 
-Default workload: the k-d tree of about 1e6 leaves on the exponential disk
-(mass threshold 1e-6, max level 24) with 1e7 paths emitted by a stellar disk
-and isotropic directions.  Besides the step throughput the JSON line carries
-the FP64 tracer's throughput on the same paths, the leaf-for-leaf comparison
-FP32-recheck vs FP64, an oracle spot check, the roofline of the dominant
-kernel and the CPU oracle's rate on the host cores.
+Workloads (--workload):
+  2 (default)  k-d tree of about 1e6 leaves on the exponential disk (mass
+               threshold 1e-6, max level 24), 1e7 stellar-disk paths,
+               records mode.  The JSON line also carries the FP64 tracer's
+               throughput on the same paths, the leaf-for-leaf comparison
+               FP32-recheck vs FP64, an oracle spot check, the roofline of the
+               dominant kernel and the CPU oracle's rate on the host cores.
+  1            octree of about 5e3 leaves on the same disk, 1e4 paths (FP64
+               parity case; timed like 2).
+  3            torus plus 500 clumps, k-d (--tree octree for the octree), 1e8
+               uniform paths: tau-only walk over all of them, records mode on
+               the first batch of 1e7.
+  4            64 clump grids of uneven size (octree and k-d), 10^U[3,6]
+               paths each: the batch built and traced by one replay of a
+               captured graph, against the same 64 grids built and traced one
+               by one.
+  5            k-d tree of about 2e7 leaves on 97336 clustered clumps: the
+               build timed end to end, then batches of 1e8 stellar-disk paths
+               in tau-only mode.
+The launch shape of the walk is autotuned (grid_tune / batch_tune) before the
+timed region unless --no-tune is given.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -36,15 +52,7 @@ HBM_PEAK_GBS = 8000.0
 #   4 B leaf id + 4 B ds32 written = 32 B per crossing.
 #   The record-filling walk also reads the path (48 B) and its offset (8 B).
 #   The counting (tau-only) walk reads 24 B per crossing, the path (48 B), and
-#   writes tau + count (12 B).
-# HBM traffic of the dominant kernel from rocprofv3 --pmc runs (FETCH_SIZE and
-# WRITE_SIZE in KiB per dispatch), scaled by what the same counters read for a
-# 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE 1.0 GiB).
-# Valid only for the walk source it was measured on (sha256 of trace.hip).
-TRAFFIC = {"trace_sha256": "b4f12bc0c7bd9e93626cc32a1a383fe05fb3af5f38fc8354b4810373c542185b",
-           "fetch_kib": 32660382.3, "write_kib": 10795357.5,
-           "fetch_scale": 2.0, "write_scale": 1.0}
-
+#   writes tau + count (12 B).  FP64: 28 B (tau-only) / 40 B (records).
 B_X_FILL32 = 32
 B_RAY_FILL = 48 + 8
 B_X_COUNT32 = 24
@@ -52,22 +60,593 @@ B_RAY_COUNT = 48 + 12
 B_X_FILL64 = 40
 B_X_COUNT64 = 28
 
+# HBM traffic of the dominant kernel from rocprofv3 --pmc runs (FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch), scaled by what the same counters read for a
+# 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE 1.0 GiB).
+# Valid only for the walk source it was measured on (sha256 of trace.hip) and
+# the workload it was measured on.
+TRAFFIC = {}
+
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3])
+    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
     p.add_argument("--tree", choices=["kd", "octree"], default=None)
     p.add_argument("--rays", type=int, default=None, help="override the path count")
+    p.add_argument("--batches", type=int, default=10, help="workload 5: batches of 1e8 paths")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
                    help="target CPU time of the oracle baseline sample")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-compare", action="store_true")
+    p.add_argument("--no-tune", action="store_true")
     p.add_argument("--calib-copy", type=int, default=0,
                    help="also run a device copy of this many MiB (counter calibration)")
     return p.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def trace_sha():
+    src = os.path.join(ROOT, "paper_1311_0705_amd", "csrc", "trace.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of the dominant kernel, if its counters were taken
+    on the current walk source for this workload; else None."""
+    t = TRAFFIC.get(key)
+    if not t or t["trace_sha256"] != trace_sha():
+        return None
+    return int(t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"])
+
+
+def roofline(kernel, ms, alg_bytes, traffic_key):
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(traffic_key),
+            "kernel": kernel, "kernel_ms": round(ms, 3), "alg_bytes_per_launch": int(alg_bytes)}
+
+
+def base_line(a, value, step_s, unit, dtype, config):
+    return {"metric": METRIC, "value": round(value, 1), "unit": unit, "n_gpus": 1,
+            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(step_s * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def tree_name(t):
+    import workloads as W
+    return "kd" if t == W.KDTREE else "octree"
+
+
+def persistent_kernel(tree, prec, fill, block):
+    return (f"k_walk_persistent<{'kd' if tree == 1 else 'octree'},"
+            f"{'fp32_recheck' if prec == 1 else 'fp64'},{'fill' if fill else 'count'},"
+            f"u32,{block}>")
+
+
+def oracle_sample_check(g, w, o_np, k_np, r64, dev, m=4000):
+    """FP64 GPU walk vs the oracle on a sample of paths through the same grid."""
+    import torch
+
+    import oracle as O
+    n = o_np.shape[0]
+    e = g.export()
+    og = O.Grid.from_first_child(w.tree_type, e["first_child"].cpu().numpy(), e["rho"].cpu().numpy())
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(n, size=min(n, m), replace=False))
+    ref = og.trace(o_np[idx], k_np[idx])
+    ok = np.array_equal(r64["count"].cpu().numpy()[idx], ref["count"])
+    ok = ok and np.array_equal(r64["tau"].cpu().numpy()[idx], ref["tau"])
+    if ok and "offsets" in r64:
+        off = r64["offsets"].cpu().numpy()
+        pos = torch.from_numpy(np.concatenate([np.arange(off[i], off[i + 1]) for i in idx])).to(dev)
+        ok = (np.array_equal(r64["leaf"].index_select(0, pos).cpu().numpy(), ref["leaf"])
+              and np.array_equal(r64["ds"].index_select(0, pos).cpu().numpy(), ref["ds"]))
+    return {"oracle_sample_paths": int(idx.size), "oracle_sample_bitwise_fp64": bool(ok)}
+
+
+def compare_fp32r_fp64(r32, r64, records):
+    import torch
+    out = {}
+    same_counts = bool(torch.equal(r32["count"], r64["count"]))
+    if records:
+        x = int(r64["needed"])
+        out["leaf_exact_vs_fp64"] = same_counts and bool(torch.equal(r32["leaf"][:x], r64["leaf"][:x]))
+        out["ds32_equals_rounded_fp64"] = bool(torch.equal(r32["ds"][:x], r64["ds"][:x].float()))
+    else:
+        out["counts_equal_fp64"] = same_counts
+    t64 = r64["tau"]
+    rel = (r32["tau"] - t64).abs() / t64.abs().clamp_min(1e-300)
+    out["tau_max_rel_err_vs_fp64"] = float(rel.max().item())
+    return out
+
+
+def cpu_cores():
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return max(1, min(int(cores), 64))
+
+
+def cpu_trace_sample(og, o_np, k_np, budget_s, records=True):
+    """Oracle FP64 trace of the first paths, sized to about budget_s."""
+    cores = cpu_cores()
+    n = o_np.shape[0]
+    m = min(n, 20000)
+    t0 = time.perf_counter()
+    r = og.trace(o_np[:m], k_np[:m], records=records, nthreads=cores)
+    t = time.perf_counter() - t0
+    m2 = int(min(n, max(m, m * max(0.0, budget_s - t) / max(t, 1e-6))))
+    if m2 > m:
+        t0 = time.perf_counter()
+        r = og.trace(o_np[:m2], k_np[:m2], records=records, nthreads=cores)
+        t = time.perf_counter() - t0
+        m = m2
+    return m, t, int(r["count"].sum()), cores
+
+
+# ---------------------------------------------------------------------------
+# workloads 1 and 2: build + records trace of one grid
+# ---------------------------------------------------------------------------
+
+def run_single(a, w):
+    import torch
+
+    import paper_1311_0705_amd as hg
+    import workloads as W
+    dev = torch.device("cuda:0")
+    o_np, k_np = W.rays(w.ray_kind, w.n_rays, w.ray_seed)
+    o = torch.from_numpy(o_np).to(dev)
+    k = torch.from_numpy(k_np).to(dev)
+    n = o.shape[0]
+
+    # ---- warm-up: sizes the record buffers and tunes the walk's launch shape ----
+    g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+    n_leaves, n_nodes = g.n_leaves, g.n_nodes
+    res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, count_rechecks=True)
+    needed, rechecks = res["needed"], res["rechecks"]
+    tuned = {}
+    if not a.no_tune:
+        m = min(n, 1_000_000)
+        for prec in (hg.FP32_RECHECK, hg.FP64):
+            tuned[prec] = g.tune(o[:m], k[:m], precision=prec, mode=hg.RECORDS)
+        log(f"tuned launch shapes: {tuned}")
+    t32 = tuned.get(hg.FP32_RECHECK)
+    g.free()
+    for _ in range(max(0, a.warmup - 1)):
+        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+        g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=res, capacity=needed, tuned=t32)
+        g.free()
+    log(f"grid: {n_leaves} leaves, {n_nodes} nodes; {needed} crossings")
+
+    # ---- timed steps: build + FP32-recheck records trace ----
+    torch.cuda.synchronize()
+    fill_ms, count_ms, build_ms = [], [], []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        tb0 = time.perf_counter()
+        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+        build_ms.append((time.perf_counter() - tb0) * 1e3)
+        r = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=res, capacity=needed,
+                    timing=True, tuned=t32)
+        count_ms.append(r["kernel_ms"][0])
+        fill_ms.append(r["kernel_ms"][2])
+        if i < a.steps - 1:
+            g.free()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / a.steps
+    crossings = int(res["needed"])
+    log(f"step {step_s * 1e3:.2f} ms (build ~{np.mean(build_ms):.2f} ms host-timed)")
+
+    # ---- trace-only throughput, FP32-recheck vs FP64 (same grid, same paths) ----
+    def time_trace(prec, mode, t, reps=3):
+        out, ms = {}, []
+        for i in range(reps + 1):
+            rr = g.trace(o, k, precision=prec, mode=mode, out=out, capacity=needed, timing=True,
+                         tuned=t)
+            if i:
+                ms.append(rr["kernel_ms"])
+        ms = np.median(np.array(ms), axis=0)
+        return out, [float(x) for x in ms]
+
+    r32, ms32 = time_trace(hg.FP32_RECHECK, hg.RECORDS, t32)
+    r64, ms64 = time_trace(hg.FP64, hg.RECORDS, tuned.get(hg.FP64))
+    _, tau32 = time_trace(hg.FP32_RECHECK, hg.TAU_ONLY, t32)
+    _, tau64 = time_trace(hg.FP64, hg.TAU_ONLY, tuned.get(hg.FP64))
+    default_ms = None
+    if tuned:
+        _, dms = time_trace(hg.FP32_RECHECK, hg.RECORDS, None)
+        default_ms = dms[3]
+    extra = {}
+    if not a.no_compare:
+        extra.update(compare_fp32r_fp64(r32, r64, True))
+        extra.update(oracle_sample_check(g, w, o_np, k_np, r64, dev))
+    g.free()
+
+    block = t32["block"] if t32 else 256
+    fill_avg = float(np.mean(fill_ms))
+    line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",
+                     {"workload": w.name, "tree": tree_name(w.tree_type), "leaves": int(n_leaves),
+                      "nodes": int(n_nodes), "paths": int(n), "precision": "fp32_recheck",
+                      "mode": "records", "step": "grid_build + grid_trace"})
+
+    def trace_entry(ms, tau_ms):
+        return {"crossings_per_s": round(crossings / (ms[3] * 1e-3), 1),
+                "rays_per_s": round(n / (ms[3] * 1e-3), 1), "ms": round(ms[3], 3),
+                "count_ms": round(ms[0], 3), "fill_ms": round(ms[2], 3),
+                "tau_only_ms": round(tau_ms[0], 3),
+                "tau_only_crossings_per_s": round(crossings / (tau_ms[0] * 1e-3), 1)}
+
+    line.update({
+        "rays_per_s": round(n / step_s, 1),
+        "crossings_per_path": round(crossings / n, 3),
+        "trace_fp32r": trace_entry(ms32, tau32),
+        "trace_fp64": trace_entry(ms64, tau64),
+        "fp32r_over_fp64": round(ms64[3] / ms32[3], 3),
+        "fp32r_over_fp64_tau_only": round(tau64[0] / tau32[0], 3),
+        "recheck_rate": round(rechecks / max(crossings, 1), 6),
+        "build_ms": round(float(np.mean(build_ms)), 3),
+        "count_walk_ms": round(float(np.mean(count_ms)), 3),
+        "tuned": {str(kk): v for kk, v in tuned.items()} or None,
+        "untuned_fp32r_trace_ms": None if default_ms is None else round(default_ms, 3),
+        "roofline": roofline(persistent_kernel(w.tree_type, 1, True, block), fill_avg,
+                             crossings * B_X_FILL32 + n * B_RAY_FILL, f"w{a.workload}_fill"),
+    })
+    line.update(extra)
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_single(w, o_np, k_np, crossings, a.cpu_seconds)
+    return line
+
+
+def cpu_baseline_single(w, o_np, k_np, crossings_total, budget_s):
+    import oracle as O
+    t0 = time.perf_counter()
+    og = O.Grid.build(w.density, w.criteria, w.tree_type)
+    t_build = time.perf_counter() - t0
+    n = o_np.shape[0]
+    m, t, xs, cores = cpu_trace_sample(og, o_np, k_np, budget_s - t_build)
+    t_step = t_build + t * (n / m)
+    return {"value": round(crossings_total / t_step, 1), "unit": "crossings/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle build of the full grid ({t_build:.2f} s, one thread) + FP64 "
+                      f"records trace of the first {m} of {n} paths on {cores} threads "
+                      f"({t:.2f} s, {xs} crossings); step time extrapolated to all paths",
+            "trace_crossings_per_s": round(xs / t, 1), "build_s": round(t_build, 3),
+            "oracle_leaves": int(og.n_leaves)}
+
+
+# ---------------------------------------------------------------------------
+# workload 3: build + tau-only trace of 1e8 paths (records on the first 1e7)
+# ---------------------------------------------------------------------------
+
+def run_c3(a, w):
+    import torch
+
+    import paper_1311_0705_amd as hg
+    import workloads as W
+    dev = torch.device("cuda:0")
+    log(f"generating {w.n_rays} paths")
+    o_np, k_np = W.rays(w.ray_kind, w.n_rays, w.ray_seed)
+    o = torch.from_numpy(o_np).to(dev)
+    k = torch.from_numpy(k_np).to(dev)
+    n = o.shape[0]
+    nb = min(n, 10_000_000)
+    g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+    n_leaves, n_nodes = g.n_leaves, g.n_nodes
+    tuned = {}
+    if not a.no_tune:
+        for mode in (hg.TAU_ONLY, hg.RECORDS):
+            tuned[mode] = g.tune(o[:1_000_000], k[:1_000_000], precision=hg.FP32_RECHECK, mode=mode)
+        tuned["fp64_tau"] = g.tune(o[:1_000_000], k[:1_000_000], precision=hg.FP64, mode=hg.TAU_ONLY)
+        log(f"tuned launch shapes: {tuned}")
+    tt = tuned.get(hg.TAU_ONLY)
+    res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt, count_rechecks=True)
+    crossings = int(res["count"].sum().item())
+    rechecks = res["rechecks"]
+    g.free()
+    log(f"grid: {n_leaves} leaves; {crossings} crossings over {n} paths")
+    torch.cuda.synchronize()
+    build_ms, tau_ms = [], []
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        tb = time.perf_counter()
+        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+        build_ms.append((time.perf_counter() - tb) * 1e3)
+        r = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, out=res, timing=True, tuned=tt)
+        tau_ms.append(r["kernel_ms"][0])
+        if i < a.steps - 1:
+            g.free()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / a.steps
+    log(f"step {step_s * 1e3:.1f} ms")
+    # FP64 tau-only over all paths; records mode on the first batch, both precisions
+    t64 = g.trace(o, k, precision=hg.FP64, mode=hg.TAU_ONLY, timing=True, tuned=tuned.get("fp64_tau"))
+    t64 = g.trace(o, k, precision=hg.FP64, mode=hg.TAU_ONLY, out=t64, timing=True,
+                  tuned=tuned.get("fp64_tau"))
+    ob, kb = o[:nb], k[:nb]
+    tr = tuned.get(hg.RECORDS)
+    rec32 = g.trace(ob, kb, precision=hg.FP32_RECHECK, mode=hg.RECORDS, tuned=tr)
+    rec32 = g.trace(ob, kb, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=rec32, timing=True,
+                    capacity=rec32["needed"], tuned=tr)
+    rec64 = g.trace(ob, kb, precision=hg.FP64, mode=hg.RECORDS, capacity=rec32["needed"], tuned=tr)
+    rec64 = g.trace(ob, kb, precision=hg.FP64, mode=hg.RECORDS, out=rec64, timing=True,
+                    capacity=rec32["needed"], tuned=tr)
+    xb = rec32["needed"]
+    extra = {}
+    if not a.no_compare:
+        extra.update(compare_fp32r_fp64(res, t64, False))
+        extra["records_first_batch"] = compare_fp32r_fp64(rec32, rec64, True)
+        extra.update(oracle_sample_check(g, w, o_np[:nb], k_np[:nb], rec64, dev, m=2000))
+    tau_avg = float(np.mean(tau_ms))
+    block = tt["block"] if tt else 256
+    line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",
+                     {"workload": w.name, "tree": tree_name(w.tree_type), "leaves": int(n_leaves),
+                      "nodes": int(n_nodes), "paths": int(n), "precision": "fp32_recheck",
+                      "mode": "tau_only", "step": "grid_build + grid_trace (tau-only)"})
+    line.update({
+        "rays_per_s": round(n / step_s, 1),
+        "crossings_per_path": round(crossings / n, 3),
+        "build_ms": round(float(np.mean(build_ms)), 3),
+        "trace_fp32r_tau_only": {"ms": round(tau_avg, 3),
+                                 "crossings_per_s": round(crossings / (tau_avg * 1e-3), 1),
+                                 "rays_per_s": round(n / (tau_avg * 1e-3), 1)},
+        "trace_fp64_tau_only": {"ms": round(t64["kernel_ms"][0], 3),
+                                "crossings_per_s": round(crossings / (t64["kernel_ms"][0] * 1e-3), 1)},
+        "fp32r_over_fp64_tau_only": round(t64["kernel_ms"][0] / tau_avg, 3),
+        "records_batch": {"paths": int(nb), "crossings": int(xb),
+                          "fp32r_ms": round(rec32["kernel_ms"][3], 3),
+                          "fp32r_crossings_per_s": round(xb / (rec32["kernel_ms"][3] * 1e-3), 1),
+                          "fp32r_fill_ms": round(rec32["kernel_ms"][2], 3),
+                          "fp64_ms": round(rec64["kernel_ms"][3], 3),
+                          "fp64_crossings_per_s": round(xb / (rec64["kernel_ms"][3] * 1e-3), 1),
+                          "fill_roofline": roofline(
+                              persistent_kernel(w.tree_type, 1, True, tr["block"] if tr else 256),
+                              rec32["kernel_ms"][2], xb * B_X_FILL32 + nb * B_RAY_FILL,
+                              f"w3{tree_name(w.tree_type)}_fill")},
+        "recheck_rate": round(rechecks / max(crossings, 1), 6),
+        "tuned": {str(kk): v for kk, v in tuned.items()} or None,
+        "roofline": roofline(persistent_kernel(w.tree_type, 1, False, block), tau_avg,
+                             crossings * B_X_COUNT32 + n * B_RAY_COUNT,
+                             f"w3{tree_name(w.tree_type)}_tau"),
+    })
+    line.update(extra)
+    if not a.no_cpu:
+        import oracle as O
+        e = g.export()
+        og = O.Grid.from_first_child(w.tree_type, e["first_child"].cpu().numpy(), e["rho"].cpu().numpy())
+        del e
+        m, t, xs, cores = cpu_trace_sample(og, o_np, k_np, a.cpu_seconds, records=False)
+        line["cpu_baseline"] = {
+            "value": round(xs / t, 1), "unit": "crossings/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 tau trace of the first {m} of {n} paths ({xs} crossings, {t:.2f} s on "
+                      f"{cores} threads) through the GPU-built grid imported into the oracle; the "
+                      f"oracle build of this grid (plain loop over all 500 clumps per sample) is "
+                      f"not timed"}
+    g.free()
+    return line
+
+
+# ---------------------------------------------------------------------------
+# workload 4: 64 grids, one captured build-then-trace graph vs one by one
+# ---------------------------------------------------------------------------
+
+def run_c4(a):
+    import torch
+
+    import paper_1311_0705_amd as hg
+    import workloads as W
+    dev = torch.device("cuda:0")
+    ws = [W.workload(4, i) for i in range(64)]
+    rays = [W.rays(x.ray_kind, x.n_rays, x.ray_seed) for x in ws]
+    os_ = [torch.from_numpy(p).to(dev) for p, _ in rays]
+    ks_ = [torch.from_numpy(q).to(dev) for _, q in rays]
+    n = sum(x.n_rays for x in ws)
+
+    def one_by_one(outs=None):
+        gs, rs = [], []
+        for i, x in enumerate(ws):
+            g = hg.build(x.density, x.criteria, x.tree_type, device=dev)
+            rs.append(g.trace(os_[i], ks_[i], precision=hg.FP32_RECHECK, mode=hg.RECORDS,
+                              out=None if outs is None else outs[i],
+                              capacity=None if outs is None else outs[i]["leaf"].numel()))
+            gs.append(g)
+        return gs, rs
+
+    gs, ref = one_by_one()
+    caps_nodes = [g.n_nodes + 64 for g in gs]
+    needed = [r["needed"] for r in ref]
+    crossings = sum(needed)
+    leaves = sum(g.n_leaves for g in gs)
+    for g in gs:
+        g.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        gs, _ = one_by_one(ref)
+        for g in gs:
+            g.free()
+    torch.cuda.synchronize()
+    obo_s = (time.perf_counter() - t0) / a.steps
+    log(f"one by one: {obo_s * 1e3:.1f} ms per pass; {leaves} leaves, {crossings} crossings")
+
+    b = hg.Batch([x.density for x in ws], [x.criteria for x in ws], [x.tree_type for x in ws],
+                 caps_nodes, device=dev)
+    res = b.bind(os_, ks_, precision=hg.FP32_RECHECK, mode=hg.RECORDS, capacities=needed)
+    b.run(hg.STAGE_ALL)
+    b.result()
+    tuned = None
+    if not a.no_tune:
+        tuned = b.tune()
+        res = b.results
+        log(f"tuned batch walk: {tuned}")
+    tk = dict(chunk=tuned["chunk"], refill_min=tuned["refill_min"], block=tuned["block"]) if tuned \
+        else {}
+    side = torch.cuda.Stream(dev)
+    # eager batch (no graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        b.run(hg.STAGE_ALL, stream=side)
+    b.result(side)
+    eager_s = (time.perf_counter() - t0) / a.steps
+    b.capture(hg.STAGE_ALL, stream=side)
+    for _ in range(a.warmup):
+        b.replay(side)
+    b.result(side)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        b.replay(side)
+    b.result(side)
+    step_s = (time.perf_counter() - t0) / a.steps
+    log(f"graph replay {step_s * 1e3:.2f} ms, eager batch {eager_s * 1e3:.2f} ms")
+    same = all(res[i]["needed"] == ref[i]["needed"]
+               and torch.equal(res[i]["tau"], ref[i]["tau"])
+               and torch.equal(res[i]["leaf"][:needed[i]], ref[i]["leaf"][:needed[i]])
+               and torch.equal(res[i]["ds"][:needed[i]], ref[i]["ds"][:needed[i]])
+               for i in range(64))
+    # the batched walks on their own, timed with HIP events (eager, same grids)
+    log("batched walk timing")
+    grids = [b.grid(i) for i in range(64)]
+    grids_fc = {}
+    if not a.no_cpu:
+        for i in range(0, 64, 8):
+            e = grids[i].export()
+            grids_fc[i] = (e["first_child"].cpu().numpy(), e["rho"].cpu().numpy())
+            del e
+    tb = hg.trace_batched(grids, os_, ks_, precision=hg.FP32_RECHECK, mode=hg.RECORDS,
+                          capacities=needed, timing=True, **tk)
+    tb = hg.trace_batched(grids, os_, ks_, precision=hg.FP32_RECHECK, mode=hg.RECORDS,
+                          capacities=needed, timing=True, outs=tb, **tk)
+    kms = tb[0]["kernel_ms"]
+    for g in grids:
+        g.free()
+    b.free()
+    line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",
+                     {"workload": "clumps-batch-64", "grids": 64, "leaves": int(leaves),
+                      "paths": int(n), "precision": "fp32_recheck", "mode": "records",
+                      "step": "captured graph: batched grid build + batched trace"})
+    line.update({
+        "rays_per_s": round(n / step_s, 1),
+        "one_by_one_ms": round(obo_s * 1e3, 3),
+        "eager_batch_ms": round(eager_s * 1e3, 3),
+        "graph_over_one_by_one": round(obo_s / step_s, 3),
+        "batch_equals_one_by_one": bool(same),
+        "batched_walk_ms": {"count": round(kms[0], 3), "scan": round(kms[1], 3),
+                            "fill": round(kms[2], 3)},
+        "tuned": tuned,
+        "roofline": roofline("k_walk_batched<fp32_recheck,fill>", kms[2],
+                             crossings * B_X_FILL32 + n * B_RAY_FILL, "w4_fill"),
+    })
+    if not a.no_cpu:
+        import oracle as O
+        t_t, xs, m_tot = 0.0, 0, 0
+        cores = cpu_cores()
+        log("oracle trace sample")
+        for i in range(0, 64, 8):
+            e = grids_fc[i]
+            og = O.Grid.from_first_child(ws[i].tree_type, e[0], e[1])
+            m = min(20_000, ws[i].n_rays)
+            t0 = time.perf_counter()
+            r = og.trace(rays[i][0][:m], rays[i][1][:m], nthreads=cores)
+            t_t += time.perf_counter() - t0
+            xs += int(r["count"].sum())
+            m_tot += m
+        line["cpu_baseline"] = {
+            "value": round(xs / t_t, 1), "unit": "crossings/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 records trace of the first (up to) 2e4 paths of grids 0, 8, ..., 56 "
+                      f"({m_tot} paths, {xs} crossings, {t_t:.2f} s on {cores} threads) through "
+                      f"the GPU-built grids imported into the oracle; the oracle builds (a plain "
+                      f"loop over up to 2000 clumps per sample) are not timed"}
+    return line
+
+
+# ---------------------------------------------------------------------------
+# workload 5: large clumpy k-d tree, build timed, batches of 1e8 tau-only
+# ---------------------------------------------------------------------------
+
+def run_c5(a, w):
+    import torch
+
+    import paper_1311_0705_amd as hg
+    import workloads as W
+    dev = torch.device("cuda:0")
+    per = 100_000_000 if a.rays is None else a.rays
+    log(f"generating {per} paths")
+    o_np, k_np = W.rays(w.ray_kind, per, w.ray_seed)
+    o = torch.from_numpy(o_np).to(dev)
+    k0 = torch.from_numpy(k_np).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    log(f"build {build_s:.2f} s: {g.n_leaves} leaves")
+    tt = None
+    if not a.no_tune:
+        tt = g.tune(o[:1_000_000], k0[:1_000_000], precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY)
+        log(f"tuned {tt}")
+    res = g.trace(o, k0, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt)
+    batch_ms, xs = [], []
+    k = torch.empty_like(k0)
+    for bi in range(a.batches):
+        # batch bi: the paths of batch 0 with directions turned about z by 2 pi bi / batches
+        ang = 2.0 * math.pi * bi / a.batches
+        c, s = math.cos(ang), math.sin(ang)
+        k[:, 0] = c * k0[:, 0] - s * k0[:, 1]
+        k[:, 1] = s * k0[:, 0] + c * k0[:, 1]
+        k[:, 2] = k0[:, 2]
+        k.div_(k.norm(dim=1, keepdim=True))
+        r = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, out=res, timing=True, tuned=tt)
+        batch_ms.append(r["kernel_ms"][0])
+        xs.append(int(r["count"].sum().item()))
+        log(f"batch {bi}: {batch_ms[-1]:.1f} ms, {xs[-1]} crossings")
+    tot_ms = float(np.sum(batch_ms))
+    crossings = int(np.sum(xs))
+    n = per * a.batches
+    extra = {}
+    if not a.no_compare:
+        r64 = g.trace(o[:1_000_000], k0[:1_000_000], precision=hg.FP64, mode=hg.RECORDS)
+        r32 = g.trace(o[:1_000_000], k0[:1_000_000], precision=hg.FP32_RECHECK, mode=hg.RECORDS,
+                      capacity=r64["needed"])
+        extra["first_1e6_paths"] = compare_fp32r_fp64(r32, r64, True)
+        extra.update(oracle_sample_check(g, w, o_np[:1_000_000], k_np[:1_000_000], r64, dev, m=2000))
+    step_s = build_s + tot_ms * 1e-3
+    line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",
+                     {"workload": w.name, "tree": "kd", "leaves": int(g.n_leaves),
+                      "nodes": int(g.n_nodes), "paths": int(n), "batches": a.batches,
+                      "precision": "fp32_recheck", "mode": "tau_only",
+                      "step": "grid_build + grid_trace of every batch"})
+    line.update({
+        "build_s": round(build_s, 3),
+        "trace_ms_total": round(tot_ms, 3),
+        "trace_ms_per_batch": [round(x, 3) for x in batch_ms],
+        "trace_crossings_per_s": round(crossings / (tot_ms * 1e-3), 1),
+        "trace_rays_per_s": round(n / (tot_ms * 1e-3), 1),
+        "tuned": tt,
+        "roofline": roofline(persistent_kernel(1, 1, False, tt["block"] if tt else 256),
+                             float(np.mean(batch_ms)),
+                             crossings / a.batches * B_X_COUNT32 + per * B_RAY_COUNT, "w5_tau"),
+    })
+    line.update(extra)
+    if not a.no_cpu:
+        import oracle as O
+        e = g.export()
+        og = O.Grid.from_first_child(w.tree_type, e["first_child"].cpu().numpy(), e["rho"].cpu().numpy())
+        del e
+        m, t, xs1, cores = cpu_trace_sample(og, o_np, k_np, a.cpu_seconds, records=False)
+        line["cpu_baseline"] = {
+            "value": round(xs1 / t, 1), "unit": "crossings/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 tau trace of the first {m} paths of batch 0 ({xs1} crossings, {t:.2f} s "
+                      f"on {cores} threads) through the GPU-built grid imported into the oracle; "
+                      f"the oracle build is not timed"}
+    g.free()
+    return line
 
 
 def main():
@@ -80,223 +659,28 @@ def main():
 
     import torch
 
-    import paper_1311_0705_amd as hg
     import workloads as W
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    tree = None if a.tree is None else (W.KDTREE if a.tree == "kd" else W.OCTREE)
-    w = W.workload(a.workload, tree_type=tree, n_rays=a.rays)
-    print(f"[bench] workload {w.name}: {w.n_rays} paths ({w.ray_kind} origins)", file=sys.stderr,
-          flush=True)
-    o_np, k_np = W.rays(w.ray_kind, w.n_rays, w.ray_seed)
-    o = torch.from_numpy(o_np).to(dev)
-    k = torch.from_numpy(k_np).to(dev)
-    n = o.shape[0]
-    stream = torch.cuda.current_stream()
-
     if a.calib_copy:
         src = torch.empty(a.calib_copy << 20, dtype=torch.uint8, device=dev).fill_(1)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    # ---- warm-up (also sizes the record buffers) ----
-    g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
-    n_leaves, n_nodes = g.n_leaves, g.n_nodes
-    res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, timing=True,
-                  count_rechecks=True)
-    needed = res["needed"]
-    rechecks = res["rechecks"]
-    g.free()
-    del g
-    for _ in range(max(0, a.warmup - 1)):
-        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
-        g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=res, capacity=needed)
-        g.free()
-    print(f"[bench] grid: {n_leaves} leaves, {n_nodes} nodes; {needed} crossings", file=sys.stderr,
-          flush=True)
-
-    # ---- timed steps: build + FP32-recheck records trace ----
-    torch.cuda.synchronize()
-    fill_ms, count_ms, build_ms = [], [], []
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        tb0 = time.perf_counter()
-        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
-        build_ms.append((time.perf_counter() - tb0) * 1e3)
-        r = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=res, capacity=needed,
-                    timing=True)
-        count_ms.append(r["kernel_ms"][0])
-        fill_ms.append(r["kernel_ms"][2])
-        if _ < a.steps - 1:
-            g.free()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    step_s = (t1 - t0) / a.steps
-    crossings = int(res["needed"])
-    value = crossings / step_s
-    print(f"[bench] step {step_s*1e3:.2f} ms (build ~{np.mean(build_ms):.2f} ms host-timed)",
-          file=sys.stderr, flush=True)
-
-    # ---- trace-only throughput, FP32-recheck vs FP64 (same grid, same paths) ----
-    def time_trace(prec, reps=3):
-        ms_tot, ms_c, ms_f = [], [], []
-        out = {}
-        for i in range(reps + 1):
-            rr = g.trace(o, k, precision=prec, mode=hg.RECORDS, out=out, capacity=needed,
-                         timing=True)
-            if i:
-                ms_tot.append(rr["kernel_ms"][3])
-                ms_c.append(rr["kernel_ms"][0])
-                ms_f.append(rr["kernel_ms"][2])
-        return out, float(np.median(ms_tot)), float(np.median(ms_c)), float(np.median(ms_f))
-
-    r32, ms32, c32, f32 = time_trace(hg.FP32_RECHECK)
-    r64, ms64, c64, f64 = time_trace(hg.FP64)
-    tau_only = {}
-    for prec in (hg.FP32_RECHECK, hg.FP64):
-        ts = []
-        tout = {}
-        for i in range(4):
-            rr = g.trace(o, k, precision=prec, mode=hg.TAU_ONLY, out=tout, timing=True)
-            if i:
-                ts.append(rr["kernel_ms"][0])
-        tau_only[prec] = float(np.median(ts))
-
-    extra = {}
-    if not a.no_compare:
-        same_counts = bool(torch.equal(r32["count"], r64["count"]))
-        leaf_exact = same_counts and bool(torch.equal(r32["leaf"][:crossings],
-                                                      r64["leaf"][:crossings]))
-        ds_exact = bool(torch.equal(r32["ds"][:crossings], r64["ds"][:crossings].float()))
-        t64 = r64["tau"]
-        rel = ((r32["tau"] - t64).abs() / t64.abs().clamp_min(1e-300))
-        extra.update(leaf_exact_vs_fp64=leaf_exact, ds32_equals_rounded_fp64=ds_exact,
-                     tau_max_rel_err_vs_fp64=float(rel.max().item()))
-        # oracle spot check on a sample of paths through the same grid
-        import oracle as O
-        e = g.export()
-        og = O.Grid.from_first_child(w.tree_type, e["first_child"].cpu().numpy(),
-                                     e["rho"].cpu().numpy())
-        rng = np.random.default_rng(1)
-        idx = np.sort(rng.choice(n, size=min(n, 4000), replace=False))
-        ref = og.trace(o_np[idx], k_np[idx])
-        off64 = r64["offsets"].cpu().numpy()
-        ok = np.array_equal(r64["count"].cpu().numpy()[idx], ref["count"])
-        ok = ok and np.array_equal(r64["tau"].cpu().numpy()[idx], ref["tau"])
-        if ok:
-            pos = np.concatenate([np.arange(off64[i], off64[i + 1]) for i in idx])
-            pos_t = torch.from_numpy(pos).to(dev)
-            gl = r64["leaf"].index_select(0, pos_t).cpu().numpy()
-            gd = r64["ds"].index_select(0, pos_t).cpu().numpy()
-            ok = np.array_equal(gl, ref["leaf"]) and np.array_equal(gd, ref["ds"])
-        extra.update(oracle_sample_paths=int(idx.size), oracle_sample_bitwise_fp64=bool(ok))
-        del e, og
-    g.free()
-
-    # ---- roofline of the dominant kernel (record-filling FP32-recheck walk) ----
-    fill_avg = float(np.mean(fill_ms))
-    count_avg = float(np.mean(count_ms))
-    alg_fill = crossings * B_X_FILL32 + n * B_RAY_FILL
-    achieved = alg_fill / (fill_avg * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(a.workload),
-                "kernel": "k_walk_persistent<kd,fp32_recheck,fill>" if w.tree_type == W.KDTREE
-                else "k_walk_persistent<octree,fp32_recheck,fill>",
-                "kernel_ms": round(fill_avg, 3),
-                "alg_bytes_per_launch": int(alg_fill)}
-
-    line = {
-        "metric": METRIC,
-        "value": round(value, 1),
-        "unit": "crossings/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": round(step_s * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "tree": "kd" if w.tree_type == W.KDTREE else "octree",
-                   "leaves": int(n_leaves), "nodes": int(n_nodes), "paths": int(n),
-                   "precision": "fp32_recheck", "mode": "records",
-                   "step": "grid_build + grid_trace"},
-        "rays_per_s": round(n / step_s, 1),
-        "crossings_per_path": round(crossings / n, 3),
-        "trace_fp32r": {"crossings_per_s": round(crossings / (ms32 * 1e-3), 1),
-                        "rays_per_s": round(n / (ms32 * 1e-3), 1), "ms": round(ms32, 3),
-                        "count_ms": round(c32, 3), "fill_ms": round(f32, 3),
-                        "tau_only_ms": round(tau_only[hg.FP32_RECHECK], 3)},
-        "trace_fp64": {"crossings_per_s": round(crossings / (ms64 * 1e-3), 1),
-                       "rays_per_s": round(n / (ms64 * 1e-3), 1), "ms": round(ms64, 3),
-                       "count_ms": round(c64, 3), "fill_ms": round(f64, 3),
-                       "tau_only_ms": round(tau_only[hg.FP64], 3)},
-        "fp32r_over_fp64": round(ms64 / ms32, 3),
-        "fp32r_over_fp64_tau_only": round(tau_only[hg.FP64] / tau_only[hg.FP32_RECHECK], 3),
-        "recheck_rate": round(rechecks / max(crossings, 1), 6),
-        "build_ms": round(float(np.mean(build_ms)), 3),
-        "count_walk_ms": round(count_avg, 3),
-        "roofline": roofline,
-    }
-    line.update(extra)
-
-    # ---- CPU baseline: the oracle on the host cores ----
-    if not a.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, o_np, k_np, crossings, a.cpu_seconds)
+    tree = None if a.tree is None else (W.KDTREE if a.tree == "kd" else W.OCTREE)
+    if a.workload == 4:
+        line = run_c4(a)
+    else:
+        w = W.workload(a.workload, tree_type=tree, n_rays=a.rays if a.workload != 5 else None)
+        log(f"workload {w.name}")
+        if a.workload in (1, 2):
+            line = run_single(a, w)
+        elif a.workload == 3:
+            line = run_c3(a, w)
+        else:
+            line = run_c5(a, w)
     print(json.dumps(line), flush=True)
-
-
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel, if the counters were taken
-    on the current walk source; else None."""
-    import hashlib
-    if workload != 2 or TRAFFIC["trace_sha256"] is None:
-        return None
-    src = os.path.join(ROOT, "paper_1311_0705_amd", "csrc", "trace.hip")
-    with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC["trace_sha256"]:
-            return None
-    return int(TRAFFIC["fetch_kib"] * 1024 * TRAFFIC["fetch_scale"]
-               + TRAFFIC["write_kib"] * 1024 * TRAFFIC["write_scale"])
-
-
-def cpu_baseline(w, o_np, k_np, crossings_total, budget_s):
-    import oracle as O
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = max(1, min(int(cores), 64))
-    t0 = time.perf_counter()
-    og = O.Grid.build(w.density, w.criteria, w.tree_type)
-    t_build = time.perf_counter() - t0
-    n = o_np.shape[0]
-    m = min(n, 20000)
-    t0 = time.perf_counter()
-    r = og.trace(o_np[:m], k_np[:m], records=True, nthreads=cores)
-    t_probe = time.perf_counter() - t0
-    left = max(0.0, budget_s - t_build - t_probe)
-    m2 = int(min(n, max(m, m * left / max(t_probe, 1e-6))))
-    if m2 > m:
-        t0 = time.perf_counter()
-        r = og.trace(o_np[:m2], k_np[:m2], records=True, nthreads=cores)
-        t_probe = time.perf_counter() - t0
-        m = m2
-    x_sample = int(r["count"].sum())
-    trace_rate = x_sample / t_probe
-    # whole step extrapolated: one build plus the trace of all n paths
-    t_step = t_build + t_probe * (n / m)
-    return {"value": round(crossings_total / t_step, 1), "unit": "crossings/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"oracle build of the full grid ({t_build:.2f} s, one thread) + FP64 "
-                      f"records trace of the first {m} of {n} paths on {cores} threads "
-                      f"({t_probe:.2f} s, {x_sample} crossings); step time extrapolated "
-                      f"to all paths",
-            "trace_crossings_per_s": round(trace_rate, 1),
-            "build_s": round(t_build, 3),
-            "oracle_leaves": int(og.n_leaves)}
 
 
 if __name__ == "__main__":

@@ -119,12 +119,15 @@ typedef struct {
     int32_t mode;       /* HG_TAU_ONLY or HG_RECORDS */
     double kappa;       /* opacity in tau = sum kappa rho ds */
     int32_t flags;      /* HG_FLAG_* */
-    int32_t block;      /* reserved, 0 */
+    int32_t block;      /* persistent and batched walks: threads per block, 128, 256 or 512;
+                           0 = library choice (256) */
     int32_t persistent; /* persistent lane-refill walk for: bit 0 the counting / tau-only walk,
                            bit 1 the record-filling walk (else one thread per path);
                            -1 = library choice */
     int32_t chunk;      /* persistent walk: paths a wavefront takes per atomic, 0 = library choice */
     int32_t refill_min; /* persistent walk: idle lanes that trigger a refill (1..64), 0 = library choice */
+    int32_t lds_bytes;  /* persistent walk: bytes of top-level child references each block
+                           stages in LDS (at most 65536); 0 = library choice (16384), < 0 = none */
 } hg_trace_opts;
 
 /* Outputs of grid_trace; every array is a caller-owned device buffer.
@@ -219,6 +222,20 @@ int grid_trace_batched(int n_grids, const hg_grid_t *grids, const double *const 
                        const double *const *dirs, const int64_t *n, const hg_trace_opts *opts,
                        hg_trace_out *outs, void *stream);
 
+/* Autotune the launch shape of grid_trace's persistent walk for this grid and
+ * workload.  The results of a trace do not depend on the launch shape, only
+ * its speed does.  Times the walk of the n paths origins / dirs (device, a
+ * representative sample of the workload) with HIP events for candidate
+ * shapes -- threads per block, LDS bytes of staged top levels, paths per
+ * work-queue atomic and the refill threshold -- by coordinate descent from
+ * the library defaults, and writes the fastest into opts->block, lds_bytes,
+ * chunk and refill_min (opts->persistent is set to 3; precision, mode and
+ * kappa are inputs).  Records mode times the counting plus the filling walk
+ * with record buffers the call allocates.  *best_ms (may be NULL) receives
+ * the winner's walk time.  Synchronises the stream.  Errors as grid_trace. */
+int grid_tune(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
+              hg_trace_opts *opts, float *best_ms, void *stream);
+
 /* Leaf containing each point (Sect. 2.3, top-down search).  points is device
  * double[n][3]; leaf_out device int32[n].  Cells are half-open [lo, hi) along
  * each axis except that the domain's upper faces belong to the last cells;
@@ -285,9 +302,9 @@ int batch_capture(hg_batch_t batch, int stages, void *stream);
 int batch_replay(hg_batch_t batch, void *stream);
 
 /* Wait for the stream and read the results of the last run or replay:
- * per-grid node and leaf counts (arrays of n_grids, may be NULL) and, for a
- * bound batch, outs[g].needed (records mode) and the recheck count in
- * outs[0].rechecks (with HG_FLAG_RECHECKS).  Returns HG_E_LIMIT if a grid
+ * per-grid node and leaf counts (arrays of n_grids, may be NULL) and, when
+ * that run included the trace stage, outs[g].needed (records mode) and the
+ * recheck count in outs[0].rechecks (with HG_FLAG_RECHECKS).  Returns HG_E_LIMIT if a grid
  * exceeded its node capacity (its tree is incomplete), HG_E_CAPACITY if a
  * grid's records did not fit, else the trace errors of grid_trace. */
 int batch_result(hg_batch_t batch, void *stream, int64_t *n_nodes, int64_t *n_leaves,
@@ -299,6 +316,16 @@ int batch_result(hg_batch_t batch, void *stream, int64_t *n_nodes, int64_t *n_le
  * device.  Errors: HG_E_INVAL, HG_E_LIMIT (the grid exceeded its capacity),
  * HG_E_OOM, HG_E_HIP. */
 int batch_grid(hg_batch_t batch, int g, hg_grid_t *out);
+
+/* Autotune the bound trace of a built batch: times the batched walk for
+ * candidate threads per block, paths per work-queue entry and refill
+ * thresholds (coordinate descent, HIP events) and rebinds the batch with the
+ * fastest (which drops a captured graph: tune before batch_capture).  The
+ * output buffers are written during the search.  *chosen (may be NULL)
+ * receives the winning options, *best_ms (may be NULL) their walk time.
+ * Synchronises the stream.  Errors: HG_E_INVAL (no binding), HG_E_LIMIT,
+ * HG_E_OOM, HG_E_HIP. */
+int batch_tune(hg_batch_t batch, hg_trace_opts *chosen, float *best_ms, void *stream);
 
 /* Release a batch and its device memory (NULL is ignored); synchronises the
  * device.  Grid handles from batch_grid must be freed before. */

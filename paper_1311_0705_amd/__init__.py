@@ -74,7 +74,7 @@ class TraceOpts(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("mode", C.c_int32), ("kappa", C.c_double),
         ("flags", C.c_int32), ("block", C.c_int32), ("persistent", C.c_int32),
-        ("chunk", C.c_int32), ("refill_min", C.c_int32),
+        ("chunk", C.c_int32), ("refill_min", C.c_int32), ("lds_bytes", C.c_int32),
     ]
 
 
@@ -124,6 +124,9 @@ _SIGS = [
                                C.POINTER(C.c_int64), C.POINTER(TraceOut)]),
     ("batch_grid", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     ("batch_free", None, [C.c_void_p]),
+    ("batch_tune", C.c_int, [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.c_float), C.c_void_p]),
+    ("grid_tune", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(TraceOpts),
+                            C.POINTER(C.c_float), C.c_void_p]),
     ("grid_strerror", C.c_char_p, [C.c_int]),
     ("grid_last_hip_error", C.c_int, []),
 ]
@@ -303,7 +306,8 @@ class Grid:
     def trace(self, origins, dirs, precision: int = FP64, mode: int = RECORDS,
               kappa: float = 1.0, capacity: Optional[int] = None, timing: bool = False,
               count_rechecks: bool = False, stream=None, out: Optional[dict] = None,
-              block: int = 0, persistent: int = -1, chunk: int = 0, refill_min: int = 0) -> dict:
+              block: int = 0, persistent: int = -1, chunk: int = 0, refill_min: int = 0,
+              lds_bytes: int = 0, tuned: Optional[dict] = None) -> dict:
         """Trace paths; returns tau, count (and offsets, leaf, ds in records
         mode) as device tensors plus needed / rechecks / kernel_ms."""
         o = _dev_f64x3(origins, self.device)
@@ -324,6 +328,11 @@ class Grid:
         opts.persistent = persistent
         opts.chunk = chunk
         opts.refill_min = refill_min
+        opts.lds_bytes = lds_bytes
+        if tuned is not None:
+            for key in ("block", "lds_bytes", "chunk", "refill_min"):
+                setattr(opts, key, int(tuned[key]))
+            opts.persistent = 3
         dsdt = torch.float64 if precision == FP64 else torch.float32
         for attempt in range(2):
             to = TraceOut()
@@ -352,6 +361,22 @@ class Grid:
         res["rechecks"] = int(to.rechecks)
         res["kernel_ms"] = list(to.kernel_ms)
         return res
+
+    def tune(self, origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
+             kappa: float = 1.0, stream=None) -> dict:
+        """Autotuned launch shape of the walk for these paths (grid_tune):
+        dict(block, lds_bytes, chunk, refill_min, ms); pass it to trace(tuned=)."""
+        o = _dev_f64x3(origins, self.device)
+        k = _dev_f64x3(dirs, self.device)
+        opts = TraceOpts()
+        opts.precision = precision
+        opts.mode = mode
+        opts.kappa = kappa
+        ms = C.c_float()
+        _check(lib().grid_tune(self._h, _ptr(o), _ptr(k), o.shape[0], C.byref(opts), C.byref(ms),
+                               _stream(stream)), "grid_tune")
+        return dict(block=opts.block, lds_bytes=opts.lds_bytes, chunk=opts.chunk,
+                    refill_min=opts.refill_min, ms=float(ms.value))
 
     # -- arrays ----------------------------------------------------------------
     def export(self) -> dict:
@@ -386,10 +411,42 @@ class Grid:
         )
 
 
+def tune_cached(grid: "Grid", origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
+                kappa: float = 1.0, path: Optional[str] = None) -> dict:
+    """Grid.tune memoised in a JSON file (HGRID_TUNE_CACHE, else
+    ~/.cache/hgrid_tune.json), keyed by device architecture, tree type,
+    precision, mode and the grid's size class (rounded log2 of its leaf count)."""
+    import json
+    import math
+    path = path or os.environ.get("HGRID_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "hgrid_tune.json")
+    arch = torch.cuda.get_device_properties(grid.device).gcnArchName
+    key = "|".join(str(x) for x in (arch, grid.tree_type, precision, mode,
+                                     int(round(math.log2(max(grid.n_leaves, 1))))))
+    try:
+        with open(path) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        cache = {}
+    if key in cache:
+        return cache[key]
+    t = grid.tune(origins, dirs, precision=precision, mode=mode, kappa=kappa)
+    cache[key] = t
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+    return t
+
+
 def trace_batched(grids, origins, dirs, precision: int = FP64, mode: int = RECORDS,
                   kappa: float = 1.0, capacities=None, timing: bool = False,
                   count_rechecks: bool = False, chunk: int = 0, refill_min: int = 0,
-                  stream=None, outs=None):
+                  stream=None, outs=None, block: int = 0):
     """Trace len(grids) path batches in one batched call; returns one result
     dict per grid (as Grid.trace) and the batch's kernel_ms / rechecks in the
     first."""
@@ -407,6 +464,7 @@ def trace_batched(grids, origins, dirs, precision: int = FP64, mode: int = RECOR
     opts.flags = (FLAG_TIMING if timing else 0) | (FLAG_RECHECKS if count_rechecks else 0)
     opts.chunk = chunk
     opts.refill_min = refill_min
+    opts.block = block
     for attempt in range(2):
         tos = (TraceOut * ng)()
         for i in range(ng):
@@ -491,7 +549,7 @@ class Batch:
 
     def bind(self, origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
              kappa: float = 1.0, capacities=None, chunk: int = 0, refill_min: int = 0,
-             count_rechecks: bool = False):
+             count_rechecks: bool = False, block: int = 0):
         """Bind path batches (one per grid) and allocate their outputs; the
         returned result dicts are filled by each later run or replay."""
         dev = self.device
@@ -523,6 +581,7 @@ class Batch:
         opts.flags = FLAG_RECHECKS if count_rechecks else 0
         opts.chunk = chunk
         opts.refill_min = refill_min
+        opts.block = block
         op = (C.c_void_p * self.ng)(*[o.data_ptr() for o in os_])
         kp = (C.c_void_p * self.ng)(*[k.data_ptr() for k in ks_])
         np_ = (C.c_int64 * self.ng)(*ns)
@@ -535,6 +594,14 @@ class Batch:
 
     def run(self, stages: int = STAGE_ALL, stream=None):
         _check(lib().batch_run(self._h, stages, _stream(stream)), "batch_run")
+
+    def tune(self, stream=None) -> dict:
+        """Autotune the bound trace (batch_tune; needs a built batch, drops a
+        captured graph): dict(block, chunk, refill_min, ms) of the winner."""
+        ms = C.c_float()
+        o = TraceOpts()
+        _check(lib().batch_tune(self._h, C.byref(o), C.byref(ms), _stream(stream)), "batch_tune")
+        return dict(block=o.block, chunk=o.chunk, refill_min=o.refill_min, ms=float(ms.value))
 
     def capture(self, stages: int = STAGE_ALL, stream=None):
         """Record the stages into a graph (on a side stream unless one is

@@ -274,6 +274,9 @@ static int check_trace_args(hg_grid_t g, const double *origins, const double *di
     if (opts->precision != HG_FP64 && opts->precision != HG_FP32_RECHECK) return HG_E_INVAL;
     if (opts->mode != HG_TAU_ONLY && opts->mode != HG_RECORDS) return HG_E_INVAL;
     if (!isfinite(opts->kappa)) return HG_E_INVAL;
+    if (opts->block != 0 && opts->block != 128 && opts->block != 256 && opts->block != 512)
+        return HG_E_INVAL;
+    if (opts->lds_bytes > 65536 || opts->chunk < 0 || opts->refill_min < 0) return HG_E_INVAL;
     const bool records = opts->mode == HG_RECORDS;
     if (n > 0 && (!origins || !dirs || !out->tau || !out->count)) return HG_E_INVAL;
     if (records && !out->offsets) return HG_E_INVAL;

@@ -32,6 +32,10 @@ constexpr int META = LB_N + 4;   // + n_nodes, n_leaves, depth, error
 constexpr int M_NODES = LB_N, M_LEAVES = LB_N + 1, M_DEPTH = LB_N + 2, M_ERR = LB_N + 3;
 constexpr unsigned FLAT_BLOCKS = 1024;    // grid-stride launches over device-sized ranges
 constexpr unsigned SAMPLE_BLOCKS = 2048;  // wavefront-per-node sampling (4 waves per block)
+// launch shapes the batch tuner tries
+const int BLOCKS[] = {128, 256, 512};
+const int BATCH_CHUNKS[] = {128, 256, 512, 1024, 2048, 4096};
+const int REFILLS[] = {4, 8, 16, 32};
 
 struct ForestGrid {
     int tree, nc, lg, pad;
@@ -353,6 +357,7 @@ struct hg_batch {
     TraceStatus *status = nullptr;
     std::vector<void *> arrays;     // every per-grid allocation
     // bound trace
+    std::vector<WalkArgs> hA;
     bool bound = false;
     hg_trace_opts opts{};
     std::vector<int64_t> n;
@@ -365,6 +370,8 @@ struct hg_batch {
     // captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int graph_stages = 0;
+    int last_stages = 0;   // stages of the last run or replay (what batch_result reads)
 };
 
 namespace {
@@ -404,6 +411,17 @@ int grid_array(hg_batch *b, T **p, size_t n)
     int rc = dalloc_n(p, n, nullptr);
     if (!rc) b->arrays.push_back(*p);
     return rc;
+}
+
+std::vector<BatchChunk> chunk_table(const std::vector<int64_t> &n, int64_t chunk)
+{
+    std::vector<BatchChunk> hC;
+    for (size_t i = 0; i < n.size(); i++) {
+        const int32_t head = int32_t(hC.size());
+        for (int64_t a = 0; a < n[i]; a += chunk)
+            hC.push_back(BatchChunk{int32_t(i), head, a, std::min(n[i], a + chunk)});
+    }
+    return hC;
 }
 
 int enqueue_build(hg_batch *b, hipStream_t s)
@@ -551,6 +569,9 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
     if (opts->precision != HG_FP64 && opts->precision != HG_FP32_RECHECK) return HG_E_INVAL;
     if (opts->mode != HG_TAU_ONLY && opts->mode != HG_RECORDS) return HG_E_INVAL;
     if (!isfinite(opts->kappa)) return HG_E_INVAL;
+    if (opts->block != 0 && opts->block != 128 && opts->block != 256 && opts->block != 512)
+        return HG_E_INVAL;
+    if (opts->chunk < 0 || opts->refill_min < 0) return HG_E_INVAL;
     const bool records = opts->mode == HG_RECORDS;
     for (int i = 0; i < b->ng; i++) {
         const hg_trace_out &o = outs[i];
@@ -571,7 +592,7 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
     free_bound(b);
     const int64_t chunk = opts->chunk > 0 ? opts->chunk : 1024;
     std::vector<WalkArgs> hA(size_t(b->ng));
-    std::vector<BatchChunk> hC;
+    const std::vector<BatchChunk> hC = chunk_table(std::vector<int64_t>(n, n + b->ng), chunk);
     for (int i = 0; i < b->ng; i++) {
         WalkArgs &A = hA[size_t(i)];
         A.O = origins[i];
@@ -586,9 +607,6 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
         A.capacity = records ? outs[i].capacity : 0;
         A.st = b->status;
         A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
-        const int32_t head = int32_t(hC.size());
-        for (int64_t a = 0; a < n[i]; a += chunk)
-            hC.push_back(BatchChunk{i, head, a, std::min(n[i], a + chunk)});
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
     int rc = dalloc_n(&b->dA, size_t(b->ng), nullptr);
@@ -607,10 +625,12 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
         return rc;
     }
     b->opts = *opts;
+    b->hA = hA;
     b->n.assign(n, n + b->ng);
     b->outs.assign(outs, outs + b->ng);
     b->n_chunks = int(hC.size());
     b->bound = true;
+    b->last_stages &= ~HG_STAGE_TRACE;
     return HG_OK;
 }
 
@@ -622,6 +642,7 @@ int batch_run(hg_batch_t b, int stages, void *stream)
     int rc = HG_OK;
     if (stages & HG_STAGE_BUILD) rc = enqueue_build(b, s);
     if (!rc && (stages & HG_STAGE_TRACE)) rc = enqueue_trace(b, s);
+    b->last_stages = rc ? 0 : stages;
     return rc;
 }
 
@@ -640,7 +661,9 @@ int batch_capture(hg_batch_t b, int stages, void *stream)
         b->graph = nullptr;
     }
     HG_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    const int before = b->last_stages;
     int rc = batch_run(b, stages, stream);
+    b->last_stages = before;   // nothing has run yet
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (rc) {
@@ -654,6 +677,7 @@ int batch_capture(hg_batch_t b, int stages, void *stream)
         return set_hip_error(e);
     }
     b->graph = g;
+    b->graph_stages = stages;
     return HG_OK;
 }
 
@@ -661,6 +685,7 @@ int batch_replay(hg_batch_t b, void *stream)
 {
     if (!b || !b->exec) return HG_E_INVAL;
     HG_CHECK(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    b->last_stages = b->graph_stages;
     return HG_OK;
 }
 
@@ -672,7 +697,8 @@ int batch_result(hg_batch_t b, void *stream, int64_t *n_nodes, int64_t *n_leaves
     TraceStatus st;
     memset(&st, 0, sizeof st);
     std::vector<int64_t> tot(size_t(b->ng), 0);
-    const bool records = b->bound && b->opts.mode == HG_RECORDS;
+    const bool traced = b->bound && (b->last_stages & HG_STAGE_TRACE);
+    const bool records = traced && b->opts.mode == HG_RECORDS;
     if (records) {
         k_f_totals<<<unsigned((b->ng + FT - 1) / FT), FT, 0, s>>>(b->dA, b->ng, b->totals);
         HG_CHECK(hipGetLastError());
@@ -688,13 +714,13 @@ int batch_result(hg_batch_t b, void *stream, int64_t *n_nodes, int64_t *n_leaves
         if (n_nodes) n_nodes[i] = m[M_NODES];
         if (n_leaves) n_leaves[i] = m[M_LEAVES];
         if (m[M_ERR]) rc = HG_E_LIMIT;
-        if (outs && b->bound) {
+        if (outs && traced) {
             outs[i].needed = records ? tot[size_t(i)] : 0;
             outs[i].rechecks = i == 0 ? int64_t(st.rechecks) : 0;
             if (records && tot[size_t(i)] > b->outs[size_t(i)].capacity && !rc) rc = HG_E_CAPACITY;
         }
     }
-    if (!rc && b->bound) {
+    if (!rc && traced) {
         if (st.bad_ref) rc = HG_E_FORMAT;
         else if (st.bad_dir) rc = HG_E_DIR;
         else if (st.step_guard) rc = HG_E_STEP;
@@ -739,6 +765,109 @@ int batch_grid(hg_batch_t b, int i, hg_grid_t *out)
     g->root_ref = Ref<uint32_t>::make(g->n_internal == 0, 0, 0);
     *out = g;
     return HG_OK;
+}
+
+int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream)
+{
+    if (!b || !b->bound) return HG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const bool records = b->opts.mode == HG_RECORDS;
+    const WalkGrid *G = b->opts.precision == HG_FP64 ? b->w64 : b->w32;
+    const int nchunk = int(sizeof BATCH_CHUNKS / sizeof *BATCH_CHUNKS);
+    std::vector<std::vector<BatchChunk>> tables;
+    size_t most = 1;
+    for (int c = 0; c < nchunk; c++) {
+        tables.push_back(chunk_table(b->n, BATCH_CHUNKS[c]));
+        most = std::max(most, tables.back().size());
+    }
+    if (most > size_t(0x7fffffff)) return HG_E_LIMIT;
+    BatchChunk *dC = nullptr;
+    int64_t *ctmp = nullptr;
+    int rc = dalloc_n(&dC, most * size_t(nchunk), s);
+    if (!rc) rc = dalloc_n(&ctmp, scan_chunks_tmp_elems(int(most)), s);
+    for (int c = 0; c < nchunk && !rc; c++) {
+        if (tables[size_t(c)].empty()) continue;
+        hipError_t e = hipMemcpyAsync(dC + size_t(c) * most, tables[size_t(c)].data(),
+                                      sizeof(BatchChunk) * tables[size_t(c)].size(),
+                                      hipMemcpyHostToDevice, s);
+        if (e) rc = set_hip_error(e);
+    }
+    hipEvent_t ev[4] = {};
+    for (int i = 0; i < 4 && !rc; i++)
+        if (hipEventCreate(&ev[i]) != hipSuccess) rc = HG_E_HIP;
+    hg_trace_opts best = b->opts;
+    best.block = best.block ? best.block : 256;
+    best.refill_min = best.refill_min ? best.refill_min : 16;
+    best.chunk = best.chunk ? best.chunk : 1024;
+    float best_t = INFINITY;
+    auto eval = [&](const hg_trace_opts &c, float *ms) -> int {
+        int ci = 0;
+        while (ci < nchunk - 1 && BATCH_CHUNKS[ci] != c.chunk) ci++;
+        const BatchChunk *C = dC + size_t(ci) * most;
+        const int nc = int(tables[size_t(ci)].size());
+        *ms = INFINITY;
+        for (int r = 0; r <= 3; r++) {
+            HG_CHECK(hipEventRecord(ev[0], s));
+            k_f_reset_status<<<1, 1, 0, s>>>(b->status);
+            int rc2 = nc ? launch_batched(G, b->dA, C, nc, &c, false, b->status, s) : HG_OK;
+            if (rc2) return rc2;
+            HG_CHECK(hipEventRecord(ev[1], s));
+            float t1 = 0.f, t2 = 0.f;
+            if (records) {
+                rc2 = scan_chunks(C, nc, b->dA, b->ng, ctmp, s);
+                if (rc2) return rc2;
+                HG_CHECK(hipEventRecord(ev[2], s));
+                rc2 = nc ? launch_batched(G, b->dA, C, nc, &c, true, b->status, s) : HG_OK;
+                if (rc2) return rc2;
+                HG_CHECK(hipEventRecord(ev[3], s));
+            }
+            HG_CHECK(hipEventSynchronize(records ? ev[3] : ev[1]));
+            HG_CHECK(hipEventElapsedTime(&t1, ev[0], ev[1]));
+            if (records) HG_CHECK(hipEventElapsedTime(&t2, ev[2], ev[3]));
+            if (r > 0) *ms = std::min(*ms, t1 + t2);
+        }
+        return HG_OK;
+    };
+    if (!rc) rc = eval(best, &best_t);
+    for (int round = 0; round < 2 && !rc; round++) {
+        bool moved = false;
+        for (int p = 0; p < 3 && !rc; p++) {
+            const int *vals = p == 0 ? BLOCKS : (p == 1 ? BATCH_CHUNKS : REFILLS);
+            const int nv = p == 0 ? 3 : (p == 1 ? nchunk : 4);
+            for (int v = 0; v < nv && !rc; v++) {
+                hg_trace_opts c = best;
+                int32_t &fld = p == 0 ? c.block : (p == 1 ? c.chunk : c.refill_min);
+                if (fld == vals[v]) continue;
+                fld = vals[v];
+                float ms = 0.f;
+                rc = eval(c, &ms);
+                if (!rc && ms < 0.99f * best_t) {
+                    best = c;
+                    best_t = ms;
+                    moved = true;
+                }
+            }
+        }
+        if (!moved) break;
+    }
+    for (auto &e : ev)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipStreamSynchronize(s);
+    dfree(dC, s);
+    dfree(ctmp, s);
+    if (rc) return rc;
+    // rebind the queue with the winner (a captured graph is dropped)
+    std::vector<const double *> o(size_t(b->ng)), k(size_t(b->ng));
+    for (int i = 0; i < b->ng; i++) {
+        o[size_t(i)] = b->hA[size_t(i)].O;
+        k[size_t(i)] = b->hA[size_t(i)].K;
+    }
+    std::vector<int64_t> n = b->n;
+    std::vector<hg_trace_out> outs = b->outs;
+    rc = batch_bind(b, o.data(), k.data(), n.data(), &best, outs.data());
+    if (!rc && best_ms) *best_ms = best_t;
+    if (!rc && chosen) *chosen = best;
+    return rc;
 }
 
 void batch_free(hg_batch_t b) { free_batch(b); }

@@ -519,14 +519,14 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 // path set-up and the atomic round trip are amortised over many paths.  Each
 // iteration a busy lane performs one dependent global access: a descent step
 // (the first levels of every descent come from LDS) or a crossing.
-template <int TREE, int PREC, bool FILL, typename R>
-__global__ void __launch_bounds__(TB)
+template <int TREE, int PREC, bool FILL, typename R, int BT>
+__global__ void __launch_bounds__(BT)
     k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min)
 {
     extern __shared__ uint64_t lds_raw[];
     R *lds = reinterpret_cast<R *>(lds_raw);
     const int nc = TREE == OCT ? 8 : 2;
-    for (uint32_t j = threadIdx.x; j < lds_n * nc; j += TB) lds[j] = static_cast<const R *>(G.child)[j];
+    for (uint32_t j = threadIdx.x; j < lds_n * nc; j += BT) lds[j] = static_cast<const R *>(G.child)[j];
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -647,8 +647,8 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
 // refilling lanes from the chunk.  Before taking up a chunk of another grid it
 // lets its lanes finish their paths.  Octree and k-d grids mix freely: the
 // tree type is a wavefront-uniform branch.
-template <int PREC, bool FILL>
-__global__ void __launch_bounds__(TB)
+template <int PREC, bool FILL, int BT>
+__global__ void __launch_bounds__(BT)
     k_walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                    const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min,
                    TraceStatus *st)
@@ -748,7 +748,7 @@ constexpr size_t LDS_BYTES = 16384;          // top-level child references per b
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
 
 // Occupancy-derived persistent grid size, cached per kernel instance.
-template <int TREE, int PREC, bool FILL, typename R>
+template <int TREE, int PREC, bool FILL, typename R, int BT>
 int persistent_blocks(size_t lds, unsigned *blocks)
 {
     static int occ = -1, cus = 0;
@@ -758,10 +758,39 @@ int persistent_blocks(size_t lds, unsigned *blocks)
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, FILL, R>), TB, lds));
+            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, FILL, R, BT>), BT, lds));
         occ_lds = lds;
     }
     *blocks = unsigned(std::max(1, cus) * std::max(1, occ));
+    return HG_OK;
+}
+
+template <int TREE, int PREC, bool FILL, typename R, int BT>
+int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts *o, hipStream_t s)
+{
+    const int nc = TREE == OCT ? 8 : 2;
+    const size_t want = o->lds_bytes < 0 ? 0 : (o->lds_bytes == 0 ? LDS_BYTES : size_t(o->lds_bytes));
+    const uint32_t lds_n = uint32_t(std::min<uint64_t>(G.n_internal, want / (sizeof(R) * size_t(nc))));
+    const size_t lds = size_t(lds_n) * nc * sizeof(R);
+    unsigned blocks = 0;
+    int rc = persistent_blocks<TREE, PREC, FILL, R, BT>(lds, &blocks);
+    if (rc) return rc;
+    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 128u;
+    const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : 16;
+    for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
+        WalkArgs B = A;
+        B.n = std::min(PERSIST_CHUNK, A.n - start);
+        B.O = A.O + 3 * start;
+        B.K = A.K + 3 * start;
+        B.tau = A.tau ? A.tau + start : nullptr;
+        B.count = A.count ? A.count + start : nullptr;
+        B.offsets = A.offsets ? A.offsets + start : nullptr;
+        k_reset_counter<<<1, 1, 0, s>>>(A.st);
+        HG_CHECK(hipGetLastError());
+        k_walk_persistent<TREE, PREC, FILL, R, BT><<<dim3(blocks), dim3(BT), lds, s>>>(G, B, lds_n, chunk,
+                                                                                         refill_min);
+        HG_CHECK(hipGetLastError());
+    }
     return HG_OK;
 }
 
@@ -776,30 +805,11 @@ int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trac
         HG_CHECK(hipGetLastError());
         return HG_OK;
     }
-    const int nc = TREE == OCT ? 8 : 2;
-    const uint32_t lds_n =
-        uint32_t(std::min<uint64_t>(G.n_internal, LDS_BYTES / (sizeof(R) * size_t(nc))));
-    const size_t lds = size_t(lds_n) * nc * sizeof(R);
-    unsigned blocks = 0;
-    int rc = persistent_blocks<TREE, PREC, FILL, R>(lds, &blocks);
-    if (rc) return rc;
-    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 128u;
-    const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : 16;
-    for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
-        WalkArgs B = A;
-        B.n = std::min(PERSIST_CHUNK, A.n - start);
-        B.O = A.O + 3 * start;
-        B.K = A.K + 3 * start;
-        B.tau = A.tau ? A.tau + start : nullptr;
-        B.count = A.count ? A.count + start : nullptr;
-        B.offsets = A.offsets ? A.offsets + start : nullptr;
-        k_reset_counter<<<1, 1, 0, s>>>(A.st);
-        HG_CHECK(hipGetLastError());
-        k_walk_persistent<TREE, PREC, FILL, R><<<dim3(blocks), dim3(TB), lds, s>>>(G, B, lds_n, chunk,
-                                                                                     refill_min);
-        HG_CHECK(hipGetLastError());
+    switch (o->block) {
+    case 128: return launch_persistent<TREE, PREC, FILL, R, 128>(G, A, o, s);
+    case 512: return launch_persistent<TREE, PREC, FILL, R, 512>(G, A, o, s);
+    default: return launch_persistent<TREE, PREC, FILL, R, 256>(G, A, o, s);
     }
-    return HG_OK;
 }
 
 template <int TREE, typename R>
@@ -813,7 +823,7 @@ int dispatch_walk(const WalkGrid &G, const WalkArgs &A, int prec, bool fill, int
                 : launch_t<TREE, HG_FP32_RECHECK, false, R>(G, A, persistent, o, s);
 }
 
-template <int PREC, bool FILL>
+template <int PREC, bool FILL, int BT>
 int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
                      int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
 {
@@ -823,15 +833,26 @@ int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChu
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, FILL>), TB, 0));
+            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, FILL, BT>), BT, 0));
     }
     const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
     k_reset_counter<<<1, 1, 0, s>>>(st);
     HG_CHECK(hipGetLastError());
-    k_walk_batched<PREC, FILL><<<dim3(blocks), dim3(TB), 0, s>>>(grids, args, chunks, n_chunks,
-                                                                 refill_min, st);
+    k_walk_batched<PREC, FILL, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
+                                                                     refill_min, st);
     HG_CHECK(hipGetLastError());
     return HG_OK;
+}
+
+template <int PREC, bool FILL>
+int launch_batched_b(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
+                     int n_chunks, int block, int refill_min, TraceStatus *st, hipStream_t s)
+{
+    switch (block) {
+    case 128: return launch_batched_t<PREC, FILL, 128>(grids, args, chunks, n_chunks, refill_min, st, s);
+    case 512: return launch_batched_t<PREC, FILL, 512>(grids, args, chunks, n_chunks, refill_min, st, s);
+    default: return launch_batched_t<PREC, FILL, 256>(grids, args, chunks, n_chunks, refill_min, st, s);
+    }
 }
 
 }  // namespace
@@ -863,19 +884,7 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
     const int mode = opts->persistent < 0 ? 3 : opts->persistent;
     const int persistent = fill ? (mode >> 1) & 1 : mode & 1;
     const WalkGrid G = walk_grid(g, opts->precision);
-    WalkArgs A;
-    A.O = o;
-    A.K = k;
-    A.n = n;
-    A.kappa = opts->kappa;
-    A.tau = out->tau;
-    A.count = out->count;
-    A.offsets = out->offsets;
-    A.leaf = out->leaf;
-    A.ds = out->ds;
-    A.capacity = out->capacity;
-    A.st = g->status;
-    A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
+    const WalkArgs A = walk_args(g, o, k, n, opts, out);
     const int prec = opts->precision;
     if (g->tree == KD)
         return g->wide ? dispatch_walk<KD, uint64_t>(G, A, prec, fill, persistent, opts, s)
@@ -908,11 +917,12 @@ int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk
                    hipStream_t s)
 {
     const int refill_min = opts->refill_min > 0 ? std::min(opts->refill_min, 64) : 16;
+    const int b = opts->block;
     if (opts->precision == HG_FP64)
-        return fill ? launch_batched_t<HG_FP64, true>(grids, args, chunks, n_chunks, refill_min, st, s)
-                    : launch_batched_t<HG_FP64, false>(grids, args, chunks, n_chunks, refill_min, st, s);
-    return fill ? launch_batched_t<HG_FP32_RECHECK, true>(grids, args, chunks, n_chunks, refill_min, st, s)
-                : launch_batched_t<HG_FP32_RECHECK, false>(grids, args, chunks, n_chunks, refill_min, st, s);
+        return fill ? launch_batched_b<HG_FP64, true>(grids, args, chunks, n_chunks, b, refill_min, st, s)
+                    : launch_batched_b<HG_FP64, false>(grids, args, chunks, n_chunks, b, refill_min, st, s);
+    return fill ? launch_batched_b<HG_FP32_RECHECK, true>(grids, args, chunks, n_chunks, b, refill_min, st, s)
+                : launch_batched_b<HG_FP32_RECHECK, false>(grids, args, chunks, n_chunks, b, refill_min, st, s);
 }
 
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s)
