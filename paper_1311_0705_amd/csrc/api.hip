@@ -66,7 +66,7 @@ void free_grid_arrays(hg_grid *g)
 {
     void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
                     g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->recw,
-                    g->child, g->status};
+                    g->child, g->table, g->status};
     for (void *p : ptrs) dfree(p, nullptr);
 }
 

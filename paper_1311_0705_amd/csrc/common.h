@@ -98,7 +98,29 @@ struct WalkGrid {
     uint64_t n_leaves, n_internal; // bounds every reference is checked against
     const void *rec;               // walk records of the precision in use
     const void *child;             // [n_internal][2 or 8] references
+    const void *table;             // locate table (NULL: descents start at the root)
+    int tdep;                      // its per-axis depth: 2^tdep cells per axis
 };
+
+// Locate table: a uniform grid of 2^tdep cells per axis over the domain; cell
+// (i, j, k) (index (i 2^tdep + j) 2^tdep + k) holds the encoded reference of
+// the deepest node containing the whole cell: the node at the level where
+// every axis has depth tdep (k-d 3 tdep, octree tdep), or the leaf holding the
+// cell where the tree is coarser.  A path's first descent starts there.
+constexpr int TABLE_MAX_DEPTH = 7;
+__host__ __device__ inline int table_level(int tree, int tdep) { return tree == OCT ? tdep : 3 * tdep; }
+// Table depth for a tree: about the typical leaf's per-axis depth, at most
+// TABLE_MAX_DEPTH and never deeper than the tree's levels allow.
+__host__ __device__ inline int table_depth(int tree, int64_t n_leaves, int max_level)
+{
+    int l2 = 0;
+    while ((int64_t(1) << (l2 + 1)) <= n_leaves) l2++;
+    int t = (l2 + 1) / 3;
+    const int deepest = tree == OCT ? max_level : max_level / 3;
+    if (t > deepest) t = deepest;
+    if (t > TABLE_MAX_DEPTH) t = TABLE_MAX_DEPTH;
+    return t < 0 ? 0 : t;
+}
 
 // Scratch for device-side status shared by the trace kernels.
 struct TraceStatus {
@@ -164,6 +186,8 @@ struct hg_grid {
     hg::LeafRecW *recw;        // wide layout
     void *child;               // uint32_t or uint64_t references
     uint64_t root_ref;
+    void *table;               // locate table (uint32_t or uint64_t references), or NULL
+    int tdep;                  // its per-axis depth
     hg::TraceStatus *status;   // device scratch
     int64_t level_begin[64];   // first node of each level; level_begin[max_level+1] = n_nodes
     int borrowed;              // arrays belong to a batch (only status is the grid's own)

@@ -52,6 +52,8 @@ struct ForestGrid {
     LeafRec32 *rec32;
     LeafRec64 *rec64;
     uint32_t *child;
+    uint32_t *table;  // locate table, room for 2^(3 tmax) cells
+    int tmax, pad2;
     int64_t *meta;  // [META]: level begins, then n_nodes, n_leaves, depth, error
 };
 
@@ -247,13 +249,25 @@ __global__ void __launch_bounds__(FT) k_f_number(const ForestGrid *__restrict__ 
     }
 }
 
-// Leaf counts, the leaf prefix and each grid's walk parameters.
+__device__ inline int grid_tdep(const ForestGrid &G, int64_t L)
+{
+    const int t = table_depth(G.tree, L, int(G.meta[M_DEPTH]));
+    return t < G.tmax ? t : G.tmax;
+}
+
+// Leaf counts, the leaf and table-cell prefixes and each grid's walk parameters.
 __global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restrict__ F, int ng,
                                                       const int64_t *__restrict__ PN,
                                                       const int64_t *__restrict__ rank, int64_t *PL,
-                                                      WalkGrid *__restrict__ w32, WalkGrid *__restrict__ w64)
+                                                      int64_t *PT, WalkGrid *__restrict__ w32,
+                                                      WalkGrid *__restrict__ w64)
 {
     block_prefix(ng, PL, [&](int i) { return rank[PN[i + 1]] - rank[PN[i]]; });
+    __syncthreads();
+    block_prefix(ng, PT, [&](int i) {
+        const int t = grid_tdep(F[i], rank[PN[i + 1]] - rank[PN[i]]);
+        return t > 0 ? int64_t(1) << (3 * t) : int64_t(0);
+    });
     for (int i = threadIdx.x; i < ng; i += FT) {
         const ForestGrid &G = F[i];
         const int64_t L = rank[PN[i + 1]] - rank[PN[i]];
@@ -268,6 +282,8 @@ __global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restri
         W.n_leaves = uint64_t(L);
         W.n_internal = uint64_t(I);
         W.child = G.child;
+        W.tdep = grid_tdep(G, L);
+        W.table = W.tdep > 0 ? G.table : nullptr;
         W.rec = G.rec32;
         w32[i] = W;
         W.rec = G.rec64;
@@ -299,6 +315,23 @@ __global__ void __launch_bounds__(FT) k_f_records(const ForestGrid *__restrict__
         b.rho = r;
         G.rec32[l] = a;
         G.rec64[l] = b;
+    }
+}
+
+__global__ void __launch_bounds__(FT) k_f_table(const ForestGrid *__restrict__ F, int ng,
+                                                const int64_t *__restrict__ PT,
+                                                const WalkGrid *__restrict__ W)
+{
+    const int64_t T = PT[ng];
+    for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+        const int i = owner(PT, ng, t);
+        const ForestGrid &G = F[i];
+        const int td = W[i].tdep;
+        const int64_t cell = t - PT[i];
+        const uint32_t m = (1u << td) - 1u;
+        const uint32_t c[3] = {uint32_t(cell >> (2 * td)) & m, uint32_t(cell >> td) & m, uint32_t(cell) & m};
+        G.table[cell] = encode<uint32_t>(table_node(G.tree, td, c, G.fc, G.level), G.fc, G.level,
+                                         G.leaf_of, G.int_of);
     }
 }
 
@@ -349,7 +382,7 @@ struct hg_batch {
     ForestGrid *dF = nullptr;
     int64_t *meta = nullptr;        // [ng][META]
     int64_t *P = nullptr;           // [(lmax+1)][ng+1]
-    int64_t *PN = nullptr, *PL = nullptr;
+    int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
@@ -398,8 +431,8 @@ void free_batch(hg_batch *b)
     free_bound(b);
     for (auto &d : b->dens) release_density(&d, nullptr);
     for (void *p : b->arrays) dfree(p, nullptr);
-    void *ptrs[] = {b->dF, b->meta, b->P, b->PN, b->PL, b->flag, b->off, b->stmp, b->w32, b->w64,
-                    b->status};
+    void *ptrs[] = {b->dF, b->meta, b->P, b->PN, b->PL, b->PT, b->flag, b->off, b->stmp, b->w32,
+                    b->w64, b->status};
     for (void *p : ptrs) dfree(p, nullptr);
     (void)hipDeviceSynchronize();
     delete b;
@@ -455,7 +488,9 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     if (rc) return rc;
     k_f_number<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PN, b->off);
     HG_CHECK(hipGetLastError());
-    k_f_leaf_prefix<<<1, FT, 0, s>>>(b->dF, ng, b->PN, b->off, b->PL, b->w32, b->w64);
+    k_f_leaf_prefix<<<1, FT, 0, s>>>(b->dF, ng, b->PN, b->off, b->PL, b->PT, b->w32, b->w64);
+    HG_CHECK(hipGetLastError());
+    k_f_table<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PT, b->w32);
     HG_CHECK(hipGetLastError());
     k_f_records<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, b->PL);
     HG_CHECK(hipGetLastError());
@@ -534,6 +569,8 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
         if (!rc) rc = grid_array(b, &G.rec32, cap);
         if (!rc) rc = grid_array(b, &G.rec64, cap);
         if (!rc) rc = grid_array(b, &G.child, cap);
+        G.tmax = table_depth(G.tree, int64_t(cap), c.max_level);
+        if (!rc) rc = grid_array(b, &G.table, size_t(1) << (3 * G.tmax));
     }
     const size_t ng1 = size_t(n_grids) + 1;
     if (!rc) rc = dalloc_n(&b->meta, size_t(n_grids) * META, nullptr);
@@ -542,6 +579,7 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     if (!rc) rc = dalloc_n(&b->P, size_t(lmax + 1) * ng1, nullptr);
     if (!rc) rc = dalloc_n(&b->PN, ng1, nullptr);
     if (!rc) rc = dalloc_n(&b->PL, ng1, nullptr);
+    if (!rc) rc = dalloc_n(&b->PT, ng1, nullptr);
     if (!rc) rc = dalloc_n(&b->flag, size_t(total_cap), nullptr);
     if (!rc) rc = dalloc_n(&b->off, size_t(total_cap) + 1, nullptr);
     if (!rc) rc = dalloc_n(&b->stmp, scan_dev_tmp_elems(), nullptr);
@@ -739,6 +777,8 @@ int batch_grid(hg_batch_t b, int i, hg_grid_t *out)
     HG_CHECK(hipDeviceSynchronize());
     HG_CHECK(hipMemcpy(m, F.meta, sizeof m, hipMemcpyDeviceToHost));
     if (m[M_ERR]) return HG_E_LIMIT;
+    WalkGrid W;
+    HG_CHECK(hipMemcpy(&W, b->w32 + i, sizeof W, hipMemcpyDeviceToHost));
     hg_grid *g = new_grid(F.tree, F.D.lo, F.D.side);
     if (!g) return HG_E_OOM;
     g->borrowed = 1;
@@ -763,6 +803,8 @@ int batch_grid(hg_batch_t b, int i, hg_grid_t *out)
     g->rec64 = F.rec64;
     g->child = F.child;
     g->root_ref = Ref<uint32_t>::make(g->n_internal == 0, 0, 0);
+    g->table = const_cast<void *>(W.table);
+    g->tdep = W.tdep;
     *out = g;
     return HG_OK;
 }

@@ -118,6 +118,20 @@ __global__ void __launch_bounds__(LT)
     child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, fc, level, leaf_of, int_of);
 }
 
+template <typename R>
+__global__ void __launch_bounds__(LT)
+    k_locate_table(int tree, int tdep, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+                   const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
+                   R *__restrict__ table)
+{
+    const int64_t cells = int64_t(1) << (3 * tdep);
+    const int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
+    if (t >= cells) return;
+    const uint32_t m = (1u << tdep) - 1u;
+    const uint32_t c[3] = {uint32_t(t >> (2 * tdep)) & m, uint32_t(t >> tdep) & m, uint32_t(t) & m};
+    table[t] = encode<R>(table_node(tree, tdep, c, fc, level), fc, level, leaf_of, int_of);
+}
+
 inline unsigned blocks_for(int64_t n) { return unsigned((n + LT - 1) / LT); }
 
 }  // namespace
@@ -192,6 +206,23 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
         HG_CHECK(hipGetLastError());
     }
     g->root_ref = g->wide ? Ref<uint64_t>::make(I == 0, 0, 0) : Ref<uint32_t>::make(I == 0, 0, 0);
+    // locate table
+    g->tdep = table_depth(g->tree, L, g->max_level);
+    if (g->tdep > 0) {
+        const int64_t cells = int64_t(1) << (3 * g->tdep);
+        int trc = dalloc(&g->table, size_t(cells) * rsz, s);
+        if (trc) {
+            dfree(flag, s); dfree(rank, s); dfree(tmp, s);
+            return trc;
+        }
+        if (g->wide)
+            k_locate_table<uint64_t><<<blocks_for(cells), LT, 0, s>>>(
+                g->tree, g->tdep, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->table);
+        else
+            k_locate_table<uint32_t><<<blocks_for(cells), LT, 0, s>>>(
+                g->tree, g->tdep, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->table);
+        HG_CHECK(hipGetLastError());
+    }
     dfree(flag, s);
     dfree(rank, s);
     dfree(tmp, s);

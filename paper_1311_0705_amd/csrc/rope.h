@@ -117,4 +117,27 @@ __device__ inline double leaf_rho(int64_t l, int32_t n, const double *S, const d
     return rho_in ? rho_in[l] : S[n] / n_samples;
 }
 
+// Node holding the whole locate-table cell c (per-axis depth tdep): descend
+// from the root by the cell's index bits while the node is internal and above
+// the table level.
+__device__ inline int32_t table_node(int tree, int tdep, const uint32_t c[3],
+                                     const int32_t *__restrict__ fc, const uint8_t *__restrict__ level)
+{
+    const int lt = table_level(tree, tdep);
+    int32_t n = 0;
+    for (;;) {
+        const int32_t f = fc[n];
+        const int lv = level[n];
+        if (f < 0 || lv >= lt) return n;
+        if (tree == KD) {
+            const int b = lv % 3;
+            n = f + int32_t((c[b] >> (tdep - lv / 3 - 1)) & 1u);
+        } else {
+            int idx = 0;
+            for (int d = 0; d < 3; d++) idx |= int((c[d] >> (tdep - lv - 1)) & 1u) << d;
+            n = f + idx;
+        }
+    }
+}
+
 }  // namespace hg

@@ -89,6 +89,28 @@ struct Rec {
     static constexpr int RHO32 = sizeof(R) == 8 ? 56 : 24;
 };
 
+// Per-axis depth and cell width of a node at level lv.
+template <int TREE>
+__device__ __forceinline__ void level_geom(int lg, int lv, int dep[3], double w[3])
+{
+    if (TREE == OCT) {
+        const double ww = pow2(lg - lv);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            dep[d] = lv;
+            w[d] = ww;
+        }
+    } else {
+        const int q = (lv * 43691) >> 17;  // lv / 3 for 0 <= lv < 64
+        const int r = lv - 3 * q;
+        dep[0] = q + (r >= 1);
+        dep[1] = q + (r >= 2);
+        dep[2] = q;
+#pragma unroll
+        for (int d = 0; d < 3; d++) w[d] = pow2(lg - dep[d]);
+    }
+}
+
 // One descent step from the internal node ref (level lv, lower corner lo)
 // toward the point q: returns the child's reference and moves lo to the
 // child's corner.  Split planes are lo + half the node's width (exact: every
@@ -142,6 +164,46 @@ __device__ __forceinline__ R descend(const WalkGrid &G, const R *lds, uint32_t l
         ref = child_of<TREE, R>(G, lds, lds_n, ref, lv, lo, q, dirb, tie);
     }
     return ref_ok(G, ref) ? ref : Ref<R>::NUL;
+}
+
+// Node where the first descent toward q starts: the locate-table cell holding
+// q (chosen with the descent's rule for a point on a plane with no tie
+// context: the upper side unless the direction's component is negative),
+// its reference, level and lower corner; the root without a table.  The
+// descent from there takes the same decisions as one from the root: every
+// plane above the table level is a cell boundary, and the cell is picked by
+// exact comparisons with those planes.
+template <int TREE, typename R>
+__device__ __forceinline__ R start_node(const WalkGrid &G, const double q[3], int dirb, int &lv, double lo[3])
+{
+    if (G.tdep == 0) {
+        lv = 0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) lo[d] = G.lo[d];
+        return R(G.root);
+    }
+    const int T = 1 << G.tdep;
+    const double wc = pow2(G.lg - G.tdep);
+    const double scale = pow2(G.tdep - G.lg);
+    int c[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        int i = int(floor((q[d] - G.lo[d]) * scale));
+        i = i < 0 ? 0 : (i > T - 1 ? T - 1 : i);
+        // (q - lo) may round: settle the cell by exact comparisons with its planes
+        if (i > 0 && q[d] < G.lo[d] + double(i) * wc) i--;
+        else if (i < T - 1 && q[d] >= G.lo[d] + double(i + 1) * wc) i++;
+        if (i > 0 && q[d] == G.lo[d] + double(i) * wc && ((dirb >> (3 + d)) & 1)) i--;
+        c[d] = i;
+    }
+    const R ref = static_cast<const R *>(G.table)[(int64_t(c[0]) * T + c[1]) * T + c[2]];
+    lv = Ref<R>::level(ref);
+    int dep[3];
+    double w[3];
+    level_geom<TREE>(G.lg, lv, dep, w);
+#pragma unroll
+    for (int d = 0; d < 3; d++) lo[d] = G.lo[d] + double(c[d] >> (G.tdep - dep[d])) * w[d];
+    return ref;
 }
 
 __device__ __forceinline__ bool inside_closed(const WalkGrid &G, const double x[3])
@@ -221,7 +283,7 @@ struct Path {
 
 enum { PATH_WALK = 0, PATH_MISS = 1, PATH_BAD_DIR = 2 };
 
-template <int PREC, bool FILL, typename R>
+template <int TREE, int PREC, bool FILL, typename R>
 __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Path<PREC, R> &P)
 {
     double inv[3];
@@ -242,12 +304,9 @@ __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, i
         if (P.k[d] != 0.0 && !(fabs(P.k[d]) >= 1e-30)) P.force64 = true;
     }
     if (!clip_ray(G, P.p0, P.k, inv, P.s, P.p)) return PATH_MISS;
-#pragma unroll
-    for (int d = 0; d < 3; d++) P.lo[d] = G.lo[d];
-    P.lv = 0;
-    P.ref = R(G.root);
-    P.tie = TIE_NONE;
     P.dirb = dir_bits(P.k);
+    P.ref = start_node<TREE, R>(G, P.p, P.dirb, P.lv, P.lo);
+    P.tie = TIE_NONE;
     P.cnt = 0;
     P.steps = 0;
     P.tau64 = 0.0;
@@ -312,28 +371,6 @@ __device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC
     for (int j = 0; j < 3; j++) {
         const int64_t pos = last - j;
         if (j <= ph && pos >= P.base) store_one<PREC>(A, pos, P.sl[3 - j], P.sd[3 - j]);
-    }
-}
-
-// Per-axis depth and cell width of a node at level lv.
-template <int TREE>
-__device__ __forceinline__ void level_geom(int lg, int lv, int dep[3], double w[3])
-{
-    if (TREE == OCT) {
-        const double ww = pow2(lg - lv);
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            dep[d] = lv;
-            w[d] = ww;
-        }
-    } else {
-        const int q = (lv * 43691) >> 17;  // lv / 3 for 0 <= lv < 64
-        const int r = lv - 3 * q;
-        dep[0] = q + (r >= 1);
-        dep[1] = q + (r >= 2);
-        dep[2] = q;
-#pragma unroll
-        for (int d = 0; d < 3; d++) w[d] = pow2(lg - dep[d]);
     }
 }
 
@@ -489,7 +526,7 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
     const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (i >= A.n) return;
     Path<PREC, R> P;
-    const int why = init_path<PREC, FILL, R>(G, A, i, P);
+    const int why = init_path<TREE, PREC, FILL, R>(G, A, i, P);
     if (why != PATH_WALK) {
         finish_unwalked<PREC, FILL>(A, i, why);
         return;
@@ -559,7 +596,7 @@ __global__ void __launch_bounds__(BT)
                 const uint32_t rank = uint32_t(__popcll(wmask & below));
                 if (rank < avail) {
                     const int64_t r = int64_t(cnext) + rank;
-                    const int why = init_path<PREC, FILL, R>(G, A, r, P);
+                    const int why = init_path<TREE, PREC, FILL, R>(G, A, r, P);
                     if (why == PATH_WALK) ray = r;
                     else finish_unwalked<PREC, FILL>(A, r, why);
                 } else if (drained) {
@@ -702,7 +739,8 @@ __global__ void __launch_bounds__(BT)
                 const int64_t rank = __popcll(wmask & below);
                 if (rank < avail) {
                     const int64_t r = cnext + rank;
-                    const int why = init_path<PREC, FILL, uint32_t>(G, A, r, P);
+                    const int why = G.tree == KD ? init_path<KD, PREC, FILL, uint32_t>(G, A, r, P)
+                                                 : init_path<OCT, PREC, FILL, uint32_t>(G, A, r, P);
                     if (why == PATH_WALK) ray = r;
                     else finish_unwalked<PREC, FILL>(A, r, why);
                 } else if (drained && pc < 0) {
@@ -736,9 +774,10 @@ __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restr
         out[i] = -1;
         return;
     }
-    double lo[3] = {G.lo[0], G.lo[1], G.lo[2]};
+    double lo[3];
     int lv = 0;
-    const R r = descend<TREE, R>(G, nullptr, 0u, R(G.root), lv, lo, x, 0, TIE_NONE);
+    const R start = start_node<TREE, R>(G, x, 0, lv, lo);
+    const R r = descend<TREE, R>(G, nullptr, 0u, start, lv, lo, x, 0, TIE_NONE);
     out[i] = r == Ref<R>::NUL ? -2 : int32_t(Ref<R>::id(r));
 }
 
@@ -873,6 +912,8 @@ WalkGrid walk_grid(const hg_grid *g, int precision)
                     : (precision == HG_FP64 ? static_cast<const void *>(g->rec64)
                                             : static_cast<const void *>(g->rec32));
     G.child = g->child;
+    G.table = g->table;
+    G.tdep = g->table ? g->tdep : 0;
     return G;
 }
 
