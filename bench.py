@@ -25,7 +25,8 @@ Workloads (--workload):
   5            k-d tree of about 2e7 leaves on 97336 clustered clumps: the
                build timed end to end, then batches of 1e8 stellar-disk paths
                in tau-only mode.
-The launch shape of the walk is autotuned (grid_tune / batch_tune) before the
+The launch shape of the walk is autotuned (grid_tune, memoised per device and
+grid class in the tuning cache file; batch_tune for workload 4) before the
 timed region unless --no-tune is given.
 """
 from __future__ import annotations
@@ -214,7 +215,7 @@ def run_single(a, w):
     if not a.no_tune:
         m = min(n, 1_000_000)
         for prec in (hg.FP32_RECHECK, hg.FP64):
-            tuned[prec] = g.tune(o[:m], k[:m], precision=prec, mode=hg.RECORDS)
+            tuned[prec] = hg.tune_cached(g, o[:m], k[:m], precision=prec, mode=hg.RECORDS)
         log(f"tuned launch shapes: {tuned}")
     t32 = tuned.get(hg.FP32_RECHECK)
     g.free()
@@ -341,8 +342,10 @@ def run_c3(a, w):
     tuned = {}
     if not a.no_tune:
         for mode in (hg.TAU_ONLY, hg.RECORDS):
-            tuned[mode] = g.tune(o[:1_000_000], k[:1_000_000], precision=hg.FP32_RECHECK, mode=mode)
-        tuned["fp64_tau"] = g.tune(o[:1_000_000], k[:1_000_000], precision=hg.FP64, mode=hg.TAU_ONLY)
+            tuned[mode] = hg.tune_cached(g, o[:1_000_000], k[:1_000_000], precision=hg.FP32_RECHECK,
+                                         mode=mode)
+        tuned["fp64_tau"] = hg.tune_cached(g, o[:1_000_000], k[:1_000_000], precision=hg.FP64,
+                                           mode=hg.TAU_ONLY)
         log(f"tuned launch shapes: {tuned}")
     tt = tuned.get(hg.TAU_ONLY)
     res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt, count_rechecks=True)
@@ -589,7 +592,8 @@ def run_c5(a, w):
     log(f"build {build_s:.2f} s: {g.n_leaves} leaves")
     tt = None
     if not a.no_tune:
-        tt = g.tune(o[:1_000_000], k0[:1_000_000], precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY)
+        tt = hg.tune_cached(g, o[:1_000_000], k0[:1_000_000], precision=hg.FP32_RECHECK,
+                            mode=hg.TAU_ONLY)
         log(f"tuned {tt}")
     res = g.trace(o, k0, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt)
     batch_ms, xs = [], []
