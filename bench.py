@@ -66,7 +66,12 @@ B_X_COUNT64 = 28
 # 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE 1.0 GiB).
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
-TRAFFIC = {}
+TRAFFIC = {
+    "w2_fill": {"trace_sha256": "91deb3abfb7f56c9747bca9ecc5e775d00fb528d08210a0d7ce76be2361af0de",
+                "fetch_kib": 32923160.1, "write_kib": 10747658.3, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "91deb3abfb7f56c9747bca9ecc5e775d00fb528d08210a0d7ce76be2361af0de",
+                 "fetch_kib": 93905050.0, "write_kib": 6984369.7, "fetch_scale": 2.0, "write_scale": 1.0},
+}
 
 
 def parse():

@@ -94,6 +94,7 @@ struct WalkGrid {
     int lg;                        // log2 of the domain side
     double lo[3];
     double side;
+    double hi[3];                  // lo + side
     uint64_t root;                 // encoded reference of the root
     uint64_t n_leaves, n_internal; // bounds every reference is checked against
     const void *rec;               // walk records of the precision in use

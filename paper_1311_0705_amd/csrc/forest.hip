@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restri
         W.lg = G.lg;
         for (int d = 0; d < 3; d++) W.lo[d] = G.D.lo[d];
         W.side = G.D.side;
+        for (int d = 0; d < 3; d++) W.hi[d] = G.D.lo[d] + G.D.side;
         W.root = Ref<uint32_t>::make(I == 0, 0, 0);
         W.n_leaves = uint64_t(L);
         W.n_internal = uint64_t(I);

@@ -265,6 +265,7 @@ template <int PREC, typename R>
 struct Path {
     using DsT = typename std::conditional<PREC == HG_FP64, double, float>::type;
     double p0[3], k[3], ainv[3];
+    float ainv32[3];         // FP32 copies of ainv for the FP32 exit decision
     double s, p[3];          // path length so far and the current entry point
     double lo[3];            // lower corner of the current node
     R ref;                   // current node (leaf once the descent ends)
@@ -300,6 +301,7 @@ __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, i
     for (int d = 0; d < 3; d++) {
         inv[d] = 1.0 / P.k[d];
         P.ainv[d] = fabs(inv[d]);
+        P.ainv32[d] = float(P.ainv[d]);
         // The FP32 exit decision is used only where its error bound holds.
         if (P.k[d] != 0.0 && !(fabs(P.k[d]) >= 1e-30)) P.force64 = true;
     }
@@ -378,13 +380,15 @@ __device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC
 // the rope target of the exit face (left in P.ref for the next descent).  The
 // exit face depends only on the cell and the entry point, so it is decided
 // before the leaf's record is read; then only the rope of that face and the
-// density are loaded.
+// density are loaded.  Written with few branches: the end and error outcomes
+// are flags, and the state updates that only matter for a continuing path are
+// made unconditionally.
 template <int TREE, int PREC, bool FILL, typename R>
 __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC, R> &P,
                                      unsigned long long &rechecks)
 {
-    if (!ref_ok(G, P.ref)) return STEP_ERR;
-    const uint64_t id = Ref<R>::id(P.ref);
+    const bool ok = ref_ok(G, P.ref);
+    const uint64_t id = ok ? Ref<R>::id(P.ref) : 0u;
     int dep[3];
     double w[3], hi[3], E[3], t[3];
     int edge = 0;
@@ -392,10 +396,11 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     level_geom<TREE>(G.lg, P.lv, dep, w);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
+        const bool kp = (P.dirb >> d) & 1;
         hi[d] = lo[d] + w[d];
-        E[d] = P.k[d] > 0.0 ? hi[d] : lo[d];  // the face the path moves toward
+        E[d] = kp ? hi[d] : lo[d];  // the face the path moves toward
         // that face lies on the domain boundary
-        edge |= int(E[d] == (P.k[d] > 0.0 ? G.lo[d] + G.side : G.lo[d])) << d;
+        edge |= int(kp ? hi[d] == G.hi[d] : lo[d] == G.lo[d]) << d;
         // t = Delta |1/k|; a zero direction component gives +inf or NaN, and
         // neither ever wins the strict comparisons below
         t[d] = fabs(E[d] - P.p[d]) * P.ainv[d];
@@ -406,7 +411,7 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
         int i1 = -1;
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            const float t32 = float(fabs(E[d] - P.p[d])) * float(P.ainv[d]);
+            const float t32 = float(fabs(E[d] - P.p[d])) * P.ainv32[d];
             if (t32 < m1) {
                 m2 = m1;
                 m1 = t32;
@@ -431,7 +436,8 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
                 a = d;
             }
     }
-    if (a < 0) return STEP_ERR;
+    bool err = !ok || a < 0;
+    a = a < 0 ? 0 : a;
     const double t0 = in_reg(t[0]), t1 = in_reg(t[1]), t2 = in_reg(t[2]);
     const double ds = a == 0 ? t0 : (a == 1 ? t1 : t2);
     const bool up = (P.dirb >> a) & 1;
@@ -441,8 +447,9 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     const R nref = reinterpret_cast<const R *>(rec)[face];
     if (ds > 0.0) {
         if (FILL) {
-            if (P.cnt >= P.room) return STEP_ERR;  // the fill walk must repeat the counting walk
-            stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+            // the fill walk must repeat the counting walk
+            if (P.cnt < P.room) stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+            else err = true;
         } else if (PREC == HG_FP64) {
             const double rho64 = *reinterpret_cast<const double *>(rec + Rec<R, PREC>::RHO64);
             P.tau64 = P.tau64 + A.kappa * rho64 * ds;
@@ -456,7 +463,7 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
         P.cnt++;
     }
     // exit face on the domain boundary: the path ends
-    if ((edge >> a) & 1) return STEP_END;
+    const bool end = (edge >> a) & 1;
     // re-anchor the exit point on the crossed face
     P.s = P.s + ds;
     int onlo = 0, onhi = 0;
@@ -469,7 +476,7 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
         P.p[d] = q;
     }
     P.tie = a | (onlo << 2) | (onhi << 5);
-    if (nref == Ref<R>::NUL) return STEP_ERR;
+    err = err || (!end && nref == Ref<R>::NUL);
     // Lower corner of the rope target: the corner of the leaf, moved across
     // the exit face and aligned down to the target's cell size (exact).  The
     // target is never finer than the leaf across the face; along the exit axis
@@ -490,7 +497,7 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     for (int d = 0; d < 3; d++) P.lo[d] = nlo[d];
     P.lv = nlv;
     P.ref = nref;
-    return STEP_GO;
+    return err ? STEP_ERR : (end ? STEP_END : STEP_GO);
 }
 
 template <int PREC, bool FILL, typename R>
@@ -905,6 +912,7 @@ WalkGrid walk_grid(const hg_grid *g, int precision)
     int e = 0;
     frexp(g->side, &e);
     G.lg = e - 1;
+    for (int d = 0; d < 3; d++) G.hi[d] = g->lo[d] + g->side;
     G.root = g->root_ref;
     G.n_leaves = uint64_t(g->n_leaves);
     G.n_internal = uint64_t(g->n_internal);
