@@ -174,6 +174,28 @@ def compare_fp32r_fp64(r32, r64, records):
     return out
 
 
+def grid_quality(g, w, dev, n_pts=1_000_000, n_seg=100_000, seed=0x5EED):
+    """The grid-quality measures of Sect. 3.2 on this grid: the standard
+    deviations of rho_t - rho_g over uniform points and of tau_t - tau_g over
+    segments with uniform start and end points (16-node Gauss-Legendre per
+    cell piece for tau_t)."""
+    import torch
+
+    import paper_1311_0705_amd as hg
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(-1, 1, size=(n_pts, 3))
+    a = rng.uniform(-1, 1, size=(n_seg, 3))
+    b = rng.uniform(-1, 1, size=(n_seg, 3))
+    L = np.linalg.norm(b - a, axis=1)
+    k = (b - a) / L[:, None]
+    drho = g.density_diff(w.density, pts)
+    r = g.trace(a, k, precision=hg.FP64, mode=hg.RECORDS)
+    tg = g.segment_tau(r, L)
+    tt = g.true_tau(w.density, a, k, r, L)
+    return {"delta_rho": float(drho.std().item()), "delta_tau": float((tt - tg).std().item()),
+            "mean_tau_t": float(tt.mean().item()), "points": n_pts, "segments": n_seg}
+
+
 def cpu_cores():
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return max(1, min(int(cores), 64))
@@ -272,6 +294,7 @@ def run_single(a, w):
     if not a.no_compare:
         extra.update(compare_fp32r_fp64(r32, r64, True))
         extra.update(oracle_sample_check(g, w, o_np, k_np, r64, dev))
+        extra["grid_quality"] = grid_quality(g, w, dev)
     g.free()
 
     block = t32["block"] if t32 else 256
@@ -390,6 +413,7 @@ def run_c3(a, w):
         extra.update(compare_fp32r_fp64(res, t64, False))
         extra["records_first_batch"] = compare_fp32r_fp64(rec32, rec64, True)
         extra.update(oracle_sample_check(g, w, o_np[:nb], k_np[:nb], rec64, dev, m=2000))
+        extra["grid_quality"] = grid_quality(g, w, dev)
     tau_avg = float(np.mean(tau_ms))
     block = tt["block"] if tt else 256
     line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",

@@ -236,6 +236,48 @@ int grid_trace_batched(int n_grids, const hg_grid_t *grids, const double *const 
 int grid_tune(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
               hg_trace_opts *opts, float *best_ms, void *stream);
 
+/* ---- consumers of the walk: grid quality (Sect. 3.2), interaction point -- */
+/* First quality measure of Sect. 3.2: diff_out[i] = rho_t(x_i) - rho_g(x_i)
+ * for the n points (device double[n][3]), rho_t the density model dens
+ * (host description, copied; normally the one the grid was built from), rho_g
+ * the density of the leaf holding x_i (NaN outside the domain).  Its standard
+ * deviation over uniform points is the measure.  Asynchronous except for one
+ * synchronisation when dens has clumps.  Errors: HG_E_INVAL, HG_E_DOMAIN,
+ * HG_E_OOM, HG_E_HIP. */
+int grid_density_diff(hg_grid_t grid, const hg_density *dens, const double *points, int64_t n,
+                      double *diff_out, void *stream);
+
+/* Second quality measure of Sect. 3.2, grid side: tau_out[i] = the optical
+ * depth of path i from its start up to length s_max[i] (device arrays of n),
+ * i.e. the sum of kappa rho ds over its crossings with the last one cut at
+ * s_max[i].  records: the outputs of a records-mode grid_trace of these paths
+ * on this grid (offsets, leaf, ds; ds of the given precision); paths start at
+ * their origins when those lie inside the domain.  Asynchronous.  Errors:
+ * HG_E_INVAL, HG_E_HIP. */
+int grid_segment_tau(hg_grid_t grid, const hg_trace_out *records, int precision, int64_t n,
+                     const double *s_max, double kappa, double *tau_out, void *stream);
+
+/* Second quality measure of Sect. 3.2, true side: tau_out[i] = the integral
+ * of kappa rho_t along path i (origins / dirs as traced) up to length
+ * s_max[i], by m-node Gauss-Legendre quadrature (1 <= m <= 64) on every piece
+ * between consecutive cell boundaries of the path (from records, as above).
+ * Synchronises the stream once.  Errors: HG_E_INVAL, HG_E_DOMAIN, HG_E_OOM,
+ * HG_E_HIP. */
+int grid_true_tau(hg_grid_t grid, const hg_density *dens, const double *origins, const double *dirs,
+                  const hg_trace_out *records, int precision, int64_t n, const double *s_max,
+                  double kappa, int m, double *tau_out, void *stream);
+
+/* Monte Carlo interaction point along each path: the first crossing where
+ * the cumulative optical depth reaches tau_star[i] (e.g. -ln(1 - u) for a
+ * uniform u), leaf_out[i] its leaf id and s_out[i] the distance along the
+ * path where tau reaches tau_star[i] (tau grows linearly inside a cell); if
+ * the whole path stays below, leaf_out[i] = -1 and s_out[i] = its length.
+ * records as above; kappa > 0.  Asynchronous.  Errors: HG_E_INVAL,
+ * HG_E_HIP. */
+int grid_interact(hg_grid_t grid, const hg_trace_out *records, int precision, int64_t n,
+                  const double *tau_star, double kappa, int32_t *leaf_out, double *s_out,
+                  void *stream);
+
 /* Leaf containing each point (Sect. 2.3, top-down search).  points is device
  * double[n][3]; leaf_out device int32[n].  Cells are half-open [lo, hi) along
  * each axis except that the domain's upper faces belong to the last cells;

@@ -125,6 +125,15 @@ _SIGS = [
     ("batch_grid", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_void_p)]),
     ("batch_free", None, [C.c_void_p]),
     ("batch_tune", C.c_int, [C.c_void_p, C.POINTER(TraceOpts), C.POINTER(C.c_float), C.c_void_p]),
+    ("grid_density_diff", C.c_int, [C.c_void_p, C.POINTER(Density), C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_void_p]),
+    ("grid_segment_tau", C.c_int, [C.c_void_p, C.POINTER(TraceOut), C.c_int, C.c_int64, C.c_void_p,
+                                   C.c_double, C.c_void_p, C.c_void_p]),
+    ("grid_true_tau", C.c_int, [C.c_void_p, C.POINTER(Density), C.c_void_p, C.c_void_p,
+                                C.POINTER(TraceOut), C.c_int, C.c_int64, C.c_void_p, C.c_double,
+                                C.c_int, C.c_void_p, C.c_void_p]),
+    ("grid_interact", C.c_int, [C.c_void_p, C.POINTER(TraceOut), C.c_int, C.c_int64, C.c_void_p,
+                                C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("grid_tune", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(TraceOpts),
                             C.POINTER(C.c_float), C.c_void_p]),
     ("grid_strerror", C.c_char_p, [C.c_int]),
@@ -377,6 +386,66 @@ class Grid:
                                _stream(stream)), "grid_tune")
         return dict(block=opts.block, lds_bytes=opts.lds_bytes, chunk=opts.chunk,
                     refill_min=opts.refill_min, ms=float(ms.value))
+
+    # -- consumers of the walk (Sect. 3.2 measures, interaction point) -------
+    @staticmethod
+    def _records(res):
+        to = TraceOut()
+        to.offsets = res["offsets"].data_ptr()
+        to.leaf = res["leaf"].data_ptr()
+        to.ds = res["ds"].data_ptr()
+        to.capacity = res["leaf"].numel()
+        prec = FP64 if res["ds"].dtype == torch.float64 else FP32_RECHECK
+        return to, prec
+
+    def density_diff(self, density, points, stream=None) -> torch.Tensor:
+        """rho_t(x) - rho_g(x) at the points (grid_density_diff)."""
+        p = _dev_f64x3(points, self.device)
+        out = torch.empty(p.shape[0], dtype=torch.float64, device=self.device)
+        st, keep = _density_struct(density)
+        rc = lib().grid_density_diff(self._h, C.byref(st), _ptr(p), p.shape[0], _ptr(out),
+                                     _stream(stream))
+        del keep
+        _check(rc, "grid_density_diff")
+        return out
+
+    def segment_tau(self, res: dict, s_max, kappa: float = 1.0, stream=None) -> torch.Tensor:
+        """Grid optical depth of every traced path up to s_max (grid_segment_tau)."""
+        to, prec = self._records(res)
+        n = res["count"].numel()
+        sm = torch.as_tensor(s_max, dtype=torch.float64).to(self.device).contiguous()
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(lib().grid_segment_tau(self._h, C.byref(to), prec, n, _ptr(sm), kappa, _ptr(out),
+                                      _stream(stream)), "grid_segment_tau")
+        return out
+
+    def true_tau(self, density, origins, dirs, res: dict, s_max, kappa: float = 1.0, m: int = 16,
+                 stream=None) -> torch.Tensor:
+        """Gauss-Legendre integral of kappa rho_t along the traced paths up to
+        s_max (grid_true_tau)."""
+        to, prec = self._records(res)
+        o = _dev_f64x3(origins, self.device)
+        k = _dev_f64x3(dirs, self.device)
+        n = o.shape[0]
+        sm = torch.as_tensor(s_max, dtype=torch.float64).to(self.device).contiguous()
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        st, keep = _density_struct(density)
+        rc = lib().grid_true_tau(self._h, C.byref(st), _ptr(o), _ptr(k), C.byref(to), prec, n,
+                                 _ptr(sm), kappa, m, _ptr(out), _stream(stream))
+        del keep
+        _check(rc, "grid_true_tau")
+        return out
+
+    def interact(self, res: dict, tau_star, kappa: float = 1.0, stream=None):
+        """(leaf, s) of the interaction point of every traced path (grid_interact)."""
+        to, prec = self._records(res)
+        n = res["count"].numel()
+        ts = torch.as_tensor(tau_star, dtype=torch.float64).to(self.device).contiguous()
+        leaf = torch.empty(n, dtype=torch.int32, device=self.device)
+        s = torch.empty(n, dtype=torch.float64, device=self.device)
+        _check(lib().grid_interact(self._h, C.byref(to), prec, n, _ptr(ts), kappa, _ptr(leaf),
+                                   _ptr(s), _stream(stream)), "grid_interact")
+        return leaf, s
 
     # -- arrays ----------------------------------------------------------------
     def export(self) -> dict:
