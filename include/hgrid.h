@@ -278,6 +278,26 @@ int grid_interact(hg_grid_t grid, const hg_trace_out *records, int precision, in
                   const double *tau_star, double kappa, int32_t *leaf_out, double *s_out,
                   void *stream);
 
+/* ---- the optical-depth recipe of Sect. 4.1 ---------------------------- */
+/* tau_out[l] (device, n_leaves) = the optical depth of leaf l by Eq. (2) with
+ * its sampled mass M = S (V / n_samples) of Eq. (1) (n_samples as in the
+ * build).  Asynchronous.  Errors: HG_E_INVAL, HG_E_HIP. */
+int grid_leaf_tau(hg_grid_t grid, double kappa, int n_samples, double *tau_out, void *stream);
+
+/* *tau_max (host) = the leaf optical depth at position floor(fraction
+ * n_leaves) (0-based, at most n_leaves - 1) of the ascending order, found on
+ * the device by radix select.  Synchronises the stream.  Errors: HG_E_INVAL,
+ * HG_E_OOM, HG_E_HIP. */
+int grid_tau_percentile(hg_grid_t grid, double kappa, int n_samples, double fraction,
+                        double *tau_max, void *stream);
+
+/* The recipe of Sect. 4.1: build with criteria minus the optical-depth
+ * criterion, take tau_max = grid_tau_percentile(fraction) (0.9 in the paper),
+ * build again with criteria and that tau_max; *tau_max receives it.
+ * Synchronises the stream.  Errors as grid_build. */
+int grid_build_tau_recipe(const hg_density *dens, const hg_criteria *criteria, int tree_type,
+                          double fraction, void *stream, hg_grid_t *out, double *tau_max);
+
 /* Leaf containing each point (Sect. 2.3, top-down search).  points is device
  * double[n][3]; leaf_out device int32[n].  Cells are half-open [lo, hi) along
  * each axis except that the domain's upper faces belong to the last cells;

@@ -134,6 +134,11 @@ _SIGS = [
                                 C.c_int, C.c_void_p, C.c_void_p]),
     ("grid_interact", C.c_int, [C.c_void_p, C.POINTER(TraceOut), C.c_int, C.c_int64, C.c_void_p,
                                 C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grid_leaf_tau", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_void_p]),
+    ("grid_tau_percentile", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_double,
+                                      C.POINTER(C.c_double), C.c_void_p]),
+    ("grid_build_tau_recipe", C.c_int, [C.POINTER(Density), C.POINTER(Criteria), C.c_int, C.c_double,
+                                        C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_double)]),
     ("grid_tune", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(TraceOpts),
                             C.POINTER(C.c_float), C.c_void_p]),
     ("grid_strerror", C.c_char_p, [C.c_int]),
@@ -272,6 +277,36 @@ class Grid:
         del keep
         _check(rc, "grid_build")
         return cls(h, device)
+
+    @classmethod
+    def build_tau_recipe(cls, density, criteria, tree_type: int, fraction: float = 0.9, stream=None,
+                         device="cuda", max_nodes: int = 0):
+        """The optical-depth recipe of Sect. 4.1 (grid_build_tau_recipe):
+        returns (grid, tau_max)."""
+        s, keep = _density_struct(density)
+        c = _criteria_struct(criteria, max_nodes)
+        h = C.c_void_p()
+        tm = C.c_double()
+        with torch.cuda.device(device):
+            rc = lib().grid_build_tau_recipe(C.byref(s), C.byref(c), tree_type, fraction,
+                                             _stream(stream), C.byref(h), C.byref(tm))
+        del keep
+        _check(rc, "grid_build_tau_recipe")
+        return cls(h, device), float(tm.value)
+
+    def leaf_tau(self, kappa: float, n_samples: int = 64, stream=None) -> torch.Tensor:
+        """Eq. (2) per leaf from its sampled mass (grid_leaf_tau)."""
+        out = torch.empty(self.n_leaves, dtype=torch.float64, device=self.device)
+        _check(lib().grid_leaf_tau(self._h, kappa, n_samples, _ptr(out), _stream(stream)),
+               "grid_leaf_tau")
+        return out
+
+    def tau_percentile(self, kappa: float, n_samples: int = 64, fraction: float = 0.9,
+                       stream=None) -> float:
+        tm = C.c_double()
+        _check(lib().grid_tau_percentile(self._h, kappa, n_samples, fraction, C.byref(tm),
+                                         _stream(stream)), "grid_tau_percentile")
+        return float(tm.value)
 
     @classmethod
     def from_arrays(cls, tree_type: int, first_child, rho, lo=(-1.0, -1.0, -1.0), side=2.0,

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "libhgrid.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "build.hip", "forest.hip", "layout.hip", "quality.hip", "scan.hip", "trace.hip", "tune.hip"]
+SOURCES = ["api.hip", "build.hip", "forest.hip", "layout.hip", "quality.hip", "recipe.hip", "scan.hip", "trace.hip", "tune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HGRID_ARCH", "gfx950")

@@ -92,6 +92,17 @@ __device__ inline double read_lane_f64(double v, int lane)
     return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
 }
 
+// Optical depth of a node of sides w[3] with sampled sum S over n samples,
+// Eq. (2) with the node mass of Eq. (1): kappa M sqrt(a^2+b^2+c^2)/(abc),
+// M = S (V/N).
+__host__ __device__ inline double node_tau(double kappa, double S, const double w[3], int n_samples)
+{
+    const double V = w[0] * w[1] * w[2];
+    const double M = S * (V / double(n_samples));
+    const double diag = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    return kappa * M * diag / (w[0] * w[1] * w[2]);
+}
+
 struct NodeSample {
     double S, mn, mx;
     bool split;
@@ -138,8 +149,7 @@ __device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const Cri
     double V = w[0] * w[1] * w[2];
     double M = S * (V / double(C.n_samples));
     double delta = M / C.total_mass;
-    double diag = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    double tau = C.kappa * M * diag / (w[0] * w[1] * w[2]);
+    double tau = node_tau(C.kappa, S, w, C.n_samples);
     double q = mx > 0.0 ? (mx - mn) / mx : 0.0;
     bool sp;
     if (lv < C.min_level) sp = true;
