@@ -407,25 +407,21 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     }
     int a = -1;
     if (PREC == HG_FP32_RECHECK) {
-        float m1 = INFINITY, m2 = INFINITY;
-        int i1 = -1;
+        // smallest and second smallest exit time in FP32 (NaN counts as +inf);
+        // a tie between the two always goes to the FP64 decision below
+        float t32[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            const float t32 = float(fabs(E[d] - P.p[d])) * P.ainv32[d];
-            if (t32 < m1) {
-                m2 = m1;
-                m1 = t32;
-                i1 = d;
-            } else if (t32 < m2) {
-                m2 = t32;
-            }
+            const float v = float(fabs(E[d] - P.p[d])) * P.ainv32[d];
+            t32[d] = v == v ? v : INFINITY;
         }
+        const float m1 = fminf(fminf(t32[0], t32[1]), t32[2]);
+        const float m2 = __builtin_amdgcn_fmed3f(t32[0], t32[1], t32[2]);
+        const int i1 = t32[0] == m1 ? 0 : (t32[1] == m1 ? 1 : 2);
         const float hmin = float(w[0]);  // axis 0 is never coarser than the others
-        if (P.force64 || !(m2 - m1 >= 1e-5f * hmin)) {
-            rechecks++;
-            i1 = -1;
-        }
-        a = i1;
+        const bool recheck = P.force64 || !(m2 - m1 >= 1e-5f * hmin);
+        rechecks += recheck ? 1u : 0u;
+        a = recheck ? -1 : i1;
     }
     if (a < 0) {
         double tmin = INFINITY;
@@ -616,8 +612,10 @@ __global__ void __launch_bounds__(BT)
             if (!__ballot(!done)) break;
             continue;
         }
-        if (ray < 0) continue;
-        if (!Ref<R>::leaf(P.ref)) {
+        // One predicate per region (no nesting), so the path state needs no
+        // copies at region boundaries.
+        bool bad = false, fin = false;
+        if (ray >= 0 && !Ref<R>::leaf(P.ref)) {
             // LDS levels, then at most one global level this iteration
             for (;;) {
                 if (!ref_ok(G, P.ref) || P.lv >= 62) {
@@ -628,23 +626,18 @@ __global__ void __launch_bounds__(BT)
                 P.ref = child_of<TREE, R>(G, lds, lds_n, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
                 if (global || Ref<R>::leaf(P.ref)) break;
             }
-            if (P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref))) {
-                A.st->bad_ref = 1;
-                finish_path<PREC, FILL, R>(A, ray, P);
-                ray = -1;
-                continue;
-            }
+            bad = P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref));
         }
-        if (Ref<R>::leaf(P.ref)) {
+        if (ray >= 0 && !bad && Ref<R>::leaf(P.ref)) {
             const int r = cross<TREE, PREC, FILL, R>(G, A, P, rechecks);
-            if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
-                A.st->step_guard = 1;
-                finish_path<PREC, FILL, R>(A, ray, P);
-                ray = -1;
-            } else if (r == STEP_END) {
-                finish_path<PREC, FILL, R>(A, ray, P);
-                ray = -1;
-            }
+            const bool guard = r == STEP_ERR || ++P.steps >= STEP_GUARD;
+            if (guard) A.st->step_guard = 1;
+            fin = guard || r == STEP_END;
+        }
+        if (bad || fin) {
+            if (bad) A.st->bad_ref = 1;
+            finish_path<PREC, FILL, R>(A, ray, P);
+            ray = -1;
         }
     }
     if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
