@@ -128,6 +128,13 @@ typedef struct {
     int32_t refill_min; /* persistent walk: idle lanes that trigger a refill (1..64), 0 = library choice */
     int32_t lds_bytes;  /* persistent walk: bytes of top-level child references each block
                            stages in LDS (at most 65536); 0 = library choice (16384), < 0 = none */
+    int32_t passes;     /* grid_trace, records mode: 1 = one walk writing tau, counts and each
+                           path's first `slab` records into a per-path row, then a copy into the
+                           CSR slices (paths with more records are walked again); 2 = a counting
+                           walk, then a record-filling walk; 0 = library choice (1 when the rows
+                           of all paths fit in 32 GiB, else 2) */
+    int32_t slab;       /* records per path row of the one-pass mode (multiple of 4),
+                           0 = library choice (256) */
 } hg_trace_opts;
 
 /* Outputs of grid_trace; every array is a caller-owned device buffer.

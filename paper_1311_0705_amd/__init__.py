@@ -75,6 +75,7 @@ class TraceOpts(C.Structure):
         ("precision", C.c_int32), ("mode", C.c_int32), ("kappa", C.c_double),
         ("flags", C.c_int32), ("block", C.c_int32), ("persistent", C.c_int32),
         ("chunk", C.c_int32), ("refill_min", C.c_int32), ("lds_bytes", C.c_int32),
+        ("passes", C.c_int32), ("slab", C.c_int32),
     ]
 
 
@@ -351,7 +352,8 @@ class Grid:
               kappa: float = 1.0, capacity: Optional[int] = None, timing: bool = False,
               count_rechecks: bool = False, stream=None, out: Optional[dict] = None,
               block: int = 0, persistent: int = -1, chunk: int = 0, refill_min: int = 0,
-              lds_bytes: int = 0, tuned: Optional[dict] = None) -> dict:
+              lds_bytes: int = 0, tuned: Optional[dict] = None, passes: int = 0,
+              slab: int = 0) -> dict:
         """Trace paths; returns tau, count (and offsets, leaf, ds in records
         mode) as device tensors plus needed / rechecks / kernel_ms."""
         o = _dev_f64x3(origins, self.device)
@@ -373,6 +375,8 @@ class Grid:
         opts.chunk = chunk
         opts.refill_min = refill_min
         opts.lds_bytes = lds_bytes
+        opts.passes = passes
+        opts.slab = slab
         if tuned is not None:
             for key in ("block", "lds_bytes", "chunk", "refill_min"):
                 setattr(opts, key, int(tuned[key]))
@@ -407,7 +411,7 @@ class Grid:
         return res
 
     def tune(self, origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
-             kappa: float = 1.0, stream=None) -> dict:
+             kappa: float = 1.0, stream=None, passes: int = 0) -> dict:
         """Autotuned launch shape of the walk for these paths (grid_tune):
         dict(block, lds_bytes, chunk, refill_min, ms); pass it to trace(tuned=)."""
         o = _dev_f64x3(origins, self.device)
@@ -416,6 +420,7 @@ class Grid:
         opts.precision = precision
         opts.mode = mode
         opts.kappa = kappa
+        opts.passes = passes
         ms = C.c_float()
         _check(lib().grid_tune(self._h, _ptr(o), _ptr(k), o.shape[0], C.byref(opts), C.byref(ms),
                                _stream(stream)), "grid_tune")

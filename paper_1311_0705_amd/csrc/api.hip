@@ -277,6 +277,7 @@ static int check_trace_args(hg_grid_t g, const double *origins, const double *di
     if (opts->block != 0 && opts->block != 128 && opts->block != 256 && opts->block != 512)
         return HG_E_INVAL;
     if (opts->lds_bytes > 65536 || opts->chunk < 0 || opts->refill_min < 0) return HG_E_INVAL;
+    if (opts->passes < 0 || opts->passes > 2 || opts->slab < 0 || opts->slab > (1 << 20)) return HG_E_INVAL;
     const bool records = opts->mode == HG_RECORDS;
     if (n > 0 && (!origins || !dirs || !out->tau || !out->count)) return HG_E_INVAL;
     if (records && !out->offsets) return HG_E_INVAL;
@@ -413,6 +414,111 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     return rc;
 }
 
+static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
+                          const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev)
+{
+    const bool records = opts->mode == HG_RECORDS;
+    const bool timing = ev[0] != nullptr;
+    k_reset_status<<<1, 1, 0, s>>>(g->status);
+    if (timing) (void)hipEventRecord(ev[0], s);
+    int rc = launch_walk(g, origins, dirs, n, opts, out, WM_COUNT, s, nullptr);
+    if (timing) (void)hipEventRecord(ev[1], s);
+    TraceStatus st;
+    if (!rc) rc = read_status(g, &st, s);
+    if (!rc) out->rechecks = int64_t(st.rechecks);
+    if (rc || !records) return rc;
+    int64_t *tmp = nullptr;
+    rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
+    if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
+    if (timing) (void)hipEventRecord(ev[2], s);
+    int64_t needed = 0;
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(&needed, out->offsets + n, 8, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) rc = set_hip_error(e);
+    }
+    if (!rc) {
+        out->needed = needed;
+        if (needed > out->capacity) rc = HG_E_CAPACITY;
+    }
+    if (!rc && needed > 0) rc = launch_walk(g, origins, dirs, n, opts, out, WM_FILL, s, nullptr);
+    if (timing) (void)hipEventRecord(ev[3], s);
+    dfree(tmp, s);
+    if (!rc) rc = read_status(g, &st, s);
+    return rc;
+}
+
+// Records mode in one walk: tau, counts and each path's first `slab` records
+// into a row per path, the prefix sum of the counts, the rows copied into the
+// CSR slices, and a record-filling walk over the paths whose records did not
+// fit their row.
+static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n, int64_t slab,
+                          const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev)
+{
+    const bool timing = ev[0] != nullptr;
+    const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
+    int32_t *sleaf = nullptr;
+    void *sds = nullptr;
+    int64_t *tmp = nullptr, *list = nullptr;
+    unsigned long long *n_list = nullptr;
+    int rc = dalloc_n(&sleaf, size_t(n) * size_t(slab), s);
+    if (!rc) rc = dalloc(&sds, size_t(n) * size_t(slab) * dsz, s);
+    if (!rc) rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
+    if (!rc) rc = dalloc_n(&list, size_t(n), s);
+    if (!rc) rc = dalloc_n(&n_list, 1, s);
+    TraceStatus st;
+    struct {
+        int64_t needed;
+        unsigned long long n_over;
+    } h = {0, 0};
+    if (!rc) {
+        k_reset_status<<<1, 1, 0, s>>>(g->status);
+        hipError_t e = hipMemsetAsync(n_list, 0, sizeof *n_list, s);
+        if (e) rc = set_hip_error(e);
+    }
+    if (!rc) {
+        WalkArgs A = walk_args(g, origins, dirs, n, opts, out);
+        A.leaf = sleaf;
+        A.ds = sds;
+        A.slab = slab;
+        A.capacity = n * slab;
+        if (timing) (void)hipEventRecord(ev[0], s);
+        rc = launch_walk_args(g, A, opts, WM_SLAB, s);
+        if (timing) (void)hipEventRecord(ev[1], s);
+    }
+    if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
+    if (!rc) rc = launch_overflow_list(out->count, n, slab, list, n_list, s);
+    if (timing) (void)hipEventRecord(ev[2], s);
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(&h.needed, out->offsets + n, 8, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipMemcpyAsync(&h.n_over, n_list, sizeof h.n_over, hipMemcpyDeviceToHost, s);
+        if (e) rc = set_hip_error(e);
+    }
+    if (!rc) rc = read_status(g, &st, s);   // synchronises
+    if (!rc) {
+        out->rechecks = int64_t(st.rechecks);
+        out->needed = h.needed;
+        if (h.needed > out->capacity) rc = HG_E_CAPACITY;
+    }
+    if (!rc) rc = launch_slab_compact(sleaf, sds, slab, opts->precision, out->count, out->offsets, n,
+                                      out->leaf, out->ds, s);
+    if (!rc && h.n_over > 0) {
+        WalkArgs F = walk_args(g, origins, dirs, n, opts, out);
+        F.index = list;
+        F.n = int64_t(h.n_over);
+        rc = launch_walk_args(g, F, opts, WM_FILL, s);
+    }
+    if (timing) (void)hipEventRecord(ev[3], s);
+    if (!rc) rc = read_status(g, &st, s);
+    (void)hipStreamSynchronize(s);
+    dfree(sleaf, s);
+    dfree(sds, s);
+    dfree(tmp, s);
+    dfree(list, s);
+    dfree(n_list, s);
+    return rc;
+}
+
 int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
                const hg_trace_opts *opts, hg_trace_out *out, void *stream)
 {
@@ -423,77 +529,28 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     const bool records = opts->mode == HG_RECORDS;
     hipStream_t s = (hipStream_t)stream;
     const bool timing = (opts->flags & HG_FLAG_TIMING) != 0;
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[4] = {};
     for (int i = 0; i < 4; i++) out->kernel_ms[i] = 0.f;
-    if (timing)
-        for (int i = 0; i < 5; i++) HG_CHECK(hipEventCreate(&ev[i]));
-    auto cleanup = [&]() {
-        if (timing)
-            for (int i = 0; i < 5; i++)
-                if (ev[i]) (void)hipEventDestroy(ev[i]);
-    };
-    int rc = HG_OK;
     out->needed = 0;
     out->rechecks = 0;
-    k_reset_status<<<1, 1, 0, s>>>(g->status);
-    if (timing) (void)hipEventRecord(ev[0], s);
-    rc = launch_walk(g, origins, dirs, n, opts, out, false, s, nullptr);
-    if (timing) (void)hipEventRecord(ev[1], s);
-    TraceStatus st;
-    if (!rc) {
-        hipError_t e = hipMemcpyAsync(&st, g->status, sizeof st, hipMemcpyDeviceToHost, s);
-        if (!e) e = hipStreamSynchronize(s);
-        if (e) rc = set_hip_error(e);
-    }
-    if (!rc) {
-        out->rechecks = int64_t(st.rechecks);
-        if (st.bad_ref) rc = HG_E_FORMAT;
-        else if (st.bad_dir) rc = HG_E_DIR;
-        else if (st.step_guard) rc = HG_E_STEP;
-    }
-    int64_t *tmp = nullptr;
-    if (!rc && records) {
-        rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
-        if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
-        if (timing) (void)hipEventRecord(ev[2], s);
-        int64_t needed = 0;
-        if (!rc) {
-            hipError_t e = hipMemcpyAsync(&needed, out->offsets + n, 8, hipMemcpyDeviceToHost, s);
-            if (!e) e = hipStreamSynchronize(s);
-            if (e) rc = set_hip_error(e);
-        }
-        if (!rc) {
-            out->needed = needed;
-            if (needed > out->capacity) rc = HG_E_CAPACITY;
-        }
-        if (!rc && needed > 0) {
-            if (timing) (void)hipEventRecord(ev[3], s);
-            rc = launch_walk(g, origins, dirs, n, opts, out, true, s, nullptr);
-            if (timing) (void)hipEventRecord(ev[4], s);
-        }
-        dfree(tmp, s);
-        if (!rc) {
-            hipError_t e = hipStreamSynchronize(s);
-            if (e) rc = set_hip_error(e);
-        }
-        if (!rc) {
-            hipError_t e = hipMemcpyAsync(&st, g->status, sizeof st, hipMemcpyDeviceToHost, s);
-            if (!e) e = hipStreamSynchronize(s);
-            if (e) rc = set_hip_error(e);
-            else if (st.bad_ref) rc = HG_E_FORMAT;
-            else if (st.step_guard) rc = HG_E_STEP;
-        }
-    }
+    if (timing)
+        for (int i = 0; i < 4; i++) HG_CHECK(hipEventCreate(&ev[i]));
+    const int64_t slab = opts->slab > 0 ? (int64_t(opts->slab) + 3) / 4 * 4 : 256;
+    const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
+    const bool fits = n > 0 && double(n) * double(slab) * double(4 + dsz) <= double(int64_t(32) << 30);
+    const bool one_pass = records && opts->passes != 2 && fits;
+    const int rc = one_pass ? trace_one_pass(g, origins, dirs, n, slab, opts, out, s, ev)
+                            : trace_two_pass(g, origins, dirs, n, opts, out, s, ev);
     if (timing && (rc == HG_OK || rc == HG_E_CAPACITY)) {
         (void)hipEventSynchronize(ev[1]);
         (void)hipEventElapsedTime(&out->kernel_ms[0], ev[0], ev[1]);
         if (records) {
             (void)hipEventSynchronize(ev[2]);
             (void)hipEventElapsedTime(&out->kernel_ms[1], ev[1], ev[2]);
-            if (rc == HG_OK && out->needed > 0) {
-                (void)hipEventSynchronize(ev[4]);
-                (void)hipEventElapsedTime(&out->kernel_ms[2], ev[3], ev[4]);
-                (void)hipEventElapsedTime(&out->kernel_ms[3], ev[0], ev[4]);
+            if (rc == HG_OK) {
+                (void)hipEventSynchronize(ev[3]);
+                (void)hipEventElapsedTime(&out->kernel_ms[2], ev[2], ev[3]);
+                (void)hipEventElapsedTime(&out->kernel_ms[3], ev[0], ev[3]);
             } else {
                 (void)hipEventElapsedTime(&out->kernel_ms[3], ev[0], ev[2]);
             }
@@ -501,7 +558,9 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
             out->kernel_ms[3] = out->kernel_ms[0];
         }
     }
-    cleanup();
+    if (timing)
+        for (int i = 0; i < 4; i++)
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
     return rc;
 }
 

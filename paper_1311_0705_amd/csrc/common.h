@@ -148,7 +148,12 @@ struct WalkArgs {
     int64_t capacity;              // record slots behind leaf / ds
     TraceStatus *st;
     int count_rechecks;
+    int64_t slab;                  // slab walk: record slots per path row
+    const int64_t *index;          // paths to walk (NULL: 0 .. n-1)
 };
+
+// Walk modes (see trace.hip).
+enum { WM_COUNT = 0, WM_FILL = 1, WM_SLAB = 2 };
 
 // One entry of the batched walk's work queue: paths [start, end) of a grid.
 // One entry of the batched walk's work table: paths [start, end) of grid
@@ -258,9 +263,18 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
 // ---- trace / locate (trace.hip) --------------------------------------------
 WalkGrid walk_grid(const hg_grid *g, int precision);
 int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
-                const hg_trace_opts *opts, hg_trace_out *out, bool fill, hipStream_t s,
+                const hg_trace_opts *opts, hg_trace_out *out, int wm, hipStream_t s,
                 float *ms);
+int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *opts, int wm,
+                     hipStream_t s);
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s);
+// One-pass records mode: slab rows to CSR slices (paths whose count fits the
+// row), and the list of the other paths.
+int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision,
+                        const int32_t *count, const int64_t *offsets, int64_t n, int32_t *leaf, void *ds,
+                        hipStream_t s);
+int launch_overflow_list(const int32_t *count, int64_t n, int64_t slab, int64_t *list,
+                         unsigned long long *n_list, hipStream_t s);
 WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
                    const hg_trace_opts *opts, hg_trace_out *out);
 int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,

@@ -646,6 +646,8 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
         A.capacity = records ? outs[i].capacity : 0;
         A.st = b->status;
         A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
+        A.slab = 0;
+        A.index = nullptr;
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
     int rc = dalloc_n(&b->dA, size_t(b->ng), nullptr);

@@ -283,8 +283,12 @@ struct Path {
 };
 
 enum { PATH_WALK = 0, PATH_MISS = 1, PATH_BAD_DIR = 2 };
+// Walk modes: WM_COUNT (tau and counts; also the tau-only mode), WM_FILL
+// (records into the slices given by the offsets of a counting walk),
+// WM_SLAB (tau, counts and the first A.slab records of every path into a
+// fixed-size row per path, for the one-pass records mode).
 
-template <int TREE, int PREC, bool FILL, typename R>
+template <int TREE, int PREC, int WM, typename R>
 __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Path<PREC, R> &P)
 {
     double inv[3];
@@ -314,9 +318,12 @@ __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, i
     P.tau64 = 0.0;
     P.tau32 = 0.f;
     P.comp32 = 0.f;
-    if (FILL) {
+    if (WM == WM_FILL) {
         P.base = A.offsets[i];
         P.room = A.offsets[i + 1] - P.base;
+    } else if (WM == WM_SLAB) {
+        P.base = i * A.slab;
+        P.room = A.slab;
     }
     return PATH_WALK;
 }
@@ -366,7 +373,7 @@ template <int PREC, typename R>
 __device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC, R> &P)
 {
     if (P.cnt == 0) return;
-    const int64_t last = P.base + P.cnt - 1;
+    const int64_t last = P.base + (P.cnt < P.room ? P.cnt : P.room) - 1;
     const int ph = int(last & 3);
     if (ph == 3) return;
 #pragma unroll
@@ -383,7 +390,7 @@ __device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC
 // density are loaded.  Written with few branches: the end and error outcomes
 // are flags, and the state updates that only matter for a continuing path are
 // made unconditionally.
-template <int TREE, int PREC, bool FILL, typename R>
+template <int TREE, int PREC, int WM, typename R>
 __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC, R> &P,
                                      unsigned long long &rechecks)
 {
@@ -442,10 +449,15 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     const char *rec = static_cast<const char *>(G.rec) + id * Rec<R, PREC>::STRIDE;
     const R nref = reinterpret_cast<const R *>(rec)[face];
     if (ds > 0.0) {
-        if (FILL) {
+        if (WM == WM_FILL) {
             // the fill walk must repeat the counting walk
             if (P.cnt < P.room) stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
             else err = true;
+        } else if (WM == WM_SLAB && P.cnt < P.room) {
+            // records beyond the slab are dropped; such paths are walked again
+            stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+        }
+        if (WM == WM_FILL) {
         } else if (PREC == HG_FP64) {
             const double rho64 = *reinterpret_cast<const double *>(rec + Rec<R, PREC>::RHO64);
             P.tau64 = P.tau64 + A.kappa * rho64 * ds;
@@ -496,23 +508,24 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     return err ? STEP_ERR : (end ? STEP_END : STEP_GO);
 }
 
-template <int PREC, bool FILL, typename R>
+template <int PREC, int WM, typename R>
 __device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Path<PREC, R> &P)
 {
-    if (FILL) {
+    if (WM == WM_FILL) {
         flush_records<PREC, R>(A, P);
         if (P.cnt != P.room) A.st->step_guard = 1;
         return;
     }
+    if (WM == WM_SLAB) flush_records<PREC, R>(A, P);
     A.count[i] = P.cnt;
     if (PREC == HG_FP64) A.tau[i] = P.tau64;
     else A.tau[i] = double(P.tau32) - double(P.comp32);
 }
 
-template <int PREC, bool FILL>
+template <int PREC, int WM>
 __device__ __forceinline__ void finish_unwalked(const WalkArgs &A, int64_t i, int why)
 {
-    if (FILL) return;
+    if (WM == WM_FILL) return;
     A.count[i] = 0;
     if (why == PATH_BAD_DIR) {
         A.tau[i] = __longlong_as_double(0x7ff8000000000000ll);
@@ -523,15 +536,16 @@ __device__ __forceinline__ void finish_unwalked(const WalkArgs &A, int64_t i, in
 }
 
 // One lane per path, the whole walk in one loop.
-template <int TREE, int PREC, bool FILL, typename R>
+template <int TREE, int PREC, int WM, typename R>
 __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 {
-    const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
-    if (i >= A.n) return;
+    const int64_t q = int64_t(blockIdx.x) * TB + threadIdx.x;
+    if (q >= A.n) return;
+    const int64_t i = A.index ? A.index[q] : q;
     Path<PREC, R> P;
-    const int why = init_path<TREE, PREC, FILL, R>(G, A, i, P);
+    const int why = init_path<TREE, PREC, WM, R>(G, A, i, P);
     if (why != PATH_WALK) {
-        finish_unwalked<PREC, FILL>(A, i, why);
+        finish_unwalked<PREC, WM>(A, i, why);
         return;
     }
     unsigned long long rechecks = 0;
@@ -541,15 +555,15 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
             A.st->bad_ref = 1;
             break;
         }
-        const int r = cross<TREE, PREC, FILL, R>(G, A, P, rechecks);
+        const int r = cross<TREE, PREC, WM, R>(G, A, P, rechecks);
         if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
             A.st->step_guard = 1;
             break;
         }
         if (r == STEP_END) break;
     }
-    finish_path<PREC, FILL, R>(A, i, P);
-    if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
+    finish_path<PREC, WM, R>(A, i, P);
+    if (!(WM == WM_FILL) && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
 // Persistent walk: each wavefront keeps its lanes busy by handing new paths
@@ -559,7 +573,7 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 // path set-up and the atomic round trip are amortised over many paths.  Each
 // iteration a busy lane performs one dependent global access: a descent step
 // (the first levels of every descent come from LDS) or a crossing.
-template <int TREE, int PREC, bool FILL, typename R, int BT>
+template <int TREE, int PREC, int WM, typename R, int BT>
 __global__ void __launch_bounds__(BT)
     k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min)
 {
@@ -598,10 +612,11 @@ __global__ void __launch_bounds__(BT)
             if (want) {
                 const uint32_t rank = uint32_t(__popcll(wmask & below));
                 if (rank < avail) {
-                    const int64_t r = int64_t(cnext) + rank;
-                    const int why = init_path<TREE, PREC, FILL, R>(G, A, r, P);
+                    const int64_t q = int64_t(cnext) + rank;
+                    const int64_t r = A.index ? A.index[q] : q;
+                    const int why = init_path<TREE, PREC, WM, R>(G, A, r, P);
                     if (why == PATH_WALK) ray = r;
-                    else finish_unwalked<PREC, FILL>(A, r, why);
+                    else finish_unwalked<PREC, WM>(A, r, why);
                 } else if (drained) {
                     done = true;
                 }
@@ -629,23 +644,23 @@ __global__ void __launch_bounds__(BT)
             bad = P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref));
         }
         if (ray >= 0 && !bad && Ref<R>::leaf(P.ref)) {
-            const int r = cross<TREE, PREC, FILL, R>(G, A, P, rechecks);
+            const int r = cross<TREE, PREC, WM, R>(G, A, P, rechecks);
             const bool guard = r == STEP_ERR || ++P.steps >= STEP_GUARD;
             if (guard) A.st->step_guard = 1;
             fin = guard || r == STEP_END;
         }
         if (bad || fin) {
             if (bad) A.st->bad_ref = 1;
-            finish_path<PREC, FILL, R>(A, ray, P);
+            finish_path<PREC, WM, R>(A, ray, P);
             ray = -1;
         }
     }
-    if (!FILL && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
+    if (!(WM == WM_FILL) && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
 // One step of a busy lane in the batched walk: at most one global descent
 // level, or one crossing.  Returns false when the path ended (or failed).
-template <int TREE, int PREC, bool FILL>
+template <int TREE, int PREC, int WM>
 __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &A,
                                              Path<PREC, uint32_t> &P, int64_t ray,
                                              unsigned long long &rechecks)
@@ -653,25 +668,25 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
     if (!Ref<uint32_t>::leaf(P.ref)) {
         if (!ref_ok(G, P.ref) || P.lv >= 62) {
             A.st->bad_ref = 1;
-            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            finish_path<PREC, WM, uint32_t>(A, ray, P);
             return false;
         }
         P.ref = child_of<TREE, uint32_t>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
         if (Ref<uint32_t>::leaf(P.ref) && !ref_ok(G, P.ref)) {
             A.st->bad_ref = 1;
-            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            finish_path<PREC, WM, uint32_t>(A, ray, P);
             return false;
         }
     }
     if (Ref<uint32_t>::leaf(P.ref)) {
-        const int r = cross<TREE, PREC, FILL, uint32_t>(G, A, P, rechecks);
+        const int r = cross<TREE, PREC, WM, uint32_t>(G, A, P, rechecks);
         if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
             A.st->step_guard = 1;
-            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            finish_path<PREC, WM, uint32_t>(A, ray, P);
             return false;
         }
         if (r == STEP_END) {
-            finish_path<PREC, FILL, uint32_t>(A, ray, P);
+            finish_path<PREC, WM, uint32_t>(A, ray, P);
             return false;
         }
     }
@@ -684,7 +699,7 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
 // refilling lanes from the chunk.  Before taking up a chunk of another grid it
 // lets its lanes finish their paths.  Octree and k-d grids mix freely: the
 // tree type is a wavefront-uniform branch.
-template <int PREC, bool FILL, int BT>
+template <int PREC, int WM, int BT>
 __global__ void __launch_bounds__(BT)
     k_walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                    const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min,
@@ -727,7 +742,7 @@ __global__ void __launch_bounds__(BT)
                         cend = chunks[pc].end;
                         pc = -1;
                         // records of a grid that does not fit are not written
-                        if (FILL && A.offsets[A.n] > A.capacity) {
+                        if ((WM == WM_FILL) && A.offsets[A.n] > A.capacity) {
                             if (lane == 0) st->cap_overflow = 1;
                             cnext = cend;
                         }
@@ -739,10 +754,10 @@ __global__ void __launch_bounds__(BT)
                 const int64_t rank = __popcll(wmask & below);
                 if (rank < avail) {
                     const int64_t r = cnext + rank;
-                    const int why = G.tree == KD ? init_path<KD, PREC, FILL, uint32_t>(G, A, r, P)
-                                                 : init_path<OCT, PREC, FILL, uint32_t>(G, A, r, P);
+                    const int why = G.tree == KD ? init_path<KD, PREC, WM, uint32_t>(G, A, r, P)
+                                                 : init_path<OCT, PREC, WM, uint32_t>(G, A, r, P);
                     if (why == PATH_WALK) ray = r;
-                    else finish_unwalked<PREC, FILL>(A, r, why);
+                    else finish_unwalked<PREC, WM>(A, r, why);
                 } else if (drained && pc < 0) {
                     done = true;
                 }
@@ -754,11 +769,11 @@ __global__ void __launch_bounds__(BT)
             continue;
         }
         if (ray < 0) continue;
-        const bool alive = G.tree == KD ? batched_step<KD, PREC, FILL>(G, A, P, ray, rechecks)
-                                        : batched_step<OCT, PREC, FILL>(G, A, P, ray, rechecks);
+        const bool alive = G.tree == KD ? batched_step<KD, PREC, WM>(G, A, P, ray, rechecks)
+                                        : batched_step<OCT, PREC, WM>(G, A, P, ray, rechecks);
         if (!alive) ray = -1;
     }
-    if (!FILL && rechecks && A.count_rechecks) atomicAdd(&st->rechecks, rechecks);
+    if (!(WM == WM_FILL) && rechecks && A.count_rechecks) atomicAdd(&st->rechecks, rechecks);
 }
 
 template <int TREE, typename R>
@@ -783,11 +798,50 @@ __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restr
 
 __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
 
+// One-pass records mode: copy every path's row of the slab (its first
+// `slab` records) to its slice of the CSR arrays; one wavefront per path,
+// paths with more records than the row holds are left to the fill walk.
+template <typename DsT>
+__global__ void __launch_bounds__(TB)
+    k_slab_compact(const int32_t *__restrict__ sleaf, const DsT *__restrict__ sds, int64_t slab,
+                   const int32_t *__restrict__ count, const int64_t *__restrict__ offsets, int64_t n,
+                   int32_t *__restrict__ leaf, DsT *__restrict__ ds)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = int64_t(gridDim.x) * (TB / 64);
+    for (int64_t i = (int64_t(blockIdx.x) * TB + threadIdx.x) >> 6; i < n; i += nw) {
+        const int64_t c = count[i];
+        if (c > slab) continue;
+        const int64_t src = i * slab, dst = offsets[i];
+        for (int64_t j = lane; j < c; j += 64) {
+            leaf[dst + j] = sleaf[src + j];
+            ds[dst + j] = sds[src + j];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(TB)
+    k_overflow_list(const int32_t *__restrict__ count, int64_t n, int64_t slab, int64_t *__restrict__ list,
+                    unsigned long long *__restrict__ n_list)
+{
+    const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
+    const bool over = i < n && count[i] > slab;
+    // one atomic per wavefront
+    const uint64_t m = __ballot(over);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == first) base = atomicAdd(n_list, (unsigned long long)__popcll(m));
+    base = __shfl(base, first, 64);
+    if (over) list[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+}
+
 constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
 
 // Occupancy-derived persistent grid size, cached per kernel instance.
-template <int TREE, int PREC, bool FILL, typename R, int BT>
+template <int TREE, int PREC, int WM, typename R, int BT>
 int persistent_blocks(size_t lds, unsigned *blocks)
 {
     static int occ = -1, cus = 0;
@@ -797,14 +851,14 @@ int persistent_blocks(size_t lds, unsigned *blocks)
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, FILL, R, BT>), BT, lds));
+            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, WM, R, BT>), BT, lds));
         occ_lds = lds;
     }
     *blocks = unsigned(std::max(1, cus) * std::max(1, occ));
     return HG_OK;
 }
 
-template <int TREE, int PREC, bool FILL, typename R, int BT>
+template <int TREE, int PREC, int WM, typename R, int BT>
 int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts *o, hipStream_t s)
 {
     const int nc = TREE == OCT ? 8 : 2;
@@ -812,57 +866,69 @@ int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts 
     const uint32_t lds_n = uint32_t(std::min<uint64_t>(G.n_internal, want / (sizeof(R) * size_t(nc))));
     const size_t lds = size_t(lds_n) * nc * sizeof(R);
     unsigned blocks = 0;
-    int rc = persistent_blocks<TREE, PREC, FILL, R, BT>(lds, &blocks);
+    int rc = persistent_blocks<TREE, PREC, WM, R, BT>(lds, &blocks);
     if (rc) return rc;
     const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 128u;
     const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : 16;
     for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
         WalkArgs B = A;
         B.n = std::min(PERSIST_CHUNK, A.n - start);
-        B.O = A.O + 3 * start;
-        B.K = A.K + 3 * start;
-        B.tau = A.tau ? A.tau + start : nullptr;
-        B.count = A.count ? A.count + start : nullptr;
-        B.offsets = A.offsets ? A.offsets + start : nullptr;
+        if (A.index) {
+            B.index = A.index + start;
+        } else {
+            B.O = A.O + 3 * start;
+            B.K = A.K + 3 * start;
+            B.tau = A.tau ? A.tau + start : nullptr;
+            B.count = A.count ? A.count + start : nullptr;
+            B.offsets = A.offsets ? A.offsets + start : nullptr;
+        }
         k_reset_counter<<<1, 1, 0, s>>>(A.st);
         HG_CHECK(hipGetLastError());
-        k_walk_persistent<TREE, PREC, FILL, R, BT><<<dim3(blocks), dim3(BT), lds, s>>>(G, B, lds_n, chunk,
+        k_walk_persistent<TREE, PREC, WM, R, BT><<<dim3(blocks), dim3(BT), lds, s>>>(G, B, lds_n, chunk,
                                                                                          refill_min);
         HG_CHECK(hipGetLastError());
     }
     return HG_OK;
 }
 
-template <int TREE, int PREC, bool FILL, typename R>
+template <int TREE, int PREC, int WM, typename R>
 int launch_t(const WalkGrid &G, const WalkArgs &A, int persistent, const hg_trace_opts *o,
              hipStream_t s)
 {
     if (A.n == 0) return HG_OK;
     if (!persistent) {
         const int64_t nb = (A.n + TB - 1) / TB;
-        k_walk<TREE, PREC, FILL, R><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, A);
+        k_walk<TREE, PREC, WM, R><<<dim3(unsigned(nb)), dim3(TB), 0, s>>>(G, A);
         HG_CHECK(hipGetLastError());
         return HG_OK;
     }
     switch (o->block) {
-    case 128: return launch_persistent<TREE, PREC, FILL, R, 128>(G, A, o, s);
-    case 512: return launch_persistent<TREE, PREC, FILL, R, 512>(G, A, o, s);
-    default: return launch_persistent<TREE, PREC, FILL, R, 256>(G, A, o, s);
+    case 128: return launch_persistent<TREE, PREC, WM, R, 128>(G, A, o, s);
+    case 512: return launch_persistent<TREE, PREC, WM, R, 512>(G, A, o, s);
+    default: return launch_persistent<TREE, PREC, WM, R, 256>(G, A, o, s);
+    }
+}
+
+template <int TREE, int PREC, typename R>
+int dispatch_mode(const WalkGrid &G, const WalkArgs &A, int wm, int persistent, const hg_trace_opts *o,
+                  hipStream_t s)
+{
+    switch (wm) {
+    case WM_FILL: return launch_t<TREE, PREC, WM_FILL, R>(G, A, persistent, o, s);
+    case WM_SLAB: return launch_t<TREE, PREC, WM_SLAB, R>(G, A, persistent, o, s);
+    default: return launch_t<TREE, PREC, WM_COUNT, R>(G, A, persistent, o, s);
     }
 }
 
 template <int TREE, typename R>
-int dispatch_walk(const WalkGrid &G, const WalkArgs &A, int prec, bool fill, int persistent,
+int dispatch_walk(const WalkGrid &G, const WalkArgs &A, int prec, int wm, int persistent,
                   const hg_trace_opts *o, hipStream_t s)
 {
-    if (prec == HG_FP64)
-        return fill ? launch_t<TREE, HG_FP64, true, R>(G, A, persistent, o, s)
-                    : launch_t<TREE, HG_FP64, false, R>(G, A, persistent, o, s);
-    return fill ? launch_t<TREE, HG_FP32_RECHECK, true, R>(G, A, persistent, o, s)
-                : launch_t<TREE, HG_FP32_RECHECK, false, R>(G, A, persistent, o, s);
+    if (prec == HG_FP64) return dispatch_mode<TREE, HG_FP64, R>(G, A, wm, persistent, o, s);
+    return dispatch_mode<TREE, HG_FP32_RECHECK, R>(G, A, wm, persistent, o, s);
 }
 
-template <int PREC, bool FILL, int BT>
+template <int PREC, int WM, int BT>
 int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
                      int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
 {
@@ -872,25 +938,25 @@ int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChu
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, FILL, BT>), BT, 0));
+            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, WM, BT>), BT, 0));
     }
     const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
     k_reset_counter<<<1, 1, 0, s>>>(st);
     HG_CHECK(hipGetLastError());
-    k_walk_batched<PREC, FILL, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
+    k_walk_batched<PREC, WM, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
                                                                      refill_min, st);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }
 
-template <int PREC, bool FILL>
+template <int PREC, int WM>
 int launch_batched_b(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
                      int n_chunks, int block, int refill_min, TraceStatus *st, hipStream_t s)
 {
     switch (block) {
-    case 128: return launch_batched_t<PREC, FILL, 128>(grids, args, chunks, n_chunks, refill_min, st, s);
-    case 512: return launch_batched_t<PREC, FILL, 512>(grids, args, chunks, n_chunks, refill_min, st, s);
-    default: return launch_batched_t<PREC, FILL, 256>(grids, args, chunks, n_chunks, refill_min, st, s);
+    case 128: return launch_batched_t<PREC, WM, 128>(grids, args, chunks, n_chunks, refill_min, st, s);
+    case 512: return launch_batched_t<PREC, WM, 512>(grids, args, chunks, n_chunks, refill_min, st, s);
+    default: return launch_batched_t<PREC, WM, 256>(grids, args, chunks, n_chunks, refill_min, st, s);
     }
 }
 
@@ -918,21 +984,26 @@ WalkGrid walk_grid(const hg_grid *g, int precision)
     return G;
 }
 
-int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
-                const hg_trace_opts *opts, hg_trace_out *out, bool fill, hipStream_t s, float *ms)
+int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *opts, int wm,
+                     hipStream_t s)
 {
-    (void)ms;
-    // bit 0: persistent counting / tau-only walk, bit 1: persistent fill walk
+    // bit 0: persistent counting / tau-only / slab walk, bit 1: persistent fill walk
     const int mode = opts->persistent < 0 ? 3 : opts->persistent;
-    const int persistent = fill ? (mode >> 1) & 1 : mode & 1;
+    const int persistent = wm == WM_FILL ? (mode >> 1) & 1 : mode & 1;
     const WalkGrid G = walk_grid(g, opts->precision);
-    const WalkArgs A = walk_args(g, o, k, n, opts, out);
     const int prec = opts->precision;
     if (g->tree == KD)
-        return g->wide ? dispatch_walk<KD, uint64_t>(G, A, prec, fill, persistent, opts, s)
-                       : dispatch_walk<KD, uint32_t>(G, A, prec, fill, persistent, opts, s);
-    return g->wide ? dispatch_walk<OCT, uint64_t>(G, A, prec, fill, persistent, opts, s)
-                   : dispatch_walk<OCT, uint32_t>(G, A, prec, fill, persistent, opts, s);
+        return g->wide ? dispatch_walk<KD, uint64_t>(G, A, prec, wm, persistent, opts, s)
+                       : dispatch_walk<KD, uint32_t>(G, A, prec, wm, persistent, opts, s);
+    return g->wide ? dispatch_walk<OCT, uint64_t>(G, A, prec, wm, persistent, opts, s)
+                   : dispatch_walk<OCT, uint32_t>(G, A, prec, wm, persistent, opts, s);
+}
+
+int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
+                const hg_trace_opts *opts, hg_trace_out *out, int wm, hipStream_t s, float *ms)
+{
+    (void)ms;
+    return launch_walk_args(g, walk_args(g, o, k, n, opts, out), opts, wm, s);
 }
 
 WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
@@ -951,6 +1022,8 @@ WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n
     A.capacity = out->capacity;
     A.st = g->status;
     A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
+    A.slab = 0;
+    A.index = nullptr;
     return A;
 }
 
@@ -961,10 +1034,35 @@ int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk
     const int refill_min = opts->refill_min > 0 ? std::min(opts->refill_min, 64) : 16;
     const int b = opts->block;
     if (opts->precision == HG_FP64)
-        return fill ? launch_batched_b<HG_FP64, true>(grids, args, chunks, n_chunks, b, refill_min, st, s)
-                    : launch_batched_b<HG_FP64, false>(grids, args, chunks, n_chunks, b, refill_min, st, s);
-    return fill ? launch_batched_b<HG_FP32_RECHECK, true>(grids, args, chunks, n_chunks, b, refill_min, st, s)
-                : launch_batched_b<HG_FP32_RECHECK, false>(grids, args, chunks, n_chunks, b, refill_min, st, s);
+        return fill ? launch_batched_b<HG_FP64, WM_FILL>(grids, args, chunks, n_chunks, b, refill_min, st, s)
+                    : launch_batched_b<HG_FP64, WM_COUNT>(grids, args, chunks, n_chunks, b, refill_min, st, s);
+    return fill ? launch_batched_b<HG_FP32_RECHECK, WM_FILL>(grids, args, chunks, n_chunks, b, refill_min, st, s)
+                : launch_batched_b<HG_FP32_RECHECK, WM_COUNT>(grids, args, chunks, n_chunks, b, refill_min, st, s);
+}
+
+int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision,
+                        const int32_t *count, const int64_t *offsets, int64_t n, int32_t *leaf, void *ds,
+                        hipStream_t s)
+{
+    if (n == 0) return HG_OK;
+    const unsigned blocks = unsigned(std::min<int64_t>((n + 3) / 4, 65536));
+    if (precision == HG_FP64)
+        k_slab_compact<double><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const double *)sds, slab,
+                                                     count, offsets, n, leaf, (double *)ds);
+    else
+        k_slab_compact<float><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const float *)sds, slab,
+                                                    count, offsets, n, leaf, (float *)ds);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
+}
+
+int launch_overflow_list(const int32_t *count, int64_t n, int64_t slab, int64_t *list,
+                         unsigned long long *n_list, hipStream_t s)
+{
+    if (n == 0) return HG_OK;
+    k_overflow_list<<<unsigned((n + TB - 1) / TB), TB, 0, s>>>(count, n, slab, list, n_list);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
 }
 
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s)

@@ -134,13 +134,21 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     if (!rc) rc = dalloc_n(&out.offsets, size_t(n) + 1, s);
     if (!rc) rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
     int64_t needed = 0;
+    // records mode: the one-pass walk (as grid_trace runs it) unless two passes are asked for
+    const bool slab_mode = records && opts->passes != 2;
+    const int64_t slab = opts->slab > 0 ? (int64_t(opts->slab) + 3) / 4 * 4 : 256;
+    const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
+    int32_t *sleaf = nullptr;
+    void *sds = nullptr;
+    if (!rc && slab_mode) rc = dalloc_n(&sleaf, size_t(n) * size_t(slab), s);
+    if (!rc && slab_mode) rc = dalloc(&sds, size_t(n) * size_t(slab) * dsz, s);
     if (!rc) {
         hipError_t e = hipMemsetAsync(g->status, 0, sizeof(TraceStatus), s);
         if (e) rc = set_hip_error(e);
     }
-    if (!rc) rc = launch_walk(g, origins, dirs, n, &base, &out, false, s, nullptr);
+    if (!rc) rc = launch_walk(g, origins, dirs, n, &base, &out, WM_COUNT, s, nullptr);
     if (!rc) rc = status_error(g, s);
-    if (!rc && records) {
+    if (!rc && records && !slab_mode) {
         rc = scan_i32_to_i64(out.count, out.offsets, n, tmp, s);
         if (!rc) {
             hipError_t e = hipMemcpyAsync(&needed, out.offsets + n, 8, hipMemcpyDeviceToHost, s);
@@ -155,11 +163,19 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     Events ev;
     if (!rc) rc = ev.create();
     if (!rc) {
+        WalkArgs SA = walk_args(g, origins, dirs, n, &base, &out);
+        SA.leaf = sleaf;
+        SA.ds = sds;
+        SA.slab = slab;
         auto eval = [&](const hg_trace_opts &c, float *ms) {
+            if (slab_mode)
+                return time_candidate(
+                    ev, false, 3, s, [&]() { return launch_walk_args(g, SA, &c, WM_SLAB, s); },
+                    [&]() { return HG_OK; }, ms);
             return time_candidate(
                 ev, records, 3, s,
-                [&]() { return launch_walk(g, origins, dirs, n, &c, &out, false, s, nullptr); },
-                [&]() { return launch_walk(g, origins, dirs, n, &c, &out, true, s, nullptr); }, ms);
+                [&]() { return launch_walk(g, origins, dirs, n, &c, &out, WM_COUNT, s, nullptr); },
+                [&]() { return launch_walk(g, origins, dirs, n, &c, &out, WM_FILL, s, nullptr); }, ms);
         };
         const int *vals[] = {LDS, BLOCKS, CHUNKS, REFILLS};
         const int nvals[] = {int(sizeof LDS / sizeof *LDS), int(sizeof BLOCKS / sizeof *BLOCKS),
@@ -186,6 +202,8 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     dfree(out.leaf, s);
     dfree(out.ds, s);
     dfree(tmp, s);
+    dfree(sleaf, s);
+    dfree(sds, s);
     return rc;
 }
 
