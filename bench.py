@@ -90,6 +90,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--no-tune", action="store_true")
+    p.add_argument("--max-nodes", type=int, default=None,
+                   help="node capacity passed to grid_build (0: size levels on the host); "
+                        "default 2^22 for workloads 1-2, 2^24 for workload 3")
     p.add_argument("--calib-copy", type=int, default=0,
                    help="also run a device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -236,7 +239,8 @@ def run_single(a, w):
     n = o.shape[0]
 
     # ---- warm-up: sizes the record buffers and tunes the walk's launch shape ----
-    g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+    mx = (1 << 22) if a.max_nodes is None else a.max_nodes
+    g = hg.build(w.density, w.criteria, w.tree_type, device=dev, max_nodes=mx)
     n_leaves, n_nodes = g.n_leaves, g.n_nodes
     res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, count_rechecks=True)
     needed, rechecks = res["needed"], res["rechecks"]
@@ -249,7 +253,7 @@ def run_single(a, w):
     t32 = tuned.get(hg.FP32_RECHECK)
     g.free()
     for _ in range(max(0, a.warmup - 1)):
-        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+        g = hg.build(w.density, w.criteria, w.tree_type, device=dev, max_nodes=mx)
         g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=res, capacity=needed, tuned=t32)
         g.free()
     log(f"grid: {n_leaves} leaves, {n_nodes} nodes; {needed} crossings")
@@ -260,7 +264,7 @@ def run_single(a, w):
     t0 = time.perf_counter()
     for i in range(a.steps):
         tb0 = time.perf_counter()
-        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+        g = hg.build(w.density, w.criteria, w.tree_type, device=dev, max_nodes=mx)
         build_ms.append((time.perf_counter() - tb0) * 1e3)
         r = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, out=res, capacity=needed,
                     timing=True, tuned=t32)
@@ -313,7 +317,7 @@ def run_single(a, w):
     line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",
                      {"workload": w.name, "tree": tree_name(w.tree_type), "leaves": int(n_leaves),
                       "nodes": int(n_nodes), "paths": int(n), "precision": "fp32_recheck",
-                      "mode": "records", "step": "grid_build + grid_trace"})
+                      "mode": "records", "step": "grid_build + grid_trace", "max_nodes": mx})
 
     def trace_entry(ms, tau_ms):
         # records mode in one walk: [0] the walk into per-path rows, [1] prefix
@@ -378,7 +382,8 @@ def run_c3(a, w):
     k = torch.from_numpy(k_np).to(dev)
     n = o.shape[0]
     nb = min(n, 10_000_000)
-    g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+    mx = (1 << 24) if a.max_nodes is None else a.max_nodes
+    g = hg.build(w.density, w.criteria, w.tree_type, device=dev, max_nodes=mx)
     n_leaves, n_nodes = g.n_leaves, g.n_nodes
     tuned = {}
     if not a.no_tune:
@@ -399,7 +404,7 @@ def run_c3(a, w):
     t0 = time.perf_counter()
     for i in range(a.steps):
         tb = time.perf_counter()
-        g = hg.build(w.density, w.criteria, w.tree_type, device=dev)
+        g = hg.build(w.density, w.criteria, w.tree_type, device=dev, max_nodes=mx)
         build_ms.append((time.perf_counter() - tb) * 1e3)
         r = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, out=res, timing=True, tuned=tt)
         tau_ms.append(r["kernel_ms"][0])
@@ -432,7 +437,8 @@ def run_c3(a, w):
     line = base_line(a, crossings / step_s, step_s, "crossings/s", "f32+f64",
                      {"workload": w.name, "tree": tree_name(w.tree_type), "leaves": int(n_leaves),
                       "nodes": int(n_nodes), "paths": int(n), "precision": "fp32_recheck",
-                      "mode": "tau_only", "step": "grid_build + grid_trace (tau-only)"})
+                      "mode": "tau_only", "step": "grid_build + grid_trace (tau-only)",
+                      "max_nodes": mx})
     line.update({
         "rays_per_s": round(n / step_s, 1),
         "crossings_per_path": round(crossings / n, 3),

@@ -186,7 +186,7 @@ typedef struct {
     const double *rho_max;      /* [n_nodes] */
     const int32_t *leaf_of;     /* [n_nodes] leaf id or -1 */
     const int32_t *node_of;     /* [n_leaves] */
-    const int32_t *rope;        /* [n_leaves][6] */
+    const int32_t *rope;        /* [n_nodes][6] rope target of each face (node index, -1: domain face) */
 } hg_grid_arrays;
 
 typedef struct hg_grid *hg_grid_t;
@@ -194,8 +194,12 @@ typedef struct hg_grid *hg_grid_t;
 /* Build a grid (Sect. 2.2: the node list grows breadth-first; each node's mass
  * is the Monte Carlo estimate of Eq. 1 and it is split by the criteria above;
  * leaves are the unsplit nodes).  The construction runs level by level on the
- * GPU and synchronises the stream once per level to size the next one.  Leaf
- * density rho = S/n_samples = M/V (Sect. 3.2).  On success *out owns the grid.
+ * GPU.  With criteria.max_nodes = 0 it synchronises the stream once per level
+ * to size the next one; with 0 < max_nodes <= 2^25 every array is reserved
+ * for max_nodes nodes up front (about 160 bytes per node) and the levels run
+ * with their counts kept on the device, synchronising only at the end (the
+ * same tree either way).  Leaf density rho = S/n_samples = M/V (Sect. 3.2).
+ * On success *out owns the grid.
  * Errors: HG_E_INVAL, HG_E_DOMAIN, HG_E_LIMIT, HG_E_OOM, HG_E_HIP. */
 int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_type,
                void *stream, hg_grid_t *out);

@@ -11,6 +11,8 @@
 namespace hg {
 
 int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s, hg_grid *g);
+int build_single_batched(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s,
+                         hg_grid **out);
 int import_structure(int tree, const std::vector<int32_t> &fc, std::vector<uint8_t> &level,
                      std::vector<uint32_t> &coord, int64_t level_begin[64], int *max_level);
 
@@ -161,9 +163,17 @@ int grid_build(const hg_density *dn, const hg_criteria *cr, int tree_type, void 
     *out = nullptr;
     int rc = check_build_args(dn, cr, tree_type);
     if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (cr->max_nodes > 0 && cr->max_nodes <= MAX_IDS) {
+        // a known capacity: the construction without per-level synchronisation
+        hg_grid *gb = nullptr;
+        rc = build_single_batched(dn, cr, tree_type, s, &gb);
+        if (rc) return rc;
+        *out = gb;
+        return HG_OK;
+    }
     hg_grid *g = new_grid(tree_type, dn->lo, dn->side);
     if (!g) return HG_E_OOM;
-    hipStream_t s = (hipStream_t)stream;
     rc = build_grid(dn, cr, tree_type, s, g);
     if (rc) {
         (void)hipStreamSynchronize(s);

@@ -129,10 +129,14 @@ __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ 
     const int64_t T = P[ng];
     const int64_t nw = int64_t(gridDim.x) * (FT / 64);
     for (int64_t t = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; t < T; t += nw) {
-        const int i = owner(P, ng, t);
+        // the node and its grid are the same for the whole wavefront: keep the
+        // grid's density and criteria in scalar registers
+        const int i = __builtin_amdgcn_readfirstlane(owner(P, ng, t));
         const ForestGrid &G = F[i];
+        const Dens D = G.D;
+        const CritDev C = G.C;
         const int64_t n = G.meta[lv] + (t - P[i]);
-        const NodeSample r = sample_node_wave(G.tree, G.D, G.C, lv, G.coord[3 * n], G.coord[3 * n + 1],
+        const NodeSample r = sample_node_wave(G.tree, D, C, lv, G.coord[3 * n], G.coord[3 * n + 1],
                                               G.coord[3 * n + 2], G.bin_start);
         if (lane == 0) {
             G.S[n] = r.S;
@@ -918,3 +922,39 @@ int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream
 void batch_free(hg_batch_t b) { free_batch(b); }
 
 }  // extern "C"
+
+namespace hg {
+
+// One grid built by the batch construction (every level count on the device,
+// no synchronisation per level) with node capacity cr->max_nodes; the grid
+// takes over the batch's arrays.
+int build_single_batched(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s,
+                         hg_grid **out)
+{
+    *out = nullptr;
+    hg_batch_t b = nullptr;
+    int rc = batch_create(1, dn, cr, &tree, &b);
+    if (rc) return rc;
+    rc = batch_run(b, HG_STAGE_BUILD, s);
+    if (!rc) rc = batch_result(b, s, nullptr, nullptr, nullptr);
+    hg_grid_t g = nullptr;
+    if (!rc) rc = batch_grid(b, 0, &g);
+    if (!rc) {
+        const void *own[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
+                             g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64,
+                             g->child, g->table};
+        std::vector<void *> keep;
+        for (void *p : b->arrays) {
+            bool owned = false;
+            for (const void *q : own) owned = owned || p == q;
+            if (!owned) keep.push_back(p);
+        }
+        b->arrays.swap(keep);
+        g->borrowed = 0;
+        *out = g;
+    }
+    batch_free(b);
+    return rc;
+}
+
+}  // namespace hg

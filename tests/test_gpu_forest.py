@@ -161,3 +161,23 @@ def test_record_capacity_overrun_and_empty_batch(clumps):
     assert torch.equal(res[0]["leaf"][:n], ref[0]["leaf"][:n])
     assert torch.equal(res[0]["ds"][:n], ref[0]["ds"][:n])
     b.free()
+
+
+@pytest.mark.parametrize("tree", [W.OCTREE, W.KDTREE], ids=["octree", "kd"])
+def test_grid_build_with_capacity_equals_level_synchronised(tree):
+    # grid_build with a node capacity runs the batch construction for one grid
+    w = W.workload(3, tree_type=tree)
+    cr = w.criteria
+    cr.max_level = 9 if tree == W.OCTREE else 24
+    a = hg.build(w.density, cr, tree, device=DEV)
+    b = hg.build(w.density, cr, tree, device=DEV, max_nodes=a.n_nodes + 10)
+    _same_arrays(a, b)
+    o, k = W.rays("uniform", 20000, 5)
+    ra = a.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS)
+    rb = b.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS)
+    assert torch.equal(ra["tau"], rb["tau"]) and torch.equal(ra["leaf"][:ra["needed"]], rb["leaf"][:rb["needed"]])
+    with pytest.raises(hg.HGError) as ei:
+        hg.build(w.density, cr, tree, device=DEV, max_nodes=a.n_nodes - 1)
+    assert ei.value.code == hg.HG_E_LIMIT
+    a.free()
+    b.free()
