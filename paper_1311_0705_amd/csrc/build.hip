@@ -230,12 +230,13 @@ int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *ou
     D.cc = (const double *)st->cc;
     D.cs = (const double *)st->cs;
     D.ca = (const double *)st->ca;
-    // bin width about twice the mean truncation radius, at most 128 bins per axis
+    // bin width about half the mean truncation radius (a sample then tests
+    // about N (w + 2r)^3 / side^3 clumps), at most 256 bins per axis
     double rsum = 0.0;
     for (size_t i = 0; i < n; i++) rsum += dn->clump_trunc * fabs(dn->clump_sigma[i]);
     double rmean = rsum / double(n);
-    int B = rmean > 0.0 ? int(dn->side / (2.0 * rmean)) : 1;
-    B = std::max(1, std::min(128, B));
+    int B = rmean > 0.0 ? int(std::min(1e6, dn->side / (0.5 * rmean))) : 1;
+    B = std::max(1, std::min(256, B));
     D.B = B;
     D.bin_scale = double(B) / dn->side;
     const int64_t nb = int64_t(B) * B * B;
