@@ -798,43 +798,62 @@ __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restr
 
 __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
 
-// One-pass records mode: copy every path's row of the slab (its first
-// `slab` records) to its slice of the CSR arrays; one wavefront per path,
-// paths with more records than the row holds are left to the fill walk.
+// One-pass records mode: copy the rows of the slab (each path's first `slab`
+// records) into the CSR slices.  A block takes CP consecutive paths, whose
+// slices form one contiguous range of the output, and its threads walk that
+// range in order (coalesced writes), each finding its path by a binary search
+// over the block's offsets in LDS.  Paths with more records than their row are
+// left to the fill walk.
+constexpr int CP = 256;
+
 template <typename DsT>
 __global__ void __launch_bounds__(TB)
     k_slab_compact(const int32_t *__restrict__ sleaf, const DsT *__restrict__ sds, int64_t slab,
                    const int32_t *__restrict__ count, const int64_t *__restrict__ offsets, int64_t n,
                    int32_t *__restrict__ leaf, DsT *__restrict__ ds)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t nw = int64_t(gridDim.x) * (TB / 64);
-    for (int64_t i = (int64_t(blockIdx.x) * TB + threadIdx.x) >> 6; i < n; i += nw) {
-        const int64_t c = count[i];
-        if (c > slab) continue;
-        const int64_t src = i * slab, dst = offsets[i];
-        for (int64_t j = lane; j < c; j += 64) {
-            leaf[dst + j] = sleaf[src + j];
-            ds[dst + j] = sds[src + j];
+    __shared__ int64_t off[CP + 1];
+    const int64_t p0 = int64_t(blockIdx.x) * CP;
+    const int np = int(n - p0 < CP ? n - p0 : CP);
+    for (int j = threadIdx.x; j <= np; j += TB) off[j] = offsets[p0 + j];
+    __syncthreads();
+    const int64_t d0 = off[0], d1 = off[np];
+    for (int64_t d = d0 + threadIdx.x; d < d1; d += TB) {
+        int lo = 0, hi = np;   // the path q with off[q] <= d < off[q+1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= d) lo = mid;
+            else hi = mid;
         }
+        const int64_t c = off[lo + 1] - off[lo];
+        if (c > slab) continue;
+        const int64_t src = (p0 + lo) * slab + (d - off[lo]);
+        leaf[d] = sleaf[src];
+        ds[d] = sds[src];
     }
 }
+
+// Paths whose records overflow their row; one atomic per block.
+constexpr int OV_PER = 16;
 
 __global__ void __launch_bounds__(TB)
     k_overflow_list(const int32_t *__restrict__ count, int64_t n, int64_t slab, int64_t *__restrict__ list,
                     unsigned long long *__restrict__ n_list)
 {
-    const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
-    const bool over = i < n && count[i] > slab;
-    // one atomic per wavefront
-    const uint64_t m = __ballot(over);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    const int first = __ffsll((unsigned long long)m) - 1;
-    unsigned long long base = 0;
-    if (lane == first) base = atomicAdd(n_list, (unsigned long long)__popcll(m));
-    base = __shfl(base, first, 64);
-    if (over) list[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+    __shared__ int64_t found[TB * OV_PER];
+    __shared__ unsigned nf;
+    __shared__ unsigned long long base;
+    if (threadIdx.x == 0) nf = 0u;
+    __syncthreads();
+    const int64_t b0 = int64_t(blockIdx.x) * TB * OV_PER;
+    for (int j = 0; j < OV_PER; j++) {
+        const int64_t i = b0 + int64_t(j) * TB + threadIdx.x;
+        if (i < n && count[i] > slab) found[atomicAdd(&nf, 1u)] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base = nf ? atomicAdd(n_list, (unsigned long long)nf) : 0ull;
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < nf; j += TB) list[base + j] = found[j];
 }
 
 constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
@@ -1045,7 +1064,9 @@ int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int pr
                         hipStream_t s)
 {
     if (n == 0) return HG_OK;
-    const unsigned blocks = unsigned(std::min<int64_t>((n + 3) / 4, 65536));
+    const int64_t nb = (n + CP - 1) / CP;
+    if (nb > 0x7fffffff) return HG_E_LIMIT;
+    const unsigned blocks = unsigned(nb);
     if (precision == HG_FP64)
         k_slab_compact<double><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const double *)sds, slab,
                                                      count, offsets, n, leaf, (double *)ds);
@@ -1060,7 +1081,8 @@ int launch_overflow_list(const int32_t *count, int64_t n, int64_t slab, int64_t 
                          unsigned long long *n_list, hipStream_t s)
 {
     if (n == 0) return HG_OK;
-    k_overflow_list<<<unsigned((n + TB - 1) / TB), TB, 0, s>>>(count, n, slab, list, n_list);
+    const int64_t per = int64_t(TB) * OV_PER;
+    k_overflow_list<<<unsigned((n + per - 1) / per), TB, 0, s>>>(count, n, slab, list, n_list);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }
