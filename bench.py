@@ -69,10 +69,10 @@ B_RAY_SLAB = 48 + 12
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_fill": {"trace_sha256": "91deb3abfb7f56c9747bca9ecc5e775d00fb528d08210a0d7ce76be2361af0de",
-                "fetch_kib": 32923160.1, "write_kib": 10747658.3, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "91deb3abfb7f56c9747bca9ecc5e775d00fb528d08210a0d7ce76be2361af0de",
-                 "fetch_kib": 93905050.0, "write_kib": 6984369.7, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "76099b5cc86302a183a02c847bc5552102c3b75a97c956b13c9d0ff5768342bb",
+                "fetch_kib": 30386684.1, "write_kib": 11106693.4, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "76099b5cc86302a183a02c847bc5552102c3b75a97c956b13c9d0ff5768342bb",
+                 "fetch_kib": 93699529.8, "write_kib": 6975292.0, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
