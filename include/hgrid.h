@@ -132,7 +132,7 @@ typedef struct {
                            path's first `slab` records into a per-path row, then a copy into the
                            CSR slices (paths with more records are walked again); 2 = a counting
                            walk, then a record-filling walk; 0 = library choice (1 when the rows
-                           of all paths fit in 32 GiB, else 2) */
+                           of all paths fit in 32 GiB and the scratch can be had, else 2) */
     int32_t slab;       /* records per path row of the one-pass mode (multiple of 4),
                            0 = library choice (256) */
 } hg_trace_opts;
@@ -209,13 +209,26 @@ int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_
  * its entry point into the domain when the origin lies outside; a path that
  * misses the domain has count 0 and tau 0.  The walk visits, in order, every
  * leaf the path crosses with positive length and stops where the path leaves
- * the domain.  Records mode runs a counting walk, a prefix sum into offsets
- * and a record-filling walk; if capacity < needed it returns HG_E_CAPACITY
- * after the first two with tau, count, offsets and needed valid.  The call
- * synchronises the stream before returning.  Errors: HG_E_INVAL, HG_E_DIR,
- * HG_E_CAPACITY, HG_E_STEP, HG_E_HIP. */
+ * the domain.  Records mode (opts->passes 0 or 1) walks once, writing each
+ * path's first opts->slab records (0 = 256) into a row of a scratch buffer,
+ * then takes the prefix sum of the counts into offsets, copies the rows into
+ * the caller's leaf / ds slices and walks again only the paths whose records
+ * overflowed their row.  The scratch (n x slab x (4 + sizeof ds) bytes plus
+ * 16 bytes per path) belongs to the library: one buffer per device, grown on
+ * demand and kept for later calls until grid_release_scratch(); calls that
+ * share a device take turns on it.  When it would exceed 32 GiB or cannot be
+ * allocated, and with opts->passes == 2, records mode runs a counting walk, a
+ * prefix sum and a record-filling walk instead (the same results).  If
+ * capacity < needed it returns HG_E_CAPACITY with tau, count, offsets and
+ * needed valid.  The call synchronises the stream before returning.
+ * Errors: HG_E_INVAL, HG_E_DIR, HG_E_CAPACITY, HG_E_STEP, HG_E_HIP. */
 int grid_trace(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
                const hg_trace_opts *opts, hg_trace_out *out, void *stream);
+
+/* Free the current device's records-mode scratch of grid_trace (waits for
+ * the calls using it; the next records-mode call allocates it again).
+ * Errors: HG_E_HIP. */
+int grid_release_scratch(void);
 
 /* Trace several grids' path batches in one persistent launch per walk pass
  * (Sect. 2.3, as grid_trace).  Entry g traces n[g] paths origins[g] / dirs[g]

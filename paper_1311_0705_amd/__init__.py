@@ -114,6 +114,7 @@ _SIGS = [
     ("grid_import", C.c_int, [C.POINTER(GridArrays), C.c_void_p, C.POINTER(C.c_void_p)]),
     ("grid_export", C.c_int, [C.c_void_p, C.POINTER(GridArrays)]),
     ("grid_free", None, [C.c_void_p]),
+    ("grid_release_scratch", C.c_int, []),
     ("batch_create", C.c_int, [C.c_int, C.POINTER(Density), C.POINTER(Criteria),
                                C.POINTER(C.c_int), C.POINTER(C.c_void_p)]),
     ("batch_bind", C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -615,6 +616,12 @@ def trace_batched(grids, origins, dirs, precision: int = FP64, mode: int = RECOR
         res[i]["rechecks"] = int(tos[i].rechecks)
         res[i]["kernel_ms"] = list(tos[i].kernel_ms)
     return res
+
+
+def release_scratch(device="cuda") -> None:
+    """Free the device's records-mode trace scratch (grid_release_scratch)."""
+    with torch.cuda.device(torch.device(device)):
+        _check(lib().grid_release_scratch(), "grid_release_scratch")
 
 
 def build(density, criteria, tree_type, stream=None, device="cuda", max_nodes=0) -> Grid:

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -66,6 +67,11 @@ void dfree(void *p, hipStream_t s)
 
 void free_grid_arrays(hg_grid *g)
 {
+    if (g->block) {
+        dfree(g->block, nullptr);
+        dfree(g->status, nullptr);
+        return;
+    }
     void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
                     g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->recw,
                     g->child, g->table, g->status};
@@ -458,24 +464,74 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
     return rc;
 }
 
+// Scratch of the one-walk records mode (rows of records, scan temporaries,
+// the overflow list): one buffer per device, allocated outside the stream-
+// ordered pool so that repeated calls neither allocate nor split the pool's
+// blocks.  It grows when a call needs more and is kept for later calls; a
+// call holds it, under the lock, until its stream has drained.
+struct Scratch {
+    std::mutex m;
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+constexpr int MAX_DEVICES = 64;
+static Scratch g_scratch[MAX_DEVICES];
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Lock the current device's scratch with at least `bytes` bytes.  On HG_OK
+// the caller owns the lock and releases it with scratch_release.
+static int scratch_acquire(size_t bytes, Scratch **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return set_hip_error(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
+    Scratch &w = g_scratch[dev];
+    w.m.lock();
+    if (w.bytes < bytes) {
+        if (w.p) (void)hipFree(w.p);   // synchronises the device: no call still uses it
+        w.p = nullptr;
+        w.bytes = 0;
+        const size_t grain = size_t(1) << 28;
+        const size_t want = (bytes + grain - 1) / grain * grain;
+        e = hipMalloc(&w.p, want);
+        if (e) {
+            (void)hipGetLastError();
+            w.p = nullptr;
+            w.m.unlock();
+            return e == hipErrorOutOfMemory ? HG_E_OOM : set_hip_error(e);
+        }
+        w.bytes = want;
+    }
+    *out = &w;
+    return HG_OK;
+}
+
+static void scratch_release(Scratch *w) { w->m.unlock(); }
+
 // Records mode in one walk: tau, counts and each path's first `slab` records
 // into a row per path, the prefix sum of the counts, the rows copied into the
 // CSR slices, and a record-filling walk over the paths whose records did not
-// fit their row.
+// fit their row.  HG_E_OOM (nothing enqueued) when the scratch cannot be had.
 static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n, int64_t slab,
                           const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev)
 {
     const bool timing = ev[0] != nullptr;
     const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
-    int32_t *sleaf = nullptr;
-    void *sds = nullptr;
-    int64_t *tmp = nullptr, *list = nullptr;
-    unsigned long long *n_list = nullptr;
-    int rc = dalloc_n(&sleaf, size_t(n) * size_t(slab), s);
-    if (!rc) rc = dalloc(&sds, size_t(n) * size_t(slab) * dsz, s);
-    if (!rc) rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
-    if (!rc) rc = dalloc_n(&list, size_t(n), s);
-    if (!rc) rc = dalloc_n(&n_list, 1, s);
+    const size_t b_leaf = align256(size_t(n) * size_t(slab) * 4);
+    const size_t b_ds = align256(size_t(n) * size_t(slab) * dsz);
+    const size_t b_tmp = align256(scan_tmp_elems(n) * 8);
+    const size_t b_list = align256(size_t(n) * 8);
+    Scratch *w = nullptr;
+    int rc = scratch_acquire(b_leaf + b_ds + b_tmp + b_list + 256, &w);
+    if (rc) return rc;
+    char *base = static_cast<char *>(w->p);
+    int32_t *sleaf = reinterpret_cast<int32_t *>(base);
+    void *sds = base + b_leaf;
+    int64_t *tmp = reinterpret_cast<int64_t *>(base + b_leaf + b_ds);
+    int64_t *list = reinterpret_cast<int64_t *>(base + b_leaf + b_ds + b_tmp);
+    unsigned long long *n_list = reinterpret_cast<unsigned long long *>(base + b_leaf + b_ds + b_tmp + b_list);
     TraceStatus st;
     struct {
         int64_t needed;
@@ -521,12 +577,25 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
     if (timing) (void)hipEventRecord(ev[3], s);
     if (!rc) rc = read_status(g, &st, s);
     (void)hipStreamSynchronize(s);
-    dfree(sleaf, s);
-    dfree(sds, s);
-    dfree(tmp, s);
-    dfree(list, s);
-    dfree(n_list, s);
+    scratch_release(w);
     return rc;
+}
+
+int grid_release_scratch(void)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return set_hip_error(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
+    Scratch &w = g_scratch[dev];
+    std::lock_guard<std::mutex> lock(w.m);
+    if (w.p) {
+        e = hipFree(w.p);
+        w.p = nullptr;
+        w.bytes = 0;
+        if (e) return set_hip_error(e);
+    }
+    return HG_OK;
 }
 
 int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
@@ -549,8 +618,8 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
     const bool fits = n > 0 && double(n) * double(slab) * double(4 + dsz) <= double(int64_t(32) << 30);
     const bool one_pass = records && opts->passes != 2 && fits;
-    const int rc = one_pass ? trace_one_pass(g, origins, dirs, n, slab, opts, out, s, ev)
-                            : trace_two_pass(g, origins, dirs, n, opts, out, s, ev);
+    int rc = one_pass ? trace_one_pass(g, origins, dirs, n, slab, opts, out, s, ev) : HG_E_OOM;
+    if (rc == HG_E_OOM) rc = trace_two_pass(g, origins, dirs, n, opts, out, s, ev);
     if (timing && (rc == HG_OK || rc == HG_E_CAPACITY)) {
         (void)hipEventSynchronize(ev[1]);
         (void)hipEventElapsedTime(&out->kernel_ms[0], ev[0], ev[1]);

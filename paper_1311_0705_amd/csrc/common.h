@@ -16,6 +16,8 @@
 // its level and the corner of the node the walk comes from.
 #pragma once
 
+#include <vector>
+
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -197,6 +199,7 @@ struct hg_grid {
     hg::TraceStatus *status;   // device scratch
     int64_t level_begin[64];   // first node of each level; level_begin[max_level+1] = n_nodes
     int borrowed;              // arrays belong to a batch (only status is the grid's own)
+    void *block;               // when set, every array above except status is carved from it
 };
 
 namespace hg {
@@ -224,6 +227,38 @@ inline int dalloc_n(T **p, size_t n, hipStream_t s)
 {
     return dalloc(reinterpret_cast<void **>(p), n * sizeof(T), s);
 }
+
+// Several arrays carved from one device block (each piece 256-byte aligned):
+// one allocation and one free instead of one per array.
+class Carve {
+  public:
+    template <typename T>
+    void add(T **p, size_t n)
+    {
+        const size_t b = (n * sizeof(T) + 255) & ~size_t(255);
+        parts_.push_back(Part{reinterpret_cast<void **>(p), b});
+        bytes_ += b;
+    }
+    int alloc(void **block, hipStream_t s)
+    {
+        int rc = dalloc(block, bytes_, s);
+        if (rc) return rc;
+        char *q = static_cast<char *>(*block);
+        for (const Part &pt : parts_) {
+            *pt.p = q;
+            q += pt.bytes;
+        }
+        return HG_OK;
+    }
+
+  private:
+    struct Part {
+        void **p;
+        size_t bytes;
+    };
+    std::vector<Part> parts_;
+    size_t bytes_ = 0;
+};
 
 // ---- prefix sums (scan.hip) --------------------------------------------------
 // out[0..n] = exclusive prefix sum of in[0..n-1] (out[n] = total).  tmp must

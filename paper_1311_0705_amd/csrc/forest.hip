@@ -393,7 +393,8 @@ struct hg_batch {
     int64_t *stmp = nullptr;
     WalkGrid *w32 = nullptr, *w64 = nullptr;
     TraceStatus *status = nullptr;
-    std::vector<void *> arrays;     // every per-grid allocation
+    void *tmp_block = nullptr;      // the batch-wide arrays above, carved from one block
+    std::vector<void *> arrays;     // one block per grid holding its arrays
     // bound trace
     std::vector<WalkArgs> hA;
     bool bound = false;
@@ -436,19 +437,9 @@ void free_batch(hg_batch *b)
     free_bound(b);
     for (auto &d : b->dens) release_density(&d, nullptr);
     for (void *p : b->arrays) dfree(p, nullptr);
-    void *ptrs[] = {b->dF, b->meta, b->P, b->PN, b->PL, b->PT, b->flag, b->off, b->stmp, b->w32,
-                    b->w64, b->status};
-    for (void *p : ptrs) dfree(p, nullptr);
+    dfree(b->tmp_block, nullptr);
     (void)hipDeviceSynchronize();
     delete b;
-}
-
-template <typename T>
-int grid_array(hg_batch *b, T **p, size_t n)
-{
-    int rc = dalloc_n(p, n, nullptr);
-    if (!rc) b->arrays.push_back(*p);
-    return rc;
 }
 
 std::vector<BatchChunk> chunk_table(const std::vector<int64_t> &n, int64_t chunk)
@@ -560,37 +551,43 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
                       c.min_level, c.max_level, c.n_samples, c.seed};
         const size_t cap = size_t(c.max_nodes);
         G.cap = int64_t(cap);
-        if (!rc) rc = grid_array(b, &G.fc, cap);
-        if (!rc) rc = grid_array(b, &G.level, cap);
-        if (!rc) rc = grid_array(b, &G.coord, 3 * cap);
-        if (!rc) rc = grid_array(b, &G.S, cap);
-        if (!rc) rc = grid_array(b, &G.rmin, cap);
-        if (!rc) rc = grid_array(b, &G.rmax, cap);
-        if (!rc) rc = grid_array(b, &G.rope, 6 * cap);
-        if (!rc) rc = grid_array(b, &G.leaf_of, cap);
-        if (!rc) rc = grid_array(b, &G.int_of, cap);
-        if (!rc) rc = grid_array(b, &G.node_of, cap);
-        if (!rc) rc = grid_array(b, &G.rho, cap);
-        if (!rc) rc = grid_array(b, &G.rec32, cap);
-        if (!rc) rc = grid_array(b, &G.rec64, cap);
-        if (!rc) rc = grid_array(b, &G.child, cap);
         G.tmax = table_depth(G.tree, int64_t(cap), c.max_level);
-        if (!rc) rc = grid_array(b, &G.table, size_t(1) << (3 * G.tmax));
+        Carve cv;
+        cv.add(&G.fc, cap);
+        cv.add(&G.level, cap);
+        cv.add(&G.coord, 3 * cap);
+        cv.add(&G.S, cap);
+        cv.add(&G.rmin, cap);
+        cv.add(&G.rmax, cap);
+        cv.add(&G.rope, 6 * cap);
+        cv.add(&G.leaf_of, cap);
+        cv.add(&G.int_of, cap);
+        cv.add(&G.node_of, cap);
+        cv.add(&G.rho, cap);
+        cv.add(&G.rec32, cap);
+        cv.add(&G.rec64, cap);
+        cv.add(&G.child, cap);
+        cv.add(&G.table, size_t(1) << (3 * G.tmax));
+        void *blk = nullptr;
+        rc = cv.alloc(&blk, nullptr);
+        if (!rc) b->arrays.push_back(blk);
     }
     const size_t ng1 = size_t(n_grids) + 1;
-    if (!rc) rc = dalloc_n(&b->meta, size_t(n_grids) * META, nullptr);
+    Carve ct;
+    ct.add(&b->meta, size_t(n_grids) * META);
+    ct.add(&b->dF, size_t(n_grids));
+    ct.add(&b->P, size_t(lmax + 1) * ng1);
+    ct.add(&b->PN, ng1);
+    ct.add(&b->PL, ng1);
+    ct.add(&b->PT, ng1);
+    ct.add(&b->flag, size_t(total_cap));
+    ct.add(&b->off, size_t(total_cap) + 1);
+    ct.add(&b->stmp, scan_dev_tmp_elems());
+    ct.add(&b->w32, size_t(n_grids));
+    ct.add(&b->w64, size_t(n_grids));
+    ct.add(&b->status, 1);
+    if (!rc) rc = ct.alloc(&b->tmp_block, nullptr);
     for (int i = 0; i < n_grids && !rc; i++) b->hF[size_t(i)].meta = b->meta + size_t(i) * META;
-    if (!rc) rc = dalloc_n(&b->dF, size_t(n_grids), nullptr);
-    if (!rc) rc = dalloc_n(&b->P, size_t(lmax + 1) * ng1, nullptr);
-    if (!rc) rc = dalloc_n(&b->PN, ng1, nullptr);
-    if (!rc) rc = dalloc_n(&b->PL, ng1, nullptr);
-    if (!rc) rc = dalloc_n(&b->PT, ng1, nullptr);
-    if (!rc) rc = dalloc_n(&b->flag, size_t(total_cap), nullptr);
-    if (!rc) rc = dalloc_n(&b->off, size_t(total_cap) + 1, nullptr);
-    if (!rc) rc = dalloc_n(&b->stmp, scan_dev_tmp_elems(), nullptr);
-    if (!rc) rc = dalloc_n(&b->w32, size_t(n_grids), nullptr);
-    if (!rc) rc = dalloc_n(&b->w64, size_t(n_grids), nullptr);
-    if (!rc) rc = dalloc_n(&b->status, 1, nullptr);
     if (!rc) {
         hipError_t e = hipMemcpy(b->dF, b->hF.data(), sizeof(ForestGrid) * size_t(n_grids),
                                  hipMemcpyHostToDevice);
@@ -940,16 +937,9 @@ int build_single_batched(const hg_density *dn, const hg_criteria *cr, int tree, 
     hg_grid_t g = nullptr;
     if (!rc) rc = batch_grid(b, 0, &g);
     if (!rc) {
-        const void *own[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
-                             g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64,
-                             g->child, g->table};
-        std::vector<void *> keep;
-        for (void *p : b->arrays) {
-            bool owned = false;
-            for (const void *q : own) owned = owned || p == q;
-            if (!owned) keep.push_back(p);
-        }
-        b->arrays.swap(keep);
+        // the grid takes over the block holding its arrays
+        g->block = b->arrays[0];
+        b->arrays.clear();
         g->borrowed = 0;
         *out = g;
     }
