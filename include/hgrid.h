@@ -133,8 +133,9 @@ typedef struct {
                            CSR slices (paths with more records are walked again); 2 = a counting
                            walk, then a record-filling walk; 0 = library choice (1 when the rows
                            of all paths fit in 32 GiB and the scratch can be had, else 2) */
-    int32_t slab;       /* records per path row of the one-pass mode (multiple of 4),
-                           0 = library choice (256) */
+    int32_t slab;       /* records per path row of the one-pass mode (rounded up to a multiple
+                           of 4), 0 = library choice (as many as keep the rows of all paths
+                           within 32 GiB, at most 2048; two walks below 256) */
 } hg_trace_opts;
 
 /* Outputs of grid_trace; every array is a caller-owned device buffer.
@@ -210,11 +211,12 @@ int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_
  * misses the domain has count 0 and tau 0.  The walk visits, in order, every
  * leaf the path crosses with positive length and stops where the path leaves
  * the domain.  Records mode (opts->passes 0 or 1) walks once, writing each
- * path's first opts->slab records (0 = 256) into a row of a scratch buffer,
+ * path's first opts->slab records into a row of a scratch buffer,
  * then takes the prefix sum of the counts into offsets, copies the rows into
- * the caller's leaf / ds slices and walks again only the paths whose records
- * overflowed their row.  The scratch (n x slab x (4 + sizeof ds) bytes plus
- * 16 bytes per path) belongs to the library: one buffer per device, grown on
+ * the caller's leaf / ds slices and resumes the paths whose records overflowed
+ * their row from the state the walk saved at their first record beyond it.
+ * The scratch (n x slab x (4 + sizeof ds) bytes plus about 90 bytes per path)
+ * belongs to the library: one buffer per device, grown on
  * demand and kept for later calls until grid_release_scratch(); calls that
  * share a device take turns on it.  When it would exceed 32 GiB or cannot be
  * allocated, and with opts->passes == 2, records mode runs a counting walk, a

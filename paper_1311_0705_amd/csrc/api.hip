@@ -137,6 +137,65 @@ int check_build_args(const hg_density *dn, const hg_criteria *cr, int tree_type)
     return HG_OK;
 }
 
+// Scratch of the one-walk records mode (rows of records, scan temporaries,
+// resume entries): one buffer per device, allocated outside the stream-
+// ordered pool so that repeated calls neither allocate nor split the pool's
+// blocks.  It grows when a call needs more and is kept for later calls; a
+// call holds it, under the lock, until its stream has drained.
+struct Scratch {
+    std::mutex m;
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+constexpr int MAX_DEVICES = 64;
+static Scratch g_scratch[MAX_DEVICES];
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int scratch_acquire(size_t bytes, Scratch **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return set_hip_error(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
+    Scratch &w = g_scratch[dev];
+    w.m.lock();
+    if (w.bytes < bytes) {
+        if (w.p) (void)hipFree(w.p);   // synchronises the device: no call still uses it
+        w.p = nullptr;
+        w.bytes = 0;
+        const size_t grain = size_t(1) << 28;
+        const size_t want = (bytes + grain - 1) / grain * grain;
+        e = hipMalloc(&w.p, want);
+        if (e) {
+            (void)hipGetLastError();
+            w.p = nullptr;
+            w.m.unlock();
+            return e == hipErrorOutOfMemory ? HG_E_OOM : set_hip_error(e);
+        }
+        w.bytes = want;
+    }
+    *out = &w;
+    return HG_OK;
+}
+
+void *scratch_ptr(Scratch *w) { return w->p; }
+
+void scratch_release(Scratch *w) { w->m.unlock(); }
+
+int64_t slab_rows(const hg_trace_opts *opts, int64_t n)
+{
+    const double per = double(4 + (opts->precision == HG_FP64 ? 8 : 4));
+    if (n <= 0) return 0;
+    if (opts->slab > 0) {
+        const int64_t k = (int64_t(opts->slab) + 3) / 4 * 4;
+        return double(n) * (double(k) * per + double(sizeof(Resume))) <= SLAB_BUDGET ? k : 0;
+    }
+    const double fit = (SLAB_BUDGET / double(n) - double(sizeof(Resume))) / per;
+    if (fit < double(SLAB_MIN)) return 0;
+    return std::min<int64_t>(SLAB_MAX, int64_t(fit) / 4 * 4);
+}
+
 }  // namespace hg
 
 using namespace hg;
@@ -464,56 +523,11 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
     return rc;
 }
 
-// Scratch of the one-walk records mode (rows of records, scan temporaries,
-// the overflow list): one buffer per device, allocated outside the stream-
-// ordered pool so that repeated calls neither allocate nor split the pool's
-// blocks.  It grows when a call needs more and is kept for later calls; a
-// call holds it, under the lock, until its stream has drained.
-struct Scratch {
-    std::mutex m;
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-constexpr int MAX_DEVICES = 64;
-static Scratch g_scratch[MAX_DEVICES];
-
-static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
-
-// Lock the current device's scratch with at least `bytes` bytes.  On HG_OK
-// the caller owns the lock and releases it with scratch_release.
-static int scratch_acquire(size_t bytes, Scratch **out)
-{
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e) return set_hip_error(e);
-    if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
-    Scratch &w = g_scratch[dev];
-    w.m.lock();
-    if (w.bytes < bytes) {
-        if (w.p) (void)hipFree(w.p);   // synchronises the device: no call still uses it
-        w.p = nullptr;
-        w.bytes = 0;
-        const size_t grain = size_t(1) << 28;
-        const size_t want = (bytes + grain - 1) / grain * grain;
-        e = hipMalloc(&w.p, want);
-        if (e) {
-            (void)hipGetLastError();
-            w.p = nullptr;
-            w.m.unlock();
-            return e == hipErrorOutOfMemory ? HG_E_OOM : set_hip_error(e);
-        }
-        w.bytes = want;
-    }
-    *out = &w;
-    return HG_OK;
-}
-
-static void scratch_release(Scratch *w) { w->m.unlock(); }
 
 // Records mode in one walk: tau, counts and each path's first `slab` records
 // into a row per path, the prefix sum of the counts, the rows copied into the
-// CSR slices, and a record-filling walk over the paths whose records did not
-// fit their row.  HG_E_OOM (nothing enqueued) when the scratch cannot be had.
+// CSR slices, and a record-filling walk that resumes the paths whose records
+// did not fit their row at their first record beyond it.  HG_E_OOM (nothing enqueued) when the scratch cannot be had.
 static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n, int64_t slab,
                           const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev)
 {
@@ -522,24 +536,24 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
     const size_t b_leaf = align256(size_t(n) * size_t(slab) * 4);
     const size_t b_ds = align256(size_t(n) * size_t(slab) * dsz);
     const size_t b_tmp = align256(scan_tmp_elems(n) * 8);
-    const size_t b_list = align256(size_t(n) * 8);
+    const size_t b_res = align256(size_t(n) * sizeof(Resume));
     Scratch *w = nullptr;
-    int rc = scratch_acquire(b_leaf + b_ds + b_tmp + b_list + 256, &w);
+    int rc = scratch_acquire(b_leaf + b_ds + b_tmp + b_res + 256, &w);
     if (rc) return rc;
-    char *base = static_cast<char *>(w->p);
+    char *base = static_cast<char *>(scratch_ptr(w));
     int32_t *sleaf = reinterpret_cast<int32_t *>(base);
     void *sds = base + b_leaf;
     int64_t *tmp = reinterpret_cast<int64_t *>(base + b_leaf + b_ds);
-    int64_t *list = reinterpret_cast<int64_t *>(base + b_leaf + b_ds + b_tmp);
-    unsigned long long *n_list = reinterpret_cast<unsigned long long *>(base + b_leaf + b_ds + b_tmp + b_list);
+    Resume *res = reinterpret_cast<Resume *>(base + b_leaf + b_ds + b_tmp);
+    unsigned long long *n_res = reinterpret_cast<unsigned long long *>(base + b_leaf + b_ds + b_tmp + b_res);
     TraceStatus st;
     struct {
         int64_t needed;
-        unsigned long long n_over;
+        unsigned long long n_res;
     } h = {0, 0};
     if (!rc) {
         k_reset_status<<<1, 1, 0, s>>>(g->status);
-        hipError_t e = hipMemsetAsync(n_list, 0, sizeof *n_list, s);
+        hipError_t e = hipMemsetAsync(n_res, 0, sizeof *n_res, s);
         if (e) rc = set_hip_error(e);
     }
     if (!rc) {
@@ -548,16 +562,17 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
         A.ds = sds;
         A.slab = slab;
         A.capacity = n * slab;
+        A.resume = res;
+        A.n_resume = n_res;
         if (timing) (void)hipEventRecord(ev[0], s);
         rc = launch_walk_args(g, A, opts, WM_SLAB, s);
         if (timing) (void)hipEventRecord(ev[1], s);
     }
     if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
-    if (!rc) rc = launch_overflow_list(out->count, n, slab, list, n_list, s);
     if (timing) (void)hipEventRecord(ev[2], s);
     if (!rc) {
         hipError_t e = hipMemcpyAsync(&h.needed, out->offsets + n, 8, hipMemcpyDeviceToHost, s);
-        if (!e) e = hipMemcpyAsync(&h.n_over, n_list, sizeof h.n_over, hipMemcpyDeviceToHost, s);
+        if (!e) e = hipMemcpyAsync(&h.n_res, n_res, sizeof h.n_res, hipMemcpyDeviceToHost, s);
         if (e) rc = set_hip_error(e);
     }
     if (!rc) rc = read_status(g, &st, s);   // synchronises
@@ -568,10 +583,12 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
     }
     if (!rc) rc = launch_slab_compact(sleaf, sds, slab, opts->precision, out->count, out->offsets, n,
                                       out->leaf, out->ds, s);
-    if (!rc && h.n_over > 0) {
+    if (!rc && h.n_res > 0) {
+        // the paths past their row, resumed where their row filled up
         WalkArgs F = walk_args(g, origins, dirs, n, opts, out);
-        F.index = list;
-        F.n = int64_t(h.n_over);
+        F.resume = res;
+        F.n = int64_t(std::min<unsigned long long>(h.n_res, (unsigned long long)n));
+        F.slab = slab;
         rc = launch_walk_args(g, F, opts, WM_FILL, s);
     }
     if (timing) (void)hipEventRecord(ev[3], s);
@@ -614,10 +631,8 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     out->rechecks = 0;
     if (timing)
         for (int i = 0; i < 4; i++) HG_CHECK(hipEventCreate(&ev[i]));
-    const int64_t slab = opts->slab > 0 ? (int64_t(opts->slab) + 3) / 4 * 4 : 256;
-    const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
-    const bool fits = n > 0 && double(n) * double(slab) * double(4 + dsz) <= double(int64_t(32) << 30);
-    const bool one_pass = records && opts->passes != 2 && fits;
+    const int64_t slab = slab_rows(opts, n);
+    const bool one_pass = records && opts->passes != 2 && slab > 0;
     int rc = one_pass ? trace_one_pass(g, origins, dirs, n, slab, opts, out, s, ev) : HG_E_OOM;
     if (rc == HG_E_OOM) rc = trace_two_pass(g, origins, dirs, n, opts, out, s, ev);
     if (timing && (rc == HG_OK || rc == HG_E_CAPACITY)) {

@@ -137,6 +137,16 @@ struct TraceStatus {
 };
 
 // Per-grid arguments of a walk launch.
+// Walk state of a path at its first record beyond its row (one-walk records
+// mode), taken on entry to that leaf: the record-filling walk resumes the
+// path from here instead of from its origin.
+struct Resume {
+    double s, p[3], lo[3];
+    uint64_t ref;
+    int64_t path;
+    int32_t lv, steps;
+};
+
 struct WalkArgs {
     const double *O;
     const double *K;
@@ -151,7 +161,9 @@ struct WalkArgs {
     TraceStatus *st;
     int count_rechecks;
     int64_t slab;                  // slab walk: record slots per path row
-    const int64_t *index;          // paths to walk (NULL: 0 .. n-1)
+    Resume *resume;                // slab walk: where paths past their row are saved;
+                                   // fill walk: the paths to resume (NULL: walk 0 .. n-1)
+    unsigned long long *n_resume;  // slab walk: entries written to resume
 };
 
 // Walk modes (see trace.hip).
@@ -264,6 +276,24 @@ class Carve {
 // out[0..n] = exclusive prefix sum of in[0..n-1] (out[n] = total).  tmp must
 // hold scan_tmp_elems(n) int64 values.
 size_t scan_tmp_elems(int64_t n);
+
+// Records per path row of the one-walk records mode: opts->slab rounded up to
+// a multiple of 4, else as many as keep the rows and resume entries of n
+// paths within SLAB_BUDGET bytes (at most SLAB_MAX); 0 when the rows do not
+// fit (or, for the library's choice, when fewer than SLAB_MIN would).
+constexpr double SLAB_BUDGET = double(int64_t(32) << 30);
+constexpr int64_t SLAB_MIN = 256, SLAB_MAX = 2048;
+int64_t slab_rows(const hg_trace_opts *opts, int64_t n);
+
+// The records-mode scratch of the current device: one buffer, grown on
+// demand and kept for later calls (outside the stream-ordered pool).
+// scratch_acquire locks it with at least `bytes` bytes (HG_E_OOM, nothing
+// held, when that cannot be had); the holder drains its stream before
+// scratch_release.
+struct Scratch;
+int scratch_acquire(size_t bytes, Scratch **out);
+void *scratch_ptr(Scratch *w);
+void scratch_release(Scratch *w);
 int scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
 int scan_u8_to_i64(const uint8_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
 // The same with the element count read from the device at run time (a fixed
@@ -303,13 +333,11 @@ int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
 int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *opts, int wm,
                      hipStream_t s);
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s);
-// One-pass records mode: slab rows to CSR slices (paths whose count fits the
-// row), and the list of the other paths.
+// One-pass records mode: each path's first min(count, slab) records from its
+// slab row into its CSR slice.
 int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision,
                         const int32_t *count, const int64_t *offsets, int64_t n, int32_t *leaf, void *ds,
                         hipStream_t s);
-int launch_overflow_list(const int32_t *count, int64_t n, int64_t slab, int64_t *list,
-                         unsigned long long *n_list, hipStream_t s);
 WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
                    const hg_trace_opts *opts, hg_trace_out *out);
 int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,

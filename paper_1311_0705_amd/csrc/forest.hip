@@ -31,7 +31,7 @@ constexpr int LB_N = 66;         // level-begin slots per grid
 constexpr int META = LB_N + 4;   // + n_nodes, n_leaves, depth, error
 constexpr int M_NODES = LB_N, M_LEAVES = LB_N + 1, M_DEPTH = LB_N + 2, M_ERR = LB_N + 3;
 constexpr unsigned FLAT_BLOCKS = 1024;    // grid-stride launches over device-sized ranges
-constexpr unsigned SAMPLE_BLOCKS = 2048;  // wavefront-per-node sampling (4 waves per block)
+constexpr unsigned SAMPLE_BLOCKS = 2048;  // node sampling: 4 wavefronts of 64 nodes per block
 // launch shapes the batch tuner tries
 const int BLOCKS[] = {128, 256, 512};
 const int BATCH_CHUNKS[] = {128, 256, 512, 1024, 2048, 4096};
@@ -115,34 +115,39 @@ __global__ void __launch_bounds__(FT) k_f_init(const ForestGrid *__restrict__ F,
     G.meta[M_ERR] = 0;
 }
 
+// P: prefix of the per-grid node counts of level lv; PW: prefix of the same
+// counts in wavefronts of 64 nodes (a wavefront never spans two grids).
 __global__ void __launch_bounds__(FT) k_f_level_prefix(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                       int64_t *P)
+                                                       int64_t *P, int64_t *PW)
 {
     block_prefix(ng, P, [&](int i) { return F[i].meta[lv + 1] - F[i].meta[lv]; });
+    __syncthreads();
+    block_prefix(ng, PW, [&](int i) { return (F[i].meta[lv + 1] - F[i].meta[lv] + 63) / 64; });
 }
 
-// One wavefront per node of level lv, over all grids.
+// One lane per node of level lv: a wavefront takes up to 64 consecutive nodes
+// of one grid, whose density and criteria then sit in scalar registers.
 __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                 const int64_t *__restrict__ P, uint8_t *__restrict__ flag)
+                                                 const int64_t *__restrict__ P,
+                                                 const int64_t *__restrict__ PW, uint8_t *__restrict__ flag)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t T = P[ng];
+    const int64_t TW = PW[ng];
     const int64_t nw = int64_t(gridDim.x) * (FT / 64);
-    for (int64_t t = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; t < T; t += nw) {
-        // the node and its grid are the same for the whole wavefront: keep the
-        // grid's density and criteria in scalar registers
-        const int i = __builtin_amdgcn_readfirstlane(owner(P, ng, t));
+    for (int64_t w = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; w < TW; w += nw) {
+        const int i = __builtin_amdgcn_readfirstlane(owner(PW, ng, w));
         const ForestGrid &G = F[i];
         const Dens D = G.D;
         const CritDev C = G.C;
-        const int64_t n = G.meta[lv] + (t - P[i]);
-        const NodeSample r = sample_node_wave(G.tree, D, C, lv, G.coord[3 * n], G.coord[3 * n + 1],
-                                              G.coord[3 * n + 2], G.bin_start);
-        if (lane == 0) {
+        const int64_t k = (w - PW[i]) * 64 + lane;   // rank of the lane's node in the level
+        if (k < P[i + 1] - P[i]) {
+            const int64_t n = G.meta[lv] + k;
+            const NodeSample r = sample_node_lane(G.tree, D, C, lv, G.coord[3 * n], G.coord[3 * n + 1],
+                                                  G.coord[3 * n + 2], G.bin_start);
             G.S[n] = r.S;
             G.rmin[n] = r.mn;
             G.rmax[n] = r.mx;
-            flag[t] = r.split ? 1 : 0;
+            flag[P[i] + k] = r.split ? 1 : 0;
         }
     }
 }
@@ -388,6 +393,7 @@ struct hg_batch {
     int64_t *meta = nullptr;        // [ng][META]
     int64_t *P = nullptr;           // [(lmax+1)][ng+1]
     int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
+    int64_t *PW = nullptr;          // [ng+1] wavefronts of 64 nodes per grid, current level
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
@@ -461,9 +467,9 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     HG_CHECK(hipGetLastError());
     for (int lv = 0; lv <= b->lmax; lv++) {
         int64_t *P = b->P + size_t(lv) * size_t(ng + 1);
-        k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, lv, P);
+        k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, lv, P, b->PW);
         HG_CHECK(hipGetLastError());
-        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag);
+        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag);
         HG_CHECK(hipGetLastError());
         int rc = scan_u8_to_i64_dev(b->flag, b->off, P + ng, b->stmp, s);
         if (rc) return rc;
@@ -580,6 +586,7 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     ct.add(&b->PN, ng1);
     ct.add(&b->PL, ng1);
     ct.add(&b->PT, ng1);
+    ct.add(&b->PW, ng1);
     ct.add(&b->flag, size_t(total_cap));
     ct.add(&b->off, size_t(total_cap) + 1);
     ct.add(&b->stmp, scan_dev_tmp_elems());
@@ -648,7 +655,8 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
         A.st = b->status;
         A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
         A.slab = 0;
-        A.index = nullptr;
+        A.resume = nullptr;
+        A.n_resume = nullptr;
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
     int rc = dalloc_n(&b->dA, size_t(b->ng), nullptr);

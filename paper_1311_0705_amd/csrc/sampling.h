@@ -86,12 +86,6 @@ __device__ inline double density_at(const Dens &D, double x0, double x1, double 
     return rho;
 }
 
-__device__ inline double read_lane_f64(double v, int lane)
-{
-    int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
-}
-
 // Optical depth of a node of sides w[3] with sampled sum S over n samples,
 // Eq. (2) with the node mass of Eq. (1): kappa M sqrt(a^2+b^2+c^2)/(abc),
 // M = S (V/N).
@@ -108,16 +102,15 @@ struct NodeSample {
     bool split;
 };
 
-// Sampling and decision for one node by one whole 64-lane wavefront (every
-// lane must call it with the same node).  Lane j draws samples j, j+64, ...;
-// the sum S runs in sample order (an ordered reduction through readlane), min
-// and max are order-free.  Eq. (1): M = V/N sum rho, delta = M/M_tot;
-// Eq. (2): tau = kappa M sqrt(a^2+b^2+c^2)/(abc); Eq. (3): q = (max-min)/max.
-__device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const CritDev &C, int lv,
+// Sampling and decision for one node by one lane: samples j = 0 .. N-1 are
+// drawn and summed in order, so S is the sequential sum of Eq. (1) with no
+// cross-lane reduction (the lanes of a wavefront take different nodes).
+// Eq. (1): M = V/N sum rho, delta = M/M_tot; Eq. (2): tau = kappa M
+// sqrt(a^2+b^2+c^2)/(abc); Eq. (3): q = (max-min)/max.
+__device__ inline NodeSample sample_node_lane(int tree, const Dens &D, const CritDev &C, int lv,
                                               uint32_t c0, uint32_t c1, uint32_t c2,
                                               const int64_t *__restrict__ bin_start)
 {
-    const int lane = threadIdx.x & 63;
     double w[3], lo[3];
     const uint32_t c[3] = {c0, c1, c2};
 #pragma unroll
@@ -127,30 +120,20 @@ __device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const Cri
     }
     const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
     double S = 0.0, mn = INFINITY, mx = -INFINITY;
-    for (int base = 0; base < C.n_samples; base += 64) {
-        const int j = base + lane;
-        double r = 0.0;
-        if (j < C.n_samples) {
-            double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
-            double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
-            double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
-            r = density_at(D, x0, x1, x2, bin_start);
-            mn = fmin(mn, r);
-            mx = fmax(mx, r);
-        }
-        const int m = min(64, C.n_samples - base);
-        for (int jj = 0; jj < m; jj++) S = S + read_lane_f64(r, jj);
+    for (int j = 0; j < C.n_samples; j++) {
+        const double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
+        const double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
+        const double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
+        const double r = density_at(D, x0, x1, x2, bin_start);
+        S = S + r;
+        mn = fmin(mn, r);
+        mx = fmax(mx, r);
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = fmin(mn, __shfl_xor(mn, o, 64));
-        mx = fmax(mx, __shfl_xor(mx, o, 64));
-    }
-    double V = w[0] * w[1] * w[2];
-    double M = S * (V / double(C.n_samples));
-    double delta = M / C.total_mass;
-    double tau = node_tau(C.kappa, S, w, C.n_samples);
-    double q = mx > 0.0 ? (mx - mn) / mx : 0.0;
+    const double V = w[0] * w[1] * w[2];
+    const double M = S * (V / double(C.n_samples));
+    const double delta = M / C.total_mass;
+    const double tau = node_tau(C.kappa, S, w, C.n_samples);
+    const double q = mx > 0.0 ? (mx - mn) / mx : 0.0;
     bool sp;
     if (lv < C.min_level) sp = true;
     else if (lv >= C.max_level) sp = false;

@@ -328,6 +328,58 @@ __device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, i
     return PATH_WALK;
 }
 
+// Fill walk of the one-walk records mode: path S.path continues from the
+// state the slab walk saved on entry to the leaf of its first record beyond
+// its row; records from there on go to its slice past the first A.slab.
+template <int TREE, int PREC, typename R>
+__device__ __forceinline__ int64_t resume_path(const WalkArgs &A, const Resume &S, Path<PREC, R> &P)
+{
+    const int64_t i = S.path;
+    P.force64 = false;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        P.p0[d] = A.O[3 * i + d];
+        P.k[d] = A.K[3 * i + d];
+        P.ainv[d] = fabs(1.0 / P.k[d]);
+        P.ainv32[d] = float(P.ainv[d]);
+        if (P.k[d] != 0.0 && !(fabs(P.k[d]) >= 1e-30)) P.force64 = true;
+        P.p[d] = S.p[d];
+        P.lo[d] = S.lo[d];
+    }
+    P.dirb = dir_bits(P.k);
+    P.s = S.s;
+    P.ref = R(S.ref);
+    P.lv = S.lv;
+    P.steps = S.steps;
+    P.tie = TIE_NONE;
+    P.cnt = 0;
+    P.tau64 = 0.0;
+    P.tau32 = 0.f;
+    P.comp32 = 0.f;
+    P.base = A.offsets[i] + A.slab;
+    P.room = A.offsets[i + 1] - P.base;
+    return i;
+}
+
+template <int PREC, typename R>
+__device__ __forceinline__ void save_resume(const WalkArgs &A, const Path<PREC, R> &P)
+{
+    if (!A.resume) return;   // a slab walk that only counts (the autotuner's)
+    const unsigned long long j = atomicAdd(A.n_resume, 1ull);
+    if (j >= (unsigned long long)A.n) return;   // at most one entry per path: never taken
+    Resume &S = A.resume[j];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        S.p[d] = P.p[d];
+        S.lo[d] = P.lo[d];
+    }
+    S.s = P.s;
+    S.ref = uint64_t(P.ref);
+    S.path = P.base / A.slab;
+    S.lv = P.lv;
+    S.steps = P.steps;
+}
+
 enum { STEP_GO = 0, STEP_END = 1, STEP_ERR = 2 };
 
 // Fill walk: records are staged four at a time and written as aligned 16-byte
@@ -453,9 +505,11 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
             // the fill walk must repeat the counting walk
             if (P.cnt < P.room) stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
             else err = true;
-        } else if (WM == WM_SLAB && P.cnt < P.room) {
-            // records beyond the slab are dropped; such paths are walked again
-            stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+        } else if (WM == WM_SLAB) {
+            // records beyond the row are left to the fill walk, which resumes
+            // the path at the first of them
+            if (P.cnt < P.room) stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+            else if (P.cnt == P.room) save_resume<PREC, R>(A, P);
         }
         if (WM == WM_FILL) {
         } else if (PREC == HG_FP64) {
@@ -541,9 +595,11 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 {
     const int64_t q = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (q >= A.n) return;
-    const int64_t i = A.index ? A.index[q] : q;
     Path<PREC, R> P;
-    const int why = init_path<TREE, PREC, WM, R>(G, A, i, P);
+    int64_t i = q;
+    int why = PATH_WALK;
+    if (WM == WM_FILL && A.resume) i = resume_path<TREE, PREC, R>(A, A.resume[q], P);
+    else why = init_path<TREE, PREC, WM, R>(G, A, i, P);
     if (why != PATH_WALK) {
         finish_unwalked<PREC, WM>(A, i, why);
         return;
@@ -613,8 +669,10 @@ __global__ void __launch_bounds__(BT)
                 const uint32_t rank = uint32_t(__popcll(wmask & below));
                 if (rank < avail) {
                     const int64_t q = int64_t(cnext) + rank;
-                    const int64_t r = A.index ? A.index[q] : q;
-                    const int why = init_path<TREE, PREC, WM, R>(G, A, r, P);
+                    int64_t r = q;
+                    int why = PATH_WALK;
+                    if (WM == WM_FILL && A.resume) r = resume_path<TREE, PREC, R>(A, A.resume[q], P);
+                    else why = init_path<TREE, PREC, WM, R>(G, A, r, P);
                     if (why == PATH_WALK) ray = r;
                     else finish_unwalked<PREC, WM>(A, r, why);
                 } else if (drained) {
@@ -802,9 +860,12 @@ __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
 // records) into the CSR slices.  A block takes CP consecutive paths, whose
 // slices form one contiguous range of the output, and its threads walk that
 // range in order (coalesced writes), each finding its path by a binary search
-// over the block's offsets in LDS.  Paths with more records than their row are
-// left to the fill walk.
+// over the block's offsets in LDS.  Each thread moves CU records per round
+// (TB apart), issuing all their loads before any store.  A path with more
+// records than its row gets its first `slab` here, the rest from the fill
+// walk.
 constexpr int CP = 256;
+constexpr int CU = 4;
 
 template <typename DsT>
 __global__ void __launch_bounds__(TB)
@@ -818,42 +879,38 @@ __global__ void __launch_bounds__(TB)
     for (int j = threadIdx.x; j <= np; j += TB) off[j] = offsets[p0 + j];
     __syncthreads();
     const int64_t d0 = off[0], d1 = off[np];
-    for (int64_t d = d0 + threadIdx.x; d < d1; d += TB) {
-        int lo = 0, hi = np;   // the path q with off[q] <= d < off[q+1]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (off[mid] <= d) lo = mid;
-            else hi = mid;
+    int lo = 0;   // the path of the thread's previous record: the search starts there
+    for (int64_t db = d0 + threadIdx.x; db < d1; db += int64_t(CU) * TB) {
+        int64_t src[CU];
+        bool ok[CU];
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            const int64_t d = db + int64_t(u) * TB;
+            int hi = np;   // the path q with off[q] <= d < off[q+1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid] <= d) lo = mid;
+                else hi = mid;
+            }
+            ok[u] = d < d1 && d - off[lo] < slab;
+            src[u] = (p0 + lo) * slab + (d - off[lo]);
         }
-        const int64_t c = off[lo + 1] - off[lo];
-        if (c > slab) continue;
-        const int64_t src = (p0 + lo) * slab + (d - off[lo]);
-        leaf[d] = sleaf[src];
-        ds[d] = sds[src];
+        int32_t lf[CU];
+        DsT dv[CU];
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            lf[u] = ok[u] ? sleaf[src[u]] : 0;
+            dv[u] = ok[u] ? sds[src[u]] : DsT(0);
+        }
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            const int64_t d = db + int64_t(u) * TB;
+            if (ok[u]) {
+                leaf[d] = lf[u];
+                ds[d] = dv[u];
+            }
+        }
     }
-}
-
-// Paths whose records overflow their row; one atomic per block.
-constexpr int OV_PER = 16;
-
-__global__ void __launch_bounds__(TB)
-    k_overflow_list(const int32_t *__restrict__ count, int64_t n, int64_t slab, int64_t *__restrict__ list,
-                    unsigned long long *__restrict__ n_list)
-{
-    __shared__ int64_t found[TB * OV_PER];
-    __shared__ unsigned nf;
-    __shared__ unsigned long long base;
-    if (threadIdx.x == 0) nf = 0u;
-    __syncthreads();
-    const int64_t b0 = int64_t(blockIdx.x) * TB * OV_PER;
-    for (int j = 0; j < OV_PER; j++) {
-        const int64_t i = b0 + int64_t(j) * TB + threadIdx.x;
-        if (i < n && count[i] > slab) found[atomicAdd(&nf, 1u)] = i;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) base = nf ? atomicAdd(n_list, (unsigned long long)nf) : 0ull;
-    __syncthreads();
-    for (unsigned j = threadIdx.x; j < nf; j += TB) list[base + j] = found[j];
 }
 
 constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
@@ -892,8 +949,8 @@ int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts 
     for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
         WalkArgs B = A;
         B.n = std::min(PERSIST_CHUNK, A.n - start);
-        if (A.index) {
-            B.index = A.index + start;
+        if (WM == WM_FILL && A.resume) {
+            B.resume = A.resume + start;
         } else {
             B.O = A.O + 3 * start;
             B.K = A.K + 3 * start;
@@ -1042,7 +1099,8 @@ WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n
     A.st = g->status;
     A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
     A.slab = 0;
-    A.index = nullptr;
+    A.resume = nullptr;
+    A.n_resume = nullptr;
     return A;
 }
 
@@ -1073,16 +1131,6 @@ int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int pr
     else
         k_slab_compact<float><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const float *)sds, slab,
                                                     count, offsets, n, leaf, (float *)ds);
-    HG_CHECK(hipGetLastError());
-    return HG_OK;
-}
-
-int launch_overflow_list(const int32_t *count, int64_t n, int64_t slab, int64_t *list,
-                         unsigned long long *n_list, hipStream_t s)
-{
-    if (n == 0) return HG_OK;
-    const int64_t per = int64_t(TB) * OV_PER;
-    k_overflow_list<<<unsigned((n + per - 1) / per), TB, 0, s>>>(count, n, slab, list, n_list);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }

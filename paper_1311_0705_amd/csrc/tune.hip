@@ -135,13 +135,23 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     if (!rc) rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
     int64_t needed = 0;
     // records mode: the one-pass walk (as grid_trace runs it) unless two passes are asked for
-    const bool slab_mode = records && opts->passes != 2;
-    const int64_t slab = opts->slab > 0 ? (int64_t(opts->slab) + 3) / 4 * 4 : 256;
+    const int64_t slab = slab_rows(opts, n);
+    bool slab_mode = records && opts->passes != 2 && slab > 0;
     const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
     int32_t *sleaf = nullptr;
     void *sds = nullptr;
-    if (!rc && slab_mode) rc = dalloc_n(&sleaf, size_t(n) * size_t(slab), s);
-    if (!rc && slab_mode) rc = dalloc(&sds, size_t(n) * size_t(slab) * dsz, s);
+    Scratch *w = nullptr;
+    if (!rc && slab_mode) {
+        const size_t b_leaf = (size_t(n) * size_t(slab) * 4 + 255) & ~size_t(255);
+        rc = scratch_acquire(b_leaf + size_t(n) * size_t(slab) * dsz, &w);
+        if (!rc) {
+            sleaf = static_cast<int32_t *>(scratch_ptr(w));
+            sds = static_cast<char *>(scratch_ptr(w)) + b_leaf;
+        } else if (rc == HG_E_OOM) {
+            rc = HG_OK;   // tune the two-walk records mode, as grid_trace would run it
+            slab_mode = false;
+        }
+    }
     if (!rc) {
         hipError_t e = hipMemsetAsync(g->status, 0, sizeof(TraceStatus), s);
         if (e) rc = set_hip_error(e);
@@ -202,8 +212,7 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     dfree(out.leaf, s);
     dfree(out.ds, s);
     dfree(tmp, s);
-    dfree(sleaf, s);
-    dfree(sds, s);
+    if (w) scratch_release(w);
     return rc;
 }
 

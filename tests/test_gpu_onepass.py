@@ -58,3 +58,18 @@ def test_one_pass_capacity_error(disk):
     # the binding retries with the size it reports
     r1 = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, passes=1)
     assert r1["needed"] == need and torch.equal(r1["tau"], r["tau"])
+
+
+def test_scratch_grows_and_is_released(disk):
+    # the one-walk scratch is kept per device: a smaller call after a larger
+    # one reuses it, a larger row size grows it, and after its release the
+    # next call allocates it again; every result equals the two-walk result
+    g, o, k = disk
+    two = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, passes=2)
+    m = o.shape[0] // 3
+    small = g.trace(o[:m], k[:m], precision=hg.FP32_RECHECK, mode=hg.RECORDS, passes=2)
+    for slab, oo, kk, want in ((64, o, k, two), (64, o[:m], k[:m], small), (512, o, k, two)):
+        _same(want, g.trace(oo, kk, precision=hg.FP32_RECHECK, mode=hg.RECORDS, passes=1, slab=slab))
+    hg.release_scratch(DEV)
+    hg.release_scratch(DEV)   # nothing held: a no-op
+    _same(two, g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, passes=1))
