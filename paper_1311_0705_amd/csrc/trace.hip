@@ -444,7 +444,8 @@ __device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC
 // made unconditionally.
 template <int TREE, int PREC, int WM, typename R>
 __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC, R> &P,
-                                     unsigned long long &rechecks)
+                                     unsigned long long &rechecks, uint32_t *sl = nullptr,
+                                     typename Path<PREC, R>::DsT *sd = nullptr, int sgm = 0)
 {
     const bool ok = ref_ok(G, P.ref);
     const uint64_t id = ok ? Ref<R>::id(P.ref) : 0u;
@@ -501,15 +502,33 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     const char *rec = static_cast<const char *>(G.rec) + id * Rec<R, PREC>::STRIDE;
     const R nref = reinterpret_cast<const R *>(rec)[face];
     if (ds > 0.0) {
+        // sl / sd: the lane's record slots in LDS (persistent walk), else
+        // records are staged in registers
         if (WM == WM_FILL) {
             // the fill walk must repeat the counting walk
-            if (P.cnt < P.room) stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
-            else err = true;
+            if (P.cnt < P.room) {
+                if (sl) {
+                    sl[P.cnt & sgm] = uint32_t(id);
+                    sd[P.cnt & sgm] = typename Path<PREC, R>::DsT(ds);
+                } else {
+                    stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+                }
+            } else {
+                err = true;
+            }
         } else if (WM == WM_SLAB) {
             // records beyond the row are left to the fill walk, which resumes
             // the path at the first of them
-            if (P.cnt < P.room) stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
-            else if (P.cnt == P.room) save_resume<PREC, R>(A, P);
+            if (P.cnt < P.room) {
+                if (sl) {
+                    sl[P.cnt & sgm] = uint32_t(id);
+                    sd[P.cnt & sgm] = typename Path<PREC, R>::DsT(ds);
+                } else {
+                    stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+                }
+            } else if (P.cnt == P.room) {
+                save_resume<PREC, R>(A, P);
+            }
         }
         if (WM == WM_FILL) {
         } else if (PREC == HG_FP64) {
@@ -562,15 +581,15 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     return err ? STEP_ERR : (end ? STEP_END : STEP_GO);
 }
 
-template <int PREC, int WM, typename R>
+template <int PREC, int WM, typename R, bool STG = false>
 __device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Path<PREC, R> &P)
 {
     if (WM == WM_FILL) {
-        flush_records<PREC, R>(A, P);
+        if (!STG) flush_records<PREC, R>(A, P);
         if (P.cnt != P.room) A.st->step_guard = 1;
         return;
     }
-    if (WM == WM_SLAB) flush_records<PREC, R>(A, P);
+    if (WM == WM_SLAB && !STG) flush_records<PREC, R>(A, P);
     A.count[i] = P.cnt;
     if (PREC == HG_FP64) A.tau[i] = P.tau64;
     else A.tau[i] = double(P.tau32) - double(P.comp32);
@@ -622,6 +641,51 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
     if (!(WM == WM_FILL) && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
 }
 
+// Records staged in LDS by the persistent walk (record modes): each lane owns
+// SG slots of leaf ids and SG of ds (rows of SG + 1 words against bank
+// conflicts).  A lane's group is written out once it holds SG records, its
+// row is full or its path ends, by the whole wavefront: SG lanes per group,
+// 64 / SG groups per store instruction, so that a store covers a few cache
+// lines instead of one line per lane.
+template <int BT>
+struct StageShape {
+    static constexpr int SG = BT <= 256 ? 16 : 8;
+    static constexpr int SP = SG + 1;
+};
+
+// Write the groups of the lanes with nr > 0: records pos .. pos+nr-1 of the
+// output come from slots 0 .. nr-1 of that lane.  Wavefront-uniform.
+template <int BT, typename DsT>
+__device__ __forceinline__ void flush_stage(const WalkArgs &A, const uint32_t *stl, const DsT *stds, int nr,
+                                            int64_t pos, int lane)
+{
+    constexpr int SG = StageShape<BT>::SG, SP = StageShape<BT>::SP, PER = 64 / SG;
+    uint64_t fm = __ballot(nr > 0);
+    if (!fm) return;
+    __builtin_amdgcn_wave_barrier();
+    const int g = lane / SG, j = lane % SG;
+    const int wbase = int(threadIdx.x) & ~63;
+    while (fm) {
+        int src = -1;
+#pragma unroll
+        for (int k = 0; k < PER; k++) {
+            const int b = fm ? __builtin_ctzll(fm) : -1;
+            if (k == g) src = b;
+            fm &= fm - 1;
+        }
+        const int s = src < 0 ? 0 : src;
+        const int rr = __shfl(nr, s, 64);
+        const int plo = __shfl(int(uint64_t(pos) & 0xffffffffu), s, 64);
+        const int phi = __shfl(int(uint64_t(pos) >> 32), s, 64);
+        const int64_t pp = int64_t((uint64_t(uint32_t(phi)) << 32) | uint32_t(plo));
+        if (src >= 0 && j < rr) {
+            const int t = (wbase + s) * SP + j;
+            A.leaf[pp + j] = int32_t(stl[t]);
+            static_cast<DsT *>(A.ds)[pp + j] = stds[t];
+        }
+    }
+}
+
 // Persistent walk: each wavefront keeps its lanes busy by handing new paths
 // to lanes whose path ended.  Refills happen in batches (once at least
 // refill_min lanes are idle, or none is busy) from a wavefront-local chunk of
@@ -631,7 +695,8 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 // (the first levels of every descent come from LDS) or a crossing.
 template <int TREE, int PREC, int WM, typename R, int BT>
 __global__ void __launch_bounds__(BT)
-    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min)
+    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min,
+                      uint32_t stage_off)
 {
     extern __shared__ uint64_t lds_raw[];
     R *lds = reinterpret_cast<R *>(lds_raw);
@@ -639,6 +704,19 @@ __global__ void __launch_bounds__(BT)
     for (uint32_t j = threadIdx.x; j < lds_n * nc; j += BT) lds[j] = static_cast<const R *>(G.child)[j];
     __syncthreads();
     const int lane = threadIdx.x & 63;
+    // record modes: LDS staging of the records (see flush_stage)
+    constexpr bool STG = WM != WM_COUNT;
+    constexpr int SG = StageShape<BT>::SG, SP = StageShape<BT>::SP;
+    using DsT = typename Path<PREC, R>::DsT;
+    uint32_t *stl = nullptr, *my_l = nullptr;
+    DsT *stds = nullptr, *my_d = nullptr;
+    if (STG) {
+        char *sb = reinterpret_cast<char *>(lds_raw) + stage_off;
+        stl = reinterpret_cast<uint32_t *>(sb);
+        stds = reinterpret_cast<DsT *>(sb + size_t(BT) * SP * 4);
+        my_l = stl + threadIdx.x * SP;
+        my_d = stds + threadIdx.x * SP;
+    }
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     Path<PREC, R> P;
     int64_t ray = -1;
@@ -687,7 +765,8 @@ __global__ void __launch_bounds__(BT)
         }
         // One predicate per region (no nesting), so the path state needs no
         // copies at region boundaries.
-        bool bad = false, fin = false;
+        bool bad = false, fin = false, crossed = false;
+        int32_t c_before = 0;
         if (ray >= 0 && !Ref<R>::leaf(P.ref)) {
             // LDS levels, then at most one global level this iteration
             for (;;) {
@@ -702,14 +781,30 @@ __global__ void __launch_bounds__(BT)
             bad = P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref));
         }
         if (ray >= 0 && !bad && Ref<R>::leaf(P.ref)) {
-            const int r = cross<TREE, PREC, WM, R>(G, A, P, rechecks);
+            c_before = P.cnt;
+            const int r = cross<TREE, PREC, WM, R>(G, A, P, rechecks, my_l, my_d, SG - 1);
+            crossed = true;
             const bool guard = r == STEP_ERR || ++P.steps >= STEP_GUARD;
             if (guard) A.st->step_guard = 1;
             fin = guard || r == STEP_END;
         }
+        if (STG) {
+            // the group to write out this iteration: complete, the row full, or
+            // the last records of an ended path
+            int nr = 0;
+            int64_t pos = 0;
+            if (ray >= 0 && (crossed || bad)) {
+                const int64_t c = P.cnt < P.room ? P.cnt : P.room;
+                const bool wrote = crossed && P.cnt > c_before && c_before < P.room;
+                if (wrote && ((c & (SG - 1)) == 0 || c == P.room)) nr = int(((c - 1) & (SG - 1)) + 1);
+                else if ((bad || fin) && c != P.room) nr = int(c & (SG - 1));
+                pos = P.base + c - nr;
+            }
+            flush_stage<BT, DsT>(A, stl, stds, nr, pos, lane);
+        }
         if (bad || fin) {
             if (bad) A.st->bad_ref = 1;
-            finish_path<PREC, WM, R>(A, ray, P);
+            finish_path<PREC, WM, R, STG>(A, ray, P);
             ray = -1;
         }
     }
@@ -934,13 +1029,35 @@ int persistent_blocks(size_t lds, unsigned *blocks)
     return HG_OK;
 }
 
+// LDS a block may allocate on the current device (cached).
+inline size_t max_block_lds()
+{
+    static size_t v = 0;
+    if (!v) {
+        int dev = 0, b = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
+            v = size_t(b);
+        else
+            v = 65536;
+    }
+    return v;
+}
+
 template <int TREE, int PREC, int WM, typename R, int BT>
 int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts *o, hipStream_t s)
 {
     const int nc = TREE == OCT ? 8 : 2;
-    const size_t want = o->lds_bytes < 0 ? 0 : (o->lds_bytes == 0 ? LDS_BYTES : size_t(o->lds_bytes));
+    // record modes stage records in LDS behind the top-level child references
+    const size_t stage = WM == WM_COUNT ? 0
+                                        : size_t(BT) * StageShape<BT>::SP * (4 + (PREC == HG_FP64 ? 8 : 4));
+    const size_t cap = max_block_lds();
+    if (stage + 16 > cap) return HG_E_INVAL;
+    const size_t want = std::min(o->lds_bytes < 0 ? 0 : (o->lds_bytes == 0 ? LDS_BYTES : size_t(o->lds_bytes)),
+                                 cap - stage - 16);
     const uint32_t lds_n = uint32_t(std::min<uint64_t>(G.n_internal, want / (sizeof(R) * size_t(nc))));
-    const size_t lds = size_t(lds_n) * nc * sizeof(R);
+    const uint32_t stage_off = uint32_t((size_t(lds_n) * nc * sizeof(R) + 15) & ~size_t(15));
+    const size_t lds = stage_off + stage;
     unsigned blocks = 0;
     int rc = persistent_blocks<TREE, PREC, WM, R, BT>(lds, &blocks);
     if (rc) return rc;
@@ -961,7 +1078,7 @@ int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts 
         k_reset_counter<<<1, 1, 0, s>>>(A.st);
         HG_CHECK(hipGetLastError());
         k_walk_persistent<TREE, PREC, WM, R, BT><<<dim3(blocks), dim3(BT), lds, s>>>(G, B, lds_n, chunk,
-                                                                                         refill_min);
+                                                                                         refill_min, stage_off);
         HG_CHECK(hipGetLastError());
     }
     return HG_OK;
