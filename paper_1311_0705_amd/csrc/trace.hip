@@ -693,8 +693,10 @@ __device__ __forceinline__ void flush_stage(const WalkArgs &A, const uint32_t *s
 // path set-up and the atomic round trip are amortised over many paths.  Each
 // iteration a busy lane performs one dependent global access: a descent step
 // (the first levels of every descent come from LDS) or a crossing.
+// Four wavefronts per SIMD: the record modes would otherwise take a few more
+// than 128 VGPRs and run three (the few spills this costs are cheaper).
 template <int TREE, int PREC, int WM, typename R, int BT>
-__global__ void __launch_bounds__(BT)
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min,
                       uint32_t stage_off)
 {
