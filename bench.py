@@ -63,6 +63,10 @@ B_X_COUNT64 = 28
 # The one-pass records walk reads the path (48 B) and writes tau + count (12 B).
 B_RAY_SLAB = 48 + 12
 
+# Paths the launch-shape autotuner times each candidate on (a sample large
+# enough that the walk's tail does not dominate the timing).
+TUNE_PATHS = 10_000_000
+
 # HBM traffic of the dominant kernel from rocprofv3 --pmc runs (FETCH_SIZE and
 # WRITE_SIZE in KiB per dispatch), scaled by what the same counters read for a
 # 1 GiB device copy (FETCH_SIZE reads 0.5 GiB for it, WRITE_SIZE 1.0 GiB).
@@ -246,7 +250,7 @@ def run_single(a, w):
     needed, rechecks = res["needed"], res["rechecks"]
     tuned = {}
     if not a.no_tune:
-        m = min(n, 1_000_000)
+        m = min(n, TUNE_PATHS)
         for prec in (hg.FP32_RECHECK, hg.FP64):
             tuned[prec] = hg.tune_cached(g, o[:m], k[:m], precision=prec, mode=hg.RECORDS)
         log(f"tuned launch shapes: {tuned}")
@@ -388,9 +392,9 @@ def run_c3(a, w):
     tuned = {}
     if not a.no_tune:
         for mode in (hg.TAU_ONLY, hg.RECORDS):
-            tuned[mode] = hg.tune_cached(g, o[:1_000_000], k[:1_000_000], precision=hg.FP32_RECHECK,
+            tuned[mode] = hg.tune_cached(g, o[:TUNE_PATHS], k[:TUNE_PATHS], precision=hg.FP32_RECHECK,
                                          mode=mode)
-        tuned["fp64_tau"] = hg.tune_cached(g, o[:1_000_000], k[:1_000_000], precision=hg.FP64,
+        tuned["fp64_tau"] = hg.tune_cached(g, o[:TUNE_PATHS], k[:TUNE_PATHS], precision=hg.FP64,
                                            mode=hg.TAU_ONLY)
         log(f"tuned launch shapes: {tuned}")
     tt = tuned.get(hg.TAU_ONLY)
@@ -641,7 +645,7 @@ def run_c5(a, w):
     log(f"build {build_s:.2f} s: {g.n_leaves} leaves")
     tt = None
     if not a.no_tune:
-        tt = hg.tune_cached(g, o[:1_000_000], k0[:1_000_000], precision=hg.FP32_RECHECK,
+        tt = hg.tune_cached(g, o[:TUNE_PATHS], k0[:TUNE_PATHS], precision=hg.FP32_RECHECK,
                             mode=hg.TAU_ONLY)
         log(f"tuned {tt}")
     res = g.trace(o, k0, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt)

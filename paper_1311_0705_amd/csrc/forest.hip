@@ -125,6 +125,32 @@ __global__ void __launch_bounds__(FT) k_f_level_prefix(const ForestGrid *__restr
     block_prefix(ng, PW, [&](int i) { return (F[i].meta[lv + 1] - F[i].meta[lv] + 63) / 64; });
 }
 
+// One wavefront per node of level lv, over all grids.
+__global__ void __launch_bounds__(FT) k_f_sample_wave(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                      const int64_t *__restrict__ P,
+                                                      uint8_t *__restrict__ flag)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t T = P[ng];
+    const int64_t nw = int64_t(gridDim.x) * (FT / 64);
+    for (int64_t t = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; t < T; t += nw) {
+        // the node and its grid are the same for the whole wavefront
+        const int i = __builtin_amdgcn_readfirstlane(owner(P, ng, t));
+        const ForestGrid &G = F[i];
+        const Dens D = G.D;
+        const CritDev C = G.C;
+        const int64_t n = G.meta[lv] + (t - P[i]);
+        const NodeSample r = sample_node_wave(G.tree, D, C, lv, G.coord[3 * n], G.coord[3 * n + 1],
+                                              G.coord[3 * n + 2], G.bin_start);
+        if (lane == 0) {
+            G.S[n] = r.S;
+            G.rmin[n] = r.mn;
+            G.rmax[n] = r.mx;
+            flag[t] = r.split ? 1 : 0;
+        }
+    }
+}
+
 // One lane per node of level lv: a wavefront takes up to 64 consecutive nodes
 // of one grid, whose density and criteria then sit in scalar registers.
 __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ F, int ng, int lv,
@@ -394,6 +420,7 @@ struct hg_batch {
     int64_t *P = nullptr;           // [(lmax+1)][ng+1]
     int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
     int64_t *PW = nullptr;          // [ng+1] wavefronts of 64 nodes per grid, current level
+    bool wave_sampling = false;     // one wavefront per node (densities with many clumps)
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
@@ -469,7 +496,10 @@ int enqueue_build(hg_batch *b, hipStream_t s)
         int64_t *P = b->P + size_t(lv) * size_t(ng + 1);
         k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, lv, P, b->PW);
         HG_CHECK(hipGetLastError());
-        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag);
+        if (b->wave_sampling)
+            k_f_sample_wave<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag);
+        else
+            k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag);
         HG_CHECK(hipGetLastError());
         int rc = scan_u8_to_i64_dev(b->flag, b->off, P + ng, b->stmp, s);
         if (rc) return rc;
@@ -537,6 +567,7 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     }
     hg_batch *b = new hg_batch;
     b->ng = n_grids;
+    for (int i = 0; i < n_grids; i++) b->wave_sampling |= dens[i].n_clumps >= WAVE_SAMPLING_CLUMPS;
     b->lmax = lmax;
     b->dens.resize(size_t(n_grids));
     b->hF.resize(size_t(n_grids));

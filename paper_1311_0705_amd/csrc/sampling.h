@@ -102,33 +102,12 @@ struct NodeSample {
     bool split;
 };
 
-// Sampling and decision for one node by one lane: samples j = 0 .. N-1 are
-// drawn and summed in order, so S is the sequential sum of Eq. (1) with no
-// cross-lane reduction (the lanes of a wavefront take different nodes).
-// Eq. (1): M = V/N sum rho, delta = M/M_tot; Eq. (2): tau = kappa M
-// sqrt(a^2+b^2+c^2)/(abc); Eq. (3): q = (max-min)/max.
-__device__ inline NodeSample sample_node_lane(int tree, const Dens &D, const CritDev &C, int lv,
-                                              uint32_t c0, uint32_t c1, uint32_t c2,
-                                              const int64_t *__restrict__ bin_start)
+// The criteria of Sect. 2.2 / 4 for a node of sides w with sampled sum S,
+// minimum mn and maximum mx: Eq. (1) M = V/N sum rho, delta = M/M_tot;
+// Eq. (2) tau = kappa M sqrt(a^2+b^2+c^2)/(abc); Eq. (3) q = (max-min)/max.
+__device__ inline NodeSample decide_node(const CritDev &C, int lv, const double w[3], double S, double mn,
+                                         double mx)
 {
-    double w[3], lo[3];
-    const uint32_t c[3] = {c0, c1, c2};
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        w[d] = ldexp(D.side, -axis_depth(tree, lv, d));
-        lo[d] = D.lo[d] + double(c[d]) * w[d];
-    }
-    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
-    double S = 0.0, mn = INFINITY, mx = -INFINITY;
-    for (int j = 0; j < C.n_samples; j++) {
-        const double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
-        const double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
-        const double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
-        const double r = density_at(D, x0, x1, x2, bin_start);
-        S = S + r;
-        mn = fmin(mn, r);
-        mx = fmax(mx, r);
-    }
     const double V = w[0] * w[1] * w[2];
     const double M = S * (V / double(C.n_samples));
     const double delta = M / C.total_mass;
@@ -140,6 +119,86 @@ __device__ inline NodeSample sample_node_lane(int tree, const Dens &D, const Cri
     else sp = delta > C.delta_max || tau > C.tau_max || q > C.q_max;
     return NodeSample{S, mn, mx, sp};
 }
+
+__device__ inline void node_box(int tree, const Dens &D, int lv, const uint32_t c[3], double w[3], double lo[3])
+{
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        w[d] = ldexp(D.side, -axis_depth(tree, lv, d));
+        lo[d] = D.lo[d] + double(c[d]) * w[d];
+    }
+}
+
+// One node per lane: samples j = 0 .. N-1 are drawn and summed in order, so
+// S is the sequential sum of Eq. (1) with no cross-lane reduction (the lanes
+// of a wavefront take different nodes).
+__device__ inline NodeSample sample_node_lane(int tree, const Dens &D, const CritDev &C, int lv,
+                                              uint32_t c0, uint32_t c1, uint32_t c2,
+                                              const int64_t *__restrict__ bin_start)
+{
+    const uint32_t c[3] = {c0, c1, c2};
+    double w[3], lo[3];
+    node_box(tree, D, lv, c, w, lo);
+    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
+    double S = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int j = 0; j < C.n_samples; j++) {
+        const double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
+        const double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
+        const double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
+        const double r = density_at(D, x0, x1, x2, bin_start);
+        S = S + r;
+        mn = fmin(mn, r);
+        mx = fmax(mx, r);
+    }
+    return decide_node(C, lv, w, S, mn, mx);
+}
+
+__device__ inline double read_lane_f64(double v, int lane)
+{
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
+}
+
+// One node per wavefront (every lane calls it with the same node): lane l
+// draws samples l, l+64, ...; S runs in sample order through an ordered
+// readlane reduction, min and max are order-free.  All lanes then evaluate
+// the density in the same clump bin, which pays when bins hold many clumps.
+__device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const CritDev &C, int lv,
+                                              uint32_t c0, uint32_t c1, uint32_t c2,
+                                              const int64_t *__restrict__ bin_start)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t c[3] = {c0, c1, c2};
+    double w[3], lo[3];
+    node_box(tree, D, lv, c, w, lo);
+    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
+    double S = 0.0, mn = INFINITY, mx = -INFINITY;
+    for (int base = 0; base < C.n_samples; base += 64) {
+        const int j = base + lane;
+        double r = 0.0;
+        if (j < C.n_samples) {
+            const double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
+            const double x1 = lo[1] + sample_unit(key, j, 1) * w[1];
+            const double x2 = lo[2] + sample_unit(key, j, 2) * w[2];
+            r = density_at(D, x0, x1, x2, bin_start);
+            mn = fmin(mn, r);
+            mx = fmax(mx, r);
+        }
+        const int m = min(64, C.n_samples - base);
+        for (int jj = 0; jj < m; jj++) S = S + read_lane_f64(r, jj);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mn = fmin(mn, __shfl_xor(mn, o, 64));
+        mx = fmax(mx, __shfl_xor(mx, o, 64));
+    }
+    return decide_node(C, lv, w, S, mn, mx);
+}
+
+// Node sampling one wavefront per node for densities with at least this many
+// clumps (clustered clumps fill bins with many of them; lanes on different
+// nodes would then loop over different bins), one lane per node otherwise.
+constexpr int64_t WAVE_SAMPLING_CLUMPS = 10000;
 
 // Level and cell coordinates of child k of a node (k-d: split axis level mod
 // 3, lower half first; octree: octant k = bx + 2 by + 4 bz).
