@@ -73,12 +73,11 @@ TUNE_PATHS = 10_000_000
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_slab": {"trace_sha256": "76099b5cc86302a183a02c847bc5552102c3b75a97c956b13c9d0ff5768342bb",
-                "fetch_kib": 30386684.1, "write_kib": 11106693.4, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "76099b5cc86302a183a02c847bc5552102c3b75a97c956b13c9d0ff5768342bb",
-                 "fetch_kib": 93699529.8, "write_kib": 6975292.0, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "76dffd241aa16e7281584f6795403f5de12bb70beee2ce9c64241bb258fc40bf",
+                "fetch_kib": 28734270.4, "write_kib": 6090678.9, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "76dffd241aa16e7281584f6795403f5de12bb70beee2ce9c64241bb258fc40bf",
+                 "fetch_kib": 93925011.0, "write_kib": 6937152.4, "fetch_scale": 2.0, "write_scale": 1.0},
 }
-
 
 def parse():
     p = argparse.ArgumentParser()
