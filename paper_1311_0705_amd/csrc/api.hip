@@ -545,6 +545,10 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
     void *sds = base + b_leaf;
     int64_t *tmp = reinterpret_cast<int64_t *>(base + b_leaf + b_ds);
     Resume *res = reinterpret_cast<Resume *>(base + b_leaf + b_ds + b_tmp);
+    // FP32 records of the persistent slab walk go to rows of (leaf, ds) pairs
+    // (the leaf and ds areas together); other walks write the two areas
+    const int pmode = opts->persistent < 0 ? 3 : opts->persistent;
+    const int pairs = (pmode & 1) && opts->precision != HG_FP64 ? 1 : 0;
     unsigned long long *n_res = reinterpret_cast<unsigned long long *>(base + b_leaf + b_ds + b_tmp + b_res);
     TraceStatus st;
     struct {
@@ -564,6 +568,7 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
         A.capacity = n * slab;
         A.resume = res;
         A.n_resume = n_res;
+        A.pairs = pairs;
         if (timing) (void)hipEventRecord(ev[0], s);
         rc = launch_walk_args(g, A, opts, WM_SLAB, s);
         if (timing) (void)hipEventRecord(ev[1], s);
@@ -581,7 +586,7 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
         out->needed = h.needed;
         if (h.needed > out->capacity) rc = HG_E_CAPACITY;
     }
-    if (!rc) rc = launch_slab_compact(sleaf, sds, slab, opts->precision, out->count, out->offsets, n,
+    if (!rc) rc = launch_slab_compact(sleaf, sds, slab, opts->precision, pairs, out->count, out->offsets, n,
                                       out->leaf, out->ds, s);
     if (!rc && h.n_res > 0) {
         // the paths past their row, resumed where their row filled up

@@ -164,6 +164,8 @@ struct WalkArgs {
     Resume *resume;                // slab walk: where paths past their row are saved;
                                    // fill walk: the paths to resume (NULL: walk 0 .. n-1)
     unsigned long long *n_resume;  // slab walk: entries written to resume
+    int pairs;                     // persistent slab walk, FP32 records: rows of (leaf, ds32)
+                                   // pairs in leaf (ds unused)
 };
 
 // Walk modes (see trace.hip).
@@ -334,8 +336,8 @@ int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *o
                      hipStream_t s);
 int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, hipStream_t s);
 // One-pass records mode: each path's first min(count, slab) records from its
-// slab row into its CSR slice.
-int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision,
+// slab row into its CSR slice (rows of (leaf, ds32) pairs when pairs is set).
+int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision, int pairs,
                         const int32_t *count, const int64_t *offsets, int64_t n, int32_t *leaf, void *ds,
                         hipStream_t s);
 WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,

@@ -688,6 +688,7 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
         A.slab = 0;
         A.resume = nullptr;
         A.n_resume = nullptr;
+        A.pairs = 0;
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
     int rc = dalloc_n(&b->dA, size_t(b->ng), nullptr);

@@ -654,7 +654,8 @@ struct StageShape {
 };
 
 // Write the groups of the lanes with nr > 0: records pos .. pos+nr-1 of the
-// output come from slots 0 .. nr-1 of that lane.  Wavefront-uniform.
+// output come from slots 0 .. nr-1 of that lane (into the rows of (leaf, ds)
+// pairs when A.pairs is set).  Wavefront-uniform.
 template <int BT, typename DsT>
 __device__ __forceinline__ void flush_stage(const WalkArgs &A, const uint32_t *stl, const DsT *stds, int nr,
                                             int64_t pos, int lane)
@@ -680,8 +681,12 @@ __device__ __forceinline__ void flush_stage(const WalkArgs &A, const uint32_t *s
         const int64_t pp = int64_t((uint64_t(uint32_t(phi)) << 32) | uint32_t(plo));
         if (src >= 0 && j < rr) {
             const int t = (wbase + s) * SP + j;
-            A.leaf[pp + j] = int32_t(stl[t]);
-            static_cast<DsT *>(A.ds)[pp + j] = stds[t];
+            if (sizeof(DsT) == 4 && A.pairs) {
+                reinterpret_cast<uint2 *>(A.leaf)[pp + j] = make_uint2(stl[t], __float_as_uint(float(stds[t])));
+            } else {
+                A.leaf[pp + j] = int32_t(stl[t]);
+                static_cast<DsT *>(A.ds)[pp + j] = stds[t];
+            }
         }
     }
 }
@@ -1010,6 +1015,47 @@ __global__ void __launch_bounds__(TB)
     }
 }
 
+// As k_slab_compact for rows of (leaf, ds32) pairs: one 8-byte load per record.
+__global__ void __launch_bounds__(TB)
+    k_slab_compact_pairs(const uint2 *__restrict__ srow, int64_t slab, const int64_t *__restrict__ offsets,
+                         int64_t n, int32_t *__restrict__ leaf, float *__restrict__ ds)
+{
+    __shared__ int64_t off[CP + 1];
+    const int64_t p0 = int64_t(blockIdx.x) * CP;
+    const int np = int(n - p0 < CP ? n - p0 : CP);
+    for (int j = threadIdx.x; j <= np; j += TB) off[j] = offsets[p0 + j];
+    __syncthreads();
+    const int64_t d0 = off[0], d1 = off[np];
+    int lo = 0;
+    for (int64_t db = d0 + threadIdx.x; db < d1; db += int64_t(CU) * TB) {
+        int64_t src[CU];
+        bool ok[CU];
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            const int64_t d = db + int64_t(u) * TB;
+            int hi = np;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (off[mid] <= d) lo = mid;
+                else hi = mid;
+            }
+            ok[u] = d < d1 && d - off[lo] < slab;
+            src[u] = (p0 + lo) * slab + (d - off[lo]);
+        }
+        uint2 v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; u++) v[u] = ok[u] ? srow[src[u]] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < CU; u++) {
+            const int64_t d = db + int64_t(u) * TB;
+            if (ok[u]) {
+                leaf[d] = int32_t(v[u].x);
+                ds[d] = __uint_as_float(v[u].y);
+            }
+        }
+    }
+}
+
 constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
 
@@ -1220,6 +1266,7 @@ WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n
     A.slab = 0;
     A.resume = nullptr;
     A.n_resume = nullptr;
+    A.pairs = 0;
     return A;
 }
 
@@ -1236,7 +1283,7 @@ int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk
                 : launch_batched_b<HG_FP32_RECHECK, WM_COUNT>(grids, args, chunks, n_chunks, b, refill_min, st, s);
 }
 
-int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision,
+int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision, int pairs,
                         const int32_t *count, const int64_t *offsets, int64_t n, int32_t *leaf, void *ds,
                         hipStream_t s)
 {
@@ -1244,7 +1291,9 @@ int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int pr
     const int64_t nb = (n + CP - 1) / CP;
     if (nb > 0x7fffffff) return HG_E_LIMIT;
     const unsigned blocks = unsigned(nb);
-    if (precision == HG_FP64)
+    if (pairs && precision != HG_FP64)
+        k_slab_compact_pairs<<<blocks, TB, 0, s>>>((const uint2 *)sleaf, slab, offsets, n, leaf, (float *)ds);
+    else if (precision == HG_FP64)
         k_slab_compact<double><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const double *)sds, slab,
                                                      count, offsets, n, leaf, (double *)ds);
     else

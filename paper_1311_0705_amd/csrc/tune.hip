@@ -177,6 +177,7 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
         SA.leaf = sleaf;
         SA.ds = sds;
         SA.slab = slab;
+        SA.pairs = opts->precision != HG_FP64 ? 1 : 0;   // as grid_trace's persistent slab walk
         auto eval = [&](const hg_trace_opts &c, float *ms) {
             if (slab_mode)
                 return time_candidate(

@@ -73,3 +73,16 @@ def test_scratch_grows_and_is_released(disk):
     hg.release_scratch(DEV)
     hg.release_scratch(DEV)   # nothing held: a no-op
     _same(two, g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, passes=1))
+
+
+@pytest.mark.parametrize("prec", [hg.FP32_RECHECK, hg.FP64], ids=["fp32r", "fp64"])
+@pytest.mark.parametrize("persistent", [0, 1, 2])
+def test_one_pass_walk_kinds(disk, prec, persistent):
+    # one thread per path or persistent, for the row walk (bit 0) and the
+    # resuming fill walk (bit 1): rows of separate leaf / ds areas or of
+    # (leaf, ds) pairs, records staged in registers or in LDS
+    g, o, k = disk
+    two = g.trace(o, k, precision=prec, mode=hg.RECORDS, passes=2)
+    one = g.trace(o, k, precision=prec, mode=hg.RECORDS, passes=1, slab=64, persistent=persistent,
+                  capacity=two["needed"])
+    _same(two, one)
