@@ -179,33 +179,41 @@ __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ 
 }
 
 // Per grid: the next level's extent, or an error if it would not fit.
-__global__ void __launch_bounds__(FT) k_f_close(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                const int64_t *__restrict__ P,
-                                                const int64_t *__restrict__ off)
-{
-    const int i = int(blockIdx.x) * FT + threadIdx.x;
-    if (i >= ng) return;
-    const ForestGrid &G = F[i];
-    int64_t nn = (off[P[i + 1]] - off[P[i]]) * G.nc;
-    const int64_t end = G.meta[lv + 1];
-    if (end + nn > G.cap) {
-        G.meta[M_ERR] = 1;
-        nn = 0;
-    }
-    for (int l = lv + 2; l < LB_N; l++) G.meta[l] = end + nn;
-}
-
+// Children of the split nodes of level lv, over all grids.  Each thread
+// derives its grid's next-level size from the split-flag prefix (so no
+// separate pass has to publish it first); the thread of a grid's first node
+// records that size in meta (or the capacity error), and block 0 computes
+// the per-grid prefixes of the next level's node counts (P_next, PW; nothing
+// when P_next is null).
 __global__ void __launch_bounds__(FT) k_f_append(const ForestGrid *__restrict__ F, int ng, int lv,
                                                  const int64_t *__restrict__ P,
                                                  const uint8_t *__restrict__ flag,
-                                                 const int64_t *__restrict__ off)
+                                                 const int64_t *__restrict__ off, int64_t *P_next,
+                                                 int64_t *PW)
 {
+    // the next level's node count of grid i (0 if it would not fit)
+    auto next_count = [&](int i) {
+        const ForestGrid &G = F[i];
+        const int64_t nn = (off[P[i + 1]] - off[P[i]]) * G.nc;
+        return G.meta[lv + 1] + nn > G.cap ? int64_t(0) : nn;
+    };
+    if (P_next && blockIdx.x == 0) {
+        block_prefix(ng, P_next, next_count);
+        __syncthreads();
+        block_prefix(ng, PW, [&](int i) { return (next_count(i) + 63) / 64; });
+    }
     const int64_t T = P[ng];
     for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
         const int i = owner(P, ng, t);
         const ForestGrid &G = F[i];
+        const int64_t nn = (off[P[i + 1]] - off[P[i]]) * G.nc;
+        const bool over = G.meta[lv + 1] + nn > G.cap;
+        if (t == P[i]) {
+            if (over) G.meta[M_ERR] = 1;
+            for (int l = lv + 2; l < LB_N; l++) G.meta[l] = G.meta[lv + 1] + (over ? 0 : nn);
+        }
         const int64_t n = G.meta[lv] + (t - P[i]);
-        if (!flag[t] || G.meta[lv + 2] == G.meta[lv + 1]) {
+        if (!flag[t] || over) {
             G.fc[n] = -1;
             continue;
         }
@@ -492,10 +500,11 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     const unsigned gb = unsigned((ng + FT - 1) / FT);
     k_f_init<<<gb, FT, 0, s>>>(b->dF, ng);
     HG_CHECK(hipGetLastError());
+    k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, 0, b->P, b->PW);
+    HG_CHECK(hipGetLastError());
     for (int lv = 0; lv <= b->lmax; lv++) {
         int64_t *P = b->P + size_t(lv) * size_t(ng + 1);
-        k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, lv, P, b->PW);
-        HG_CHECK(hipGetLastError());
+        int64_t *P_next = lv < b->lmax ? P + (ng + 1) : nullptr;
         if (b->wave_sampling)
             k_f_sample_wave<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag);
         else
@@ -503,9 +512,7 @@ int enqueue_build(hg_batch *b, hipStream_t s)
         HG_CHECK(hipGetLastError());
         int rc = scan_u8_to_i64_dev(b->flag, b->off, P + ng, b->stmp, s);
         if (rc) return rc;
-        k_f_close<<<gb, FT, 0, s>>>(b->dF, ng, lv, P, b->off);
-        HG_CHECK(hipGetLastError());
-        k_f_append<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag, b->off);
+        k_f_append<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag, b->off, P_next, b->PW);
         HG_CHECK(hipGetLastError());
     }
     for (int lv = 0; lv < b->lmax; lv++) {

@@ -1,6 +1,7 @@
 // Exclusive prefix sums for the CSR offsets of crossing records, child slots of
-// split nodes and leaf / internal-node numbering.  Three passes: per-block
-// totals, a single-block scan of the totals, per-block scan plus carry-in.
+// split nodes and leaf / internal-node numbering.  Per-block totals, a scan of
+// the totals, per-block scans plus carry-in (the device-count scan folds the
+// middle step into the last).
 #include "common.h"
 
 namespace hg {
@@ -171,15 +172,23 @@ __global__ void __launch_bounds__(SCAN_THREADS)
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
+// Each block scans the DSCAN_BLOCKS block totals itself for its carry-in (no
+// separate pass over them); block 0 stores the grand total at out[n].
 template <typename T>
 __global__ void __launch_bounds__(SCAN_THREADS)
     k_dscan_apply(const T *in, const int64_t *n_dev, const int64_t *bsum, int64_t *out)
 {
+    static_assert(DSCAN_BLOCKS == SCAN_THREADS, "one block total per thread");
+    __shared__ int64_t s_carry;
     const int64_t n = *n_dev;
     const int64_t per = dscan_per(n);
     const int64_t b0 = int64_t(blockIdx.x) * per;
     const int64_t b1 = b0 + per < n ? b0 + per : n;
-    int64_t carry = bsum[blockIdx.x];
+    int64_t grand;
+    const int64_t ex = block_excl_scan(bsum[threadIdx.x], &grand);
+    if (int(threadIdx.x) == int(blockIdx.x)) s_carry = ex;
+    __syncthreads();
+    int64_t carry = s_carry;
     for (int64_t tile = b0; tile < b1; tile += SCAN_TILE) {
         const int64_t base = tile + int64_t(threadIdx.x) * SCAN_ITEMS;
         int64_t v[SCAN_ITEMS];
@@ -198,7 +207,7 @@ __global__ void __launch_bounds__(SCAN_THREADS)
         }
         carry += total;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = bsum[DSCAN_BLOCKS];
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = grand;
 }
 
 // ---- per-chunk segmented scan of the batched walk's counts --------------------
@@ -264,8 +273,6 @@ int scan_u8_to_i64_dev(const uint8_t *in, int64_t *out, const int64_t *n_dev, in
                        hipStream_t s)
 {
     k_dscan_sums<uint8_t><<<DSCAN_BLOCKS, SCAN_THREADS, 0, s>>>(in, n_dev, tmp);
-    HG_CHECK(hipGetLastError());
-    k_scan_tile_sums<<<1, SCAN_THREADS, 0, s>>>(tmp, DSCAN_BLOCKS);
     HG_CHECK(hipGetLastError());
     k_dscan_apply<uint8_t><<<DSCAN_BLOCKS, SCAN_THREADS, 0, s>>>(in, n_dev, tmp, out);
     HG_CHECK(hipGetLastError());
