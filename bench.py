@@ -73,11 +73,12 @@ TUNE_PATHS = 10_000_000
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_slab": {"trace_sha256": "76dffd241aa16e7281584f6795403f5de12bb70beee2ce9c64241bb258fc40bf",
-                "fetch_kib": 28734270.4, "write_kib": 6090678.9, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "76dffd241aa16e7281584f6795403f5de12bb70beee2ce9c64241bb258fc40bf",
-                 "fetch_kib": 93925011.0, "write_kib": 6937152.4, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "e289ee5a05c0b1c339b49928550fb2d4757d52fe5e5f7c4fe4a1473fa875b105",
+                "fetch_kib": 27995720.4, "write_kib": 5903178.5, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "e289ee5a05c0b1c339b49928550fb2d4757d52fe5e5f7c4fe4a1473fa875b105",
+                 "fetch_kib": 93923783.8, "write_kib": 6936609.7, "fetch_scale": 2.0, "write_scale": 1.0},
 }
+
 
 def parse():
     p = argparse.ArgumentParser()
