@@ -247,7 +247,7 @@ def run_single(a, w):
     g = hg.build(w.density, w.criteria, w.tree_type, device=dev, max_nodes=mx)
     n_leaves, n_nodes = g.n_leaves, g.n_nodes
     res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, count_rechecks=True)
-    needed, rechecks = res["needed"], res["rechecks"]
+    needed, rechecks, descents = res["needed"], res["rechecks"], res["descents"]
     tuned = {}
     if not a.no_tune:
         m = min(n, TUNE_PATHS)
@@ -340,6 +340,7 @@ def run_single(a, w):
         "fp32r_over_fp64": round(ms64[3] / ms32[3], 3),
         "fp32r_over_fp64_tau_only": round(tau64[0] / tau32[0], 3),
         "recheck_rate": round(rechecks / max(crossings, 1), 6),
+        "descent_levels_per_crossing": round(descents / max(crossings, 1), 4),
         "build_ms": round(float(np.mean(build_ms)), 3),
         "tuned": {str(kk): v for kk, v in tuned.items()} or None,
         "untuned_fp32r_trace_ms": None if default_ms is None else round(default_ms, 3),
@@ -400,7 +401,7 @@ def run_c3(a, w):
     tt = tuned.get(hg.TAU_ONLY)
     res = g.trace(o, k, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt, count_rechecks=True)
     crossings = int(res["count"].sum().item())
-    rechecks = res["rechecks"]
+    rechecks, descents = res["rechecks"], res["descents"]
     g.free()
     log(f"grid: {n_leaves} leaves; {crossings} crossings over {n} paths")
     torch.cuda.synchronize()
@@ -465,6 +466,7 @@ def run_c3(a, w):
                               rec32["kernel_ms"][0], xb * B_X_FILL32 + nb * B_RAY_SLAB,
                               f"w3{tree_name(w.tree_type)}_slab")},
         "recheck_rate": round(rechecks / max(crossings, 1), 6),
+        "descent_levels_per_crossing": round(descents / max(crossings, 1), 4),
         "tuned": {str(kk): v for kk, v in tuned.items()} or None,
         "roofline": roofline(persistent_kernel(w.tree_type, 1, False, block), tau_avg,
                              crossings * B_X_COUNT32 + n * B_RAY_COUNT,

@@ -61,7 +61,7 @@ extern "C" {
 #define HG_RECORDS  1      /* also the ordered (leaf id, ds) records, CSR by path */
 
 #define HG_FLAG_TIMING   1 /* grid_trace: time the walk kernels with HIP events */
-#define HG_FLAG_RECHECKS 2 /* grid_trace: count FP64 rechecks (HG_FP32_RECHECK) */
+#define HG_FLAG_RECHECKS 2 /* grid_trace: count FP64 rechecks (HG_FP32_RECHECK) and descent levels */
 
 #define HG_MAX_CLUMPS (1 << 24)
 #define HG_MAX_BATCH  (1 << 16) /* grids per batch (batch_create) */
@@ -145,9 +145,12 @@ typedef struct {
  *   leaf[cap]    int32 leaf ids in path order (HG_RECORDS only)
  *   ds[cap]      double (HG_FP64) or float (HG_FP32_RECHECK) lengths
  *   (leaf and ds must be 16-byte aligned; HG_E_INVAL otherwise)
- * Set by the call: needed (= offsets[n], the total crossings), rechecks
- * (with HG_FLAG_RECHECKS) and kernel_ms[] (with HG_FLAG_TIMING: [0] count or
- * tau-only walk, [1] prefix sum, [2] record-filling walk, [3] whole call). */
+ * Set by the call: needed (= offsets[n], the total crossings), rechecks and
+ * descents (with HG_FLAG_RECHECKS: exit decisions taken again in FP64, and
+ * child levels descended from locate-table cells and rope targets, over all
+ * paths of the counting / one-pass walk) and kernel_ms[] (with
+ * HG_FLAG_TIMING: [0] count or tau-only walk, [1] prefix sum, [2]
+ * record-filling walk, [3] whole call). */
 typedef struct {
     double *tau;
     int32_t *count;
@@ -158,6 +161,7 @@ typedef struct {
     int64_t needed;
     int64_t rechecks;
     float kernel_ms[4];
+    int64_t descents;
 } hg_trace_out;
 
 /* ---- flat grid arrays (the data exchanged with the oracle and the tests) -- */

@@ -84,6 +84,7 @@ class TraceOut(C.Structure):
         ("tau", C.c_void_p), ("count", C.c_void_p), ("offsets", C.c_void_p),
         ("leaf", C.c_void_p), ("ds", C.c_void_p), ("capacity", C.c_int64),
         ("needed", C.c_int64), ("rechecks", C.c_int64), ("kernel_ms", C.c_float * 4),
+        ("descents", C.c_int64),
     ]
 
 
@@ -408,6 +409,7 @@ class Grid:
             break
         res["needed"] = int(to.needed)
         res["rechecks"] = int(to.rechecks)
+        res["descents"] = int(to.descents)
         res["kernel_ms"] = list(to.kernel_ms)
         return res
 
@@ -614,6 +616,7 @@ def trace_batched(grids, origins, dirs, precision: int = FP64, mode: int = RECOR
     for i in range(ng):
         res[i]["needed"] = int(tos[i].needed)
         res[i]["rechecks"] = int(tos[i].rechecks)
+        res[i]["descents"] = int(tos[i].descents)
         res[i]["kernel_ms"] = list(tos[i].kernel_ms)
     return res
 
@@ -742,6 +745,7 @@ class Batch:
             for i, r in enumerate(self.results):
                 r["needed"] = int(self._outs[i].needed)
                 r["rechecks"] = int(self._outs[i].rechecks)
+                r["descents"] = int(self._outs[i].descents)
         _check(rc, "batch_result")
         return list(nn), list(nl)
 

@@ -81,6 +81,7 @@ void free_grid_arrays(hg_grid *g)
 __global__ void k_reset_status(TraceStatus *st)
 {
     st->rechecks = 0;
+    st->descents = 0;
     st->bad_dir = 0;
     st->step_guard = 0;
     st->bad_ref = 0;
@@ -410,6 +411,7 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         nmax = std::max(nmax, n[i]);
         outs[i].needed = 0;
         outs[i].rechecks = 0;
+        outs[i].descents = 0;
         for (int t = 0; t < 4; t++) outs[i].kernel_ms[t] = 0.f;
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
@@ -439,7 +441,10 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         if (timing) (void)hipEventRecord(ev[1], s);
     }
     if (!rc) rc = read_status(g0, &st, s);
-    if (!rc) outs[0].rechecks = int64_t(st.rechecks);
+    if (!rc) {
+        outs[0].rechecks = int64_t(st.rechecks);
+        outs[0].descents = int64_t(st.descents);
+    }
     if (!rc && records) {
         for (int i = 0; i < ng && !rc; i++)
             rc = scan_i32_to_i64(outs[i].count, outs[i].offsets, n[i], tmp, s);
@@ -500,7 +505,10 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
     if (timing) (void)hipEventRecord(ev[1], s);
     TraceStatus st;
     if (!rc) rc = read_status(g, &st, s);
-    if (!rc) out->rechecks = int64_t(st.rechecks);
+    if (!rc) {
+        out->rechecks = int64_t(st.rechecks);
+        out->descents = int64_t(st.descents);
+    }
     if (rc || !records) return rc;
     int64_t *tmp = nullptr;
     rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
@@ -583,6 +591,7 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
     if (!rc) rc = read_status(g, &st, s);   // synchronises
     if (!rc) {
         out->rechecks = int64_t(st.rechecks);
+        out->descents = int64_t(st.descents);
         out->needed = h.needed;
         if (h.needed > out->capacity) rc = HG_E_CAPACITY;
     }
@@ -634,6 +643,7 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     for (int i = 0; i < 4; i++) out->kernel_ms[i] = 0.f;
     out->needed = 0;
     out->rechecks = 0;
+    out->descents = 0;
     if (timing)
         for (int i = 0; i < 4; i++) HG_CHECK(hipEventCreate(&ev[i]));
     const int64_t slab = slab_rows(opts, n);

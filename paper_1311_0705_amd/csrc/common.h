@@ -128,6 +128,7 @@ __host__ __device__ inline int table_depth(int tree, int64_t n_leaves, int max_l
 // Scratch for device-side status shared by the trace kernels.
 struct TraceStatus {
     unsigned long long rechecks;
+    unsigned long long descents;   // child levels descended (walk statistics)
     int bad_dir;
     int step_guard;
     int bad_ref;                   // a reference out of range: the layout is corrupt
@@ -136,7 +137,6 @@ struct TraceStatus {
     unsigned int done_waves;
 };
 
-// Per-grid arguments of a walk launch.
 // Walk state of a path at its first record beyond its row (one-walk records
 // mode), taken on entry to that leaf: the record-filling walk resumes the
 // path from here instead of from its origin.
@@ -147,6 +147,7 @@ struct Resume {
     int32_t lv, steps;
 };
 
+// Per-grid arguments of a walk launch.
 struct WalkArgs {
     const double *O;
     const double *K;

@@ -398,6 +398,7 @@ __global__ void __launch_bounds__(FT) k_f_child_refs(const ForestGrid *__restric
 __global__ void k_f_reset_status(TraceStatus *st)
 {
     st->rechecks = 0;
+    st->descents = 0;
     st->bad_dir = 0;
     st->step_guard = 0;
     st->bad_ref = 0;
@@ -806,6 +807,7 @@ int batch_result(hg_batch_t b, void *stream, int64_t *n_nodes, int64_t *n_leaves
         if (outs && traced) {
             outs[i].needed = records ? tot[size_t(i)] : 0;
             outs[i].rechecks = i == 0 ? int64_t(st.rechecks) : 0;
+            outs[i].descents = i == 0 ? int64_t(st.descents) : 0;
             if (records && tot[size_t(i)] > b->outs[size_t(i)].capacity && !rc) rc = HG_E_CAPACITY;
         }
     }

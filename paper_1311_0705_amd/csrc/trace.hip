@@ -624,8 +624,11 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
         return;
     }
     unsigned long long rechecks = 0;
+    uint32_t desc = 0;   // child levels descended
     for (;;) {
+        const int lv0 = P.lv;
         P.ref = descend<TREE, R>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+        desc += uint32_t(P.lv - lv0);
         if (P.ref == Ref<R>::NUL) {
             A.st->bad_ref = 1;
             break;
@@ -638,7 +641,10 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
         if (r == STEP_END) break;
     }
     finish_path<PREC, WM, R>(A, i, P);
-    if (!(WM == WM_FILL) && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
+    if (!(WM == WM_FILL) && A.count_rechecks) {
+        if (rechecks) atomicAdd(&A.st->rechecks, rechecks);
+        if (desc) atomicAdd(&A.st->descents, (unsigned long long)desc);
+    }
 }
 
 // Records staged in LDS by the persistent walk (record modes): each lane owns
@@ -731,6 +737,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     uint32_t cnext = 0, cend = 0;   // wavefront-local chunk [cnext, cend)
     bool drained = false;           // the global counter is exhausted
     unsigned long long rechecks = 0;
+    uint32_t desc = 0;   // child levels descended
     for (;;) {
         const bool want = ray < 0 && !done;
         const uint64_t wmask = __ballot(want);
@@ -776,6 +783,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         int32_t c_before = 0;
         if (ray >= 0 && !Ref<R>::leaf(P.ref)) {
             // LDS levels, then at most one global level this iteration
+            const int lv0 = P.lv;
             for (;;) {
                 if (!ref_ok(G, P.ref) || P.lv >= 62) {
                     P.ref = Ref<R>::NUL;
@@ -786,6 +794,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
                 if (global || Ref<R>::leaf(P.ref)) break;
             }
             bad = P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref));
+            desc += uint32_t(P.lv - lv0);
         }
         if (ray >= 0 && !bad && Ref<R>::leaf(P.ref)) {
             c_before = P.cnt;
@@ -815,7 +824,10 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
             ray = -1;
         }
     }
-    if (!(WM == WM_FILL) && A.count_rechecks && rechecks) atomicAdd(&A.st->rechecks, rechecks);
+    if (!(WM == WM_FILL) && A.count_rechecks) {
+        if (rechecks) atomicAdd(&A.st->rechecks, rechecks);
+        if (desc) atomicAdd(&A.st->descents, (unsigned long long)desc);
+    }
 }
 
 // One step of a busy lane in the batched walk: at most one global descent
@@ -823,7 +835,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 template <int TREE, int PREC, int WM>
 __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &A,
                                              Path<PREC, uint32_t> &P, int64_t ray,
-                                             unsigned long long &rechecks)
+                                             unsigned long long &rechecks, uint32_t &desc)
 {
     if (!Ref<uint32_t>::leaf(P.ref)) {
         if (!ref_ok(G, P.ref) || P.lv >= 62) {
@@ -832,6 +844,7 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
             return false;
         }
         P.ref = child_of<TREE, uint32_t>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+        desc++;
         if (Ref<uint32_t>::leaf(P.ref) && !ref_ok(G, P.ref)) {
             A.st->bad_ref = 1;
             finish_path<PREC, WM, uint32_t>(A, ray, P);
@@ -876,6 +889,7 @@ __global__ void __launch_bounds__(BT)
     WalkGrid G;
     WalkArgs A;
     unsigned long long rechecks = 0;
+    uint32_t desc = 0;   // child levels descended
     for (;;) {
         const bool want = ray < 0 && !done;
         const uint64_t wmask = __ballot(want);
@@ -929,11 +943,14 @@ __global__ void __launch_bounds__(BT)
             continue;
         }
         if (ray < 0) continue;
-        const bool alive = G.tree == KD ? batched_step<KD, PREC, WM>(G, A, P, ray, rechecks)
-                                        : batched_step<OCT, PREC, WM>(G, A, P, ray, rechecks);
+        const bool alive = G.tree == KD ? batched_step<KD, PREC, WM>(G, A, P, ray, rechecks, desc)
+                                        : batched_step<OCT, PREC, WM>(G, A, P, ray, rechecks, desc);
         if (!alive) ray = -1;
     }
-    if (!(WM == WM_FILL) && rechecks && A.count_rechecks) atomicAdd(&st->rechecks, rechecks);
+    if (!(WM == WM_FILL) && A.count_rechecks) {
+        if (rechecks) atomicAdd(&st->rechecks, rechecks);
+        if (desc) atomicAdd(&st->descents, (unsigned long long)desc);
+    }
 }
 
 template <int TREE, typename R>
