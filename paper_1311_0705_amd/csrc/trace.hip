@@ -830,40 +830,60 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     }
 }
 
+// The group of LDS-staged records a lane writes out after a step: complete
+// (SG records), the row or slice full, or the last records of an ended path.
+template <int SG, int PREC, typename R>
+__device__ __forceinline__ void stage_group(const Path<PREC, R> &P, bool crossed, int32_t c_before,
+                                            bool ended, int &nr, int64_t &pos)
+{
+    const int64_t c = P.cnt < P.room ? P.cnt : P.room;
+    const bool wrote = crossed && P.cnt > c_before && c_before < P.room;
+    nr = 0;
+    if (wrote && ((c & (SG - 1)) == 0 || c == P.room)) nr = int(((c - 1) & (SG - 1)) + 1);
+    else if (ended && c != P.room) nr = int(c & (SG - 1));
+    pos = P.base + c - nr;
+}
+
 // One step of a busy lane in the batched walk: at most one global descent
 // level, or one crossing.  Returns false when the path ended (or failed).
-template <int TREE, int PREC, int WM>
+// With LDS staging (sl != nullptr) the records go to the lane's slots and
+// nr / pos name the group to write out after the step.
+template <int TREE, int PREC, int WM, int SG>
 __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &A,
                                              Path<PREC, uint32_t> &P, int64_t ray,
-                                             unsigned long long &rechecks, uint32_t &desc)
+                                             unsigned long long &rechecks, uint32_t &desc, uint32_t *sl,
+                                             typename Path<PREC, uint32_t>::DsT *sd, int &nr, int64_t &pos)
 {
+    constexpr bool STG = SG > 0;
+    bool crossed = false, ended = false;
+    int32_t c_before = 0;
     if (!Ref<uint32_t>::leaf(P.ref)) {
         if (!ref_ok(G, P.ref) || P.lv >= 62) {
             A.st->bad_ref = 1;
-            finish_path<PREC, WM, uint32_t>(A, ray, P);
-            return false;
-        }
-        P.ref = child_of<TREE, uint32_t>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
-        desc++;
-        if (Ref<uint32_t>::leaf(P.ref) && !ref_ok(G, P.ref)) {
-            A.st->bad_ref = 1;
-            finish_path<PREC, WM, uint32_t>(A, ray, P);
-            return false;
+            ended = true;
+        } else {
+            P.ref = child_of<TREE, uint32_t>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
+            desc++;
+            if (Ref<uint32_t>::leaf(P.ref) && !ref_ok(G, P.ref)) {
+                A.st->bad_ref = 1;
+                ended = true;
+            }
         }
     }
-    if (Ref<uint32_t>::leaf(P.ref)) {
-        const int r = cross<TREE, PREC, WM, uint32_t>(G, A, P, rechecks);
+    if (!ended && Ref<uint32_t>::leaf(P.ref)) {
+        c_before = P.cnt;
+        const int r = cross<TREE, PREC, WM, uint32_t>(G, A, P, rechecks, sl, sd, STG ? SG - 1 : 0);
+        crossed = true;
         if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
             A.st->step_guard = 1;
-            finish_path<PREC, WM, uint32_t>(A, ray, P);
-            return false;
-        }
-        if (r == STEP_END) {
-            finish_path<PREC, WM, uint32_t>(A, ray, P);
-            return false;
+            ended = true;
+        } else if (r == STEP_END) {
+            ended = true;
         }
     }
-    return true;
+    if (STG) stage_group<STG ? SG : 1>(P, crossed, c_before, ended, nr, pos);
+    if (ended) finish_path<PREC, WM, uint32_t, STG>(A, ray, P);
+    return !ended;
 }
 
 // Batched walk over many grids in one persistent launch.  The device work
@@ -871,14 +891,30 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
 // per atomic and keeps that grid's parameters uniform across its lanes,
 // refilling lanes from the chunk.  Before taking up a chunk of another grid it
 // lets its lanes finish their paths.  Octree and k-d grids mix freely: the
-// tree type is a wavefront-uniform branch.
+// tree type is a wavefront-uniform branch.  Asked for three wavefronts per
+// SIMD (the FP32 record-filling walk would otherwise take 170 VGPRs and run
+// two).
 template <int PREC, int WM, int BT>
-__global__ void __launch_bounds__(BT)
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(3, 8)))
     k_walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                    const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min,
                    TraceStatus *st)
 {
     const int lane = threadIdx.x & 63;
+    // the record-filling walk stages its records in LDS (see flush_stage)
+    constexpr bool STG = WM == WM_FILL;
+    constexpr int SP = StageShape<BT>::SP;
+    using DsT = typename Path<PREC, uint32_t>::DsT;
+    extern __shared__ uint64_t lds_raw[];
+    uint32_t *stl = nullptr, *my_l = nullptr;
+    DsT *stds = nullptr, *my_d = nullptr;
+    if (STG) {
+        char *sb = reinterpret_cast<char *>(lds_raw);
+        stl = reinterpret_cast<uint32_t *>(sb);
+        stds = reinterpret_cast<DsT *>(sb + size_t(BT) * SP * 4);
+        my_l = stl + threadIdx.x * SP;
+        my_d = stds + threadIdx.x * SP;
+    }
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     Path<PREC, uint32_t> P;
     int64_t ray = -1;
@@ -942,10 +978,17 @@ __global__ void __launch_bounds__(BT)
             if (!__ballot(!done)) break;
             continue;
         }
-        if (ray < 0) continue;
-        const bool alive = G.tree == KD ? batched_step<KD, PREC, WM>(G, A, P, ray, rechecks, desc)
-                                        : batched_step<OCT, PREC, WM>(G, A, P, ray, rechecks, desc);
-        if (!alive) ray = -1;
+        constexpr int SGS = STG ? StageShape<BT>::SG : 0;
+        int nr = 0;
+        int64_t pos = 0;
+        if (ray >= 0) {
+            const bool alive =
+                G.tree == KD ? batched_step<KD, PREC, WM, SGS>(G, A, P, ray, rechecks, desc, my_l, my_d, nr, pos)
+                             : batched_step<OCT, PREC, WM, SGS>(G, A, P, ray, rechecks, desc, my_l, my_d, nr, pos);
+            if (!alive) ray = -1;
+        }
+        // every lane holds the wavefront's current grid, so A is uniform here
+        if (STG) flush_stage<BT, DsT>(A, stl, stds, nr, pos, lane);
     }
     if (!(WM == WM_FILL) && A.count_rechecks) {
         if (rechecks) atomicAdd(&st->rechecks, rechecks);
@@ -1191,18 +1234,20 @@ int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChu
                      int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
 {
     static int occ = -1, cus = 0;
+    const size_t lds = WM == WM_FILL ? size_t(BT) * StageShape<BT>::SP * (4 + (PREC == HG_FP64 ? 8 : 4)) : 0;
+    if (lds > max_block_lds()) return HG_E_INVAL;
     if (occ < 0) {
         int dev = 0;
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, WM, BT>), BT, 0));
+            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, WM, BT>), BT, lds));
     }
     const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
     k_reset_counter<<<1, 1, 0, s>>>(st);
     HG_CHECK(hipGetLastError());
-    k_walk_batched<PREC, WM, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
-                                                                     refill_min, st);
+    k_walk_batched<PREC, WM, BT><<<dim3(blocks), dim3(BT), lds, s>>>(grids, args, chunks, n_chunks,
+                                                                       refill_min, st);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }
