@@ -598,7 +598,7 @@ def run_c4(a):
         "batched_walk_ms": {"count": round(kms[0], 3), "scan": round(kms[1], 3),
                             "fill": round(kms[2], 3)},
         "tuned": tuned,
-        "roofline": roofline("k_walk_batched<fp32_recheck,fill>", kms[2],
+        "roofline": roofline("k_walk_batched_fill<fp32_recheck>", kms[2],
                              crossings * B_X_FILL32 + n * B_RAY_FILL, "w4_fill"),
     })
     if not a.no_cpu:

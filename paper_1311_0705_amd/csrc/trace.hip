@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
             if (cnext >= cend && !drained) {
                 uint32_t b = 0;
                 if (lane == 0) b = atomicAdd(&A.st->next_ray, chunk);
-                b = __shfl(b, 0, 64);
+                b = __builtin_amdgcn_readfirstlane(b);   // wavefront-uniform from here on
                 if (int64_t(b) >= A.n) {
                     drained = true;
                     cnext = cend = 0;
@@ -891,25 +891,21 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
 // per atomic and keeps that grid's parameters uniform across its lanes,
 // refilling lanes from the chunk.  Before taking up a chunk of another grid it
 // lets its lanes finish their paths.  Octree and k-d grids mix freely: the
-// tree type is a wavefront-uniform branch.  Asked for three wavefronts per
-// SIMD (the FP32 record-filling walk would otherwise take 170 VGPRs and run
-// two).
+// tree type is a wavefront-uniform branch.
 template <int PREC, int WM, int BT>
-__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(3, 8)))
-    k_walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
-                   const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min,
-                   TraceStatus *st)
+__device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
+                                             const BatchChunk *__restrict__ chunks, int n_chunks,
+                                             int refill_min, TraceStatus *st, char *lds_stage)
 {
     const int lane = threadIdx.x & 63;
     // the record-filling walk stages its records in LDS (see flush_stage)
     constexpr bool STG = WM == WM_FILL;
     constexpr int SP = StageShape<BT>::SP;
     using DsT = typename Path<PREC, uint32_t>::DsT;
-    extern __shared__ uint64_t lds_raw[];
     uint32_t *stl = nullptr, *my_l = nullptr;
     DsT *stds = nullptr, *my_d = nullptr;
     if (STG) {
-        char *sb = reinterpret_cast<char *>(lds_raw);
+        char *sb = lds_stage;
         stl = reinterpret_cast<uint32_t *>(sb);
         stds = reinterpret_cast<DsT *>(sb + size_t(BT) * SP * 4);
         my_l = stl + threadIdx.x * SP;
@@ -936,7 +932,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(3, 8)))
                 if (pc < 0 && !drained) {
                     int c = 0;
                     if (lane == 0) c = int(atomicAdd(&st->next_ray, 1u));
-                    c = __shfl(c, 0, 64);
+                    c = __builtin_amdgcn_readfirstlane(c);   // wavefront-uniform from here on
                     if (c >= n_chunks) drained = true;
                     else pc = c;
                 }
@@ -994,6 +990,27 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(3, 8)))
         if (rechecks) atomicAdd(&st->rechecks, rechecks);
         if (desc) atomicAdd(&st->descents, (unsigned long long)desc);
     }
+}
+
+// The batched walks as kernels: the counting walk at four wavefronts per SIMD,
+// the record-filling walk at three (it would otherwise take 170 VGPRs and run
+// two).
+template <int PREC, int BT>
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+    k_walk_batched_count(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
+                         const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min, TraceStatus *st)
+{
+    walk_batched<PREC, WM_COUNT, BT>(grids, args, chunks, n_chunks, refill_min, st, nullptr);
+}
+
+template <int PREC, int BT>
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(3, 8)))
+    k_walk_batched_fill(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
+                        const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min, TraceStatus *st)
+{
+    extern __shared__ uint64_t lds_raw[];
+    walk_batched<PREC, WM_FILL, BT>(grids, args, chunks, n_chunks, refill_min, st,
+                                    reinterpret_cast<char *>(lds_raw));
 }
 
 template <int TREE, typename R>
@@ -1236,18 +1253,23 @@ int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChu
     static int occ = -1, cus = 0;
     const size_t lds = WM == WM_FILL ? size_t(BT) * StageShape<BT>::SP * (4 + (PREC == HG_FP64 ? 8 : 4)) : 0;
     if (lds > max_block_lds()) return HG_E_INVAL;
+    const void *kern = WM == WM_FILL ? reinterpret_cast<const void *>(k_walk_batched_fill<PREC, BT>)
+                                     : reinterpret_cast<const void *>(k_walk_batched_count<PREC, BT>);
     if (occ < 0) {
         int dev = 0;
         HG_CHECK(hipGetDevice(&dev));
         HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_batched<PREC, WM, BT>), BT, lds));
+        HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, BT, lds));
     }
     const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
     k_reset_counter<<<1, 1, 0, s>>>(st);
     HG_CHECK(hipGetLastError());
-    k_walk_batched<PREC, WM, BT><<<dim3(blocks), dim3(BT), lds, s>>>(grids, args, chunks, n_chunks,
-                                                                       refill_min, st);
+    if (WM == WM_FILL)
+        k_walk_batched_fill<PREC, BT><<<dim3(blocks), dim3(BT), lds, s>>>(grids, args, chunks, n_chunks,
+                                                                          refill_min, st);
+    else
+        k_walk_batched_count<PREC, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
+                                                                         refill_min, st);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }
