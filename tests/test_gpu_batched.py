@@ -30,11 +30,14 @@ def batch():
     return grids, os_, ks_, ws
 
 
+@pytest.mark.parametrize("block", [128, 256, 512])
 @pytest.mark.parametrize("prec", [hg.FP32_RECHECK, hg.FP64], ids=["fp32r", "fp64"])
-def test_batched_equals_one_by_one(batch, prec):
+def test_batched_equals_one_by_one(batch, prec, block):
+    # every block size (records staged in LDS in groups of 16, or 8 for
+    # 512-thread blocks)
     grids, os_, ks_, ws = batch
-    rb = hg.trace_batched(grids, os_, ks_, precision=prec, mode=hg.RECORDS, chunk=333)
-    tb = hg.trace_batched(grids, os_, ks_, precision=prec, mode=hg.TAU_ONLY)
+    rb = hg.trace_batched(grids, os_, ks_, precision=prec, mode=hg.RECORDS, chunk=333, block=block)
+    tb = hg.trace_batched(grids, os_, ks_, precision=prec, mode=hg.TAU_ONLY, block=block)
     for i, g in enumerate(grids):
         r1 = g.trace(os_[i], ks_[i], precision=prec, mode=hg.RECORDS)
         n = r1["needed"]
