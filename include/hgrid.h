@@ -231,9 +231,11 @@ int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_
 int grid_trace(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
                const hg_trace_opts *opts, hg_trace_out *out, void *stream);
 
-/* Free the current device's records-mode scratch of grid_trace (waits for
- * the calls using it; the next records-mode call allocates it again).
- * Errors: HG_E_HIP. */
+/* Free the device memory the library keeps for reuse on the current device:
+ * the records-mode scratch of grid_trace (waiting for the calls using it;
+ * the next records-mode call allocates it again) and the array blocks of
+ * freed grids and batches (up to four blocks, 16 GiB in total, handed to
+ * later builds that fit them).  Errors: HG_E_HIP. */
 int grid_release_scratch(void);
 
 /* Trace several grids' path batches in one persistent launch per walk pass

@@ -622,7 +622,8 @@ def trace_batched(grids, origins, dirs, precision: int = FP64, mode: int = RECOR
 
 
 def release_scratch(device="cuda") -> None:
-    """Free the device's records-mode trace scratch (grid_release_scratch)."""
+    """Free the device memory the library keeps for reuse: the records-mode
+    trace scratch and the array blocks of freed grids (grid_release_scratch)."""
     with torch.cuda.device(torch.device(device)):
         _check(lib().grid_release_scratch(), "grid_release_scratch")
 

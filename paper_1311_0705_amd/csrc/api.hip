@@ -68,7 +68,7 @@ void dfree(void *p, hipStream_t s)
 void free_grid_arrays(hg_grid *g)
 {
     if (g->block) {
-        dfree(g->block, nullptr);
+        block_free(g->block, g->block_bytes, g->block_dev);
         dfree(g->status, nullptr);
         return;
     }
@@ -195,6 +195,57 @@ int64_t slab_rows(const hg_trace_opts *opts, int64_t n)
     const double fit = (SLAB_BUDGET / double(n) - double(sizeof(Resume))) / per;
     if (fit < double(SLAB_MIN)) return 0;
     return std::min<int64_t>(SLAB_MAX, int64_t(fit) / 4 * 4);
+}
+
+// The block cache of block_alloc / block_free.
+struct BlockCache {
+    std::mutex m;
+    std::vector<std::pair<void *, size_t>> blocks;
+    size_t bytes = 0;
+};
+static BlockCache g_blocks[MAX_DEVICES];
+constexpr size_t BLOCK_CACHE_COUNT = 4;
+constexpr size_t BLOCK_CACHE_BYTES = size_t(16) << 30;
+
+int block_alloc(void **p, size_t bytes, int *dev)
+{
+    *p = nullptr;
+    hipError_t e = hipGetDevice(dev);
+    if (e) return set_hip_error(e);
+    if (*dev < 0 || *dev >= MAX_DEVICES) return HG_E_INVAL;
+    {
+        // the smallest cached block that holds bytes without wasting half of it
+        BlockCache &c = g_blocks[*dev];
+        std::lock_guard<std::mutex> lock(c.m);
+        size_t best = c.blocks.size();
+        for (size_t i = 0; i < c.blocks.size(); i++) {
+            const size_t b = c.blocks[i].second;
+            if (b >= bytes && b / 2 <= bytes && (best == c.blocks.size() || b < c.blocks[best].second))
+                best = i;
+        }
+        if (best < c.blocks.size()) {
+            *p = c.blocks[best].first;
+            c.bytes -= c.blocks[best].second;
+            c.blocks.erase(c.blocks.begin() + long(best));
+            return HG_OK;
+        }
+    }
+    return dalloc(p, bytes, nullptr);
+}
+
+void block_free(void *p, size_t bytes, int dev)
+{
+    if (!p) return;
+    if (dev >= 0 && dev < MAX_DEVICES) {
+        BlockCache &c = g_blocks[dev];
+        std::lock_guard<std::mutex> lock(c.m);
+        if (c.blocks.size() < BLOCK_CACHE_COUNT && c.bytes + bytes <= BLOCK_CACHE_BYTES) {
+            c.blocks.emplace_back(p, bytes);
+            c.bytes += bytes;
+            return;
+        }
+    }
+    dfree(p, nullptr);
 }
 
 }  // namespace hg
@@ -618,6 +669,13 @@ int grid_release_scratch(void)
     hipError_t e = hipGetDevice(&dev);
     if (e) return set_hip_error(e);
     if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
+    {
+        BlockCache &c = g_blocks[dev];
+        std::lock_guard<std::mutex> lock(c.m);
+        for (auto &b : c.blocks) dfree(b.first, nullptr);
+        c.blocks.clear();
+        c.bytes = 0;
+    }
     Scratch &w = g_scratch[dev];
     std::lock_guard<std::mutex> lock(w.m);
     if (w.p) {

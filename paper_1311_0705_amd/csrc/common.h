@@ -215,6 +215,8 @@ struct hg_grid {
     int64_t level_begin[64];   // first node of each level; level_begin[max_level+1] = n_nodes
     int borrowed;              // arrays belong to a batch (only status is the grid's own)
     void *block;               // when set, every array above except status is carved from it
+    size_t block_bytes;        // its size and device (block_free)
+    int block_dev;
 };
 
 namespace hg {
@@ -243,6 +245,13 @@ inline int dalloc_n(T **p, size_t n, hipStream_t s)
     return dalloc(reinterpret_cast<void **>(p), n * sizeof(T), s);
 }
 
+// Blocks of grid and batch arrays: freed blocks are kept (a few per device,
+// a bounded total) and handed to later builds that fit them, so repeated
+// builds neither allocate nor free.  block_alloc stores the device in *dev;
+// block_free takes the block back for that device.
+int block_alloc(void **p, size_t bytes, int *dev);
+void block_free(void *p, size_t bytes, int dev);
+
 // Several arrays carved from one device block (each piece 256-byte aligned):
 // one allocation and one free instead of one per array.
 class Carve {
@@ -254,9 +263,11 @@ class Carve {
         parts_.push_back(Part{reinterpret_cast<void **>(p), b});
         bytes_ += b;
     }
-    int alloc(void **block, hipStream_t s)
+    size_t bytes() const { return bytes_; }
+    // from the block cache (see block_alloc)
+    int alloc(void **block, int *dev)
     {
-        int rc = dalloc(block, bytes_, s);
+        int rc = block_alloc(block, bytes_, dev);
         if (rc) return rc;
         char *q = static_cast<char *>(*block);
         for (const Part &pt : parts_) {

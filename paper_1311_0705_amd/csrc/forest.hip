@@ -436,7 +436,10 @@ struct hg_batch {
     WalkGrid *w32 = nullptr, *w64 = nullptr;
     TraceStatus *status = nullptr;
     void *tmp_block = nullptr;      // the batch-wide arrays above, carved from one block
+    size_t tmp_bytes = 0;
     std::vector<void *> arrays;     // one block per grid holding its arrays
+    std::vector<size_t> array_bytes;
+    int dev = 0;                    // device of the blocks
     // bound trace
     std::vector<WalkArgs> hA;
     bool bound = false;
@@ -478,8 +481,8 @@ void free_batch(hg_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     free_bound(b);
     for (auto &d : b->dens) release_density(&d, nullptr);
-    for (void *p : b->arrays) dfree(p, nullptr);
-    dfree(b->tmp_block, nullptr);
+    for (size_t i = 0; i < b->arrays.size(); i++) block_free(b->arrays[i], b->array_bytes[i], b->dev);
+    block_free(b->tmp_block, b->tmp_bytes, b->dev);
     (void)hipDeviceSynchronize();
     delete b;
 }
@@ -614,8 +617,11 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
         cv.add(&G.child, cap);
         cv.add(&G.table, size_t(1) << (3 * G.tmax));
         void *blk = nullptr;
-        rc = cv.alloc(&blk, nullptr);
-        if (!rc) b->arrays.push_back(blk);
+        rc = cv.alloc(&blk, &b->dev);
+        if (!rc) {
+            b->arrays.push_back(blk);
+            b->array_bytes.push_back(cv.bytes());
+        }
     }
     const size_t ng1 = size_t(n_grids) + 1;
     Carve ct;
@@ -632,7 +638,8 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     ct.add(&b->w32, size_t(n_grids));
     ct.add(&b->w64, size_t(n_grids));
     ct.add(&b->status, 1);
-    if (!rc) rc = ct.alloc(&b->tmp_block, nullptr);
+    if (!rc) rc = ct.alloc(&b->tmp_block, &b->dev);
+    if (!rc) b->tmp_bytes = ct.bytes();
     for (int i = 0; i < n_grids && !rc; i++) b->hF[size_t(i)].meta = b->meta + size_t(i) * META;
     if (!rc) {
         hipError_t e = hipMemcpy(b->dF, b->hF.data(), sizeof(ForestGrid) * size_t(n_grids),
@@ -988,7 +995,10 @@ int build_single_batched(const hg_density *dn, const hg_criteria *cr, int tree, 
     if (!rc) {
         // the grid takes over the block holding its arrays
         g->block = b->arrays[0];
+        g->block_bytes = b->array_bytes[0];
+        g->block_dev = b->dev;
         b->arrays.clear();
+        b->array_bytes.clear();
         g->borrowed = 0;
         *out = g;
     }

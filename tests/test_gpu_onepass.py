@@ -86,3 +86,20 @@ def test_one_pass_walk_kinds(disk, prec, persistent):
     one = g.trace(o, k, precision=prec, mode=hg.RECORDS, passes=1, slab=64, persistent=persistent,
                   capacity=two["needed"])
     _same(two, one)
+
+
+def test_grid_blocks_are_reused():
+    # a freed grid's array block serves the next build of the same size; the
+    # grids built in reused blocks are the same grid bit for bit
+    w = W.workload(1)
+    ref = None
+    for it in range(3):
+        g = hg.build(w.density, w.criteria, w.tree_type, device=DEV, max_nodes=1 << 16)
+        e = g.export()
+        cur = (e["first_child"].cpu(), e["rho"].cpu())
+        if ref is None:
+            ref = cur
+        else:
+            assert torch.equal(ref[0], cur[0]) and torch.equal(ref[1], cur[1])
+        g.free()
+    hg.release_scratch(DEV)
