@@ -647,10 +647,11 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
     }
 }
 
-// Records staged in LDS by the persistent walk (record modes): each lane owns
-// SG slots of leaf ids and SG of ds (rows of SG + 1 words against bank
-// conflicts).  A lane's group is written out once it holds SG records, its
-// row is full or its path ends, by the whole wavefront: SG lanes per group,
+// Records staged in LDS by the persistent and batched walks (record modes):
+// each lane owns SG slots of leaf ids and SG of ds (rows of SG + 1 words
+// against bank conflicts).  A lane's group is written out once it holds SG
+// records, its row or slice is full or its path ends, by the whole
+// wavefront: SG lanes per group,
 // 64 / SG groups per store instruction, so that a store covers a few cache
 // lines instead of one line per lane.
 template <int BT>
