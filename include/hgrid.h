@@ -130,9 +130,10 @@ typedef struct {
                            stages in LDS (at most 65536); 0 = library choice (16384), < 0 = none */
     int32_t passes;     /* grid_trace, records mode: 1 = one walk writing tau, counts and each
                            path's first `slab` records into a per-path row, then a copy into the
-                           CSR slices (paths with more records are walked again); 2 = a counting
-                           walk, then a record-filling walk; 0 = library choice (1 when the rows
-                           of all paths fit in 32 GiB and the scratch can be had, else 2) */
+                           CSR slices (paths with more records are resumed where their row
+                           filled up); 2 = a counting walk, then a record-filling walk; 0 =
+                           library choice (1 when the rows of all paths fit in 32 GiB and the
+                           scratch can be had, else 2) */
     int32_t slab;       /* records per path row of the one-pass mode (rounded up to a multiple
                            of 4), 0 = library choice (as many as keep the rows of all paths
                            within 32 GiB, at most 2048; two walks below 256) */
