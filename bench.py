@@ -73,10 +73,10 @@ TUNE_PATHS = 10_000_000
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_slab": {"trace_sha256": "e289ee5a05c0b1c339b49928550fb2d4757d52fe5e5f7c4fe4a1473fa875b105",
-                "fetch_kib": 27995720.4, "write_kib": 5903178.5, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "e289ee5a05c0b1c339b49928550fb2d4757d52fe5e5f7c4fe4a1473fa875b105",
-                 "fetch_kib": 93923783.8, "write_kib": 6936609.7, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "1ced6eba328be114cfc913092c9bebc715183273637d8d8a33d01ac99d06ab41",
+                "fetch_kib": 27994456.4, "write_kib": 5903225.8, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "1ced6eba328be114cfc913092c9bebc715183273637d8d8a33d01ac99d06ab41",
+                 "fetch_kib": 93930082.6, "write_kib": 6929511.2, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
