@@ -16,15 +16,16 @@ namespace {
 
 constexpr int LT = 256;
 
-// One thread per (node of level l, child slot): the child's six ropes.
+// One thread per (node of level l, child slot, face): one rope of the child.
 __global__ void __launch_bounds__(LT)
     k_child_ropes(int tree, int64_t begin, int64_t count, int nc, const int32_t *__restrict__ fc,
                   const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
                   int32_t *__restrict__ rope)
 {
-    int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
-    if (t >= count * nc) return;
-    child_ropes(tree, begin + t / nc, int(t % nc), fc, level, coord, rope);
+    const int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
+    if (t >= count * nc * 6) return;
+    const int64_t q = t / 6;   // one thread per (node, child, face)
+    child_rope(tree, begin + q / nc, int(q % nc), int(t % 6), fc, level, coord, rope);
 }
 
 __global__ void __launch_bounds__(LT) k_flag_leaves(const int32_t *__restrict__ fc, int64_t n,
@@ -145,7 +146,7 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     for (int l = 0; l < g->max_level; l++) {
         int64_t b = g->level_begin[l], e = g->level_begin[l + 1];
         if (e <= b) continue;
-        k_child_ropes<<<blocks_for((e - b) * nc), LT, 0, s>>>(g->tree, b, e - b, nc, g->first_child,
+        k_child_ropes<<<blocks_for((e - b) * nc * 6), LT, 0, s>>>(g->tree, b, e - b, nc, g->first_child,
                                                               g->level, g->coord, g->rope);
         HG_CHECK(hipGetLastError());
     }

@@ -70,35 +70,35 @@ __device__ inline int32_t push_down(int tree, int32_t n, int a, int up, const ui
     }
 }
 
-// The six ropes of child k of node p (whose own ropes are final).
-__device__ inline void child_ropes(int tree, int64_t p, int k, const int32_t *__restrict__ fc,
-                                   const uint8_t *__restrict__ level,
-                                   const uint32_t *__restrict__ coord, int32_t *__restrict__ rope)
+// Rope of face j (axis j / 2, upper side if j is odd) of child k of node p,
+// whose own ropes are final; nothing when p is a leaf.  A face between two
+// siblings leads to the sibling, any other face to the parent's rope target;
+// either is pushed down to the smallest node that still covers the face.
+__device__ inline void child_rope(int tree, int64_t p, int k, int j, const int32_t *__restrict__ fc,
+                                  const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
+                                  int32_t *__restrict__ rope)
 {
-    int32_t f = fc[p];
+    const int32_t f = fc[p];
     if (f < 0) return;
-    int lv = level[p];
-    int32_t child = f + k;
-    int32_t r[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) r[j] = rope[6 * p + j];
+    const int lv = level[p];
+    const int32_t child = f + k;
+    const int d = j / 2, up = j % 2;
+    int32_t r;
     if (tree == KD) {
-        int a = lv % 3;
-        if (k == 0) r[2 * a + 1] = f + 1;
-        else r[2 * a] = f;
+        const int a = lv % 3;
+        if (d == a && k == 0 && up) r = f + 1;
+        else if (d == a && k == 1 && !up) r = f;
+        else r = rope[6 * p + j];
     } else {
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            if (((k >> d) & 1) == 0) r[2 * d + 1] = f + (k | (1 << d));
-            else r[2 * d] = f + (k & ~(1 << d));
-        }
+        const int bit = (k >> d) & 1;
+        if (!bit && up) r = f + (k | (1 << d));
+        else if (bit && !up) r = f + (k & ~(1 << d));
+        else r = rope[6 * p + j];
     }
-    uint32_t c[3] = {coord[3 * child], coord[3 * child + 1], coord[3 * child + 2]};
+    const uint32_t c[3] = {coord[3 * child], coord[3 * child + 1], coord[3 * child + 2]};
     uint32_t clo[3], chi[3];
     int_extent(tree, lv + 1, c, clo, chi);
-#pragma unroll
-    for (int j = 0; j < 6; j++)
-        rope[6 * int64_t(child) + j] = push_down(tree, r[j], j / 2, j % 2, clo, chi, fc, level, coord);
+    rope[6 * int64_t(child) + j] = push_down(tree, r, d, up, clo, chi, fc, level, coord);
 }
 
 template <typename R>
