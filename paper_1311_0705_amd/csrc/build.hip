@@ -40,32 +40,39 @@ __device__ inline bool clump_bin_range(const Dens &D, uint32_t i, int lo[3], int
     return true;
 }
 
-__global__ void __launch_bounds__(BT) k_bin_count(Dens D, int32_t *__restrict__ cnt)
+// Binning: one 64-lane block per clump, its lanes over the clump's bins.
+constexpr int BIN_T = 64;
+
+__global__ void __launch_bounds__(BIN_T) k_bin_count(Dens D, int32_t *__restrict__ cnt)
 {
-    uint32_t i = blockIdx.x * BT + threadIdx.x;
-    if (int(i) >= D.n_clumps) return;
+    const uint32_t i = blockIdx.x;
     int lo[3], hi[3];
     if (!clump_bin_range(D, i, lo, hi)) return;
-    for (int x = lo[0]; x <= hi[0]; x++)
-        for (int y = lo[1]; y <= hi[1]; y++)
-            for (int z = lo[2]; z <= hi[2]; z++) atomicAdd(&cnt[(x * D.B + y) * D.B + z], 1);
+    const int ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+    const int total = (hi[0] - lo[0] + 1) * ny * nz;
+    for (int t = threadIdx.x; t < total; t += BIN_T) {
+        const int x = lo[0] + t / (ny * nz), y = lo[1] + (t / nz) % ny, z = lo[2] + t % nz;
+        atomicAdd(&cnt[(x * D.B + y) * D.B + z], 1);
+    }
 }
 
-__global__ void __launch_bounds__(BT) k_bin_fill(Dens D, const int64_t *__restrict__ start,
-                                                 int32_t *__restrict__ cursor,
-                                                 uint32_t *__restrict__ items)
+// The clump indices into their bins' slices (in any order; k_bin_sort
+// restores ascending order).
+__global__ void __launch_bounds__(BIN_T) k_bin_fill(Dens D, const int64_t *__restrict__ start,
+                                                    int32_t *__restrict__ cursor,
+                                                    uint32_t *__restrict__ items)
 {
-    uint32_t i = blockIdx.x * BT + threadIdx.x;
-    if (int(i) >= D.n_clumps) return;
+    const uint32_t i = blockIdx.x;
     int lo[3], hi[3];
     if (!clump_bin_range(D, i, lo, hi)) return;
-    for (int x = lo[0]; x <= hi[0]; x++)
-        for (int y = lo[1]; y <= hi[1]; y++)
-            for (int z = lo[2]; z <= hi[2]; z++) {
-                int b = (x * D.B + y) * D.B + z;
-                int p = atomicAdd(&cursor[b], 1);
-                items[start[b] + p] = i;
-            }
+    const int ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+    const int total = (hi[0] - lo[0] + 1) * ny * nz;
+    for (int t = threadIdx.x; t < total; t += BIN_T) {
+        const int x = lo[0] + t / (ny * nz), y = lo[1] + (t / nz) % ny, z = lo[2] + t % nz;
+        const int b = (x * D.B + y) * D.B + z;
+        const int p = atomicAdd(&cursor[b], 1);
+        items[start[b] + p] = i;
+    }
 }
 
 // Sort each bin's clump list ascending (insertion sort; lists are short).
@@ -266,7 +273,7 @@ int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *ou
     if (!rc) rc = btmp.alloc(scan_tmp_elems(nb) * 8);
     if (rc) return rc;
     HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
-    k_bin_count<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (int32_t *)bcnt.p);
+    k_bin_count<<<unsigned(D.n_clumps), BIN_T, 0, s>>>(D, (int32_t *)bcnt.p);
     HG_CHECK(hipGetLastError());
     rc = scan_i32_to_i64((const int32_t *)bcnt.p, (int64_t *)st->bin_start, nb, (int64_t *)btmp.p, s);
     if (rc) return rc;
@@ -275,8 +282,8 @@ int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *ou
     HG_CHECK(hipStreamSynchronize(s));
     if ((rc = dalloc(&st->bin_items, size_t(items > 0 ? items : 1) * 4, s))) return rc;
     HG_CHECK(hipMemsetAsync(bcnt.p, 0, size_t(nb) * 4, s));
-    k_bin_fill<<<nblocks(D.n_clumps, BT), BT, 0, s>>>(D, (const int64_t *)st->bin_start,
-                                                      (int32_t *)bcnt.p, (uint32_t *)st->bin_items);
+    k_bin_fill<<<unsigned(D.n_clumps), BIN_T, 0, s>>>(D, (const int64_t *)st->bin_start,
+                                                     (int32_t *)bcnt.p, (uint32_t *)st->bin_items);
     HG_CHECK(hipGetLastError());
     k_bin_sort<<<nblocks(nb, BT), BT, 0, s>>>(int(nb), (const int64_t *)st->bin_start,
                                               (uint32_t *)st->bin_items);
