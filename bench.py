@@ -713,8 +713,8 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only; runs on more than one GPU are not "
-              "part of it (rays shard with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; multi-GPU runs are not implemented (paths would "
+              "shard across GPUs with no exchange during the walk)", file=sys.stderr)
         sys.exit(2)
 
     import torch
