@@ -74,9 +74,9 @@ TUNE_PATHS = 10_000_000
 # the workload it was measured on.
 TRAFFIC = {
     "w2_slab": {"trace_sha256": "1ced6eba328be114cfc913092c9bebc715183273637d8d8a33d01ac99d06ab41",
-                "fetch_kib": 27994456.4, "write_kib": 5903225.8, "fetch_scale": 2.0, "write_scale": 1.0},
+                "fetch_kib": 27994964.0, "write_kib": 5903237.7, "fetch_scale": 2.0, "write_scale": 1.0},
     "w3kd_tau": {"trace_sha256": "1ced6eba328be114cfc913092c9bebc715183273637d8d8a33d01ac99d06ab41",
-                 "fetch_kib": 93930082.6, "write_kib": 6929511.2, "fetch_scale": 2.0, "write_scale": 1.0},
+                 "fetch_kib": 93939200.2, "write_kib": 6928821.9, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
