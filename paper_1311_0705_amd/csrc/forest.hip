@@ -233,22 +233,30 @@ __global__ void __launch_bounds__(FT) k_f_append(const ForestGrid *__restrict__ 
     }
 }
 
-// Ropes of the children of level lv's nodes: one thread per (node, child,
-// face), nc_max children per node (threads beyond a k-d node's two children
-// have nothing to do).
+// Ropes of the children of level lv's nodes.  A single grid: one thread per
+// (node, child, face), so the push-downs of a node's children overlap.  Many
+// grids: one thread per node (its children's faces in turn), which keeps the
+// search for each item's grid to one per node.
 __global__ void __launch_bounds__(FT) k_f_ropes(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                const int64_t *__restrict__ P, int nc_max)
+                                                const int64_t *__restrict__ P)
 {
-    const int64_t per = int64_t(nc_max) * 6;
-    const int64_t T = P[ng] * per;
+    if (ng == 1) {
+        const ForestGrid &G = F[0];
+        const int64_t per = int64_t(G.nc) * 6;
+        const int64_t T = P[1] * per;
+        for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
+            const int64_t tp = t / per;
+            const int rem = int(t - tp * per);
+            child_rope(G.tree, G.meta[lv] + tp, rem / 6, rem % 6, G.fc, G.level, G.coord, G.rope);
+        }
+        return;
+    }
+    const int64_t T = P[ng];
     for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
-        const int64_t tp = t / per;
-        const int rem = int(t - tp * per), k = rem / 6, j = rem % 6;
-        const int i = owner(P, ng, tp);
+        const int i = owner(P, ng, t);
         const ForestGrid &G = F[i];
-        if (k >= G.nc) continue;
-        const int64_t p = G.meta[lv] + (tp - P[i]);
-        child_rope(G.tree, p, k, j, G.fc, G.level, G.coord, G.rope);
+        const int64_t p = G.meta[lv] + (t - P[i]);
+        for (int k = 0; k < G.nc; k++) child_ropes(G.tree, p, k, G.fc, G.level, G.coord, G.rope);
     }
 }
 
@@ -436,7 +444,6 @@ struct hg_batch {
     int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
     int64_t *PW = nullptr;          // [ng+1] wavefronts of 64 nodes per grid, current level
     bool wave_sampling = false;     // one wavefront per node (densities with many clumps)
-    int nc_max = 2;                 // children per node: 8 if any grid is an octree
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
@@ -527,7 +534,7 @@ int enqueue_build(hg_batch *b, hipStream_t s)
         HG_CHECK(hipGetLastError());
     }
     for (int lv = 0; lv < b->lmax; lv++) {
-        k_f_ropes<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, b->P + size_t(lv) * size_t(ng + 1), b->nc_max);
+        k_f_ropes<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, b->P + size_t(lv) * size_t(ng + 1));
         HG_CHECK(hipGetLastError());
     }
     k_f_node_prefix<<<1, FT, 0, s>>>(b->dF, ng, b->lmax, b->PN);
@@ -585,10 +592,7 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     }
     hg_batch *b = new hg_batch;
     b->ng = n_grids;
-    for (int i = 0; i < n_grids; i++) {
-        b->wave_sampling |= dens[i].n_clumps >= WAVE_SAMPLING_CLUMPS;
-        if (tree_types[i] == HG_OCTREE) b->nc_max = 8;
-    }
+    for (int i = 0; i < n_grids; i++) b->wave_sampling |= dens[i].n_clumps >= WAVE_SAMPLING_CLUMPS;
     b->lmax = lmax;
     b->dens.resize(size_t(n_grids));
     b->hF.resize(size_t(n_grids));

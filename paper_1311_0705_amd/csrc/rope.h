@@ -70,6 +70,38 @@ __device__ inline int32_t push_down(int tree, int32_t n, int a, int up, const ui
     }
 }
 
+// The six ropes of child k of node p (whose own ropes are final), as
+// child_rope for every face with the node's loads shared.
+__device__ inline void child_ropes(int tree, int64_t p, int k, const int32_t *__restrict__ fc,
+                                   const uint8_t *__restrict__ level,
+                                   const uint32_t *__restrict__ coord, int32_t *__restrict__ rope)
+{
+    const int32_t f = fc[p];
+    if (f < 0) return;
+    const int lv = level[p];
+    const int32_t child = f + k;
+    int32_t r[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) r[j] = rope[6 * p + j];
+    if (tree == KD) {
+        const int a = lv % 3;
+        if (k == 0) r[2 * a + 1] = f + 1;
+        else r[2 * a] = f;
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            if (((k >> d) & 1) == 0) r[2 * d + 1] = f + (k | (1 << d));
+            else r[2 * d] = f + (k & ~(1 << d));
+        }
+    }
+    const uint32_t c[3] = {coord[3 * child], coord[3 * child + 1], coord[3 * child + 2]};
+    uint32_t clo[3], chi[3];
+    int_extent(tree, lv + 1, c, clo, chi);
+#pragma unroll
+    for (int j = 0; j < 6; j++)
+        rope[6 * int64_t(child) + j] = push_down(tree, r[j], j / 2, j % 2, clo, chi, fc, level, coord);
+}
+
 // Rope of face j (axis j / 2, upper side if j is odd) of child k of node p,
 // whose own ropes are final; nothing when p is a leaf.  A face between two
 // siblings leads to the sibling, any other face to the parent's rope target;
