@@ -6,7 +6,8 @@
 // slice, and an exclusive prefix sum of their split flags gives every child its
 // slot in level l+1 in exactly the order the sequential loop would append it.
 // Per level:  k_sample_decide (one lane per node, its Monte Carlo samples in
-// order, or one wavefront per node for densities with many clumps: node mass
+// order, or one wavefront per node for densities with many clumps and for
+// levels with few nodes: node mass
 // of Eq. 1, criteria delta, tau of Eq. 2, q of Eq. 3),
 // prefix sum of split flags, k_append (children's level and cell coordinates).
 #include <math.h>
@@ -350,7 +351,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
             if ((rc = tmp.alloc(scan_tmp_elems(c) * 8))) return rc;
             scap = c;
         }
-        if (D.n_clumps >= WAVE_SAMPLING_CLUMPS)
+        if (D.n_clumps >= WAVE_SAMPLING_CLUMPS || cnt <= WAVE_LEVEL_NODES)
             k_sample_decide_wave<<<nblocks(cnt * 64, BT), BT, 0, s>>>(tree, D, C, begin, cnt, g->level,
                                                                      g->coord, bin_start, g->S, g->rmin,
                                                                      g->rmax, (uint8_t *)split.p);

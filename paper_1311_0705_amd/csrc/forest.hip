@@ -126,9 +126,8 @@ __global__ void __launch_bounds__(FT) k_f_level_prefix(const ForestGrid *__restr
 }
 
 // One wavefront per node of level lv, over all grids.
-__global__ void __launch_bounds__(FT) k_f_sample_wave(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                      const int64_t *__restrict__ P,
-                                                      uint8_t *__restrict__ flag)
+__device__ __forceinline__ void sample_level_wave(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                  const int64_t *__restrict__ P, uint8_t *__restrict__ flag)
 {
     const int lane = threadIdx.x & 63;
     const int64_t T = P[ng];
@@ -153,9 +152,9 @@ __global__ void __launch_bounds__(FT) k_f_sample_wave(const ForestGrid *__restri
 
 // One lane per node of level lv: a wavefront takes up to 64 consecutive nodes
 // of one grid, whose density and criteria then sit in scalar registers.
-__global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                 const int64_t *__restrict__ P,
-                                                 const int64_t *__restrict__ PW, uint8_t *__restrict__ flag)
+__device__ __forceinline__ void sample_level_lane(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                  const int64_t *__restrict__ P,
+                                                  const int64_t *__restrict__ PW, uint8_t *__restrict__ flag)
 {
     const int lane = threadIdx.x & 63;
     const int64_t TW = PW[ng];
@@ -176,6 +175,19 @@ __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ 
             flag[P[i] + k] = r.split ? 1 : 0;
         }
     }
+}
+
+// Node sampling of level lv over all grids: one wavefront per node when the
+// level holds at most wave_max nodes in all (the level size is on the device,
+// so the choice is made here, the same for the whole launch), one lane per
+// node otherwise.
+__global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                 const int64_t *__restrict__ P,
+                                                 const int64_t *__restrict__ PW, uint8_t *__restrict__ flag,
+                                                 int64_t wave_max)
+{
+    if (P[ng] <= wave_max) sample_level_wave(F, ng, lv, P, flag);
+    else sample_level_lane(F, ng, lv, P, PW, flag);
 }
 
 // Per grid: the next level's extent, or an error if it would not fit.
@@ -523,10 +535,8 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     for (int lv = 0; lv <= b->lmax; lv++) {
         int64_t *P = b->P + size_t(lv) * size_t(ng + 1);
         int64_t *P_next = lv < b->lmax ? P + (ng + 1) : nullptr;
-        if (b->wave_sampling)
-            k_f_sample_wave<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag);
-        else
-            k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag);
+        const int64_t wave_max = b->wave_sampling ? INT64_MAX : WAVE_LEVEL_NODES;
+        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag, wave_max);
         HG_CHECK(hipGetLastError());
         int rc = scan_u8_to_i64_dev(b->flag, b->off, P + ng, b->stmp, s);
         if (rc) return rc;

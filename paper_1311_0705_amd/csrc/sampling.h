@@ -200,6 +200,13 @@ __device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const Cri
 // nodes would then loop over different bins), one lane per node otherwise.
 constexpr int64_t WAVE_SAMPLING_CLUMPS = 10000;
 
+// Levels with at most this many nodes are sampled one wavefront per node
+// whatever the density: one lane per node would leave most of the chip idle
+// while each busy lane draws all n_samples points in sequence, where a
+// wavefront per node needs one round of draws and the ordered sum.  Both
+// forms give the same bits.
+constexpr int64_t WAVE_LEVEL_NODES = 16384;
+
 // Level and cell coordinates of child k of a node (k-d: split axis level mod
 // 3, lower half first; octree: octant k = bx + 2 by + 4 bz).
 __host__ __device__ inline void child_coord(int tree, int lv, const uint32_t c[3], int k, uint32_t cc[3])
