@@ -6,8 +6,8 @@
 // slice, and an exclusive prefix sum of their split flags gives every child its
 // slot in level l+1 in exactly the order the sequential loop would append it.
 // Per level:  k_sample_decide (one lane per node, its Monte Carlo samples in
-// order, or one wavefront per node for densities with many clumps and for
-// levels with few nodes: node mass
+// order; on levels too small to fill the chip, and for densities with many
+// clumps, k_sample_decide_group with 2 to 64 lanes per node: node mass
 // of Eq. 1, criteria delta, tau of Eq. 2, q of Eq. 3),
 // prefix sum of split flags, k_append (children's level and cell coordinates).
 #include <math.h>
@@ -96,21 +96,21 @@ __global__ void __launch_bounds__(BT) k_bin_sort(int n_bins, const int64_t *__re
 
 // ---- per-level kernels ------------------------------------------------------
 
-// One wavefront per node of the level slice [begin, begin+count).
+// G lanes per node of the level slice [begin, begin+count).
+template <int G>
 __global__ void __launch_bounds__(BT)
-    k_sample_decide_wave(int tree, Dens D, CritDev C, int64_t begin, int64_t count,
-                         const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
-                         const int64_t *__restrict__ bin_start, double *__restrict__ S_out,
-                         double *__restrict__ mn_out, double *__restrict__ mx_out,
-                         uint8_t *__restrict__ split)
+    k_sample_decide_group(int tree, Dens D, CritDev C, int64_t begin, int64_t count,
+                          const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
+                          const int64_t *__restrict__ bin_start, double *__restrict__ S_out,
+                          double *__restrict__ mn_out, double *__restrict__ mx_out,
+                          uint8_t *__restrict__ split)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t(blockIdx.x) * BT + threadIdx.x) >> 6;
-    if (t >= count) return;  // whole wavefront leaves together
+    const int64_t t = (int64_t(blockIdx.x) * BT + threadIdx.x) / G;
+    if (t >= count) return;  // the whole group leaves together
     const int64_t i = begin + t;
-    const NodeSample r = sample_node_wave(tree, D, C, level[i], coord[3 * i], coord[3 * i + 1],
-                                          coord[3 * i + 2], bin_start);
-    if (lane != 0) return;
+    const NodeSample r = sample_node_group<G>(tree, D, C, level[i], coord[3 * i], coord[3 * i + 1],
+                                              coord[3 * i + 2], bin_start);
+    if ((threadIdx.x & (G - 1)) != 0) return;
     S_out[i] = r.S;
     mn_out[i] = r.mn;
     mx_out[i] = r.mx;
@@ -351,14 +351,19 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
             if ((rc = tmp.alloc(scan_tmp_elems(c) * 8))) return rc;
             scap = c;
         }
-        if (D.n_clumps >= WAVE_SAMPLING_CLUMPS || cnt <= WAVE_LEVEL_NODES)
-            k_sample_decide_wave<<<nblocks(cnt * 64, BT), BT, 0, s>>>(tree, D, C, begin, cnt, g->level,
-                                                                     g->coord, bin_start, g->S, g->rmin,
-                                                                     g->rmax, (uint8_t *)split.p);
-        else
-            k_sample_decide<<<nblocks(cnt, BT), BT, 0, s>>>(tree, D, C, begin, cnt, g->level,
-                                                           g->coord, bin_start, g->S, g->rmin,
-                                                           g->rmax, (uint8_t *)split.p);
+        const int gs = sample_group(cnt, D.n_clumps >= WAVE_SAMPLING_CLUMPS ? 64 : 1);
+#define HG_SAMPLE_ARGS tree, D, C, begin, cnt, g->level, g->coord, bin_start, g->S, g->rmin, g->rmax, \
+                       (uint8_t *)split.p
+        switch (gs) {
+        case 1: k_sample_decide<<<nblocks(cnt, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        case 2: k_sample_decide_group<2><<<nblocks(cnt * 2, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        case 4: k_sample_decide_group<4><<<nblocks(cnt * 4, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        case 8: k_sample_decide_group<8><<<nblocks(cnt * 8, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        case 16: k_sample_decide_group<16><<<nblocks(cnt * 16, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        case 32: k_sample_decide_group<32><<<nblocks(cnt * 32, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        default: k_sample_decide_group<64><<<nblocks(cnt * 64, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
+        }
+#undef HG_SAMPLE_ARGS
         HG_CHECK(hipGetLastError());
         rc = scan_u8_to_i64((const uint8_t *)split.p, (int64_t *)off.p, cnt, (int64_t *)tmp.p, s);
         if (rc) return rc;

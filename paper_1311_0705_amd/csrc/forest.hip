@@ -69,9 +69,10 @@ __device__ inline int owner(const int64_t *__restrict__ P, int ng, int64_t t)
     return lo;
 }
 
-// Exclusive prefix of per-grid values v(i) into P[0..ng] by one block.
+// Exclusive prefix of per-grid values v(i) into P[0..ng] by one block;
+// returns the total to every thread.
 template <typename F>
-__device__ inline void block_prefix(int ng, int64_t *P, F v)
+__device__ inline int64_t block_prefix(int ng, int64_t *P, F v)
 {
     __shared__ int64_t part[FT + 1];
     const int per = (ng + FT - 1) / FT;
@@ -96,6 +97,7 @@ __device__ inline void block_prefix(int ng, int64_t *P, F v)
         run += v(i);
     }
     if (threadIdx.x == 0) P[ng] = part[FT];
+    return part[FT];
 }
 
 __global__ void __launch_bounds__(FT) k_f_init(const ForestGrid *__restrict__ F, int ng)
@@ -115,37 +117,56 @@ __global__ void __launch_bounds__(FT) k_f_init(const ForestGrid *__restrict__ F,
     G.meta[M_ERR] = 0;
 }
 
-// P: prefix of the per-grid node counts of level lv; PW: prefix of the same
-// counts in wavefronts of 64 nodes (a wavefront never spans two grids).
-__global__ void __launch_bounds__(FT) k_f_level_prefix(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                       int64_t *P, int64_t *PW)
+// Wavefronts of the sampling of a level with per-grid node counts n(i):
+// the lanes per node g for the level's total (sample_group, at least gmin)
+// goes to PW[ng+1], and PW[0..ng] is the prefix of the per-grid wavefront
+// counts (64/g nodes to a wavefront; a wavefront never spans two grids).
+template <typename N>
+__device__ inline void sample_waves(int ng, int64_t total, int gmin, int64_t *PW, N n)
 {
-    block_prefix(ng, P, [&](int i) { return F[i].meta[lv + 1] - F[i].meta[lv]; });
-    __syncthreads();
-    block_prefix(ng, PW, [&](int i) { return (F[i].meta[lv + 1] - F[i].meta[lv] + 63) / 64; });
+    const int g = sample_group(total, gmin);
+    block_prefix(ng, PW, [&](int i) { return (n(i) * g + 63) / 64; });
+    if (threadIdx.x == 0) PW[ng + 1] = g;
 }
 
-// One wavefront per node of level lv, over all grids.
-__device__ __forceinline__ void sample_level_wave(const ForestGrid *__restrict__ F, int ng, int lv,
-                                                  const int64_t *__restrict__ P, uint8_t *__restrict__ flag)
+// P: prefix of the per-grid node counts of level lv; PW: its sampling
+// wavefronts (sample_waves).
+__global__ void __launch_bounds__(FT) k_f_level_prefix(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                       int64_t *P, int64_t *PW, int gmin)
+{
+    auto count = [&](int i) { return F[i].meta[lv + 1] - F[i].meta[lv]; };
+    const int64_t total = block_prefix(ng, P, count);
+    __syncthreads();
+    sample_waves(ng, total, gmin, PW, count);
+}
+
+// G lanes per node of level lv (2 <= G <= 64), over all grids: a wavefront
+// takes 64/G consecutive nodes of one grid.
+template <int G>
+__device__ __forceinline__ void sample_level_group(const ForestGrid *__restrict__ F, int ng, int lv,
+                                                   const int64_t *__restrict__ P,
+                                                   const int64_t *__restrict__ PW, uint8_t *__restrict__ flag)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t T = P[ng];
+    const int64_t TW = PW[ng];
     const int64_t nw = int64_t(gridDim.x) * (FT / 64);
-    for (int64_t t = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; t < T; t += nw) {
-        // the node and its grid are the same for the whole wavefront
-        const int i = __builtin_amdgcn_readfirstlane(owner(P, ng, t));
-        const ForestGrid &G = F[i];
-        const Dens D = G.D;
-        const CritDev C = G.C;
-        const int64_t n = G.meta[lv] + (t - P[i]);
-        const NodeSample r = sample_node_wave(G.tree, D, C, lv, G.coord[3 * n], G.coord[3 * n + 1],
-                                              G.coord[3 * n + 2], G.bin_start);
-        if (lane == 0) {
-            G.S[n] = r.S;
-            G.rmin[n] = r.mn;
-            G.rmax[n] = r.mx;
-            flag[t] = r.split ? 1 : 0;
+    for (int64_t w = (int64_t(blockIdx.x) * FT + threadIdx.x) >> 6; w < TW; w += nw) {
+        // the grid is the same for the whole wavefront
+        const int i = __builtin_amdgcn_readfirstlane(owner(PW, ng, w));
+        const ForestGrid &Gr = F[i];
+        const Dens D = Gr.D;
+        const CritDev C = Gr.C;
+        const int64_t k = (w - PW[i]) * (64 / G) + lane / G;   // rank of the group's node in the level
+        if (k < P[i + 1] - P[i]) {
+            const int64_t n = Gr.meta[lv] + k;
+            const NodeSample r = sample_node_group<G>(Gr.tree, D, C, lv, Gr.coord[3 * n],
+                                                      Gr.coord[3 * n + 1], Gr.coord[3 * n + 2], Gr.bin_start);
+            if ((lane & (G - 1)) == 0) {
+                Gr.S[n] = r.S;
+                Gr.rmin[n] = r.mn;
+                Gr.rmax[n] = r.mx;
+                flag[P[i] + k] = r.split ? 1 : 0;
+            }
         }
     }
 }
@@ -177,17 +198,22 @@ __device__ __forceinline__ void sample_level_lane(const ForestGrid *__restrict__
     }
 }
 
-// Node sampling of level lv over all grids: one wavefront per node when the
-// level holds at most wave_max nodes in all (the level size is on the device,
-// so the choice is made here, the same for the whole launch), one lane per
-// node otherwise.
+// Node sampling of level lv over all grids, with the lanes per node that the
+// level's wavefront prefix was made for (PW[ng+1]; the same for the whole
+// launch).
 __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ F, int ng, int lv,
                                                  const int64_t *__restrict__ P,
-                                                 const int64_t *__restrict__ PW, uint8_t *__restrict__ flag,
-                                                 int64_t wave_max)
+                                                 const int64_t *__restrict__ PW, uint8_t *__restrict__ flag)
 {
-    if (P[ng] <= wave_max) sample_level_wave(F, ng, lv, P, flag);
-    else sample_level_lane(F, ng, lv, P, PW, flag);
+    switch (int(PW[ng + 1])) {
+    case 1: sample_level_lane(F, ng, lv, P, PW, flag); break;
+    case 2: sample_level_group<2>(F, ng, lv, P, PW, flag); break;
+    case 4: sample_level_group<4>(F, ng, lv, P, PW, flag); break;
+    case 8: sample_level_group<8>(F, ng, lv, P, PW, flag); break;
+    case 16: sample_level_group<16>(F, ng, lv, P, PW, flag); break;
+    case 32: sample_level_group<32>(F, ng, lv, P, PW, flag); break;
+    default: sample_level_group<64>(F, ng, lv, P, PW, flag); break;
+    }
 }
 
 // Per grid: the next level's extent, or an error if it would not fit.
@@ -195,13 +221,13 @@ __global__ void __launch_bounds__(FT) k_f_sample(const ForestGrid *__restrict__ 
 // derives its grid's next-level size from the split-flag prefix (so no
 // separate pass has to publish it first); the thread of a grid's first node
 // records that size in meta (or the capacity error), and block 0 computes
-// the per-grid prefixes of the next level's node counts (P_next, PW; nothing
-// when P_next is null).
+// the per-grid prefix of the next level's node counts (P_next) and its
+// sampling wavefronts (PW; nothing when P_next is null).
 __global__ void __launch_bounds__(FT) k_f_append(const ForestGrid *__restrict__ F, int ng, int lv,
                                                  const int64_t *__restrict__ P,
                                                  const uint8_t *__restrict__ flag,
                                                  const int64_t *__restrict__ off, int64_t *P_next,
-                                                 int64_t *PW)
+                                                 int64_t *PW, int gmin)
 {
     // the next level's node count of grid i (0 if it would not fit)
     auto next_count = [&](int i) {
@@ -210,9 +236,9 @@ __global__ void __launch_bounds__(FT) k_f_append(const ForestGrid *__restrict__ 
         return G.meta[lv + 1] + nn > G.cap ? int64_t(0) : nn;
     };
     if (P_next && blockIdx.x == 0) {
-        block_prefix(ng, P_next, next_count);
+        const int64_t total = block_prefix(ng, P_next, next_count);
         __syncthreads();
-        block_prefix(ng, PW, [&](int i) { return (next_count(i) + 63) / 64; });
+        sample_waves(ng, total, gmin, PW, next_count);
     }
     const int64_t T = P[ng];
     for (int64_t t = int64_t(blockIdx.x) * FT + threadIdx.x; t < T; t += int64_t(gridDim.x) * FT) {
@@ -454,7 +480,7 @@ struct hg_batch {
     int64_t *meta = nullptr;        // [ng][META]
     int64_t *P = nullptr;           // [(lmax+1)][ng+1]
     int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
-    int64_t *PW = nullptr;          // [ng+1] wavefronts of 64 nodes per grid, current level
+    int64_t *PW = nullptr;          // [ng+2] sampling wavefronts per grid and lanes per node, current level
     bool wave_sampling = false;     // one wavefront per node (densities with many clumps)
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
@@ -530,17 +556,17 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     const unsigned gb = unsigned((ng + FT - 1) / FT);
     k_f_init<<<gb, FT, 0, s>>>(b->dF, ng);
     HG_CHECK(hipGetLastError());
-    k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, 0, b->P, b->PW);
+    const int gmin = b->wave_sampling ? 64 : 1;
+    k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, 0, b->P, b->PW, gmin);
     HG_CHECK(hipGetLastError());
     for (int lv = 0; lv <= b->lmax; lv++) {
         int64_t *P = b->P + size_t(lv) * size_t(ng + 1);
         int64_t *P_next = lv < b->lmax ? P + (ng + 1) : nullptr;
-        const int64_t wave_max = b->wave_sampling ? INT64_MAX : WAVE_LEVEL_NODES;
-        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag, wave_max);
+        k_f_sample<<<SAMPLE_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->PW, b->flag);
         HG_CHECK(hipGetLastError());
         int rc = scan_u8_to_i64_dev(b->flag, b->off, P + ng, b->stmp, s);
         if (rc) return rc;
-        k_f_append<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag, b->off, P_next, b->PW);
+        k_f_append<<<FLAT_BLOCKS, FT, 0, s>>>(b->dF, ng, lv, P, b->flag, b->off, P_next, b->PW, gmin);
         HG_CHECK(hipGetLastError());
     }
     for (int lv = 0; lv < b->lmax; lv++) {
@@ -655,7 +681,7 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     ct.add(&b->PN, ng1);
     ct.add(&b->PL, ng1);
     ct.add(&b->PT, ng1);
-    ct.add(&b->PW, ng1);
+    ct.add(&b->PW, ng1 + 1);
     ct.add(&b->flag, size_t(total_cap));
     ct.add(&b->off, size_t(total_cap) + 1);
     ct.add(&b->stmp, scan_dev_tmp_elems());

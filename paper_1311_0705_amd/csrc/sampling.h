@@ -159,22 +159,35 @@ __device__ inline double read_lane_f64(double v, int lane)
     return __hiloint2double(__builtin_amdgcn_readlane(hi, lane), __builtin_amdgcn_readlane(lo, lane));
 }
 
-// One node per wavefront (every lane calls it with the same node): lane l
-// draws samples l, l+64, ...; S runs in sample order through an ordered
-// readlane reduction, min and max are order-free.  All lanes then evaluate
-// the density in the same clump bin, which pays when bins hold many clumps.
-__device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const CritDev &C, int lv,
-                                              uint32_t c0, uint32_t c1, uint32_t c2,
-                                              const int64_t *__restrict__ bin_start)
+// Value of v in lane j of the caller's group of G lanes (groups are aligned
+// in the wavefront; every lane of the group is active).
+template <int G>
+__device__ inline double group_read_f64(double v, int j)
 {
-    const int lane = threadIdx.x & 63;
+    if (G == 64) return read_lane_f64(v, j);
+    return __shfl(v, j, G);
+}
+
+// G lanes per node (G a power of two, 2 <= G <= 64; all lanes of a group call
+// it with the same node): lane l of the group draws samples l, l+G, ...; each
+// lane keeps its own copy of S and adds the G values of a round in sample
+// order, so S is the same sequential sum as with one lane per node.  Min and
+// max are order-free.  With G = 64 all lanes evaluate the density in the same
+// clump bin, which pays when bins hold many clumps; smaller groups shorten the
+// sequence of samples per lane on levels too small to fill the chip.
+template <int G>
+__device__ inline NodeSample sample_node_group(int tree, const Dens &D, const CritDev &C, int lv,
+                                               uint32_t c0, uint32_t c1, uint32_t c2,
+                                               const int64_t *__restrict__ bin_start)
+{
+    const int l = threadIdx.x & (G - 1);
     const uint32_t c[3] = {c0, c1, c2};
     double w[3], lo[3];
     node_box(tree, D, lv, c, w, lo);
     const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
     double S = 0.0, mn = INFINITY, mx = -INFINITY;
-    for (int base = 0; base < C.n_samples; base += 64) {
-        const int j = base + lane;
+    for (int base = 0; base < C.n_samples; base += G) {
+        const int j = base + l;
         double r = 0.0;
         if (j < C.n_samples) {
             const double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
@@ -184,11 +197,11 @@ __device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const Cri
             mn = fmin(mn, r);
             mx = fmax(mx, r);
         }
-        const int m = min(64, C.n_samples - base);
-        for (int jj = 0; jj < m; jj++) S = S + read_lane_f64(r, jj);
+        const int m = min(G, C.n_samples - base);
+        for (int jj = 0; jj < m; jj++) S = S + group_read_f64<G>(r, jj);
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
+    for (int o = G / 2; o > 0; o >>= 1) {
         mn = fmin(mn, __shfl_xor(mn, o, 64));
         mx = fmax(mx, __shfl_xor(mx, o, 64));
     }
@@ -197,15 +210,25 @@ __device__ inline NodeSample sample_node_wave(int tree, const Dens &D, const Cri
 
 // Node sampling one wavefront per node for densities with at least this many
 // clumps (clustered clumps fill bins with many of them; lanes on different
-// nodes would then loop over different bins), one lane per node otherwise.
+// nodes would then loop over different bins).
 constexpr int64_t WAVE_SAMPLING_CLUMPS = 10000;
 
-// Levels with at most this many nodes are sampled one wavefront per node
-// whatever the density: one lane per node would leave most of the chip idle
-// while each busy lane draws all n_samples points in sequence, where a
-// wavefront per node needs one round of draws and the ordered sum.  Both
-// forms give the same bits.
-constexpr int64_t WAVE_LEVEL_NODES = 16384;
+// Lanes kept busy by node sampling: eight wavefronts on each of the 1024
+// SIMDs of the chip.
+constexpr int64_t SAMPLE_LANES = int64_t(1) << 19;
+
+// Lanes per node for a level of n nodes (over all grids sampled together):
+// one lane per node where the level fills the chip, otherwise the smallest
+// power of two up to a wavefront that does, so a small level is not one
+// lane drawing all n_samples points in sequence while the rest idle; at
+// least gmin (64 for densities with many clumps).  Every group size gives the
+// same bits.
+__host__ __device__ inline int sample_group(int64_t n, int gmin)
+{
+    int g = 1;
+    while (g < 64 && n * (2 * g) <= SAMPLE_LANES) g *= 2;
+    return g < gmin ? gmin : g;
+}
 
 // Level and cell coordinates of child k of a node (k-d: split axis level mod
 // 3, lower half first; octree: octant k = bx + 2 by + 4 bz).
