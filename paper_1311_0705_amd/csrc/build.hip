@@ -351,7 +351,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
             if ((rc = tmp.alloc(scan_tmp_elems(c) * 8))) return rc;
             scap = c;
         }
-        const int gs = sample_group(cnt, D.n_clumps >= WAVE_SAMPLING_CLUMPS ? 64 : 1);
+        const int gs = sample_group(cnt, D.n_clumps >= WAVE_SAMPLING_CLUMPS ? 16 : 1);
 #define HG_SAMPLE_ARGS tree, D, C, begin, cnt, g->level, g->coord, bin_start, g->S, g->rmin, g->rmax, \
                        (uint8_t *)split.p
         switch (gs) {

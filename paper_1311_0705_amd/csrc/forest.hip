@@ -481,7 +481,7 @@ struct hg_batch {
     int64_t *P = nullptr;           // [(lmax+1)][ng+1]
     int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
     int64_t *PW = nullptr;          // [ng+2] sampling wavefronts per grid and lanes per node, current level
-    bool wave_sampling = false;     // one wavefront per node (densities with many clumps)
+    bool wave_sampling = false;     // at least 16 lanes per node (densities with many clumps)
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
@@ -556,7 +556,7 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     const unsigned gb = unsigned((ng + FT - 1) / FT);
     k_f_init<<<gb, FT, 0, s>>>(b->dF, ng);
     HG_CHECK(hipGetLastError());
-    const int gmin = b->wave_sampling ? 64 : 1;
+    const int gmin = b->wave_sampling ? 16 : 1;
     k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, 0, b->P, b->PW, gmin);
     HG_CHECK(hipGetLastError());
     for (int lv = 0; lv <= b->lmax; lv++) {

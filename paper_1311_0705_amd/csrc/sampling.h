@@ -208,9 +208,9 @@ __device__ inline NodeSample sample_node_group(int tree, const Dens &D, const Cr
     return decide_node(C, lv, w, S, mn, mx);
 }
 
-// Node sampling one wavefront per node for densities with at least this many
-// clumps (clustered clumps fill bins with many of them; lanes on different
-// nodes would then loop over different bins).
+// Node sampling with at least 16 lanes per node for densities with at least
+// this many clumps (clustered clumps fill bins with many of them; lanes on
+// different nodes would then loop over different bins).
 constexpr int64_t WAVE_SAMPLING_CLUMPS = 10000;
 
 // Lanes kept busy by node sampling: eight wavefronts on each of the 1024
@@ -221,8 +221,8 @@ constexpr int64_t SAMPLE_LANES = int64_t(1) << 19;
 // one lane per node where the level fills the chip, otherwise the smallest
 // power of two up to a wavefront that does, so a small level is not one
 // lane drawing all n_samples points in sequence while the rest idle; at
-// least gmin (64 for densities with many clumps).  Every group size gives the
-// same bits.
+// least gmin.  Every group size gives the
+// same bits.  gmin is 16 for densities with many clumps, else 1.
 __host__ __device__ inline int sample_group(int64_t n, int gmin)
 {
     int g = 1;
