@@ -94,6 +94,26 @@ __global__ void __launch_bounds__(BT) k_bin_sort(int n_bins, const int64_t *__re
     }
 }
 
+// Bin list entries as records (ClumpRec) of the clumps they name: (trunc
+// sigma)^2 as (trunc sigma)(trunc sigma) and 2 sigma^2 as (2 sigma) sigma, the
+// products the density sum compares and divides by.
+__global__ void __launch_bounds__(BT) k_bin_recs(Dens D, int64_t items, ClumpRec *__restrict__ recs)
+{
+    const int64_t j = int64_t(blockIdx.x) * BT + threadIdx.x;
+    if (j >= items) return;
+    const uint32_t i = D.bin_items[j];
+    const double s = D.cs[i];
+    const double lim = D.trunc * s;
+    ClumpRec r;
+    r.cx = D.cc[3 * i + 0];
+    r.cy = D.cc[3 * i + 1];
+    r.cz = D.cc[3 * i + 2];
+    r.lim2 = lim * lim;
+    r.d2 = 2.0 * s * s;
+    r.a = D.ca[i];
+    recs[j] = r;
+}
+
 // ---- per-level kernels ------------------------------------------------------
 
 // G lanes per node of the level slice [begin, begin+count).
@@ -290,6 +310,12 @@ int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *ou
                                               (uint32_t *)st->bin_items);
     HG_CHECK(hipGetLastError());
     D.bin_items = (const uint32_t *)st->bin_items;
+    if ((rc = dalloc(&st->bin_recs, size_t(items > 0 ? items : 1) * sizeof(ClumpRec), s))) return rc;
+    if (items > 0) {
+        k_bin_recs<<<nblocks(items, BT), BT, 0, s>>>(D, items, (ClumpRec *)st->bin_recs);
+        HG_CHECK(hipGetLastError());
+    }
+    D.bin_recs = (const ClumpRec *)st->bin_recs;
     *out = D;
     return HG_OK;
 }
@@ -301,6 +327,7 @@ void release_density(DensStore *st, hipStream_t s)
     dfree(st->ca, s);
     dfree(st->bin_start, s);
     dfree(st->bin_items, s);
+    dfree(st->bin_recs, s);
     *st = DensStore{};
 }
 

@@ -74,6 +74,12 @@ static_assert(sizeof(LeafRecW) == 64, "record size");
 // Density field on the device.  Clumps are found through a uniform binning
 // grid whose per-bin lists are sorted by clump index, so the sum over clumps
 // in range runs in the same (ascending) order as a plain loop over all clumps.
+// A clump as the density loop reads it: centre, (trunc sigma)^2, 2 sigma^2
+// and amplitude, the products formed as the loop would form them.
+struct alignas(16) ClumpRec {
+    double cx, cy, cz, lim2, d2, a;
+};
+
 struct Dens {
     double lo[3];
     double side;
@@ -88,6 +94,7 @@ struct Dens {
     int B;                // bins per axis
     double bin_scale;     // B / side
     const uint32_t *bin_items;  // clump indices, ascending within a bin (bin starts passed apart)
+    const ClumpRec *bin_recs;   // the clumps of bin_items, entry for entry
 };
 
 // What the walk and locate kernels read.
@@ -327,6 +334,7 @@ int scan_chunks(const BatchChunk *chunks, int n_chunks, const WalkArgs *args, in
 // Device copies of a density's clump arrays and its clump binning grid.
 struct DensStore {
     void *cc = nullptr, *cs = nullptr, *ca = nullptr, *bin_start = nullptr, *bin_items = nullptr;
+    void *bin_recs = nullptr;
 };
 // Copies the density to the device and bins its clumps (synchronises s once
 // when there are clumps).  release_density frees what it allocated.

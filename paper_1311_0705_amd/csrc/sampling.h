@@ -64,17 +64,17 @@ __device__ inline double density_at(const Dens &D, double x0, double x1, double 
     if (D.n_clumps > 0) {
         int b = (bin_of(D, x0, 0) * D.B + bin_of(D, x1, 1)) * D.B + bin_of(D, x2, 2);
         int64_t e = bin_start[b + 1];
+        // the bin's clumps in ascending index, each a record read in one go
+        // (no dependent load through the clump index)
         for (int64_t j = bin_start[b]; j < e; j++) {
-            uint32_t i = D.bin_items[j];
-            double s = D.cs[i];
-            double lim = D.trunc * s;
-            double dx = x0 - D.cc[3 * i + 0];
-            double dy = x1 - D.cc[3 * i + 1];
-            double dz = x2 - D.cc[3 * i + 2];
+            const ClumpRec c = D.bin_recs[j];
+            double dx = x0 - c.cx;
+            double dy = x1 - c.cy;
+            double dz = x2 - c.cz;
             double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 <= lim * lim) {
-                double ee = r2 / (2.0 * s * s);
-                rho = rho + D.ca[i] * exp(-ee);
+            if (r2 <= c.lim2) {
+                double ee = r2 / c.d2;
+                rho = rho + c.a * exp(-ee);
             }
         }
     }
