@@ -310,6 +310,7 @@ int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *ou
                                               (uint32_t *)st->bin_items);
     HG_CHECK(hipGetLastError());
     D.bin_items = (const uint32_t *)st->bin_items;
+    st->bin_load = double(items) / double(nb);
     if ((rc = dalloc(&st->bin_recs, size_t(items > 0 ? items : 1) * sizeof(ClumpRec), s))) return rc;
     if (items > 0) {
         k_bin_recs<<<nblocks(items, BT), BT, 0, s>>>(D, items, (ClumpRec *)st->bin_recs);
@@ -378,7 +379,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
             if ((rc = tmp.alloc(scan_tmp_elems(c) * 8))) return rc;
             scap = c;
         }
-        const int gs = sample_group(cnt, D.n_clumps >= WAVE_SAMPLING_CLUMPS ? 16 : 1);
+        const int gs = sample_group(cnt, density_group_min(D.n_clumps, store.bin_load));
 #define HG_SAMPLE_ARGS tree, D, C, begin, cnt, g->level, g->coord, bin_start, g->S, g->rmin, g->rmax, \
                        (uint8_t *)split.p
         switch (gs) {

@@ -335,6 +335,7 @@ int scan_chunks(const BatchChunk *chunks, int n_chunks, const WalkArgs *args, in
 struct DensStore {
     void *cc = nullptr, *cs = nullptr, *ca = nullptr, *bin_start = nullptr, *bin_items = nullptr;
     void *bin_recs = nullptr;
+    double bin_load = 0.0;   // clump records per bin, on average over all bins
 };
 // Copies the density to the device and bins its clumps (synchronises s once
 // when there are clumps).  release_density frees what it allocated.

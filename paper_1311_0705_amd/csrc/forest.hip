@@ -481,7 +481,7 @@ struct hg_batch {
     int64_t *P = nullptr;           // [(lmax+1)][ng+1]
     int64_t *PN = nullptr, *PL = nullptr, *PT = nullptr;
     int64_t *PW = nullptr;          // [ng+2] sampling wavefronts per grid and lanes per node, current level
-    bool wave_sampling = false;     // at least 16 lanes per node (densities with many clumps)
+    int sample_gmin = 1;            // least lanes per node in sampling (density_group_min over the grids)
     uint8_t *flag = nullptr;        // [sum of capacities]
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
@@ -556,7 +556,7 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     const unsigned gb = unsigned((ng + FT - 1) / FT);
     k_f_init<<<gb, FT, 0, s>>>(b->dF, ng);
     HG_CHECK(hipGetLastError());
-    const int gmin = b->wave_sampling ? 16 : 1;
+    const int gmin = b->sample_gmin;
     k_f_level_prefix<<<1, FT, 0, s>>>(b->dF, ng, 0, b->P, b->PW, gmin);
     HG_CHECK(hipGetLastError());
     for (int lv = 0; lv <= b->lmax; lv++) {
@@ -628,7 +628,6 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     }
     hg_batch *b = new hg_batch;
     b->ng = n_grids;
-    for (int i = 0; i < n_grids; i++) b->wave_sampling |= dens[i].n_clumps >= WAVE_SAMPLING_CLUMPS;
     b->lmax = lmax;
     b->dens.resize(size_t(n_grids));
     b->hF.resize(size_t(n_grids));
@@ -644,6 +643,8 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
         G.lg = e - 1;
         rc = prepare_density(&dens[i], nullptr, &b->dens[size_t(i)], &G.D);
         if (rc) break;
+        b->sample_gmin = std::max(b->sample_gmin,
+                                  density_group_min(dens[i].n_clumps, b->dens[size_t(i)].bin_load));
         G.bin_start = (const int64_t *)b->dens[size_t(i)].bin_start;
         G.C = CritDev{c.total_mass, c.delta_max, c.tau_max, c.q_max, c.kappa,
                       c.min_level, c.max_level, c.n_samples, c.seed};

@@ -210,8 +210,17 @@ __device__ inline NodeSample sample_node_group(int tree, const Dens &D, const Cr
 
 // Node sampling with at least 16 lanes per node for densities with at least
 // this many clumps (clustered clumps fill bins with many of them; lanes on
-// different nodes would then loop over different bins).
+// different nodes would then loop over different bins), and with at least 4
+// where a clump bin holds at least one clump on average.
 constexpr int64_t WAVE_SAMPLING_CLUMPS = 10000;
+
+// Least lanes per node for a density with n_clumps clumps and bin_load
+// clump records per bin on average.
+inline int density_group_min(int64_t n_clumps, double bin_load)
+{
+    if (n_clumps >= WAVE_SAMPLING_CLUMPS) return 16;
+    return bin_load >= 1.0 ? 4 : 1;
+}
 
 // Lanes kept busy by node sampling: eight wavefronts on each of the 1024
 // SIMDs of the chip.
@@ -222,7 +231,7 @@ constexpr int64_t SAMPLE_LANES = int64_t(1) << 19;
 // power of two up to a wavefront that does, so a small level is not one
 // lane drawing all n_samples points in sequence while the rest idle; at
 // least gmin.  Every group size gives the
-// same bits.  gmin is 16 for densities with many clumps, else 1.
+// same bits.  gmin comes from density_group_min.
 __host__ __device__ inline int sample_group(int64_t n, int gmin)
 {
     int g = 1;
