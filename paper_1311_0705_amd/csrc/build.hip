@@ -279,12 +279,15 @@ int prepare_density(const hg_density *dn, hipStream_t s, DensStore *st, Dens *ou
     D.cs = (const double *)st->cs;
     D.ca = (const double *)st->ca;
     // bin width about half the mean truncation radius (a sample then tests
-    // about N (w + 2r)^3 / side^3 clumps), at most 256 bins per axis
+    // about N (w + 2r)^3 / side^3 clumps), at most 256 bins per axis; a
+    // quarter of it and at most 512 bins per axis for densities with many
+    // clumps, whose crowded bins make the clump tests the sampling cost
+    const bool many = int64_t(n) >= WAVE_SAMPLING_CLUMPS;
     double rsum = 0.0;
     for (size_t i = 0; i < n; i++) rsum += dn->clump_trunc * fabs(dn->clump_sigma[i]);
     double rmean = rsum / double(n);
-    int B = rmean > 0.0 ? int(std::min(1e6, dn->side / (0.5 * rmean))) : 1;
-    B = std::max(1, std::min(256, B));
+    int B = rmean > 0.0 ? int(std::min(1e6, dn->side / ((many ? 0.25 : 0.5) * rmean))) : 1;
+    B = std::max(1, std::min(many ? 512 : 256, B));
     D.B = B;
     D.bin_scale = double(B) / dn->side;
     const int64_t nb = int64_t(B) * B * B;
