@@ -172,9 +172,10 @@ __device__ inline double group_read_f64(double v, int j)
 // it with the same node): lane l of the group draws samples l, l+G, ...; each
 // lane keeps its own copy of S and adds the G values of a round in sample
 // order, so S is the same sequential sum as with one lane per node.  Min and
-// max are order-free.  With G = 64 all lanes evaluate the density in the same
-// clump bin, which pays when bins hold many clumps; smaller groups shorten the
-// sequence of samples per lane on levels too small to fill the chip.
+// max are order-free.  The lanes of a group sample one node and so mostly
+// walk the same clump bin, which pays when bins hold many clumps; groups also
+// shorten the sequence of samples per lane on levels too small to fill the
+// chip.
 template <int G>
 __device__ inline NodeSample sample_node_group(int tree, const Dens &D, const CritDev &C, int lv,
                                                uint32_t c0, uint32_t c1, uint32_t c2,
@@ -227,11 +228,11 @@ inline int density_group_min(int64_t n_clumps, double bin_load)
 constexpr int64_t SAMPLE_LANES = int64_t(1) << 19;
 
 // Lanes per node for a level of n nodes (over all grids sampled together):
-// one lane per node where the level fills the chip, otherwise the smallest
-// power of two up to a wavefront that does, so a small level is not one
-// lane drawing all n_samples points in sequence while the rest idle; at
-// least gmin.  Every group size gives the
-// same bits.  gmin comes from density_group_min.
+// the largest power of two up to 64 with n times it within SAMPLE_LANES (one
+// lane per node once the level alone fills the chip), so a small level is
+// not a few lanes each drawing all n_samples points in sequence while the
+// rest idle; at least gmin (from density_group_min).  Every group size gives
+// the same bits.
 __host__ __device__ inline int sample_group(int64_t n, int gmin)
 {
     int g = 1;
