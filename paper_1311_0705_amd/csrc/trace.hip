@@ -442,7 +442,7 @@ __device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC
 // density are loaded.  Written with few branches: the end and error outcomes
 // are flags, and the state updates that only matter for a continuing path are
 // made unconditionally.
-template <int TREE, int PREC, int WM, typename R>
+template <int TREE, int PREC, int WM, typename R, bool LSLOT = false>
 __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC, R> &P,
                                      unsigned long long &rechecks, uint32_t *sl = nullptr,
                                      typename Path<PREC, R>::DsT *sd = nullptr, int sgm = 0)
@@ -502,12 +502,12 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
     const char *rec = static_cast<const char *>(G.rec) + id * Rec<R, PREC>::STRIDE;
     const R nref = reinterpret_cast<const R *>(rec)[face];
     if (ds > 0.0) {
-        // sl / sd: the lane's record slots in LDS (persistent walk), else
-        // records are staged in registers
+        // LSLOT: records go to the lane's slots sl / sd in LDS (persistent
+        // and batched walks), else they are staged in registers
         if (WM == WM_FILL) {
             // the fill walk must repeat the counting walk
             if (P.cnt < P.room) {
-                if (sl) {
+                if (LSLOT) {
                     sl[P.cnt & sgm] = uint32_t(id);
                     sd[P.cnt & sgm] = typename Path<PREC, R>::DsT(ds);
                 } else {
@@ -520,7 +520,7 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<
             // records beyond the row are left to the fill walk, which resumes
             // the path at the first of them
             if (P.cnt < P.room) {
-                if (sl) {
+                if (LSLOT) {
                     sl[P.cnt & sgm] = uint32_t(id);
                     sd[P.cnt & sgm] = typename Path<PREC, R>::DsT(ds);
                 } else {
@@ -799,7 +799,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         }
         if (ray >= 0 && !bad && Ref<R>::leaf(P.ref)) {
             c_before = P.cnt;
-            const int r = cross<TREE, PREC, WM, R>(G, A, P, rechecks, my_l, my_d, SG - 1);
+            const int r = cross<TREE, PREC, WM, R, STG>(G, A, P, rechecks, my_l, my_d, SG - 1);
             crossed = true;
             const bool guard = r == STEP_ERR || ++P.steps >= STEP_GUARD;
             if (guard) A.st->step_guard = 1;
@@ -873,7 +873,7 @@ __device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &
     }
     if (!ended && Ref<uint32_t>::leaf(P.ref)) {
         c_before = P.cnt;
-        const int r = cross<TREE, PREC, WM, uint32_t>(G, A, P, rechecks, sl, sd, STG ? SG - 1 : 0);
+        const int r = cross<TREE, PREC, WM, uint32_t, STG>(G, A, P, rechecks, sl, sd, STG ? SG - 1 : 0);
         crossed = true;
         if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
             A.st->step_guard = 1;
