@@ -73,10 +73,10 @@ TUNE_PATHS = 10_000_000
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_slab": {"trace_sha256": "1ced6eba328be114cfc913092c9bebc715183273637d8d8a33d01ac99d06ab41",
-                "fetch_kib": 27994964.0, "write_kib": 5903237.7, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "1ced6eba328be114cfc913092c9bebc715183273637d8d8a33d01ac99d06ab41",
-                 "fetch_kib": 93939200.2, "write_kib": 6928821.9, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "058869655fe4a01471346ce14b61a33c736e0f7c72b34a07553ee59b941734a0",
+                "fetch_kib": 27463078.1, "write_kib": 5896542.4, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "058869655fe4a01471346ce14b61a33c736e0f7c72b34a07553ee59b941734a0",
+                 "fetch_kib": 93931542.2, "write_kib": 6928222.4, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
