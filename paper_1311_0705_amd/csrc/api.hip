@@ -78,6 +78,13 @@ void free_grid_arrays(hg_grid *g)
     for (void *p : ptrs) dfree(p, nullptr);
 }
 
+// Records each path batch needs: the last entry of its offsets.
+__global__ void k_batch_totals(const WalkArgs *__restrict__ A, int ng, int64_t *__restrict__ out)
+{
+    const int i = int(blockIdx.x) * 256 + threadIdx.x;
+    if (i < ng) out[i] = A[i].offsets[A[i].n];
+}
+
 __global__ void k_reset_status(TraceStatus *st)
 {
     st->rechecks = 0;
@@ -452,14 +459,12 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     std::vector<WalkGrid> hG((size_t)ng);
     std::vector<WalkArgs> hA((size_t)ng);
     std::vector<BatchChunk> hC;
-    int64_t nmax = 0;
     for (int i = 0; i < ng; i++) {
         hG[size_t(i)] = walk_grid(grids[i], opts->precision);
         hA[size_t(i)] = walk_args(grids[i], origins[i], dirs[i], n[i], opts, &outs[i]);
         hA[size_t(i)].st = g0->status;
         const int32_t head = int32_t(hC.size());
         for (int64_t a = 0; a < n[i]; a += chunk) hC.push_back(BatchChunk{i, head, a, std::min(n[i], a + chunk)});
-        nmax = std::max(nmax, n[i]);
         outs[i].needed = 0;
         outs[i].rechecks = 0;
         outs[i].descents = 0;
@@ -473,7 +478,9 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     int rc = dalloc_n(&dG, size_t(ng), s);
     if (!rc) rc = dalloc_n(&dA, size_t(ng), s);
     if (!rc) rc = dalloc_n(&dC, std::max<size_t>(hC.size(), 1), s);
-    if (!rc && records) rc = dalloc_n(&tmp, scan_tmp_elems(nmax), s);
+    // records: the chunk scan's work space, then one total per grid
+    const size_t ctmp = scan_chunks_tmp_elems(int(hC.size()));
+    if (!rc && records) rc = dalloc_n(&tmp, ctmp + size_t(ng), s);
     hipEvent_t ev[4] = {};
     if (!rc && timing)
         for (int t = 0; t < 4; t++)
@@ -497,11 +504,17 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         outs[0].descents = int64_t(st.descents);
     }
     if (!rc && records) {
-        for (int i = 0; i < ng && !rc; i++)
-            rc = scan_i32_to_i64(outs[i].count, outs[i].offsets, n[i], tmp, s);
+        // every grid's offsets in one chunk scan, the totals in one copy
+        rc = scan_chunks(dC, int(hC.size()), dA, ng, tmp, s);
+        int64_t *dtot = tmp + ctmp;
+        if (!rc) {
+            k_batch_totals<<<unsigned((ng + 255) / 256), 256, 0, s>>>(dA, ng, dtot);
+            e = hipGetLastError();
+            if (e) rc = set_hip_error(e);
+        }
         std::vector<int64_t> tot((size_t)ng, 0);
-        for (int i = 0; i < ng && !rc; i++) {
-            e = hipMemcpyAsync(&tot[size_t(i)], outs[i].offsets + n[i], 8, hipMemcpyDeviceToHost, s);
+        if (!rc) {
+            e = hipMemcpyAsync(tot.data(), dtot, sizeof(int64_t) * size_t(ng), hipMemcpyDeviceToHost, s);
             if (e) rc = set_hip_error(e);
         }
         if (!rc) {
