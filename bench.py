@@ -7,17 +7,20 @@ FP32-with-FP64-recheck walk.  Inputs (ray origins and directions) are
 resident in HBM before the timed region.
 
 Workloads (--workload):
-  2 (default)  k-d tree of about 1e6 leaves on the exponential disk (mass
+  3 (default)  torus plus 500 clumps, k-d tree of about 4e6 leaves (--tree
+               octree for the octree), 1e8 uniform paths: tau-only walk over
+               all of them, records mode on the first batch of 1e7.  The JSON
+               line also carries the FP64 tracer's throughput on the same
+               paths, the comparison FP32-recheck vs FP64, the FP64 walk
+               against the oracle on the first 1e6 paths (bitwise), the
+               roofline of the dominant kernel and the CPU oracle's rate on the
+               host cores (its construction timed on a sample of the grid's
+               nodes, its walk on a sample of the paths).
+  2            k-d tree of about 1e6 leaves on the exponential disk (mass
                threshold 1e-6, max level 24), 1e7 stellar-disk paths,
-               records mode.  The JSON line also carries the FP64 tracer's
-               throughput on the same paths, the leaf-for-leaf comparison
-               FP32-recheck vs FP64, an oracle spot check, the roofline of the
-               dominant kernel and the CPU oracle's rate on the host cores.
+               records mode.
   1            octree of about 5e3 leaves on the same disk, 1e4 paths (FP64
                parity case; timed like 2).
-  3            torus plus 500 clumps, k-d (--tree octree for the octree), 1e8
-               uniform paths: tau-only walk over all of them, records mode on
-               the first batch of 1e7.
   4            64 clump grids of uneven size (octree and k-d), 10^U[3,6]
                paths each: the batch built and traced by one replay of a
                captured graph, against the same 64 grids built and traced one
@@ -85,12 +88,14 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    p.add_argument("--workload", type=int, default=3, choices=[1, 2, 3, 4, 5])
     p.add_argument("--tree", choices=["kd", "octree"], default=None)
     p.add_argument("--rays", type=int, default=None, help="override the path count")
     p.add_argument("--batches", type=int, default=10, help="workload 5: batches of 1e8 paths")
     p.add_argument("--cpu-seconds", type=float, default=20.0,
-                   help="target CPU time of the oracle baseline sample")
+                   help="target wall time of the oracle baseline samples")
+    p.add_argument("--parity-paths", type=int, default=1_000_000,
+                   help="workloads 3 and 5: paths compared with the oracle bit for bit")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--no-tune", action="store_true")
@@ -165,6 +170,72 @@ def oracle_sample_check(g, w, o_np, k_np, r64, dev, m=4000):
         ok = (np.array_equal(r64["leaf"].index_select(0, pos).cpu().numpy(), ref["leaf"])
               and np.array_equal(r64["ds"].index_select(0, pos).cpu().numpy(), ref["ds"]))
     return {"oracle_sample_paths": int(idx.size), "oracle_sample_bitwise_fp64": bool(ok)}
+
+
+def oracle_first_paths(g, w, o, k, o_np, k_np, m, cores):
+    """The first m paths through the grid, GPU FP64 and FP32-recheck records
+    walks against the oracle's FP64 walk of the same imported grid: leaf ids,
+    counts, ds and tau bitwise for FP64; leaf for leaf and tau within 1e-5 for
+    FP32-recheck.  Also returns the oracle's timing of that walk."""
+    import paper_1311_0705_amd as hg
+    import oracle as O
+    m = min(m, o_np.shape[0])
+    e = g.export()
+    og = O.Grid.from_first_child(w.tree_type, e["first_child"].cpu().numpy(), e["rho"].cpu().numpy())
+    del e
+    t0 = time.perf_counter()
+    ref = og.trace(o_np[:m], k_np[:m], records=True, nthreads=cores)
+    t_or = time.perf_counter() - t0
+    r64 = g.trace(o[:m], k[:m], precision=hg.FP64, mode=hg.RECORDS)
+    x = r64["needed"]
+    ok64 = (x == ref["leaf"].size
+            and np.array_equal(r64["count"].cpu().numpy(), ref["count"])
+            and np.array_equal(r64["tau"].cpu().numpy(), ref["tau"])
+            and np.array_equal(r64["leaf"][:x].cpu().numpy(), ref["leaf"])
+            and np.array_equal(r64["ds"][:x].cpu().numpy(), ref["ds"]))
+    del r64
+    r32 = g.trace(o[:m], k[:m], precision=hg.FP32_RECHECK, mode=hg.RECORDS, capacity=x)
+    leaf32 = (r32["needed"] == ref["leaf"].size
+              and np.array_equal(r32["count"].cpu().numpy(), ref["count"])
+              and np.array_equal(r32["leaf"][:x].cpu().numpy(), ref["leaf"]))
+    t32 = r32["tau"].cpu().numpy()
+    rel = np.abs(t32 - ref["tau"]) / np.maximum(np.abs(ref["tau"]), 1e-300)
+    del r32
+    out = {"oracle_paths": int(m), "oracle_crossings": int(ref["leaf"].size),
+           "fp64_bitwise_vs_oracle": bool(ok64), "fp32r_leaf_exact_vs_oracle": bool(leaf32),
+           "fp32r_tau_max_rel_err_vs_oracle": float(rel.max(initial=0.0))}
+    return out, og, t_or, int(ref["leaf"].size)
+
+
+def oracle_build_estimate(g, w, budget_s, seed=7):
+    """The oracle's construction time for this grid, extrapolated: its
+    per-node work (Eq. 1 sampling plus the criteria, one thread, as in its
+    construction loop) timed on a uniform random sample of the grid's nodes,
+    times the node count.  The sampled statistics are also compared with the
+    GPU build's, node for node (equal up to the last bits of exp() between the
+    host's libm and the GPU's: the largest relative difference is reported)."""
+    import oracle as O
+    e = g.export()
+    n = int(g.n_nodes)
+    rng = np.random.default_rng(seed)
+    lv_all = e["level"].cpu().numpy()
+    co_all = e["coord"].cpu().numpy().reshape(-1, 3)
+    S_all = e["S"].cpu().numpy()
+    del e
+    m, t, done, worst = 256, 0.0, 0, 0.0
+    while True:
+        idx = rng.integers(0, n, size=m)
+        t0 = time.perf_counter()
+        r = O.sample_nodes(w.density, w.criteria, w.tree_type, lv_all[idx], co_all[idx])
+        t += time.perf_counter() - t0
+        done += m
+        d = np.abs(r["S"] - S_all[idx]) / np.maximum(np.abs(r["S"]), 1e-300)
+        worst = max(worst, float(d.max(initial=0.0)))
+        if t >= budget_s or done >= n:
+            break
+        m = int(min(n, max(m, m * (budget_s - t) / max(t, 1e-6))))
+    return {"build_s_est": t / done * n, "nodes_timed": int(done), "nodes_timed_s": round(t, 3),
+            "nodes": n, "sampled_S_max_rel_diff": worst}
 
 
 def compare_fp32r_fp64(r32, r64, records):
@@ -436,6 +507,14 @@ def run_c3(a, w):
         extra.update(compare_fp32r_fp64(res, t64, False))
         extra["records_first_batch"] = compare_fp32r_fp64(rec32, rec64, True)
         extra.update(oracle_sample_check(g, w, o_np[:nb], k_np[:nb], rec64, dev, m=2000))
+    cores = cpu_cores()
+    first = None
+    if not (a.no_compare and a.no_cpu):
+        log(f"oracle: first {a.parity_paths} paths")
+        first = oracle_first_paths(g, w, o, k, o_np, k_np, a.parity_paths, cores)
+        extra["oracle_first_paths"] = first[0]
+        log(f"oracle: {first[0]}")
+    if not a.no_compare:
         extra["grid_quality"] = grid_quality(g, w, dev)
     tau_avg = float(np.mean(tau_ms))
     block = tt["block"] if tt else 256
@@ -474,17 +553,27 @@ def run_c3(a, w):
     })
     line.update(extra)
     if not a.no_cpu:
-        import oracle as O
-        e = g.export()
-        og = O.Grid.from_first_child(w.tree_type, e["first_child"].cpu().numpy(), e["rho"].cpu().numpy())
-        del e
-        m, t, xs, cores = cpu_trace_sample(og, o_np, k_np, a.cpu_seconds, records=False)
+        og = first[1]
+        be = oracle_build_estimate(g, w, 0.25 * a.cpu_seconds)
+        log(f"oracle build estimate: {be}")
+        m, t, xs, cores = cpu_trace_sample(og, o_np, k_np, 0.75 * a.cpu_seconds, records=False)
+        t_trace = t * (n / m)
+        t_step = be["build_s_est"] + t_trace
         line["cpu_baseline"] = {
-            "value": round(xs / t, 1), "unit": "crossings/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 tau trace of the first {m} of {n} paths ({xs} crossings, {t:.2f} s on "
-                      f"{cores} threads) through the GPU-built grid imported into the oracle; the "
-                      f"oracle build of this grid (plain loop over all 500 clumps per sample) is "
-                      f"not timed"}
+            "value": round(crossings / t_step, 1), "unit": "crossings/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle construction timed on {be['nodes_timed']} of the grid's {be['nodes']} "
+                      f"nodes drawn uniformly ({be['nodes_timed_s']:.2f} s, one thread, the "
+                      f"construction loop's per-node sampling and criteria), extrapolated to all "
+                      f"nodes: {be['build_s_est']:.1f} s; FP64 tau-only walk of the first {m} of {n} "
+                      f"paths ({xs} crossings, {t:.2f} s on {cores} threads) through the GPU-built "
+                      f"grid imported into the oracle, extrapolated to all paths: {t_trace:.1f} s; "
+                      f"value = crossings of the step / (construction + walk)",
+            "trace_crossings_per_s": round(xs / t, 1),
+            "build_s_est": round(be["build_s_est"], 2),
+            "build_sampled_S_max_rel_diff_vs_gpu": be["sampled_S_max_rel_diff"],
+            "records_walk_first_paths_s": round(first[2], 3),
+            "records_walk_first_paths_crossings_per_s": round(first[3] / first[2], 1)}
     g.free()
     return line
 

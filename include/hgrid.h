@@ -65,6 +65,7 @@ extern "C" {
 
 #define HG_MAX_CLUMPS (1 << 24)
 #define HG_MAX_BATCH  (1 << 16) /* grids per batch (batch_create) */
+#define HG_MAX_CHUNK  (1 << 16) /* hg_trace_opts.chunk: largest paths per work-queue atomic */
 
 #define HG_STAGE_BUILD 1   /* batch_run / batch_capture: construct every grid */
 #define HG_STAGE_TRACE 2   /* batch_run / batch_capture: trace the bound path batches */
@@ -124,7 +125,8 @@ typedef struct {
     int32_t persistent; /* persistent lane-refill walk for: bit 0 the counting / tau-only walk,
                            bit 1 the record-filling walk (else one thread per path);
                            -1 = library choice */
-    int32_t chunk;      /* persistent walk: paths a wavefront takes per atomic, 0 = library choice */
+    int32_t chunk;      /* persistent walk: paths a wavefront takes per atomic (at most
+                           HG_MAX_CHUNK), 0 = library choice */
     int32_t refill_min; /* persistent walk: idle lanes that trigger a refill (1..64), 0 = library choice */
     int32_t lds_bytes;  /* persistent walk: bytes of top-level child references each block
                            stages in LDS (at most 65536); 0 = library choice (16384), < 0 = none */

@@ -81,6 +81,7 @@ def lib():
         L.or_set_rho.argtypes = [P, P]
         L.or_leaf_boxes.argtypes = [P, P, P]
         L.or_sample_node.argtypes = [P, P, C.c_int, P, C.c_double, C.c_int, P, P]
+        L.or_sample_nodes.argtypes = [P, P, C.c_int, P, C.c_double, C.c_int64, P, P, P]
         L.or_locate.argtypes = [P, P, C.c_int64, P]
         L.or_trace.restype = C.c_int
         L.or_trace.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_int, P, P, P, P, P]
@@ -176,6 +177,22 @@ def sample_node(d, cr, tree, level, coord) -> dict:
                          _ptr(out))
     return dict(S=out[0], rmin=out[1], rmax=out[2], delta=out[3], tau=out[4], q=out[5],
                 split=bool(out[6]))
+
+
+def sample_nodes(d, cr, tree, levels, coords) -> dict:
+    """sample_node for many nodes in one C loop (one thread): arrays S, rmin,
+    rmax, delta, tau, q, split."""
+    h = _DensityHolder(d)
+    c = _criteria(cr)
+    lo = _f64(d.lo)
+    lv = np.ascontiguousarray(levels, dtype=np.uint8)
+    cc = np.ascontiguousarray(coords, dtype=np.uint32).reshape(-1, 3)
+    n = lv.shape[0]
+    out = np.empty((max(n, 1), 7))
+    lib().or_sample_nodes(h.ref, C.byref(c), tree, _ptr(lo), d.side, n, _ptr(lv), _ptr(cc), _ptr(out))
+    out = out[:n]
+    return dict(S=out[:, 0], rmin=out[:, 1], rmax=out[:, 2], delta=out[:, 3], tau=out[:, 4],
+                q=out[:, 5], split=out[:, 6] != 0)
 
 
 class Grid:

@@ -444,6 +444,16 @@ void or_sample_node(const or_density *m, const or_criteria *cr, int tree, const 
     out[6] = (double)decide_split(cr, level, v);
 }
 
+/* or_sample_node for n nodes in turn (level[i], coord[3i..3i+2]): out[7i..7i+6]
+ * as or_sample_node.  One thread; the per-node work of the construction loop,
+ * for timing it on a sample of a large tree's nodes. */
+void or_sample_nodes(const or_density *m, const or_criteria *cr, int tree, const double dom_lo[3],
+                     double side, int64_t n, const uint8_t *level, const uint32_t *coord, double *out)
+{
+    for (int64_t i = 0; i < n; i++)
+        or_sample_node(m, cr, tree, dom_lo, side, level[i], coord + 3 * i, out + 7 * i);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Point location (Sect. 2.3): descend from the root.                        */
 /* ------------------------------------------------------------------------ */

@@ -410,7 +410,8 @@ static int check_trace_args(hg_grid_t g, const double *origins, const double *di
     if (!isfinite(opts->kappa)) return HG_E_INVAL;
     if (opts->block != 0 && opts->block != 128 && opts->block != 256 && opts->block != 512)
         return HG_E_INVAL;
-    if (opts->lds_bytes > 65536 || opts->chunk < 0 || opts->refill_min < 0) return HG_E_INVAL;
+    if (opts->lds_bytes > 65536 || opts->chunk < 0 || opts->chunk > HG_MAX_CHUNK || opts->refill_min < 0)
+        return HG_E_INVAL;
     if (opts->passes < 0 || opts->passes > 2 || opts->slab < 0 || opts->slab > (1 << 20)) return HG_E_INVAL;
     const bool records = opts->mode == HG_RECORDS;
     if (n > 0 && (!origins || !dirs || !out->tau || !out->count)) return HG_E_INVAL;
@@ -558,8 +559,12 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     return rc;
 }
 
+// Records mode in two walks: a counting walk, the prefix sum of the counts and
+// a record-filling walk.  The prefix sum's work space is `tmp`
+// (scan_tmp_elems(n) entries) when given, else allocated here.
 static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
-                          const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev)
+                          const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev,
+                          int64_t *tmp_given = nullptr)
 {
     const bool records = opts->mode == HG_RECORDS;
     const bool timing = ev[0] != nullptr;
@@ -574,8 +579,8 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
         out->descents = int64_t(st.descents);
     }
     if (rc || !records) return rc;
-    int64_t *tmp = nullptr;
-    rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
+    int64_t *tmp = tmp_given;
+    if (!tmp) rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
     if (!rc) rc = scan_i32_to_i64(out->count, out->offsets, n, tmp, s);
     if (timing) (void)hipEventRecord(ev[2], s);
     int64_t needed = 0;
@@ -590,7 +595,7 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
     }
     if (!rc && needed > 0) rc = launch_walk(g, origins, dirs, n, opts, out, WM_FILL, s, nullptr);
     if (timing) (void)hipEventRecord(ev[3], s);
-    dfree(tmp, s);
+    if (!tmp_given) dfree(tmp, s);
     if (!rc) rc = read_status(g, &st, s);
     return rc;
 }

@@ -140,8 +140,9 @@ struct TraceStatus {
     int step_guard;
     int bad_ref;                   // a reference out of range: the layout is corrupt
     int cap_overflow;              // a grid's records did not fit (batched walk, device check)
-    unsigned int next_ray;         // persistent-kernel work counter
-    unsigned int done_waves;
+    unsigned long long next_ray;   // persistent-kernel work counter (64-bit: it grows by one
+                                   // chunk per atomic, the drained wavefronts' included)
+    unsigned long long done_waves;
 };
 
 // Walk state of a path at its first record beyond its row (one-walk records

@@ -22,6 +22,10 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "common.h"
@@ -746,14 +750,16 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
         const int nwant = __popcll(wmask);
         if (nwant && (nwant >= refill_min || !amask)) {
             if (cnext >= cend && !drained) {
-                uint32_t b = 0;
-                if (lane == 0) b = atomicAdd(&A.st->next_ray, chunk);
-                b = __builtin_amdgcn_readfirstlane(b);   // wavefront-uniform from here on
-                if (int64_t(b) >= A.n) {
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(&A.st->next_ray, (unsigned long long)chunk);
+                // wavefront-uniform from here on
+                b = (unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(b)) |
+                    ((unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(b >> 32)) << 32);
+                if (b >= (unsigned long long)A.n) {
                     drained = true;
                     cnext = cend = 0;
                 } else {
-                    cnext = b;
+                    cnext = uint32_t(b);
                     cend = uint32_t(std::min<int64_t>(int64_t(b) + chunk, A.n));
                 }
             }
@@ -932,7 +938,7 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
             if (cnext >= cend) {
                 if (pc < 0 && !drained) {
                     int c = 0;
-                    if (lane == 0) c = int(atomicAdd(&st->next_ray, 1u));
+                    if (lane == 0) c = int(std::min<unsigned long long>(atomicAdd(&st->next_ray, 1ull), 0x7fffffffull));
                     c = __builtin_amdgcn_readfirstlane(c);   // wavefront-uniform from here on
                     if (c >= n_chunks) drained = true;
                     else pc = c;
@@ -1034,7 +1040,7 @@ __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restr
     out[i] = r == Ref<R>::NUL ? -2 : int32_t(Ref<R>::id(r));
 }
 
-__global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0u; }
+__global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0ull; }
 
 // One-pass records mode: copy the rows of the slab (each path's first `slab`
 // records) into the CSR slices.  A block takes CP consecutive paths, whose
@@ -1137,37 +1143,60 @@ __global__ void __launch_bounds__(TB)
 constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
 
-// Occupancy-derived persistent grid size, cached per kernel instance.
-template <int TREE, int PREC, int WM, typename R, int BT>
-int persistent_blocks(size_t lds, unsigned *blocks)
+// Persistent grid size of a kernel: resident blocks per CU at this block size
+// and LDS use times the CU count of the current device.  Cached per (device,
+// kernel, block size, LDS bytes) under a lock, so concurrent calls from several
+// host threads or on several devices each get their own device's figure.
+int occupancy_blocks(const void *kern, int bt, size_t lds, unsigned *blocks)
 {
-    static int occ = -1, cus = 0;
-    static size_t occ_lds = 0;
-    if (occ < 0 || occ_lds != lds) {
-        int dev = 0;
-        HG_CHECK(hipGetDevice(&dev));
-        HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &occ, reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, WM, R, BT>), BT, lds));
-        occ_lds = lds;
+    static std::mutex m;
+    static std::map<std::tuple<int, const void *, int, size_t>, unsigned> cache;
+    int dev = 0;
+    HG_CHECK(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, kern, bt, lds);
+    {
+        std::lock_guard<std::mutex> lock(m);
+        const auto it = cache.find(key);
+        if (it != cache.end()) {
+            *blocks = it->second;
+            return HG_OK;
+        }
     }
-    *blocks = unsigned(std::max(1, cus) * std::max(1, occ));
+    int cus = 0, occ = 0;
+    HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, bt, lds));
+    const unsigned b = unsigned(std::max(1, cus) * std::max(1, occ));
+    {
+        std::lock_guard<std::mutex> lock(m);
+        cache[key] = b;
+    }
+    *blocks = b;
     return HG_OK;
 }
 
-// LDS a block may allocate on the current device (cached).
+template <int TREE, int PREC, int WM, typename R, int BT>
+int persistent_blocks(size_t lds, unsigned *blocks)
+{
+    return occupancy_blocks(reinterpret_cast<const void *>(k_walk_persistent<TREE, PREC, WM, R, BT>), BT, lds,
+                            blocks);
+}
+
+// LDS a block may allocate on the current device (cached per device).
 inline size_t max_block_lds()
 {
-    static size_t v = 0;
-    if (!v) {
-        int dev = 0, b = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0)
-            v = size_t(b);
-        else
-            v = 65536;
+    constexpr int MAXDEV = 64;
+    static std::atomic<size_t> v[MAXDEV];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return 65536;
+    size_t r = v[dev].load(std::memory_order_relaxed);
+    if (!r) {
+        int b = 0;
+        r = hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0
+                ? size_t(b)
+                : 65536;
+        v[dev].store(r, std::memory_order_relaxed);
     }
-    return v;
+    return r;
 }
 
 template <int TREE, int PREC, int WM, typename R, int BT>
@@ -1251,18 +1280,15 @@ template <int PREC, int WM, int BT>
 int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
                      int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
 {
-    static int occ = -1, cus = 0;
     const size_t lds = WM == WM_FILL ? size_t(BT) * StageShape<BT>::SP * (4 + (PREC == HG_FP64 ? 8 : 4)) : 0;
     if (lds > max_block_lds()) return HG_E_INVAL;
     const void *kern = WM == WM_FILL ? reinterpret_cast<const void *>(k_walk_batched_fill<PREC, BT>)
                                      : reinterpret_cast<const void *>(k_walk_batched_count<PREC, BT>);
-    if (occ < 0) {
-        int dev = 0;
-        HG_CHECK(hipGetDevice(&dev));
-        HG_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HG_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, BT, lds));
+    unsigned blocks = 0;
+    {
+        const int rc = occupancy_blocks(kern, BT, lds, &blocks);
+        if (rc) return rc;
     }
-    const unsigned blocks = unsigned(std::max(1, cus) * std::max(1, occ));
     k_reset_counter<<<1, 1, 0, s>>>(st);
     HG_CHECK(hipGetLastError());
     if (WM == WM_FILL)
