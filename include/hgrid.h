@@ -234,6 +234,23 @@ int grid_build(const hg_density *density, const hg_criteria *criteria, int tree_
 int grid_trace(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
                const hg_trace_opts *opts, hg_trace_out *out, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops that forbid device allocation): grid_trace without any allocation.
+ * Same arguments, results and errors as grid_trace with opts->passes = 2
+ * (records mode: a counting walk, the prefix sum of the counts, a
+ * record-filling walk); HG_FLAG_TIMING is ignored (kernel_ms stays 0).  The
+ * prefix sum's work space is a fixed device array of HG_NOALLOC_SCRATCH_BYTES
+ * that every GPU the library runs on holds until the process ends; it allows
+ * n <= HG_NOALLOC_MAX_PATHS (larger n: HG_E_LIMIT, nothing enqueued).  All
+ * calls on one GPU share that array: calls that overlap on one GPU (several
+ * host threads or streams at once) race and must be serialised by the
+ * caller.  Synchronises the stream.  Errors: HG_E_INVAL, HG_E_LIMIT, HG_E_DIR,
+ * HG_E_CAPACITY, HG_E_STEP, HG_E_HIP. */
+#define HG_NOALLOC_SCRATCH_BYTES (512 * 1024)
+#define HG_NOALLOC_MAX_PATHS ((int64_t)(HG_NOALLOC_SCRATCH_BYTES / 8 - 1) * 2048)
+int grid_trace_noalloc(hg_grid_t grid, const double *origins, const double *dirs, int64_t n,
+                       const hg_trace_opts *opts, hg_trace_out *out, void *stream);
+
 /* Free the device memory the library keeps for reuse on the current device:
  * the records-mode scratch of grid_trace (waiting for the calls using it;
  * the next records-mode call allocates it again) and the array blocks of

@@ -39,6 +39,8 @@ HG_E_LIMIT = -6
 HG_E_HIP = -7
 HG_E_STEP = -8
 HG_E_FORMAT = -9
+# fixed work space of grid_trace_noalloc (hgrid.h)
+NOALLOC_SCRATCH_BYTES = 512 * 1024
 
 
 class HGError(RuntimeError):
@@ -110,6 +112,8 @@ _SIGS = [
                              C.POINTER(TraceOpts), C.POINTER(TraceOut), C.c_void_p]),
     ("grid_trace_batched", C.c_int, [C.c_int, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                      C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                     C.POINTER(TraceOpts), C.POINTER(TraceOut), C.c_void_p]),
+    ("grid_trace_noalloc", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                      C.POINTER(TraceOpts), C.POINTER(TraceOut), C.c_void_p]),
     ("grid_locate", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     ("grid_import", C.c_int, [C.POINTER(GridArrays), C.c_void_p, C.POINTER(C.c_void_p)]),
@@ -355,9 +359,12 @@ class Grid:
               count_rechecks: bool = False, stream=None, out: Optional[dict] = None,
               block: int = 0, persistent: int = -1, chunk: int = 0, refill_min: int = 0,
               lds_bytes: int = 0, tuned: Optional[dict] = None, passes: int = 0,
-              slab: int = 0) -> dict:
+              slab: int = 0, noalloc: bool = False) -> dict:
         """Trace paths; returns tau, count (and offsets, leaf, ds in records
-        mode) as device tensors plus needed / rechecks / kernel_ms."""
+        mode) as device tensors plus needed / rechecks / kernel_ms.  With
+        noalloc the call goes to grid_trace_noalloc (no device allocation by
+        the library; output buffers are still allocated here unless `out`
+        holds them at the right size)."""
         o = _dev_f64x3(origins, self.device)
         k = _dev_f64x3(dirs, self.device)
         n = o.shape[0]
@@ -398,8 +405,8 @@ class Grid:
                 to.leaf = res["leaf"].data_ptr()
                 to.ds = res["ds"].data_ptr()
                 to.capacity = res["leaf"].numel()
-            rc = lib().grid_trace(self._h, _ptr(o), _ptr(k), n, C.byref(opts), C.byref(to),
-                                  _stream(stream))
+            fn = lib().grid_trace_noalloc if noalloc else lib().grid_trace
+            rc = fn(self._h, _ptr(o), _ptr(k), n, C.byref(opts), C.byref(to), _stream(stream))
             if rc == HG_E_CAPACITY and attempt == 0 and capacity is None:
                 capacity = int(to.needed)
                 res.pop("leaf", None)

@@ -749,4 +749,50 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     return rc;
 }
 
+// grid_trace_noalloc: the scan work space lives in a fixed device array,
+// one per GPU the library runs on (held until the process ends); its device
+// address is looked up once per device, with that device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(HG_NOALLOC_SCRATCH_BYTES);
+static_assert(NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) int64_t scratch[NOALLOC_SCRATCH_BYTES / sizeof(int64_t)];
+static std::mutex g_noalloc_m;
+static int64_t *g_noalloc_ptr[MAX_DEVICES];
+
+static int noalloc_scratch(int64_t **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return set_hip_error(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
+    std::lock_guard<std::mutex> lock(g_noalloc_m);
+    if (!g_noalloc_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e || !p) return set_hip_error(e ? e : hipErrorInvalidSymbol);
+        g_noalloc_ptr[dev] = static_cast<int64_t *>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return HG_OK;
+}
+
+int grid_trace_noalloc(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
+                       const hg_trace_opts *opts, hg_trace_out *out, void *stream)
+{
+    {
+        int rc0 = check_trace_args(g, origins, dirs, n, opts, out);
+        if (rc0) return rc0;
+    }
+    if (scan_tmp_elems(n) * sizeof(int64_t) > NOALLOC_SCRATCH_BYTES) return HG_E_LIMIT;
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < 4; i++) out->kernel_ms[i] = 0.f;
+    out->needed = 0;
+    out->rechecks = 0;
+    out->descents = 0;
+    int64_t *tmp = nullptr;
+    int rc = noalloc_scratch(&tmp);
+    if (rc) return rc;
+    hipEvent_t ev[4] = {};   // no timing: HG_FLAG_TIMING is ignored here
+    return trace_two_pass(g, origins, dirs, n, opts, out, s, ev, tmp);
+}
+
 }  // extern "C"
