@@ -24,7 +24,7 @@
  *    an exact binary fraction.
  *  - Leaf ids are ranks among the leaves in the breadth-first node list
  *    (the order in which the construction loop of Sect. 2.2 creates them).
- *  - Trees of up to 2^25 leaves and 2^25 internal nodes use a compact walk
+ *  - Trees of up to 2^24 leaves and 2^24 internal nodes use a compact walk
  *    layout (32-bit references, 32-byte leaf records); larger trees switch to
  *    64-bit references and 64-byte records automatically.  The environment
  *    variable HGRID_WIDE_REFS=1 forces the wide layout (for testing).
@@ -128,8 +128,7 @@ typedef struct {
     int32_t chunk;      /* persistent walk: paths a wavefront takes per atomic (at most
                            HG_MAX_CHUNK), 0 = library choice */
     int32_t refill_min; /* persistent walk: idle lanes that trigger a refill (1..64), 0 = library choice */
-    int32_t lds_bytes;  /* persistent walk: bytes of top-level child references each block
-                           stages in LDS (at most 65536); 0 = library choice (16384), < 0 = none */
+    int32_t lds_bytes;  /* unused (kept for the layout of this struct; at most 65536) */
     int32_t passes;     /* grid_trace, records mode: 1 = one walk writing tau, counts and each
                            path's first `slab` records into a per-path row, then a copy into the
                            CSR slices (paths with more records are resumed where their row
@@ -203,7 +202,7 @@ typedef struct hg_grid *hg_grid_t;
  * is the Monte Carlo estimate of Eq. 1 and it is split by the criteria above;
  * leaves are the unsplit nodes).  The construction runs level by level on the
  * GPU.  With criteria.max_nodes = 0 it synchronises the stream once per level
- * to size the next one; with 0 < max_nodes <= 2^25 every array is reserved
+ * to size the next one; with 0 < max_nodes <= 2^24 every array is reserved
  * for max_nodes nodes up front (about 160 bytes per node) and the levels run
  * with their counts kept on the device, synchronising only at the end (the
  * same tree either way).  Leaf density rho = S/n_samples = M/V (Sect. 3.2).
@@ -381,7 +380,7 @@ void grid_free(hg_grid_t grid);
  * allocates nor synchronises, and batch_capture records it into a HIP graph
  * that batch_replay launches again (the build-then-trace pass of a batch with
  * new contents of the bound input buffers, or simply again).  Grids use the
- * compact layout only (node capacity at most 2^25). */
+ * compact layout only (node capacity at most 2^24). */
 typedef struct hg_batch *hg_batch_t;
 
 /* Reserve a batch: density dens[g] (copied; clumps binned here), criteria
@@ -389,7 +388,7 @@ typedef struct hg_batch *hg_batch_t;
  * is grid g's node capacity: all its device arrays (about 160 bytes per node)
  * are allocated now.  Synchronises the device.  Errors: HG_E_INVAL (as
  * grid_build, or max_nodes < 1, or n_grids outside 1..HG_MAX_BATCH),
- * HG_E_DOMAIN, HG_E_LIMIT (max_nodes > 2^25), HG_E_OOM, HG_E_HIP. */
+ * HG_E_DOMAIN, HG_E_LIMIT (max_nodes > 2^24), HG_E_OOM, HG_E_HIP. */
 int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit,
                  const int *tree_types, hg_batch_t *out);
 

@@ -15,7 +15,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhgrid.so")
+# HGRID_LIB names another build of the same library (e.g. one compiled with
+# different launch bounds, for comparing builds); the default is the in-tree one.
+LIB_PATH = os.environ.get("HGRID_LIB") or os.path.join(_HERE, "libhgrid.so")
 
 OCTREE = 0
 KDTREE = 1

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <mutex>
 #include <vector>
 
@@ -69,12 +70,11 @@ void free_grid_arrays(hg_grid *g)
 {
     if (g->block) {
         block_free(g->block, g->block_bytes, g->block_dev);
-        dfree(g->status, nullptr);
         return;
     }
     void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
                     g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->recw,
-                    g->child, g->table, g->status};
+                    g->child, g->table};
     for (void *p : ptrs) dfree(p, nullptr);
 }
 
@@ -104,18 +104,13 @@ hg_grid *new_grid(int tree, const double lo[3], double side)
     g->tree = tree;
     for (int d = 0; d < 3; d++) g->lo[d] = lo[d];
     g->side = side;
-    if (dalloc((void **)&g->status, sizeof(TraceStatus), nullptr) != HG_OK) {
-        free(g);
-        return nullptr;
-    }
     return g;
 }
 
 void destroy(hg_grid *g)
 {
     if (!g) return;
-    if (g->borrowed) dfree(g->status, nullptr);
-    else free_grid_arrays(g);
+    if (!g->borrowed) free_grid_arrays(g);
     free(g);
 }
 
@@ -253,6 +248,50 @@ void block_free(void *p, size_t bytes, int dev)
         }
     }
     dfree(p, nullptr);
+}
+
+// Pool of trace status slots per device: blocks of SLOTS_PER_BLOCK slots,
+// allocated once and kept until the process ends (a slot is in use only for
+// the duration of one call).
+struct StatusPool {
+    std::mutex m;
+    std::vector<TraceStatus *> free_slots;
+};
+static StatusPool g_status_pool[MAX_DEVICES];
+constexpr int SLOTS_PER_BLOCK = 64;
+constexpr size_t SLOT_BYTES = 256;
+static_assert(sizeof(TraceStatus) <= SLOT_BYTES, "status slot");
+
+int StatusSlot::acquire()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return set_hip_error(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return HG_E_INVAL;
+    StatusPool &P = g_status_pool[dev];
+    std::lock_guard<std::mutex> lock(P.m);
+    if (P.free_slots.empty()) {
+        void *b = nullptr;
+        e = hipMalloc(&b, SLOT_BYTES * SLOTS_PER_BLOCK);
+        if (e) {
+            (void)hipGetLastError();
+            return e == hipErrorOutOfMemory ? HG_E_OOM : set_hip_error(e);
+        }
+        for (int i = SLOTS_PER_BLOCK - 1; i >= 0; i--)
+            P.free_slots.push_back(reinterpret_cast<TraceStatus *>(static_cast<char *>(b) + SLOT_BYTES * size_t(i)));
+    }
+    p_ = P.free_slots.back();
+    P.free_slots.pop_back();
+    dev_ = dev;
+    return HG_OK;
+}
+
+StatusSlot::~StatusSlot()
+{
+    if (!p_) return;
+    StatusPool &P = g_status_pool[dev_];
+    std::lock_guard<std::mutex> lock(P.m);
+    P.free_slots.push_back(p_);
 }
 
 }  // namespace hg
@@ -422,9 +461,11 @@ static int check_trace_args(hg_grid_t g, const double *origins, const double *di
     return HG_OK;
 }
 
-static int read_status(hg_grid *g, TraceStatus *st, hipStream_t s)
+}  // extern "C"
+
+int hg::read_status(const TraceStatus *dev_st, TraceStatus *st, hipStream_t s)
 {
-    hipError_t e = hipMemcpyAsync(st, g->status, sizeof *st, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(st, dev_st, sizeof *st, hipMemcpyDeviceToHost, s);
     if (!e) e = hipStreamSynchronize(s);
     if (e) return set_hip_error(e);
     if (st->bad_ref) return HG_E_FORMAT;
@@ -432,6 +473,8 @@ static int read_status(hg_grid *g, TraceStatus *st, hipStream_t s)
     if (st->step_guard) return HG_E_STEP;
     return HG_OK;
 }
+
+extern "C" {
 
 int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *origins,
                        const double *const *dirs, const int64_t *n, const hg_trace_opts *opts,
@@ -456,14 +499,18 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     const bool records = opts->mode == HG_RECORDS;
     const bool timing = (opts->flags & HG_FLAG_TIMING) != 0;
     const int64_t chunk = opts->chunk > 0 ? opts->chunk : 1024;
-    hg_grid *g0 = grids[0];
+    StatusSlot slot;
+    {
+        const int rc0 = slot.acquire();
+        if (rc0) return rc0;
+    }
+    TraceStatus *const dst = slot.get();
     std::vector<WalkGrid> hG((size_t)ng);
     std::vector<WalkArgs> hA((size_t)ng);
     std::vector<BatchChunk> hC;
     for (int i = 0; i < ng; i++) {
         hG[size_t(i)] = walk_grid(grids[i], opts->precision);
-        hA[size_t(i)] = walk_args(grids[i], origins[i], dirs[i], n[i], opts, &outs[i]);
-        hA[size_t(i)].st = g0->status;
+        hA[size_t(i)] = walk_args(grids[i], dst, origins[i], dirs[i], n[i], opts, &outs[i]);
         const int32_t head = int32_t(hC.size());
         for (int64_t a = 0; a < n[i]; a += chunk) hC.push_back(BatchChunk{i, head, a, std::min(n[i], a + chunk)});
         outs[i].needed = 0;
@@ -494,12 +541,12 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     if (!rc && e) rc = set_hip_error(e);
     TraceStatus st;
     if (!rc) {
-        k_reset_status<<<1, 1, 0, s>>>(g0->status);
+        k_reset_status<<<1, 1, 0, s>>>(dst);
         if (timing) (void)hipEventRecord(ev[0], s);
-        rc = launch_batched(dG, dA, dC, int(hC.size()), opts, false, g0->status, s);
+        rc = launch_batched(dG, dA, dC, int(hC.size()), opts, false, dst, s);
         if (timing) (void)hipEventRecord(ev[1], s);
     }
-    if (!rc) rc = read_status(g0, &st, s);
+    if (!rc) rc = read_status(dst, &st, s);
     if (!rc) {
         outs[0].rechecks = int64_t(st.rechecks);
         outs[0].descents = int64_t(st.descents);
@@ -530,10 +577,10 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         if (!rc && !fits) rc = HG_E_CAPACITY;
         if (!rc) {
             if (timing) (void)hipEventRecord(ev[2], s);
-            rc = launch_batched(dG, dA, dC, int(hC.size()), opts, true, g0->status, s);
+            rc = launch_batched(dG, dA, dC, int(hC.size()), opts, true, dst, s);
             if (timing) (void)hipEventRecord(ev[3], s);
         }
-        if (!rc) rc = read_status(g0, &st, s);
+        if (!rc) rc = read_status(dst, &st, s);
     }
     if (!rc) {
         e = hipStreamSynchronize(s);
@@ -562,18 +609,18 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
 // Records mode in two walks: a counting walk, the prefix sum of the counts and
 // a record-filling walk.  The prefix sum's work space is `tmp`
 // (scan_tmp_elems(n) entries) when given, else allocated here.
-static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
+static int trace_two_pass(hg_grid_t g, TraceStatus *dst, const double *origins, const double *dirs, int64_t n,
                           const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev,
                           int64_t *tmp_given = nullptr)
 {
     const bool records = opts->mode == HG_RECORDS;
     const bool timing = ev[0] != nullptr;
-    k_reset_status<<<1, 1, 0, s>>>(g->status);
+    k_reset_status<<<1, 1, 0, s>>>(dst);
     if (timing) (void)hipEventRecord(ev[0], s);
-    int rc = launch_walk(g, origins, dirs, n, opts, out, WM_COUNT, s, nullptr);
+    int rc = launch_walk(g, dst, origins, dirs, n, opts, out, WM_COUNT, s, nullptr);
     if (timing) (void)hipEventRecord(ev[1], s);
     TraceStatus st;
-    if (!rc) rc = read_status(g, &st, s);
+    if (!rc) rc = read_status(dst, &st, s);
     if (!rc) {
         out->rechecks = int64_t(st.rechecks);
         out->descents = int64_t(st.descents);
@@ -593,10 +640,10 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
         out->needed = needed;
         if (needed > out->capacity) rc = HG_E_CAPACITY;
     }
-    if (!rc && needed > 0) rc = launch_walk(g, origins, dirs, n, opts, out, WM_FILL, s, nullptr);
+    if (!rc && needed > 0) rc = launch_walk(g, dst, origins, dirs, n, opts, out, WM_FILL, s, nullptr);
     if (timing) (void)hipEventRecord(ev[3], s);
     if (!tmp_given) dfree(tmp, s);
-    if (!rc) rc = read_status(g, &st, s);
+    if (!rc) rc = read_status(dst, &st, s);
     return rc;
 }
 
@@ -605,8 +652,9 @@ static int trace_two_pass(hg_grid_t g, const double *origins, const double *dirs
 // into a row per path, the prefix sum of the counts, the rows copied into the
 // CSR slices, and a record-filling walk that resumes the paths whose records
 // did not fit their row at their first record beyond it.  HG_E_OOM (nothing enqueued) when the scratch cannot be had.
-static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs, int64_t n, int64_t slab,
-                          const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s, hipEvent_t *ev)
+static int trace_one_pass(hg_grid_t g, TraceStatus *dst, const double *origins, const double *dirs, int64_t n,
+                          int64_t slab, const hg_trace_opts *opts, hg_trace_out *out, hipStream_t s,
+                          hipEvent_t *ev)
 {
     const bool timing = ev[0] != nullptr;
     const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
@@ -633,12 +681,12 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
         unsigned long long n_res;
     } h = {0, 0};
     if (!rc) {
-        k_reset_status<<<1, 1, 0, s>>>(g->status);
+        k_reset_status<<<1, 1, 0, s>>>(dst);
         hipError_t e = hipMemsetAsync(n_res, 0, sizeof *n_res, s);
         if (e) rc = set_hip_error(e);
     }
     if (!rc) {
-        WalkArgs A = walk_args(g, origins, dirs, n, opts, out);
+        WalkArgs A = walk_args(g, dst, origins, dirs, n, opts, out);
         A.leaf = sleaf;
         A.ds = sds;
         A.slab = slab;
@@ -657,7 +705,7 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
         if (!e) e = hipMemcpyAsync(&h.n_res, n_res, sizeof h.n_res, hipMemcpyDeviceToHost, s);
         if (e) rc = set_hip_error(e);
     }
-    if (!rc) rc = read_status(g, &st, s);   // synchronises
+    if (!rc) rc = read_status(dst, &st, s);   // synchronises
     if (!rc) {
         out->rechecks = int64_t(st.rechecks);
         out->descents = int64_t(st.descents);
@@ -668,14 +716,14 @@ static int trace_one_pass(hg_grid_t g, const double *origins, const double *dirs
                                       out->leaf, out->ds, s);
     if (!rc && h.n_res > 0) {
         // the paths past their row, resumed where their row filled up
-        WalkArgs F = walk_args(g, origins, dirs, n, opts, out);
+        WalkArgs F = walk_args(g, dst, origins, dirs, n, opts, out);
         F.resume = res;
         F.n = int64_t(std::min<unsigned long long>(h.n_res, (unsigned long long)n));
         F.slab = slab;
         rc = launch_walk_args(g, F, opts, WM_FILL, s);
     }
     if (timing) (void)hipEventRecord(ev[3], s);
-    if (!rc) rc = read_status(g, &st, s);
+    if (!rc) rc = read_status(dst, &st, s);
     (void)hipStreamSynchronize(s);
     scratch_release(w);
     return rc;
@@ -722,10 +770,12 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
     out->descents = 0;
     if (timing)
         for (int i = 0; i < 4; i++) HG_CHECK(hipEventCreate(&ev[i]));
+    StatusSlot slot;
+    int rc = slot.acquire();
     const int64_t slab = slab_rows(opts, n);
     const bool one_pass = records && opts->passes != 2 && slab > 0;
-    int rc = one_pass ? trace_one_pass(g, origins, dirs, n, slab, opts, out, s, ev) : HG_E_OOM;
-    if (rc == HG_E_OOM) rc = trace_two_pass(g, origins, dirs, n, opts, out, s, ev);
+    if (!rc) rc = one_pass ? trace_one_pass(g, slot.get(), origins, dirs, n, slab, opts, out, s, ev) : HG_E_OOM;
+    if (rc == HG_E_OOM) rc = trace_two_pass(g, slot.get(), origins, dirs, n, opts, out, s, ev);
     if (timing && (rc == HG_OK || rc == HG_E_CAPACITY)) {
         (void)hipEventSynchronize(ev[1]);
         (void)hipEventElapsedTime(&out->kernel_ms[0], ev[0], ev[1]);
@@ -753,7 +803,9 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
 // one per GPU the library runs on (held until the process ends); its device
 // address is looked up once per device, with that device current.
 constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(HG_NOALLOC_SCRATCH_BYTES);
+constexpr size_t NOALLOC_STATUS_WORDS = 256 / sizeof(int64_t);   // status words ahead of the scan space
 static_assert(NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static_assert(sizeof(TraceStatus) <= NOALLOC_STATUS_WORDS * sizeof(int64_t), "status in scratch");
 static __device__ __align__(256) int64_t scratch[NOALLOC_SCRATCH_BYTES / sizeof(int64_t)];
 static std::mutex g_noalloc_m;
 static int64_t *g_noalloc_ptr[MAX_DEVICES];
@@ -782,17 +834,20 @@ int grid_trace_noalloc(hg_grid_t g, const double *origins, const double *dirs, i
         int rc0 = check_trace_args(g, origins, dirs, n, opts, out);
         if (rc0) return rc0;
     }
-    if (scan_tmp_elems(n) * sizeof(int64_t) > NOALLOC_SCRATCH_BYTES) return HG_E_LIMIT;
+    if ((scan_tmp_elems(n) + NOALLOC_STATUS_WORDS) * sizeof(int64_t) > NOALLOC_SCRATCH_BYTES) return HG_E_LIMIT;
     hipStream_t s = (hipStream_t)stream;
     for (int i = 0; i < 4; i++) out->kernel_ms[i] = 0.f;
     out->needed = 0;
     out->rechecks = 0;
     out->descents = 0;
-    int64_t *tmp = nullptr;
-    int rc = noalloc_scratch(&tmp);
+    int64_t *base = nullptr;
+    int rc = noalloc_scratch(&base);
     if (rc) return rc;
+    // the call's status words, then the prefix sum's work space
+    TraceStatus *st = reinterpret_cast<TraceStatus *>(base);
+    int64_t *tmp = base + NOALLOC_STATUS_WORDS;
     hipEvent_t ev[4] = {};   // no timing: HG_FLAG_TIMING is ignored here
-    return trace_two_pass(g, origins, dirs, n, opts, out, s, ev, tmp);
+    return trace_two_pass(g, st, origins, dirs, n, opts, out, s, ev, tmp);
 }
 
 }  // extern "C"

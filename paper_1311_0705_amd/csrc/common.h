@@ -8,12 +8,16 @@
 //                 and the leaf density, so one crossing reads one sector;
 //                 child: per internal node the encoded references of its
 //                 2 (k-d) or 8 (octree) children, read one per descent step.
-// An encoded reference packs  leaf flag (top bit) | level (6 bits) | id, id
-// being the leaf rank or the internal-node rank.  Compact layout: 32-bit
-// references (ids < 2^25) and 32-byte records, one f32 and one f64 record
-// array; wide layout (larger trees): 64-bit references and one 64-byte record
-// holding both densities.  The cell box of a reference's target follows from
-// its level and the corner of the node the walk comes from.
+// An encoded reference packs  kind (top two bits) | level (6 bits) | id:
+// kind 2 = leaf (id = leaf rank), 0 = internal node (id = internal-node rank),
+// 1 = "twin", an internal node whose children are all leaves (id = the leaf
+// rank of its first child; the others follow it), so a descent resolves it
+// without reading the child array; all ones is the null reference.  Compact
+// layout: 32-bit references (ids < 2^24) and 32-byte records, one f32 and
+// one f64 record array; wide layout (larger trees): 64-bit references and
+// one 64-byte record holding both densities.  The cell box of a reference's
+// target follows from its level and the integer corner of the node the walk
+// comes from.
 #pragma once
 
 #include <vector>
@@ -29,7 +33,7 @@ namespace hg {
 constexpr int OCT = HG_OCTREE;
 constexpr int KD = HG_KDTREE;
 
-constexpr int64_t MAX_IDS = int64_t(1) << 25;       // compact-layout id limit
+constexpr int64_t MAX_IDS = int64_t(1) << 24;       // compact-layout id limit
 constexpr int DEPTH_BITS = 20;  // integer box resolution: per-axis depth <= 19
 
 __host__ __device__ inline int axis_depth(int tree, int level, int d)
@@ -41,13 +45,17 @@ __host__ __device__ inline int axis_depth(int tree, int level, int d)
 template <typename R>
 struct Ref {
     static constexpr int BITS = int(sizeof(R) * 8);
-    static constexpr int LEVEL_SHIFT = BITS == 32 ? 25 : 56;
+    static constexpr int KIND_SHIFT = BITS - 2;
+    static constexpr int LEVEL_SHIFT = BITS == 32 ? 24 : 56;
     static constexpr R NUL = ~R(0);
-    __host__ __device__ static R make(bool leaf, int level, uint64_t id)
+    enum { INTERNAL = 0, TWIN = 1, LEAF = 2 };
+    __host__ __device__ static R make(int kind, int level, uint64_t id)
     {
-        return (leaf ? R(R(1) << (BITS - 1)) : R(0)) | (R(level) << LEVEL_SHIFT) | R(id);
+        return (R(kind) << KIND_SHIFT) | (R(level) << LEVEL_SHIFT) | R(id);
     }
-    __host__ __device__ static bool leaf(R r) { return ((r >> (BITS - 1)) & R(1)) != R(0); }
+    __host__ __device__ static int kind(R r) { return int(r >> KIND_SHIFT); }
+    __host__ __device__ static bool leaf(R r) { return kind(r) == LEAF; }
+    __host__ __device__ static bool twin(R r) { return kind(r) == TWIN; }
     __host__ __device__ static int level(R r) { return int((r >> LEVEL_SHIFT) & R(63)); }
     __host__ __device__ static uint64_t id(R r) { return uint64_t(r & ((R(1) << LEVEL_SHIFT) - R(1))); }
 };
@@ -110,7 +118,16 @@ struct WalkGrid {
     const void *child;             // [n_internal][2 or 8] references
     const void *table;             // locate table (NULL: descents start at the root)
     int tdep;                      // its per-axis depth: 2^tdep cells per axis
+    int dm;                        // finest per-axis depth of any node: every plane is
+                                   // lo + i unit with unit = side 2^-dm, i an integer
+    double unit;
 };
+
+// Finest per-axis depth of a tree whose levels go up to max_level.
+__host__ __device__ inline int finest_depth(int tree, int max_level)
+{
+    return axis_depth(tree, max_level < 0 ? 0 : max_level, 0);
+}
 
 // Locate table: a uniform grid of 2^tdep cells per axis over the domain; cell
 // (i, j, k) (index (i 2^tdep + j) 2^tdep + k) holds the encoded reference of
@@ -132,7 +149,7 @@ __host__ __device__ inline int table_depth(int tree, int64_t n_leaves, int max_l
     return t < 0 ? 0 : t;
 }
 
-// Scratch for device-side status shared by the trace kernels.
+// Status words of one trace call, shared by its kernels (see StatusSlot).
 struct TraceStatus {
     unsigned long long rechecks;
     unsigned long long descents;   // child levels descended (walk statistics)
@@ -149,10 +166,12 @@ struct TraceStatus {
 // mode), taken on entry to that leaf: the record-filling walk resumes the
 // path from here instead of from its origin.
 struct Resume {
-    double s, p[3], lo[3];
+    double s, p[3];
+    uint32_t X[3];                 // the node's lower corner in units of WalkGrid::unit
+    int32_t lv;
     uint64_t ref;
     int64_t path;
-    int32_t lv, steps;
+    int32_t steps, pad;
 };
 
 // Per-grid arguments of a walk launch.
@@ -219,10 +238,9 @@ struct hg_grid {
     uint64_t root_ref;
     void *table;               // locate table (uint32_t or uint64_t references), or NULL
     int tdep;                  // its per-axis depth
-    hg::TraceStatus *status;   // device scratch
     int64_t level_begin[64];   // first node of each level; level_begin[max_level+1] = n_nodes
-    int borrowed;              // arrays belong to a batch (only status is the grid's own)
-    void *block;               // when set, every array above except status is carved from it
+    int borrowed;              // arrays belong to a batch
+    void *block;               // when set, every array above is carved from it
     size_t block_bytes;        // its size and device (block_free)
     int block_dev;
 };
@@ -351,7 +369,26 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
 
 // ---- trace / locate (trace.hip) --------------------------------------------
 WalkGrid walk_grid(const hg_grid *g, int precision);
-int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
+
+// The status words of one trace call (work counter, error flags, statistics),
+// from a per-device pool for the duration of the call, so that calls on one
+// grid from several host threads or streams never share them.
+class StatusSlot {
+  public:
+    StatusSlot() = default;
+    StatusSlot(const StatusSlot &) = delete;
+    StatusSlot &operator=(const StatusSlot &) = delete;
+    ~StatusSlot();
+    int acquire();
+    TraceStatus *get() const { return p_; }
+
+  private:
+    TraceStatus *p_ = nullptr;
+    int dev_ = -1;
+};
+// Copy a call's status to the host (synchronises s) and turn its flags into a code.
+int read_status(const TraceStatus *dev_st, TraceStatus *host, hipStream_t s);
+int launch_walk(const hg_grid *g, TraceStatus *st, const double *o, const double *k, int64_t n,
                 const hg_trace_opts *opts, hg_trace_out *out, int wm, hipStream_t s,
                 float *ms);
 int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *opts, int wm,
@@ -362,7 +399,7 @@ int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, h
 int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision, int pairs,
                         const int32_t *count, const int64_t *offsets, int64_t n, int32_t *leaf, void *ds,
                         hipStream_t s);
-WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
+WalkArgs walk_args(const hg_grid *g, TraceStatus *st, const double *o, const double *k, int64_t n,
                    const hg_trace_opts *opts, hg_trace_out *out);
 int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
                    int n_chunks, const hg_trace_opts *opts, bool fill, TraceStatus *st,

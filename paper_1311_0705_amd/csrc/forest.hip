@@ -35,7 +35,7 @@ constexpr unsigned SAMPLE_BLOCKS = 2048;  // node sampling: 4 wavefronts of 64 n
 // launch shapes the batch tuner tries
 const int BLOCKS[] = {128, 256, 512};
 const int BATCH_CHUNKS[] = {128, 256, 512, 1024, 2048, 4096};
-const int REFILLS[] = {4, 8, 16, 32};
+const int REFILLS[] = {1, 2, 4, 8, 16};
 
 struct ForestGrid {
     int tree, nc, lg, pad;
@@ -374,12 +374,14 @@ __global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restri
         for (int d = 0; d < 3; d++) W.lo[d] = G.D.lo[d];
         W.side = G.D.side;
         for (int d = 0; d < 3; d++) W.hi[d] = G.D.lo[d] + G.D.side;
-        W.root = Ref<uint32_t>::make(I == 0, 0, 0);
+        W.root = Ref<uint32_t>::make(I == 0 ? Ref<uint32_t>::LEAF : Ref<uint32_t>::INTERNAL, 0, 0);
         W.n_leaves = uint64_t(L);
         W.n_internal = uint64_t(I);
         W.child = G.child;
         W.tdep = grid_tdep(G, L);
         W.table = W.tdep > 0 ? G.table : nullptr;
+        W.dm = finest_depth(G.tree, G.C.max_level);
+        W.unit = ldexp(G.D.side, -W.dm);
         W.rec = G.rec32;
         w32[i] = W;
         W.rec = G.rec64;
@@ -402,7 +404,7 @@ __global__ void __launch_bounds__(FT) k_f_records(const ForestGrid *__restrict__
         LeafRec64 b;
 #pragma unroll
         for (int j = 0; j < 6; j++) {
-            const uint32_t e = encode<uint32_t>(G.rope[6 * int64_t(n) + j], G.fc, G.level, G.leaf_of, G.int_of);
+            const uint32_t e = encode<uint32_t>(G.rope[6 * int64_t(n) + j], G.nc, G.fc, G.level, G.leaf_of, G.int_of);
             a.rope[j] = e;
             b.rope[j] = e;
         }
@@ -426,7 +428,7 @@ __global__ void __launch_bounds__(FT) k_f_table(const ForestGrid *__restrict__ F
         const int64_t cell = t - PT[i];
         const uint32_t m = (1u << td) - 1u;
         const uint32_t c[3] = {uint32_t(cell >> (2 * td)) & m, uint32_t(cell >> td) & m, uint32_t(cell) & m};
-        G.table[cell] = encode<uint32_t>(table_node(G.tree, td, c, G.fc, G.level), G.fc, G.level,
+        G.table[cell] = encode<uint32_t>(table_node(G.tree, td, c, G.fc, G.level), G.nc, G.fc, G.level,
                                          G.leaf_of, G.int_of);
     }
 }
@@ -443,7 +445,7 @@ __global__ void __launch_bounds__(FT) k_f_child_refs(const ForestGrid *__restric
         if (f < 0) continue;
         const int64_t base = int64_t(G.int_of[n]) * G.nc;
         for (int k = 0; k < G.nc; k++)
-            G.child[base + k] = encode<uint32_t>(f + k, G.fc, G.level, G.leaf_of, G.int_of);
+            G.child[base + k] = encode<uint32_t>(f + k, G.nc, G.fc, G.level, G.leaf_of, G.int_of);
     }
 }
 
@@ -913,7 +915,7 @@ int batch_grid(hg_batch_t b, int i, hg_grid_t *out)
     g->rec32 = F.rec32;
     g->rec64 = F.rec64;
     g->child = F.child;
-    g->root_ref = Ref<uint32_t>::make(g->n_internal == 0, 0, 0);
+    g->root_ref = Ref<uint32_t>::make(g->n_internal == 0 ? Ref<uint32_t>::LEAF : Ref<uint32_t>::INTERNAL, 0, 0);
     g->table = const_cast<void *>(W.table);
     g->tdep = W.tdep;
     *out = g;
@@ -950,7 +952,7 @@ int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream
         if (hipEventCreate(&ev[i]) != hipSuccess) rc = HG_E_HIP;
     hg_trace_opts best = b->opts;
     best.block = best.block ? best.block : 256;
-    best.refill_min = best.refill_min ? best.refill_min : 16;
+    best.refill_min = best.refill_min ? best.refill_min : 4;
     best.chunk = best.chunk ? best.chunk : 1024;
     float best_t = INFINITY;
     auto eval = [&](const hg_trace_opts &c, float *ms) -> int {

@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(LT)
 }
 
 __global__ void __launch_bounds__(LT)
-    k_leaf_records(int64_t n_leaves, const int32_t *__restrict__ node_of,
+    k_leaf_records(int64_t n_leaves, int nc, const int32_t *__restrict__ node_of,
                    const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                    const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
                    const int32_t *__restrict__ rope, const double *__restrict__ S,
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(LT)
     LeafRec64 b;
 #pragma unroll
     for (int j = 0; j < 6; j++) {
-        const uint32_t e = encode<uint32_t>(rope[6 * int64_t(n) + j], fc, level, leaf_of, int_of);
+        const uint32_t e = encode<uint32_t>(rope[6 * int64_t(n) + j], nc, fc, level, leaf_of, int_of);
         a.rope[j] = e;
         b.rope[j] = e;
     }
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(LT)
 }
 
 __global__ void __launch_bounds__(LT)
-    k_leaf_records_wide(int64_t n_leaves, const int32_t *__restrict__ node_of,
+    k_leaf_records_wide(int64_t n_leaves, int nc, const int32_t *__restrict__ node_of,
                         const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                         const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
                         const int32_t *__restrict__ rope, const double *__restrict__ S,
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(LT)
     LeafRecW a;
 #pragma unroll
     for (int j = 0; j < 6; j++)
-        a.rope[j] = encode<uint64_t>(rope[6 * int64_t(n) + j], fc, level, leaf_of, int_of);
+        a.rope[j] = encode<uint64_t>(rope[6 * int64_t(n) + j], nc, fc, level, leaf_of, int_of);
     a.rho64 = r;
     a.rho32 = float(r);
     a.pad = 0;
@@ -116,12 +116,12 @@ __global__ void __launch_bounds__(LT)
     int k = int(t % nc);
     int32_t f = fc[i];
     if (f < 0) return;
-    child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, fc, level, leaf_of, int_of);
+    child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, nc, fc, level, leaf_of, int_of);
 }
 
 template <typename R>
 __global__ void __launch_bounds__(LT)
-    k_locate_table(int tree, int tdep, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+    k_locate_table(int tree, int tdep, int nc, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                    const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
                    R *__restrict__ table)
 {
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(LT)
     if (t >= cells) return;
     const uint32_t m = (1u << tdep) - 1u;
     const uint32_t c[3] = {uint32_t(t >> (2 * tdep)) & m, uint32_t(t >> tdep) & m, uint32_t(t) & m};
-    table[t] = encode<R>(table_node(tree, tdep, c, fc, level), fc, level, leaf_of, int_of);
+    table[t] = encode<R>(table_node(tree, tdep, c, fc, level), nc, fc, level, leaf_of, int_of);
 }
 
 inline unsigned blocks_for(int64_t n) { return unsigned((n + LT - 1) / LT); }
@@ -188,12 +188,12 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     k_number<<<blocks_for(N), LT, 0, s>>>(g->first_child, rank, N, g->leaf_of, g->int_of, g->node_of);
     HG_CHECK(hipGetLastError());
     if (g->wide)
-        k_leaf_records_wide<<<blocks_for(L), LT, 0, s>>>(L, g->node_of, g->first_child, g->level,
+        k_leaf_records_wide<<<blocks_for(L), LT, 0, s>>>(L, nc, g->node_of, g->first_child, g->level,
                                                          g->leaf_of, g->int_of, g->rope, g->S,
                                                          rho_leaf, double(n_samples), g->rho,
                                                          g->recw);
     else
-        k_leaf_records<<<blocks_for(L), LT, 0, s>>>(L, g->node_of, g->first_child, g->level,
+        k_leaf_records<<<blocks_for(L), LT, 0, s>>>(L, nc, g->node_of, g->first_child, g->level,
                                                     g->leaf_of, g->int_of, g->rope, g->S, rho_leaf,
                                                     double(n_samples), g->rho, g->rec32, g->rec64);
     HG_CHECK(hipGetLastError());
@@ -206,7 +206,8 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
                 N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->child);
         HG_CHECK(hipGetLastError());
     }
-    g->root_ref = g->wide ? Ref<uint64_t>::make(I == 0, 0, 0) : Ref<uint32_t>::make(I == 0, 0, 0);
+    g->root_ref = g->wide ? Ref<uint64_t>::make(I == 0 ? Ref<uint64_t>::LEAF : Ref<uint64_t>::INTERNAL, 0, 0)
+                         : Ref<uint32_t>::make(I == 0 ? Ref<uint32_t>::LEAF : Ref<uint32_t>::INTERNAL, 0, 0);
     // locate table
     g->tdep = table_depth(g->tree, L, g->max_level);
     if (g->tdep > 0) {
@@ -218,10 +219,10 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
         }
         if (g->wide)
             k_locate_table<uint64_t><<<blocks_for(cells), LT, 0, s>>>(
-                g->tree, g->tdep, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->table);
+                g->tree, g->tdep, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->table);
         else
             k_locate_table<uint32_t><<<blocks_for(cells), LT, 0, s>>>(
-                g->tree, g->tdep, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->table);
+                g->tree, g->tdep, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->table);
         HG_CHECK(hipGetLastError());
     }
     dfree(flag, s);

@@ -133,13 +133,21 @@ __device__ inline void child_rope(int tree, int64_t p, int k, int j, const int32
     rope[6 * int64_t(child) + j] = push_down(tree, r, d, up, clo, chi, fc, level, coord);
 }
 
+// Encoded reference of node n (see Ref) in a tree whose nodes have nc
+// children: a leaf, an internal node, or a twin (an internal node whose
+// children are all leaves; they are consecutive in the breadth-first list,
+// so their leaf ranks are too).
 template <typename R>
-__device__ inline R encode(int32_t n, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+__device__ inline R encode(int32_t n, int nc, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                            const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of)
 {
     if (n < 0) return Ref<R>::NUL;
-    const bool leaf = fc[n] < 0;
-    return Ref<R>::make(leaf, level[n], uint64_t(uint32_t(leaf ? leaf_of[n] : int_of[n])));
+    const int32_t f = fc[n];
+    if (f < 0) return Ref<R>::make(Ref<R>::LEAF, level[n], uint64_t(uint32_t(leaf_of[n])));
+    bool all = true;
+    for (int k = 0; k < nc; k++) all = all && fc[f + k] < 0;
+    return all ? Ref<R>::make(Ref<R>::TWIN, level[n], uint64_t(uint32_t(leaf_of[f])))
+               : Ref<R>::make(Ref<R>::INTERNAL, level[n], uint64_t(uint32_t(int_of[n])));
 }
 
 // Grid density of a leaf = M/V = S/N (Sect. 3.2), or the imported value.

@@ -3,22 +3,32 @@
 // One lane walks one path.  Per crossing the lane
 //   1. finds the exit face of its leaf: the face distances Delta_d from the
 //      entry point, t_d = Delta_d |1/k_d|, and the lowest axis of the minimum;
-//   2. records (leaf, ds) and adds kappa rho ds to tau;
+//   2. adds kappa rho ds to tau (and in the record modes records (leaf, ds));
 //   3. re-anchors the exit point: the crossed face's plane on the exit axis,
 //      p0 + s k clamped to the leaf on the others (s = path length so far);
-//   4. reads the rope of the exit face from the leaf's 32-byte record and, if
-//      the rope target is not itself a leaf, descends from it with the exit
-//      point (one 4-byte child reference per level).
-// The leaf's box is never loaded: it follows from the level and the integer
-// cell coordinates the lane carries, which the rope target's level and the
-// descent update.  Ties on a split plane follow one fixed rule so that the
-// result is reproducible to the bit (see upper_side).
+//   4. takes the rope of the exit face from the leaf's 32-byte record (read at
+//      the start of the crossing, so the load overlaps the exit decision) and
+//      moves its cell to the rope target; a target that is not a leaf is
+//      descended with the exit point, one level per step: a "twin" (all
+//      children leaves) without a memory access, other nodes by one 4-byte
+//      child reference.
+// Boxes are never loaded.  A lane carries the integer lower corner of its
+// node in units of the grid's finest plane spacing (unit = side 2^-dm) and
+// its level; the planes follow exactly as lo + corner * unit, the widths from
+// a per-level table in LDS.  Ties on a split plane follow one fixed rule so
+// that the result is reproducible to the bit (see tie_upper).
 //
-// HG_FP32_RECHECK computes the exit decision in FP32 from face distances
-// rounded from FP64 and rechecks in FP64 when the two smallest FP32 exit
-// distances are closer than 1e-5 of the leaf's smallest side; positions, ds
-// and the re-anchoring stay in FP64, so the leaf sequence is that of the FP64
-// walk.  tau is then a Kahan-compensated FP32 sum of kappa rho32 ds32.
+// HG_FP32_RECHECK decides the exit face in FP32 from face distances rounded
+// from FP64 and rechecks in FP64 when the two smallest FP32 exit distances
+// are closer than 1e-5 of the leaf's smallest side; only the chosen axis'
+// exit distance (ds) and the re-anchoring are FP64, so the leaf sequence is
+// that of the FP64 walk.  tau is then a Kahan-compensated FP32 sum of
+// kappa rho32 ds32.
+//
+// The persistent walks keep lanes busy as paths end: each wavefront prepares
+// 64 paths at a time with all its lanes (direction check, inverse direction,
+// entry point, locate-table cell) into an LDS queue, and a lane whose path
+// ended takes the next prepared one.
 #include <math.h>
 
 #include <algorithm>
@@ -36,193 +46,142 @@ namespace {
 
 constexpr int TB = 256;
 constexpr int64_t STEP_GUARD = int64_t(1) << 26;
+constexpr int NLEV = 64;      // levels of the per-level table (references hold 6-bit levels)
+constexpr int RING = 64;      // prepared paths per wavefront
+constexpr int SG = 8;         // records a lane stages in LDS before its group is written
 
-// Keeps a value in registers: selecting among values passed through this stays
-// a register select instead of being folded into an indexed stack access.
+// Keep a value in registers: a choice among array elements passed through
+// this stays a register select instead of being folded into an indexed access,
+// which would move the whole array to the stack.
 __device__ __forceinline__ double in_reg(double x)
 {
     asm volatile("" : "+v"(x));
     return x;
 }
-
-// 2^e for a normal exponent.
-__device__ __forceinline__ double pow2(int e) { return __hiloint2double((e + 1023) << 20, 0); }
-
-// Tie context of a descent, packed in one register: bits 0-1 the axis of the
-// face just crossed (3 = none), bits 2-4 "point on the low face of the leaf
-// just left" per axis, bits 5-7 "on its high face".
-constexpr int TIE_NONE = 3;
-
-// Direction signs of a path, packed: bit d set if k_d > 0, bit 3+d if k_d < 0.
-__device__ __forceinline__ int dir_bits(const double k[3])
+__device__ __forceinline__ uint32_t in_reg(uint32_t x)
 {
-    int b = 0;
-#pragma unroll
-    for (int d = 0; d < 3; d++) b |= (int(k[d] > 0.0) << d) | (int(k[d] < 0.0) << (3 + d));
-    return b;
+    asm volatile("" : "+v"(x));
+    return x;
 }
 
-// Side of a split plane c on axis d that holds the point whose coordinate is
-// x.  Off the plane the comparison decides.  On it: the axis of the face just
-// crossed goes to the side the path moves to; a plane on the boundary of the
-// leaf just left keeps the point inside that leaf's slab; otherwise the
-// direction decides, a zero component going to the upper side.
-__device__ __forceinline__ int upper_side(double x, double c, int d, int dirb, int tie)
+// IEEE min / max of two doubles that are never NaN (or where a NaN operand
+// must lose, as for an exit distance): one instruction each, without the
+// quieting of operands the compiler adds to fmin / fmax of values it cannot
+// prove canonical.
+__device__ __forceinline__ double min64(double a, double b)
 {
-    const int kpos = (dirb >> d) & 1;
-    const int kneg = (dirb >> (3 + d)) & 1;
-    const int onlo = (tie >> (2 + d)) & 1;
-    const int onhi = (tie >> (5 + d)) & 1;
-    const int on_plane = d == (tie & 3) ? kpos : (onhi ? 0 : (onlo ? 1 : kneg ^ 1));
-    return x > c ? 1 : (x < c ? 0 : on_plane);
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double max64(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
-// True when ref may be dereferenced: a leaf or internal id inside the arrays.
-template <typename R>
-__device__ __forceinline__ bool ref_ok(const WalkGrid &G, R ref)
-{
-    return ref != Ref<R>::NUL && Ref<R>::id(ref) < (Ref<R>::leaf(ref) ? G.n_leaves : G.n_internal);
-}
-
-// Walk-record layout: compact (32-bit references, 32-byte records, separate
-// f32 and f64 record arrays) or wide (64-bit references, one 64-byte record).
-template <typename R, int PREC>
-struct Rec {
-    static constexpr int STRIDE = sizeof(R) == 8 ? 64 : 32;
-    static constexpr int RHO64 = sizeof(R) == 8 ? 48 : 24;
-    static constexpr int RHO32 = sizeof(R) == 8 ? 56 : 24;
+// Geometry of the nodes of one level: the widths per axis as doubles (exact
+// powers of two) and in units of WalkGrid::unit, the split axis and half
+// width a descent uses, and the FP32 recheck threshold (1e-5 of the smallest
+// width, which is axis 0's: no axis is finer).
+struct alignas(16) LevelGeo {
+    double w[3];
+    uint32_t W[3];
+    uint32_t hw;
+    float guard;
+    int32_t axis;
 };
+static_assert(sizeof(LevelGeo) == 48, "level record");
 
-// Per-axis depth and cell width of a node at level lv.
-template <int TREE>
-__device__ __forceinline__ void level_geom(int lg, int lv, int dep[3], double w[3])
+__device__ __forceinline__ LevelGeo make_level(int tree, int dm, double side, int lv)
 {
-    if (TREE == OCT) {
-        const double ww = pow2(lg - lv);
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            dep[d] = lv;
-            w[d] = ww;
-        }
-    } else {
-        const int q = (lv * 43691) >> 17;  // lv / 3 for 0 <= lv < 64
-        const int r = lv - 3 * q;
-        dep[0] = q + (r >= 1);
-        dep[1] = q + (r >= 2);
-        dep[2] = q;
-#pragma unroll
-        for (int d = 0; d < 3; d++) w[d] = pow2(lg - dep[d]);
-    }
-}
-
-// One descent step from the internal node ref (level lv, lower corner lo)
-// toward the point q: returns the child's reference and moves lo to the
-// child's corner.  Split planes are lo + half the node's width (exact: every
-// plane is a binary fraction).  Child references of the first lds_n internal
-// nodes are read from LDS.
-template <int TREE, typename R>
-__device__ __forceinline__ R child_of(const WalkGrid &G, const R *lds, uint32_t lds_n, R ref, int &lv,
-                                      double lo[3], const double q[3], int dirb, int tie)
-{
-    const uint64_t id = Ref<R>::id(ref);
-    uint64_t slot;
-    if (TREE == KD) {
-        const int q3 = (lv * 43691) >> 17;  // lv / 3: the split axis b = lv mod 3 has depth lv / 3
-        const int b = lv - 3 * q3;
-        const double l0 = in_reg(lo[0]), l1 = in_reg(lo[1]), l2 = in_reg(lo[2]);
-        const double q0 = in_reg(q[0]), q1 = in_reg(q[1]), q2 = in_reg(q[2]);
-        const double lob = b == 0 ? l0 : (b == 1 ? l1 : l2);
-        const double qb = b == 0 ? q0 : (b == 1 ? q1 : q2);
-        const double mid = lob + pow2(G.lg - q3 - 1);
-        const int up = upper_side(qb, mid, b, dirb, tie);
-        slot = 2u * id + uint64_t(up);
-        const double nlo = up ? mid : lob;
-        lo[0] = b == 0 ? nlo : l0;
-        lo[1] = b == 1 ? nlo : l1;
-        lo[2] = b == 2 ? nlo : l2;
-    } else {
-        const double wh = pow2(G.lg - lv - 1);
-        uint32_t idx = 0;
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-            const double mid = lo[d] + wh;
-            const int up = upper_side(q[d], mid, d, dirb, tie);
-            idx |= uint32_t(up) << d;
-            lo[d] = up ? mid : lo[d];
-        }
-        slot = 8u * id + idx;
-    }
-    lv++;
-    return id < lds_n ? lds[slot] : static_cast<const R *>(G.child)[slot];
-}
-
-// Descend from ref to the leaf holding q.  Returns the null reference if one is
-// out of range or the depth exceeds the format's limit (never for a valid
-// layout).
-template <int TREE, typename R>
-__device__ __forceinline__ R descend(const WalkGrid &G, const R *lds, uint32_t lds_n, R ref, int &lv,
-                                     double lo[3], const double q[3], int dirb, int tie)
-{
-    while (!Ref<R>::leaf(ref)) {
-        if (!ref_ok(G, ref) || lv >= 62) return Ref<R>::NUL;
-        ref = child_of<TREE, R>(G, lds, lds_n, ref, lv, lo, q, dirb, tie);
-    }
-    return ref_ok(G, ref) ? ref : Ref<R>::NUL;
-}
-
-// Node where the first descent toward q starts: the locate-table cell holding
-// q (chosen with the descent's rule for a point on a plane with no tie
-// context: the upper side unless the direction's component is negative),
-// its reference, level and lower corner; the root without a table.  The
-// descent from there takes the same decisions as one from the root: every
-// plane above the table level is a cell boundary, and the cell is picked by
-// exact comparisons with those planes.
-template <int TREE, typename R>
-__device__ __forceinline__ R start_node(const WalkGrid &G, const double q[3], int dirb, int &lv, double lo[3])
-{
-    if (G.tdep == 0) {
-        lv = 0;
-#pragma unroll
-        for (int d = 0; d < 3; d++) lo[d] = G.lo[d];
-        return R(G.root);
-    }
-    const int T = 1 << G.tdep;
-    const double wc = pow2(G.lg - G.tdep);
-    const double scale = pow2(G.tdep - G.lg);
-    int c[3];
+    LevelGeo e;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        int i = int(floor((q[d] - G.lo[d]) * scale));
-        i = i < 0 ? 0 : (i > T - 1 ? T - 1 : i);
-        // (q - lo) may round: settle the cell by exact comparisons with its planes
-        if (i > 0 && q[d] < G.lo[d] + double(i) * wc) i--;
-        else if (i < T - 1 && q[d] >= G.lo[d] + double(i + 1) * wc) i++;
-        if (i > 0 && q[d] == G.lo[d] + double(i) * wc && ((dirb >> (3 + d)) & 1)) i--;
-        c[d] = i;
+        const int dep = axis_depth(tree, lv, d);
+        const int sh = dm - dep;
+        e.W[d] = sh >= 0 && sh < 32 ? 1u << sh : 0u;
+        e.w[d] = ldexp(side, -dep);
     }
-    const R ref = static_cast<const R *>(G.table)[(int64_t(c[0]) * T + c[1]) * T + c[2]];
-    lv = Ref<R>::level(ref);
-    int dep[3];
-    double w[3];
-    level_geom<TREE>(G.lg, lv, dep, w);
-#pragma unroll
-    for (int d = 0; d < 3; d++) lo[d] = G.lo[d] + double(c[d] >> (G.tdep - dep[d])) * w[d];
-    return ref;
+    e.axis = tree == KD ? lv % 3 : 0;
+    const uint32_t W0 = in_reg(e.W[0]), W1 = in_reg(e.W[1]), W2 = in_reg(e.W[2]);
+    e.hw = (e.axis == 0 ? W0 : (e.axis == 1 ? W1 : W2)) >> 1;
+    e.guard = 1e-5f * float(e.w[0]);
+    return e;
 }
+
+// Fill a level table (all NLEV levels) with the threads [t0, t0 + nt).
+__device__ __forceinline__ void fill_levels(LevelGeo *geo, const WalkGrid &G, int t0, int nt)
+{
+    for (int j = t0; j < NLEV; j += nt) geo[j] = make_level(G.tree, G.dm, G.side, j);
+}
+
+// A path prepared by its wavefront, waiting in the LDS queue.
+struct alignas(16) Prep {
+    double ainv[3];     // |1/k|
+    double s;           // path length at the start (> 0 when the origin lies outside)
+    uint32_t X[3];      // start node: integer lower corner
+    uint32_t lvf;       // its level | (clip axis + 1) << 8 (0: origin inside) | force FP64 << 12
+    uint64_t ref;       // start node reference
+    int32_t idx;        // path index within the launch (resume-entry index for resumed paths)
+    int32_t pad;
+};
+static_assert(sizeof(Prep) == 64, "queue entry");
+
+// Everything a lane carries for one path.
+template <int PREC, typename R>
+struct Lane {
+    using DsT = typename std::conditional<PREC == HG_FP64, double, float>::type;
+    double p0[3], k[3], ainv[3];
+    float ainv32[3];         // FP32 copies of ainv for the FP32 exit decision
+    double s, p[3];          // path length so far and the current entry point
+    uint32_t X[3];           // integer lower corner of the current node
+    R ref;                   // current node (a leaf when a crossing is due)
+    int lv;                  // its level
+    int tie;                 // tie context of a pending descent (tie_upper)
+    int32_t cnt;             // leaves crossed with ds > 0
+    int steps;
+    double tau64;
+    float tau32, comp32;
+    bool force64;
+    int64_t base, room;      // record slice of this path (record modes)
+    uint32_t sl[4];          // one-thread walk: the last four records, staged
+    DsT sd[4];               // for 16-byte aligned vector stores
+};
+
+enum { PATH_WALK = 0, PATH_MISS = 1, PATH_BAD_DIR = 2 };
+enum { STEP_GO = 0, STEP_END = 1, STEP_ERR = 2 };
+// Walk modes: WM_COUNT (tau and counts; also the tau-only mode), WM_FILL
+// (records into the slices given by the offsets of a counting walk),
+// WM_SLAB (tau, counts and the first A.slab records of every path into a
+// fixed-size row per path, for the one-pass records mode).
 
 __device__ __forceinline__ bool inside_closed(const WalkGrid &G, const double x[3])
 {
     bool in = true;
 #pragma unroll
-    for (int d = 0; d < 3; d++) in = in && (x[d] >= G.lo[d] && x[d] <= G.lo[d] + G.side);
+    for (int d = 0; d < 3; d++) in = in && (x[d] >= G.lo[d] && x[d] <= G.hi[d]);
     return in;
 }
 
-// Start of the path inside the closed domain: the origin itself, or the entry
-// point found by the slab test, placed exactly on the entry face.
-__device__ __forceinline__ bool clip_ray(const WalkGrid &G, const double p0[3], const double k[3],
-                                const double inv[3], double &s, double p[3])
+// Coordinate d of the entry point at path length tn through the face of axis ax.
+__device__ __forceinline__ double entry_coord(const WalkGrid &G, const double p0[3], const double k[3],
+                                              double tn, int ax, int d)
 {
+    const double lo = G.lo[d], hi = G.hi[d];
+    if (d == ax) return k[d] > 0.0 ? lo : hi;
+    const double v = p0[d] + tn * k[d];
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Start of the path inside the closed domain: the origin itself, or the entry
+// point found by the slab test, placed exactly on the entry face.  ax is the
+// entry face's axis (-1 for an origin inside).
+__device__ __forceinline__ bool clip_ray(const WalkGrid &G, const double p0[3], const double k[3],
+                                         const double inv[3], double &s, double p[3], int &ax)
+{
+    ax = -1;
     if (inside_closed(G, p0)) {
         s = 0.0;
 #pragma unroll
@@ -230,11 +189,10 @@ __device__ __forceinline__ bool clip_ray(const WalkGrid &G, const double p0[3], 
         return true;
     }
     double tn = -INFINITY, tf = INFINITY;
-    int ax = -1;
     bool miss = false;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const double lo = G.lo[d], hi = G.lo[d] + G.side;
+        const double lo = G.lo[d], hi = G.hi[d];
         if (k[d] == 0.0) {
             if (p0[d] < lo || p0[d] > hi) miss = true;
             continue;
@@ -252,144 +210,149 @@ __device__ __forceinline__ bool clip_ray(const WalkGrid &G, const double p0[3], 
     if (miss || !(tn < tf) || !(tf > 0.0) || ax < 0) return false;
     s = tn;
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-        const double lo = G.lo[d], hi = G.lo[d] + G.side;
-        if (d == ax) {
-            p[d] = k[d] > 0.0 ? lo : hi;
-        } else {
-            const double v = p0[d] + tn * k[d];
-            p[d] = v < lo ? lo : (v > hi ? hi : v);
-        }
-    }
+    for (int d = 0; d < 3; d++) p[d] = entry_coord(G, p0, k, tn, ax, d);
     return true;
 }
 
-// Everything a lane carries for one path.
-template <int PREC, typename R>
-struct Path {
-    using DsT = typename std::conditional<PREC == HG_FP64, double, float>::type;
-    double p0[3], k[3], ainv[3];
-    float ainv32[3];         // FP32 copies of ainv for the FP32 exit decision
-    double s, p[3];          // path length so far and the current entry point
-    double lo[3];            // lower corner of the current node
-    R ref;                   // current node (leaf once the descent ends)
-    int lv;                  // its level
-    int tie;                 // tie context of the pending descent
-    int dirb;                // direction signs (dir_bits)
-    int32_t cnt;             // leaves crossed with ds > 0
-    int steps;
-    double tau64;
-    float tau32, comp32;
-    bool force64;
-    int64_t base, room;      // record slice of this path (fill walk)
-    uint32_t sl[4];          // fill walk: last four records, staged for
-    DsT sd[4];               // 16-byte aligned vector stores
-};
 
-enum { PATH_WALK = 0, PATH_MISS = 1, PATH_BAD_DIR = 2 };
-// Walk modes: WM_COUNT (tau and counts; also the tau-only mode), WM_FILL
-// (records into the slices given by the offsets of a counting walk),
-// WM_SLAB (tau, counts and the first A.slab records of every path into a
-// fixed-size row per path, for the one-pass records mode).
-
-template <int TREE, int PREC, int WM, typename R>
-__device__ __forceinline__ int init_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Path<PREC, R> &P)
+// Node where the first descent toward q starts: the locate-table cell holding
+// q (chosen with the descent's rule for a point on a plane with no tie
+// context: the upper side unless the direction's component is negative),
+// its reference, level and integer corner; the root without a table.  The
+// descent from there takes the same decisions as one from the root: every
+// plane above the table level is a cell boundary, and the cell is picked by
+// exact comparisons with those planes.
+template <int TREE, typename R>
+__device__ __forceinline__ R start_node(const WalkGrid &G, const double q[3], const double k[3], int &lv,
+                                        uint32_t X[3])
 {
-    double inv[3];
+    if (G.tdep == 0) {
+        lv = 0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) X[d] = 0u;
+        return R(G.root);
+    }
+    const int T = 1 << G.tdep;
+    const double wc = ldexp(G.side, -G.tdep);
+    const double scale = ldexp(1.0, G.tdep) / G.side;
+    int c[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        P.p0[d] = A.O[3 * i + d];
-        P.k[d] = A.K[3 * i + d];
+        int i = int(floor((q[d] - G.lo[d]) * scale));
+        i = i < 0 ? 0 : (i > T - 1 ? T - 1 : i);
+        // (q - lo) may round: settle the cell by exact comparisons with its planes
+        if (i > 0 && q[d] < G.lo[d] + double(i) * wc) i--;
+        else if (i < T - 1 && q[d] >= G.lo[d] + double(i + 1) * wc) i++;
+        if (i > 0 && q[d] == G.lo[d] + double(i) * wc && k[d] < 0.0) i--;
+        c[d] = i;
     }
-    const double nn = P.k[0] * P.k[0] + P.k[1] * P.k[1] + P.k[2] * P.k[2];
-    const bool finite = isfinite(P.k[0]) && isfinite(P.k[1]) && isfinite(P.k[2]);
-    if (!finite || !(fabs(sqrt(nn) - 1.0) <= 1e-6)) return PATH_BAD_DIR;
-    P.force64 = false;
+    const R ref = static_cast<const R *>(G.table)[(int64_t(c[0]) * T + c[1]) * T + c[2]];
+    lv = Ref<R>::level(ref);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        inv[d] = 1.0 / P.k[d];
-        P.ainv[d] = fabs(inv[d]);
-        P.ainv32[d] = float(P.ainv[d]);
-        // The FP32 exit decision is used only where its error bound holds.
-        if (P.k[d] != 0.0 && !(fabs(P.k[d]) >= 1e-30)) P.force64 = true;
+        const int dep = axis_depth(TREE, lv, d);
+        X[d] = (uint32_t(c[d]) >> (G.tdep - dep)) << (G.dm - dep);
     }
-    if (!clip_ray(G, P.p0, P.k, inv, P.s, P.p)) return PATH_MISS;
-    P.dirb = dir_bits(P.k);
-    P.ref = start_node<TREE, R>(G, P.p, P.dirb, P.lv, P.lo);
-    P.tie = TIE_NONE;
-    P.cnt = 0;
-    P.steps = 0;
-    P.tau64 = 0.0;
-    P.tau32 = 0.f;
-    P.comp32 = 0.f;
-    if (WM == WM_FILL) {
-        P.base = A.offsets[i];
-        P.room = A.offsets[i + 1] - P.base;
-    } else if (WM == WM_SLAB) {
-        P.base = i * A.slab;
-        P.room = A.slab;
-    }
-    return PATH_WALK;
+    return ref;
 }
 
-// Fill walk of the one-walk records mode: path S.path continues from the
-// state the slab walk saved on entry to the leaf of its first record beyond
-// its row; records from there on go to its slice past the first A.slab.
+// Side of a split plane on axis d that holds an exit point lying exactly on
+// it (off the plane the comparison decides).  tie bit d: the point lies on
+// the low face of the leaf just left, bit 3 + d: on its high face (never set
+// for the crossed face's axis); such a plane keeps the point inside that
+// leaf's slab.  Otherwise the direction decides, a zero component going to the
+// upper side (for the crossed axis this is the side the path moves to).
+__device__ __forceinline__ bool tie_upper(int tie, double kd, int d)
+{
+    const bool onlo = (tie >> d) & 1;
+    const bool onhi = (tie >> (3 + d)) & 1;
+    return onhi ? false : (onlo ? true : !(kd < 0.0));
+}
+
+// The 32-byte record of leaf id (compact layout): six encoded ropes, then the
+// density (f32, or the low and high words of the f64 record's density).  An id
+// out of range reads record 0: the crossing reports the error.
+__device__ __forceinline__ void load_record(const WalkGrid &G, uint64_t id, uint32_t rec[8])
+{
+    const uint4 *q = static_cast<const uint4 *>(G.rec) + 2 * (id < G.n_leaves ? id : 0);
+    const uint4 a = q[0], b = q[1];
+    rec[0] = a.x; rec[1] = a.y; rec[2] = a.z; rec[3] = a.w;
+    rec[4] = b.x; rec[5] = b.y; rec[6] = b.z; rec[7] = b.w;
+}
+
+// True when the node reference may be descended: an internal node or a twin
+// inside the arrays, above the format's depth limit.
+template <int TREE, typename R>
+__device__ __forceinline__ bool descend_ok(const WalkGrid &G, R ref, int lv)
+{
+    const uint64_t id = Ref<R>::id(ref);
+    const int kind = Ref<R>::kind(ref);
+    const uint64_t nc = TREE == OCT ? 8 : 2;
+    return lv < 62 && ((kind == Ref<R>::INTERNAL && id < G.n_internal) ||
+                       (kind == Ref<R>::TWIN && id + nc <= G.n_leaves));
+}
+
+// One descent level from the internal or twin node L.ref toward the point
+// L.p: the child holding it, with its corner and level.  A twin's children
+// are leaves whose ranks follow its own; an internal node's child reference is
+// read from the child array.  Returns true when the child is known to be a
+// leaf now (a twin's), so its record can be read at once.
 template <int TREE, int PREC, typename R>
-__device__ __forceinline__ int64_t resume_path(const WalkArgs &A, const Resume &S, Path<PREC, R> &P)
+__device__ __forceinline__ bool descend_step(const WalkGrid &G, const LevelGeo *geo, Lane<PREC, R> &L)
 {
-    const int64_t i = S.path;
-    P.force64 = false;
+    const uint64_t id = Ref<R>::id(L.ref);
+    const bool tw = Ref<R>::twin(L.ref);
+    const LevelGeo &g = geo[L.lv];
+    const uint32_t hw = g.hw;
+    uint32_t slot;
+    if (TREE == KD) {
+        const int b = g.axis;
+        const uint32_t X0 = in_reg(L.X[0]), X1 = in_reg(L.X[1]), X2 = in_reg(L.X[2]);
+        const double q0 = in_reg(L.p[0]), q1 = in_reg(L.p[1]), q2 = in_reg(L.p[2]);
+        const uint32_t Xb = b == 0 ? X0 : (b == 1 ? X1 : X2);
+        const double qb = b == 0 ? q0 : (b == 1 ? q1 : q2);
+        const double lob = b == 0 ? G.lo[0] : (b == 1 ? G.lo[1] : G.lo[2]);
+        const double c = fma(double(Xb + hw), G.unit, lob);
+        bool up = qb > c;
+        const bool eq = qb == c;
+        if (__ballot(eq)) {
+            const double k0 = in_reg(L.k[0]), k1 = in_reg(L.k[1]), k2 = in_reg(L.k[2]);
+            const double kb = b == 0 ? k0 : (b == 1 ? k1 : k2);
+            if (eq) up = tie_upper(L.tie, kb, b);
+        }
+        slot = up ? 1u : 0u;
+        const uint32_t add = up ? hw : 0u;
+        L.X[0] = X0 + (b == 0 ? add : 0u);
+        L.X[1] = X1 + (b == 1 ? add : 0u);
+        L.X[2] = X2 + (b == 2 ? add : 0u);
+    } else {
+        slot = 0;
 #pragma unroll
-    for (int d = 0; d < 3; d++) {
-        P.p0[d] = A.O[3 * i + d];
-        P.k[d] = A.K[3 * i + d];
-        P.ainv[d] = fabs(1.0 / P.k[d]);
-        P.ainv32[d] = float(P.ainv[d]);
-        if (P.k[d] != 0.0 && !(fabs(P.k[d]) >= 1e-30)) P.force64 = true;
-        P.p[d] = S.p[d];
-        P.lo[d] = S.lo[d];
+        for (int d = 0; d < 3; d++) {
+            const double c = fma(double(L.X[d] + hw), G.unit, G.lo[d]);
+            bool up = L.p[d] > c;
+            const bool eq = L.p[d] == c;
+            if (__ballot(eq)) {
+                if (eq) up = tie_upper(L.tie, L.k[d], d);
+            }
+            slot |= (up ? 1u : 0u) << d;
+            L.X[d] += up ? hw : 0u;
+        }
     }
-    P.dirb = dir_bits(P.k);
-    P.s = S.s;
-    P.ref = R(S.ref);
-    P.lv = S.lv;
-    P.steps = S.steps;
-    P.tie = TIE_NONE;
-    P.cnt = 0;
-    P.tau64 = 0.0;
-    P.tau32 = 0.f;
-    P.comp32 = 0.f;
-    P.base = A.offsets[i] + A.slab;
-    P.room = A.offsets[i + 1] - P.base;
-    return i;
+    L.lv = L.lv + 1;
+    if (tw) {
+        L.ref = Ref<R>::make(Ref<R>::LEAF, L.lv, id + slot);
+    } else {
+        const uint64_t nc = TREE == OCT ? 8 : 2;
+        L.ref = static_cast<const R *>(G.child)[nc * id + slot];
+    }
+    return tw;
 }
 
-template <int PREC, typename R>
-__device__ __forceinline__ void save_resume(const WalkArgs &A, const Path<PREC, R> &P)
-{
-    if (!A.resume) return;   // a slab walk that only counts (the autotuner's)
-    const unsigned long long j = atomicAdd(A.n_resume, 1ull);
-    if (j >= (unsigned long long)A.n) return;   // at most one entry per path: never taken
-    Resume &S = A.resume[j];
-#pragma unroll
-    for (int d = 0; d < 3; d++) {
-        S.p[d] = P.p[d];
-        S.lo[d] = P.lo[d];
-    }
-    S.s = P.s;
-    S.ref = uint64_t(P.ref);
-    S.path = P.base / A.slab;
-    S.lv = P.lv;
-    S.steps = P.steps;
-}
-
-enum { STEP_GO = 0, STEP_END = 1, STEP_ERR = 2 };
-
-// Fill walk: records are staged four at a time and written as aligned 16-byte
-// vectors once a group of four positions (pos = 4m .. 4m+3 of the record
-// arrays, which must be 16-byte aligned) is complete; the partial groups at
-// the two ends of a path's slice are written element by element.
+// Records of the one-thread walk: staged four at a time and written as aligned
+// 16-byte vectors once a group of four positions (pos = 4m .. 4m+3 of the
+// record arrays, which must be 16-byte aligned) is complete; the partial
+// groups at the two ends of a path's slice are written element by element.
 template <int PREC>
 __device__ __forceinline__ void store_one(const WalkArgs &A, int64_t pos, uint32_t id, double ds)
 {
@@ -399,204 +362,245 @@ __device__ __forceinline__ void store_one(const WalkArgs &A, int64_t pos, uint32
 }
 
 template <int PREC, typename R>
-__device__ __forceinline__ void stage_record(const WalkArgs &A, Path<PREC, R> &P, int64_t pos, uint32_t id,
+__device__ __forceinline__ void stage_record(const WalkArgs &A, Lane<PREC, R> &L, int64_t pos, uint32_t id,
                                              double ds)
 {
-    P.sl[0] = P.sl[1]; P.sl[1] = P.sl[2]; P.sl[2] = P.sl[3]; P.sl[3] = id;
-    P.sd[0] = P.sd[1]; P.sd[1] = P.sd[2]; P.sd[2] = P.sd[3];
-    P.sd[3] = typename Path<PREC, R>::DsT(ds);
+    L.sl[0] = L.sl[1]; L.sl[1] = L.sl[2]; L.sl[2] = L.sl[3]; L.sl[3] = id;
+    L.sd[0] = L.sd[1]; L.sd[1] = L.sd[2]; L.sd[2] = L.sd[3];
+    L.sd[3] = typename Lane<PREC, R>::DsT(ds);
     if ((pos & 3) != 3) return;
     const int64_t g = pos - 3;
-    if (g >= P.base) {
-        *reinterpret_cast<uint4 *>(A.leaf + g) = make_uint4(P.sl[0], P.sl[1], P.sl[2], P.sl[3]);
+    if (g >= L.base) {
+        *reinterpret_cast<uint4 *>(A.leaf + g) = make_uint4(L.sl[0], L.sl[1], L.sl[2], L.sl[3]);
         if (PREC == HG_FP64) {
             double2 *d = reinterpret_cast<double2 *>(reinterpret_cast<double *>(A.ds) + g);
-            d[0] = make_double2(P.sd[0], P.sd[1]);
-            d[1] = make_double2(P.sd[2], P.sd[3]);
+            d[0] = make_double2(L.sd[0], L.sd[1]);
+            d[1] = make_double2(L.sd[2], L.sd[3]);
         } else {
             *reinterpret_cast<float4 *>(reinterpret_cast<float *>(A.ds) + g) =
-                make_float4(P.sd[0], P.sd[1], P.sd[2], P.sd[3]);
+                make_float4(L.sd[0], L.sd[1], L.sd[2], L.sd[3]);
         }
     } else {
 #pragma unroll
         for (int j = 0; j < 4; j++)
-            if (g + j >= P.base) store_one<PREC>(A, g + j, P.sl[j], P.sd[j]);
+            if (g + j >= L.base) store_one<PREC>(A, g + j, L.sl[j], L.sd[j]);
     }
 }
 
 // Write the staged records of an unfinished group at the end of a path.
 template <int PREC, typename R>
-__device__ __forceinline__ void flush_records(const WalkArgs &A, const Path<PREC, R> &P)
+__device__ __forceinline__ void flush_records(const WalkArgs &A, const Lane<PREC, R> &L)
 {
-    if (P.cnt == 0) return;
-    const int64_t last = P.base + (P.cnt < P.room ? P.cnt : P.room) - 1;
+    if (L.cnt == 0) return;
+    const int64_t last = L.base + (L.cnt < L.room ? L.cnt : L.room) - 1;
     const int ph = int(last & 3);
     if (ph == 3) return;
 #pragma unroll
     for (int j = 0; j < 3; j++) {
         const int64_t pos = last - j;
-        if (j <= ph && pos >= P.base) store_one<PREC>(A, pos, P.sl[3 - j], P.sd[3 - j]);
+        if (j <= ph && pos >= L.base) store_one<PREC>(A, pos, L.sl[3 - j], L.sd[3 - j]);
     }
 }
 
-// One crossing of the leaf P.ref: exit face, record / tau, re-anchoring, and
-// the rope target of the exit face (left in P.ref for the next descent).  The
-// exit face depends only on the cell and the entry point, so it is decided
-// before the leaf's record is read; then only the rope of that face and the
-// density are loaded.  Written with few branches: the end and error outcomes
-// are flags, and the state updates that only matter for a continuing path are
-// made unconditionally.
-template <int TREE, int PREC, int WM, typename R, bool LSLOT = false>
-__device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, Path<PREC, R> &P,
-                                     unsigned long long &rechecks, uint32_t *sl = nullptr,
-                                     typename Path<PREC, R>::DsT *sd = nullptr, int sgm = 0)
+// Slab walk: the state on entry to the leaf of the path's first record beyond
+// its row, from which the record-filling walk resumes it.  The slab walk
+// reaches that point once per path, so the entries never exceed the paths.
+template <int PREC, typename R>
+__device__ __forceinline__ void save_resume(const WalkArgs &A, int64_t path, const Lane<PREC, R> &L)
 {
-    const bool ok = ref_ok(G, P.ref);
-    const uint64_t id = ok ? Ref<R>::id(P.ref) : 0u;
-    int dep[3];
-    double w[3], hi[3], E[3], t[3];
-    int edge = 0;
-    const double *lo = P.lo;
-    level_geom<TREE>(G.lg, P.lv, dep, w);
+    if (!A.resume) return;   // a slab walk that only counts (the autotuner's)
+    const unsigned long long j = atomicAdd(A.n_resume, 1ull);
+    if (j >= (unsigned long long)A.n) return;
+    Resume &S = A.resume[j];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const bool kp = (P.dirb >> d) & 1;
-        hi[d] = lo[d] + w[d];
-        E[d] = kp ? hi[d] : lo[d];  // the face the path moves toward
-        // that face lies on the domain boundary
-        edge |= int(kp ? hi[d] == G.hi[d] : lo[d] == G.lo[d]) << d;
-        // t = Delta |1/k|; a zero direction component gives +inf or NaN, and
-        // neither ever wins the strict comparisons below
-        t[d] = fabs(E[d] - P.p[d]) * P.ainv[d];
+        S.p[d] = L.p[d];
+        S.X[d] = L.X[d];
     }
-    int a = -1;
-    if (PREC == HG_FP32_RECHECK) {
-        // smallest and second smallest exit time in FP32 (NaN counts as +inf);
-        // a tie between the two always goes to the FP64 decision below
+    S.s = L.s;
+    S.lv = L.lv;
+    S.ref = uint64_t(L.ref);
+    S.path = path;
+    S.steps = L.steps;
+    S.pad = 0;
+}
+
+// One crossing of the leaf L.ref: exit face and ds, tau, the record,
+// re-anchoring, and the rope target of the exit face (left in L.ref, with its
+// level and corner, for the next step).  sl / sd (LSLOT): the lane's record
+// slots in LDS, sgm their index mask; else records are staged in registers.
+template <int TREE, int PREC, int WM, typename R, bool LSLOT>
+__device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, const LevelGeo *geo,
+                                     Lane<PREC, R> &L, int64_t path, unsigned long long &rechecks,
+                                     uint32_t *sl, typename Lane<PREC, R>::DsT *sd)
+{
+    using DsT = typename Lane<PREC, R>::DsT;
+    const uint64_t id = Ref<R>::id(L.ref);
+    bool err = !(id < G.n_leaves);
+    // the record is read first: its load overlaps the exit decision
+    uint32_t rec[8];
+    if (sizeof(R) == 4) load_record(G, id, rec);
+    const LevelGeo &g = geo[L.lv];
+    double lo[3], hi[3], E[3];
+    bool kp[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        lo[d] = fma(double(L.X[d]), G.unit, G.lo[d]);   // exact: a plane of the grid
+        hi[d] = lo[d] + g.w[d];
+        kp[d] = L.k[d] > 0.0;
+        E[d] = kp[d] ? hi[d] : lo[d];                    // the face the path moves toward
+    }
+    // exit axis: the lowest axis of the smallest t = |E - p| |1/k| (a zero
+    // direction component gives +inf or NaN, which never wins)
+    bool a0, a1;
+    double ds;
+    if (PREC == HG_FP64) {
+        double t[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) t[d] = fabs(E[d] - L.p[d]) * L.ainv[d];
+        const double m = min64(t[0], min64(t[1], t[2]));
+        a0 = t[0] == m;
+        a1 = !a0 & (t[1] == m);
+        ds = m;
+    } else {
+        double D[3];
         float t32[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
-            const float v = float(fabs(E[d] - P.p[d])) * P.ainv32[d];
-            t32[d] = v == v ? v : INFINITY;
+            D[d] = E[d] - L.p[d];
+            t32[d] = fabsf(float(D[d])) * L.ainv32[d];
         }
-        const float m1 = fminf(fminf(t32[0], t32[1]), t32[2]);
-        const float m2 = __builtin_amdgcn_fmed3f(t32[0], t32[1], t32[2]);
-        const int i1 = t32[0] == m1 ? 0 : (t32[1] == m1 ? 1 : 2);
-        const float hmin = float(w[0]);  // axis 0 is never coarser than the others
-        const bool recheck = P.force64 || !(m2 - m1 >= 1e-5f * hmin);
-        rechecks += recheck ? 1u : 0u;
-        a = recheck ? -1 : i1;
-    }
-    if (a < 0) {
-        double tmin = INFINITY;
+        const float m1 = fminf(t32[0], fminf(t32[1], t32[2]));
+        a0 = t32[0] == m1;
+        a1 = !a0 & (t32[1] == m1);
+        // near tie: a second exit distance within the guard of the smallest
+        const float lim = m1 + g.guard;
+        const bool c0 = t32[0] < lim, c1 = t32[1] < lim, c2 = t32[2] < lim;
+        const bool recheck = L.force64 | (c0 & c1) | (c0 & c2) | (c1 & c2);
+        if (__ballot(recheck)) {
+            if (recheck) {
+                rechecks++;
+                double t[3];
 #pragma unroll
-        for (int d = 0; d < 3; d++)
-            if (t[d] < tmin) {
-                tmin = t[d];
-                a = d;
+                for (int d = 0; d < 3; d++) t[d] = fabs(D[d]) * L.ainv[d];
+                const double m = min64(t[0], min64(t[1], t[2]));
+                a0 = t[0] == m;
+                a1 = !a0 & (t[1] == m);
             }
+        }
+        // FP64 exit distance of the chosen axis only
+        const double D0 = in_reg(D[0]), D1 = in_reg(D[1]), D2 = in_reg(D[2]);
+        const double i0 = in_reg(L.ainv[0]), i1 = in_reg(L.ainv[1]), i2 = in_reg(L.ainv[2]);
+        const double Da = a0 ? D0 : (a1 ? D1 : D2);
+        const double ia = a0 ? i0 : (a1 ? i1 : i2);
+        ds = fabs(Da) * ia;
     }
-    bool err = !ok || a < 0;
-    a = a < 0 ? 0 : a;
-    const double t0 = in_reg(t[0]), t1 = in_reg(t[1]), t2 = in_reg(t[2]);
-    const double ds = a == 0 ? t0 : (a == 1 ? t1 : t2);
-    const bool up = (P.dirb >> a) & 1;
-    const int face = 2 * a + (up ? 1 : 0);
+    err = err | !(ds <= 1.0e300);
+    const bool a2 = !a0 & !a1;
+    const bool up = a0 ? kp[0] : (a1 ? kp[1] : kp[2]);
     // the leaf record: rope of the exit face, density
-    const char *rec = static_cast<const char *>(G.rec) + id * Rec<R, PREC>::STRIDE;
-    const R nref = reinterpret_cast<const R *>(rec)[face];
+    R nref;
+    float rho32;
+    double rho64;
+    if (sizeof(R) == 4) {
+        const uint32_t r0 = in_reg(rec[0]), r1 = in_reg(rec[1]), r2 = in_reg(rec[2]);
+        const uint32_t r3 = in_reg(rec[3]), r4 = in_reg(rec[4]), r5 = in_reg(rec[5]);
+        const uint32_t rl = a0 ? r0 : (a1 ? r2 : r4);
+        const uint32_t rh = a0 ? r1 : (a1 ? r3 : r5);
+        nref = R(up ? rh : rl);
+        rho32 = __uint_as_float(rec[6]);
+        rho64 = __hiloint2double(int(rec[7]), int(rec[6]));
+    } else {
+        const char *rec = static_cast<const char *>(G.rec) + (err ? 0 : id) * 64;
+        const int face = 2 * (a0 ? 0 : (a1 ? 1 : 2)) + (up ? 1 : 0);
+        nref = reinterpret_cast<const R *>(rec)[face];
+        rho64 = *reinterpret_cast<const double *>(rec + 48);
+        rho32 = *reinterpret_cast<const float *>(rec + 56);
+    }
     if (ds > 0.0) {
-        // LSLOT: records go to the lane's slots sl / sd in LDS (persistent
-        // and batched walks), else they are staged in registers
-        if (WM == WM_FILL) {
-            // the fill walk must repeat the counting walk
-            if (P.cnt < P.room) {
+        if (WM == WM_FILL || WM == WM_SLAB) {
+            if (L.cnt < L.room) {
                 if (LSLOT) {
-                    sl[P.cnt & sgm] = uint32_t(id);
-                    sd[P.cnt & sgm] = typename Path<PREC, R>::DsT(ds);
+                    sl[L.cnt & (SG - 1)] = uint32_t(id);
+                    sd[L.cnt & (SG - 1)] = DsT(ds);
                 } else {
-                    stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
+                    stage_record<PREC, R>(A, L, L.base + L.cnt, uint32_t(id), ds);
                 }
-            } else {
-                err = true;
-            }
-        } else if (WM == WM_SLAB) {
-            // records beyond the row are left to the fill walk, which resumes
-            // the path at the first of them
-            if (P.cnt < P.room) {
-                if (LSLOT) {
-                    sl[P.cnt & sgm] = uint32_t(id);
-                    sd[P.cnt & sgm] = typename Path<PREC, R>::DsT(ds);
-                } else {
-                    stage_record<PREC, R>(A, P, P.base + P.cnt, uint32_t(id), ds);
-                }
-            } else if (P.cnt == P.room) {
-                save_resume<PREC, R>(A, P);
+            } else if (WM == WM_FILL) {
+                err = true;   // the fill walk must repeat the counting walk
+            } else if (L.cnt == L.room) {
+                // records beyond the row are left to the fill walk, which resumes here
+                save_resume<PREC, R>(A, path, L);
             }
         }
-        if (WM == WM_FILL) {
-        } else if (PREC == HG_FP64) {
-            const double rho64 = *reinterpret_cast<const double *>(rec + Rec<R, PREC>::RHO64);
-            P.tau64 = P.tau64 + A.kappa * rho64 * ds;
-        } else {
-            const float rho32 = *reinterpret_cast<const float *>(rec + Rec<R, PREC>::RHO32);
-            const float y = float(A.kappa) * rho32 * float(ds) - P.comp32;
-            const float tt = P.tau32 + y;
-            P.comp32 = (tt - P.tau32) - y;
-            P.tau32 = tt;
+        if (PREC != HG_FP64 && WM != WM_FILL) {
+            const float y = float(A.kappa) * rho32 * float(ds) - L.comp32;
+            const float t = L.tau32 + y;
+            L.comp32 = (t - L.tau32) - y;
+            L.tau32 = t;
         }
-        P.cnt++;
+        L.cnt++;
     }
-    // exit face on the domain boundary: the path ends
-    const bool end = (edge >> a) & 1;
+    // FP64 tau: a zero-length step adds an exact zero
+    if (PREC == HG_FP64 && WM != WM_FILL) L.tau64 = L.tau64 + A.kappa * rho64 * ds;
+    // the exit face lies on the domain boundary: its rope is null and the path ends
+    const bool end = nref == Ref<R>::NUL;
     // re-anchor the exit point on the crossed face
-    P.s = P.s + ds;
-    int onlo = 0, onhi = 0;
+    L.s = L.s + ds;
+    double q[3];
+    bool hit = false;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const double v = P.p0[d] + P.s * P.k[d];
-        const double q = d == a ? E[d] : fmin(fmax(v, lo[d]), hi[d]);
-        onlo |= int(q == lo[d]) << d;
-        onhi |= int(q == hi[d]) << d;
-        P.p[d] = q;
+        const bool isa = d == 0 ? a0 : (d == 1 ? a1 : a2);
+        const double v = L.p0[d] + L.s * L.k[d];
+        const double c = min64(max64(v, lo[d]), hi[d]);
+        q[d] = isa ? E[d] : c;
+        hit = hit | (!isa & ((c == lo[d]) | (c == hi[d])));
     }
-    P.tie = a | (onlo << 2) | (onhi << 5);
-    err = err || (!end && nref == Ref<R>::NUL);
-    // Lower corner of the rope target: the corner of the leaf, moved across
-    // the exit face and aligned down to the target's cell size (exact).  The
-    // target is never finer than the leaf across the face; along the exit axis
-    // a k-d target may be one level finer (the half of a same-size neighbour
-    // touching the face).
+    // tie context of the descent from the rope target (rare: an exit point on
+    // an edge of the leaf)
+    int tie = 0;
+    if (__ballot(hit)) {
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            const bool isa = d == 0 ? a0 : (d == 1 ? a1 : a2);
+            tie |= int(!isa & (q[d] == lo[d])) << d;
+            tie |= int(!isa & (q[d] == hi[d])) << (3 + d);
+        }
+    }
+    L.tie = tie;
+    // Corner of the rope target: the leaf's corner moved across the exit face
+    // and aligned down to the target's cell size.  The target is never finer
+    // than the leaf across the face except along the exit axis, where it may
+    // be the half of a same-size neighbour touching the face.
     const int nlv = Ref<R>::level(nref);
-    int dn[3];
-    double wn[3];
-    level_geom<TREE>(G.lg, nlv, dn, wn);
-    double nlo[3];
+    const LevelGeo &gn = geo[nlv];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const double x = d != a ? lo[d] : (up ? hi[d] : lo[d] - fmin(w[d], wn[d]));
-        const double inv = pow2(dn[d] - G.lg);
-        nlo[d] = G.lo[d] + floor((x - G.lo[d]) * inv) * wn[d];
+        const bool isa = d == 0 ? a0 : (d == 1 ? a1 : a2);
+        const uint32_t Wn = gn.W[d];
+        const uint32_t delta = isa ? (kp[d] ? g.W[d] : 0u - Wn) : 0u;
+        L.X[d] = (L.X[d] + delta) & (0u - Wn);
+        L.p[d] = q[d];
     }
-#pragma unroll
-    for (int d = 0; d < 3; d++) P.lo[d] = nlo[d];
-    P.lv = nlv;
-    P.ref = nref;
+    L.lv = nlv;
+    L.ref = nref;
+
     return err ? STEP_ERR : (end ? STEP_END : STEP_GO);
 }
 
-template <int PREC, int WM, typename R, bool STG = false>
-__device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Path<PREC, R> &P)
+template <int PREC, int WM, typename R, bool STG>
+__device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const Lane<PREC, R> &L)
 {
     if (WM == WM_FILL) {
-        if (!STG) flush_records<PREC, R>(A, P);
-        if (P.cnt != P.room) A.st->step_guard = 1;
+        if (!STG) flush_records<PREC, R>(A, L);
+        if (L.cnt != L.room) A.st->step_guard = 1;
         return;
     }
-    if (WM == WM_SLAB && !STG) flush_records<PREC, R>(A, P);
-    A.count[i] = P.cnt;
-    if (PREC == HG_FP64) A.tau[i] = P.tau64;
-    else A.tau[i] = double(P.tau32) - double(P.comp32);
+    if (WM == WM_SLAB && !STG) flush_records<PREC, R>(A, L);
+    A.count[i] = L.cnt;
+    if (PREC == HG_FP64) A.tau[i] = L.tau64;
+    else A.tau[i] = double(L.tau32) - double(L.comp32);
 }
 
 template <int PREC, int WM>
@@ -612,39 +616,164 @@ __device__ __forceinline__ void finish_unwalked(const WalkArgs &A, int64_t i, in
     }
 }
 
+// Inverse direction |1/k| and the FP64-decision flag of direction k (the FP32
+// exit decision is used only where its error bound holds).
+__device__ __forceinline__ void inverse_dir(const double k[3], double ainv[3], bool &force64)
+{
+    force64 = false;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        ainv[d] = fabs(1.0 / k[d]);
+        if (k[d] != 0.0 && !(fabs(k[d]) >= 1e-30)) force64 = true;
+    }
+}
+
+// Prepare path i: direction check, inverse direction, entry point and the
+// node of its first descent.
+template <int TREE, typename R>
+__device__ __forceinline__ int prep_path(const WalkGrid &G, const WalkArgs &A, int64_t i, Prep &e)
+{
+    double p0[3], k[3], inv[3], p[3], s;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        p0[d] = A.O[3 * i + d];
+        k[d] = A.K[3 * i + d];
+    }
+    const double nn = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const bool finite = isfinite(k[0]) && isfinite(k[1]) && isfinite(k[2]);
+    if (!finite || !(fabs(sqrt(nn) - 1.0) <= 1e-6)) return PATH_BAD_DIR;
+    bool f64;
+    inverse_dir(k, e.ainv, f64);
+#pragma unroll
+    for (int d = 0; d < 3; d++) inv[d] = 1.0 / k[d];
+    int ax;
+    if (!clip_ray(G, p0, k, inv, s, p, ax)) return PATH_MISS;
+    int lv;
+    e.ref = uint64_t(start_node<TREE, R>(G, p, k, lv, e.X));
+    e.s = s;
+    e.lvf = uint32_t(lv) | (uint32_t(ax + 1) << 8) | (f64 ? (1u << 12) : 0u);
+    e.idx = int32_t(i);
+    e.pad = 0;
+    return PATH_WALK;
+}
+
+// Prepare resume entry j of the record-filling walk.
+__device__ __forceinline__ void prep_resume(const WalkArgs &A, int64_t j, Prep &e)
+{
+    const int64_t i = A.resume[j].path;
+    double k[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) k[d] = A.K[3 * i + d];
+    bool f64;
+    inverse_dir(k, e.ainv, f64);
+    e.s = 0.0;
+    e.X[0] = e.X[1] = e.X[2] = 0u;
+    e.lvf = f64 ? (1u << 12) : 0u;
+    e.ref = 0;
+    e.idx = int32_t(j);
+    e.pad = 0;
+}
+
+// A lane takes up a prepared path: returns its path index.
+template <int WM, int PREC, typename R>
+__device__ __forceinline__ int64_t take_path(const WalkGrid &G, const WalkArgs &A, const Prep &e,
+                                             Lane<PREC, R> &L)
+{
+    const bool resumed = WM == WM_FILL && A.resume;
+    int64_t i = e.idx;
+    if (resumed) {
+        const Resume &S = A.resume[e.idx];
+        i = S.path;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            L.p[d] = S.p[d];
+            L.X[d] = S.X[d];
+        }
+        L.s = S.s;
+        L.ref = R(S.ref);
+        L.lv = S.lv;
+        L.steps = S.steps;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        L.p0[d] = A.O[3 * i + d];
+        L.k[d] = A.K[3 * i + d];
+        L.ainv[d] = e.ainv[d];
+        L.ainv32[d] = float(e.ainv[d]);
+    }
+    L.force64 = (e.lvf >> 12) & 1u;
+    if (!resumed) {
+        const int ax = int((e.lvf >> 8) & 15u) - 1;
+        L.s = e.s;
+        if (ax < 0) {
+#pragma unroll
+            for (int d = 0; d < 3; d++) L.p[d] = L.p0[d];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; d++) L.p[d] = entry_coord(G, L.p0, L.k, e.s, ax, d);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; d++) L.X[d] = e.X[d];
+        L.ref = R(e.ref);
+        L.lv = int(e.lvf & 255u);
+        L.steps = 0;
+    }
+    L.tie = 0;
+    L.cnt = 0;
+    L.tau64 = 0.0;
+    L.tau32 = 0.f;
+    L.comp32 = 0.f;
+    if (WM == WM_FILL) {
+        L.base = A.offsets[i] + (resumed ? A.slab : 0);
+        L.room = A.offsets[i + 1] - L.base;
+    } else if (WM == WM_SLAB) {
+        L.base = i * A.slab;
+        L.room = A.slab;
+    }
+    return i;
+}
+
 // One lane per path, the whole walk in one loop.
 template <int TREE, int PREC, int WM, typename R>
 __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 {
+    __shared__ LevelGeo geo[NLEV];
+    fill_levels(geo, G, threadIdx.x, TB);
+    __syncthreads();
     const int64_t q = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (q >= A.n) return;
-    Path<PREC, R> P;
-    int64_t i = q;
-    int why = PATH_WALK;
-    if (WM == WM_FILL && A.resume) i = resume_path<TREE, PREC, R>(A, A.resume[q], P);
-    else why = init_path<TREE, PREC, WM, R>(G, A, i, P);
-    if (why != PATH_WALK) {
-        finish_unwalked<PREC, WM>(A, i, why);
-        return;
+    Prep e;
+    if (WM == WM_FILL && A.resume) {
+        prep_resume(A, q, e);
+    } else {
+        const int why = prep_path<TREE, R>(G, A, q, e);
+        if (why != PATH_WALK) {
+            finish_unwalked<PREC, WM>(A, q, why);
+            return;
+        }
     }
+    Lane<PREC, R> L;
+    const int64_t i = take_path<WM, PREC, R>(G, A, e, L);
     unsigned long long rechecks = 0;
-    uint32_t desc = 0;   // child levels descended
+    uint32_t desc = 0;   // descent levels
     for (;;) {
-        const int lv0 = P.lv;
-        P.ref = descend<TREE, R>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
-        desc += uint32_t(P.lv - lv0);
-        if (P.ref == Ref<R>::NUL) {
-            A.st->bad_ref = 1;
-            break;
+        if (Ref<R>::leaf(L.ref)) {
+            const int r = cross<TREE, PREC, WM, R, false>(G, A, geo, L, i, rechecks, nullptr, nullptr);
+            if (r == STEP_ERR || ++L.steps >= STEP_GUARD) {
+                A.st->step_guard = 1;
+                break;
+            }
+            if (r == STEP_END) break;
+        } else {
+            if (!descend_ok<TREE, R>(G, L.ref, L.lv)) {
+                A.st->bad_ref = 1;
+                break;
+            }
+            descend_step<TREE, PREC, R>(G, geo, L);
+            desc++;
         }
-        const int r = cross<TREE, PREC, WM, R>(G, A, P, rechecks);
-        if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
-            A.st->step_guard = 1;
-            break;
-        }
-        if (r == STEP_END) break;
     }
-    finish_path<PREC, WM, R>(A, i, P);
+    finish_path<PREC, WM, R, false>(A, i, L);
     if (!(WM == WM_FILL) && A.count_rechecks) {
         if (rechecks) atomicAdd(&A.st->rechecks, rechecks);
         if (desc) atomicAdd(&A.st->descents, (unsigned long long)desc);
@@ -655,28 +784,23 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
 // each lane owns SG slots of leaf ids and SG of ds (rows of SG + 1 words
 // against bank conflicts).  A lane's group is written out once it holds SG
 // records, its row or slice is full or its path ends, by the whole
-// wavefront: SG lanes per group,
-// 64 / SG groups per store instruction, so that a store covers a few cache
-// lines instead of one line per lane.
-template <int BT>
-struct StageShape {
-    static constexpr int SG = BT <= 256 ? 16 : 8;
-    static constexpr int SP = SG + 1;
-};
+// wavefront: SG lanes per group, 64 / SG groups per store instruction, so
+// that a store covers a few cache lines instead of one line per lane.
+constexpr int SP = SG + 1;
 
 // Write the groups of the lanes with nr > 0: records pos .. pos+nr-1 of the
 // output come from slots 0 .. nr-1 of that lane (into the rows of (leaf, ds)
-// pairs when A.pairs is set).  Wavefront-uniform.
-template <int BT, typename DsT>
+// pairs when A.pairs is set).  Wavefront-uniform; wbase is the wavefront's
+// first thread in the block.
+template <typename DsT>
 __device__ __forceinline__ void flush_stage(const WalkArgs &A, const uint32_t *stl, const DsT *stds, int nr,
-                                            int64_t pos, int lane)
+                                            int64_t pos, int lane, int wbase)
 {
-    constexpr int SG = StageShape<BT>::SG, SP = StageShape<BT>::SP, PER = 64 / SG;
+    constexpr int PER = 64 / SG;
     uint64_t fm = __ballot(nr > 0);
     if (!fm) return;
     __builtin_amdgcn_wave_barrier();
     const int g = lane / SG, j = lane % SG;
-    const int wbase = int(threadIdx.x) & ~63;
     while (fm) {
         int src = -1;
 #pragma unroll
@@ -702,132 +826,169 @@ __device__ __forceinline__ void flush_stage(const WalkArgs &A, const uint32_t *s
     }
 }
 
-// Persistent walk: each wavefront keeps its lanes busy by handing new paths
-// to lanes whose path ended.  Refills happen in batches (once at least
-// refill_min lanes are idle, or none is busy) from a wavefront-local chunk of
-// paths taken with one atomic on the global path counter, so the divergent
-// path set-up and the atomic round trip are amortised over many paths.  Each
-// iteration a busy lane performs one dependent global access: a descent step
-// (the first levels of every descent come from LDS) or a crossing.
-// Four wavefronts per SIMD: the record modes would otherwise take a few more
-// than 128 VGPRs and run three (the few spills this costs are cheaper).
-template <int TREE, int PREC, int WM, typename R, int BT>
-__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
-    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t lds_n, uint32_t chunk, int refill_min,
-                      uint32_t stage_off)
+// The group of LDS-staged records a lane writes out after a step: complete
+// (SG records), the row or slice full, or the last records of an ended path.
+template <int PREC, typename R>
+__device__ __forceinline__ void stage_group(const Lane<PREC, R> &L, bool crossed, int32_t c_before, bool ended,
+                                            int &nr, int64_t &pos)
 {
-    extern __shared__ uint64_t lds_raw[];
-    R *lds = reinterpret_cast<R *>(lds_raw);
-    const int nc = TREE == OCT ? 8 : 2;
-    for (uint32_t j = threadIdx.x; j < lds_n * nc; j += BT) lds[j] = static_cast<const R *>(G.child)[j];
+    const int64_t c = L.cnt < L.room ? L.cnt : L.room;
+    const bool wrote = crossed && L.cnt > c_before && c_before < L.room;
+    nr = 0;
+    if (wrote && ((c & (SG - 1)) == 0 || c == L.room)) nr = int(((c - 1) & (SG - 1)) + 1);
+    else if (ended && c != L.room) nr = int(c & (SG - 1));
+    pos = L.base + c - nr;
+}
+
+// One step of a busy lane: a crossing if its node is a leaf, then (if the path
+// goes on into a node that is not a leaf) one descent level.  Returns true
+// when the path ended (or failed); crossed / c_before / bad describe the step
+// for the record staging.
+template <int TREE, int PREC, int WM, typename R, bool STG>
+__device__ __forceinline__ bool walk_step(const WalkGrid &G, const WalkArgs &A, const LevelGeo *geo,
+                                          Lane<PREC, R> &L, int64_t ray, unsigned long long &rechecks,
+                                          uint32_t &desc, uint32_t *my_l, typename Lane<PREC, R>::DsT *my_d,
+                                          bool &crossed, int32_t &c_before, bool &bad)
+{
+    int r = STEP_GO;
+    crossed = false;
+    bad = false;
+    c_before = L.cnt;
+    if (Ref<R>::leaf(L.ref)) {
+        r = cross<TREE, PREC, WM, R, STG>(G, A, geo, L, ray, rechecks, my_l, my_d);
+        crossed = true;
+        if (r == STEP_ERR || ++L.steps >= STEP_GUARD) {
+            A.st->step_guard = 1;
+            r = STEP_ERR;
+        }
+    }
+    if (r == STEP_GO && !Ref<R>::leaf(L.ref)) {
+        if (!descend_ok<TREE, R>(G, L.ref, L.lv)) {
+            bad = true;
+        } else {
+            descend_step<TREE, PREC, R>(G, geo, L);
+            desc++;
+        }
+    }
+    return bad || r != STEP_GO;
+}
+
+// Fill the wavefront's queue with the prepared paths among [cnext, cnext+64)
+// of [cnext, cend) (all lanes take part); paths that miss the domain or have
+// an invalid direction are finished here.  Returns the number queued.
+template <int TREE, int PREC, int WM, typename R>
+__device__ __forceinline__ int fill_queue(const WalkGrid &G, const WalkArgs &A, Prep *ring, int64_t cnext,
+                                          int64_t cend, int lane, uint64_t below)
+{
+    const int64_t i = cnext + lane;
+    Prep e;
+    bool ok = false;
+    if (i < cend) {
+        if (WM == WM_FILL && A.resume) {
+            prep_resume(A, i, e);
+            ok = true;
+        } else {
+            const int why = prep_path<TREE, R>(G, A, i, e);
+            ok = why == PATH_WALK;
+            if (!ok) finish_unwalked<PREC, WM>(A, i, why);
+        }
+    }
+    const uint64_t okm = __ballot(ok);
+    if (ok) ring[__popcll(okm & below)] = e;
+    // the entries are read by other lanes of the same wavefront
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return __popcll(okm);
+}
+
+__device__ __forceinline__ unsigned long long readfirstlane64(unsigned long long v)
+{
+    return (unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(v)) |
+           ((unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(v >> 32)) << 32);
+}
+
+// Persistent walk: each wavefront keeps its lanes busy by handing prepared
+// paths to lanes whose path ended.  A wavefront takes `chunk` paths per
+// atomic on the global path counter and prepares them 64 at a time into its
+// LDS queue; lanes take queued paths once at least refill_min lanes are idle
+// (or none is busy).  Each iteration a busy lane crosses its leaf and, if the
+// path goes on into a node that is not a leaf, descends one level.
+template <int TREE, int PREC, int WM, typename R, int BT>
+__global__ void __launch_bounds__(BT)
+    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t chunk, int refill_min)
+{
+    using DsT = typename Lane<PREC, R>::DsT;
+    constexpr bool STG = WM != WM_COUNT;
+    constexpr int NW = BT / 64;
+    __shared__ LevelGeo geo[NLEV];
+    __shared__ Prep ring_all[NW * RING];
+    __shared__ uint32_t stl[STG ? BT * SP : 1];
+    __shared__ DsT stds[STG ? BT * SP : 1];
+    fill_levels(geo, G, threadIdx.x, BT);
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    // record modes: LDS staging of the records (see flush_stage)
-    constexpr bool STG = WM != WM_COUNT;
-    constexpr int SG = StageShape<BT>::SG, SP = StageShape<BT>::SP;
-    using DsT = typename Path<PREC, R>::DsT;
-    uint32_t *stl = nullptr, *my_l = nullptr;
-    DsT *stds = nullptr, *my_d = nullptr;
-    if (STG) {
-        char *sb = reinterpret_cast<char *>(lds_raw) + stage_off;
-        stl = reinterpret_cast<uint32_t *>(sb);
-        stds = reinterpret_cast<DsT *>(sb + size_t(BT) * SP * 4);
-        my_l = stl + threadIdx.x * SP;
-        my_d = stds + threadIdx.x * SP;
-    }
+    const int wid = threadIdx.x >> 6;
+    Prep *ring = ring_all + wid * RING;
+    uint32_t *my_l = stl + threadIdx.x * SP;
+    DsT *my_d = stds + threadIdx.x * SP;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    Path<PREC, R> P;
+    Lane<PREC, R> L;
     int64_t ray = -1;
     bool done = false;
-    uint32_t cnext = 0, cend = 0;   // wavefront-local chunk [cnext, cend)
-    bool drained = false;           // the global counter is exhausted
+    int rhead = 0, rn = 0;           // the wavefront's queue [rhead, rn)
+    int64_t cnext = 0, cend = 0;     // its paths not yet prepared
+    bool drained = false;            // the global counter is exhausted
     unsigned long long rechecks = 0;
-    uint32_t desc = 0;   // child levels descended
+    uint32_t desc = 0;
     for (;;) {
         const bool want = ray < 0 && !done;
         const uint64_t wmask = __ballot(want);
-        const uint64_t amask = __ballot(ray >= 0);
-        const int nwant = __popcll(wmask);
-        if (nwant && (nwant >= refill_min || !amask)) {
-            if (cnext >= cend && !drained) {
-                unsigned long long b = 0;
-                if (lane == 0) b = atomicAdd(&A.st->next_ray, (unsigned long long)chunk);
-                // wavefront-uniform from here on
-                b = (unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(b)) |
-                    ((unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(b >> 32)) << 32);
-                if (b >= (unsigned long long)A.n) {
-                    drained = true;
-                    cnext = cend = 0;
-                } else {
-                    cnext = uint32_t(b);
-                    cend = uint32_t(std::min<int64_t>(int64_t(b) + chunk, A.n));
+        if (wmask) {
+            const uint64_t amask = __ballot(ray >= 0);
+            const int nwant = __popcll(wmask);
+            if (nwant >= refill_min || !amask) {
+                while (rhead >= rn && !(drained && cnext >= cend)) {
+                    if (cnext >= cend) {
+                        unsigned long long b = 0;
+                        if (lane == 0) b = atomicAdd(&A.st->next_ray, (unsigned long long)chunk);
+                        b = readfirstlane64(b);
+                        if (b >= (unsigned long long)A.n) {
+                            drained = true;
+                        } else {
+                            cnext = int64_t(b);
+                            cend = std::min<int64_t>(int64_t(b) + chunk, A.n);
+                        }
+                        continue;
+                    }
+                    rn = fill_queue<TREE, PREC, WM, R>(G, A, ring, cnext, cend, lane, below);
+                    rhead = 0;
+                    cnext = std::min<int64_t>(cnext + 64, cend);
                 }
-            }
-            const uint32_t avail = cend - cnext;
-            if (want) {
-                const uint32_t rank = uint32_t(__popcll(wmask & below));
-                if (rank < avail) {
-                    const int64_t q = int64_t(cnext) + rank;
-                    int64_t r = q;
-                    int why = PATH_WALK;
-                    if (WM == WM_FILL && A.resume) r = resume_path<TREE, PREC, R>(A, A.resume[q], P);
-                    else why = init_path<TREE, PREC, WM, R>(G, A, r, P);
-                    if (why == PATH_WALK) ray = r;
-                    else finish_unwalked<PREC, WM>(A, r, why);
-                } else if (drained) {
-                    done = true;
+                const int avail = rn - rhead;
+                if (want) {
+                    const int rank = __popcll(wmask & below);
+                    if (rank < avail) ray = take_path<WM, PREC, R>(G, A, ring[rhead + rank], L);
+                    else if (drained && cnext >= cend) done = true;
                 }
+                rhead += std::min(avail, nwant);
             }
-            cnext += std::min<uint32_t>(avail, uint32_t(nwant));
         }
-        if (!amask && !__ballot(ray >= 0)) {
-            if (!__ballot(!done)) break;
-            continue;
-        }
-        // One predicate per region (no nesting), so the path state needs no
-        // copies at region boundaries.
-        bool bad = false, fin = false, crossed = false;
+        if (!__ballot(ray >= 0) && !__ballot(!done)) break;
+        bool fin = false, crossed = false, bad = false;
         int32_t c_before = 0;
-        if (ray >= 0 && !Ref<R>::leaf(P.ref)) {
-            // LDS levels, then at most one global level this iteration
-            const int lv0 = P.lv;
-            for (;;) {
-                if (!ref_ok(G, P.ref) || P.lv >= 62) {
-                    P.ref = Ref<R>::NUL;
-                    break;
-                }
-                const bool global = Ref<R>::id(P.ref) >= lds_n;
-                P.ref = child_of<TREE, R>(G, lds, lds_n, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
-                if (global || Ref<R>::leaf(P.ref)) break;
-            }
-            bad = P.ref == Ref<R>::NUL || (Ref<R>::leaf(P.ref) && !ref_ok(G, P.ref));
-            desc += uint32_t(P.lv - lv0);
-        }
-        if (ray >= 0 && !bad && Ref<R>::leaf(P.ref)) {
-            c_before = P.cnt;
-            const int r = cross<TREE, PREC, WM, R, STG>(G, A, P, rechecks, my_l, my_d, SG - 1);
-            crossed = true;
-            const bool guard = r == STEP_ERR || ++P.steps >= STEP_GUARD;
-            if (guard) A.st->step_guard = 1;
-            fin = guard || r == STEP_END;
-        }
+        if (ray >= 0)
+            fin = walk_step<TREE, PREC, WM, R, STG>(G, A, geo, L, ray, rechecks, desc, my_l, my_d, crossed,
+                                                    c_before, bad);
         if (STG) {
-            // the group to write out this iteration: complete, the row full, or
-            // the last records of an ended path
             int nr = 0;
             int64_t pos = 0;
-            if (ray >= 0 && (crossed || bad)) {
-                const int64_t c = P.cnt < P.room ? P.cnt : P.room;
-                const bool wrote = crossed && P.cnt > c_before && c_before < P.room;
-                if (wrote && ((c & (SG - 1)) == 0 || c == P.room)) nr = int(((c - 1) & (SG - 1)) + 1);
-                else if ((bad || fin) && c != P.room) nr = int(c & (SG - 1));
-                pos = P.base + c - nr;
-            }
-            flush_stage<BT, DsT>(A, stl, stds, nr, pos, lane);
+            if (ray >= 0 && (crossed || bad)) stage_group<PREC, R>(L, crossed, c_before, fin, nr, pos);
+            flush_stage<DsT>(A, stl, stds, nr, pos, lane, wid * 64);
         }
-        if (bad || fin) {
+        if (fin) {
             if (bad) A.st->bad_ref = 1;
-            finish_path<PREC, WM, R, STG>(A, ray, P);
+            finish_path<PREC, WM, R, STG>(A, ray, L);
             ray = -1;
         }
     }
@@ -837,119 +998,77 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
     }
 }
 
-// The group of LDS-staged records a lane writes out after a step: complete
-// (SG records), the row or slice full, or the last records of an ended path.
-template <int SG, int PREC, typename R>
-__device__ __forceinline__ void stage_group(const Path<PREC, R> &P, bool crossed, int32_t c_before,
-                                            bool ended, int &nr, int64_t &pos)
-{
-    const int64_t c = P.cnt < P.room ? P.cnt : P.room;
-    const bool wrote = crossed && P.cnt > c_before && c_before < P.room;
-    nr = 0;
-    if (wrote && ((c & (SG - 1)) == 0 || c == P.room)) nr = int(((c - 1) & (SG - 1)) + 1);
-    else if (ended && c != P.room) nr = int(c & (SG - 1));
-    pos = P.base + c - nr;
-}
-
-// One step of a busy lane in the batched walk: at most one global descent
-// level, or one crossing.  Returns false when the path ended (or failed).
-// With LDS staging (sl != nullptr) the records go to the lane's slots and
-// nr / pos name the group to write out after the step.
-template <int TREE, int PREC, int WM, int SG>
-__device__ __forceinline__ bool batched_step(const WalkGrid &G, const WalkArgs &A,
-                                             Path<PREC, uint32_t> &P, int64_t ray,
-                                             unsigned long long &rechecks, uint32_t &desc, uint32_t *sl,
-                                             typename Path<PREC, uint32_t>::DsT *sd, int &nr, int64_t &pos)
-{
-    constexpr bool STG = SG > 0;
-    bool crossed = false, ended = false;
-    int32_t c_before = 0;
-    if (!Ref<uint32_t>::leaf(P.ref)) {
-        if (!ref_ok(G, P.ref) || P.lv >= 62) {
-            A.st->bad_ref = 1;
-            ended = true;
-        } else {
-            P.ref = child_of<TREE, uint32_t>(G, nullptr, 0u, P.ref, P.lv, P.lo, P.p, P.dirb, P.tie);
-            desc++;
-            if (Ref<uint32_t>::leaf(P.ref) && !ref_ok(G, P.ref)) {
-                A.st->bad_ref = 1;
-                ended = true;
-            }
-        }
-    }
-    if (!ended && Ref<uint32_t>::leaf(P.ref)) {
-        c_before = P.cnt;
-        const int r = cross<TREE, PREC, WM, uint32_t, STG>(G, A, P, rechecks, sl, sd, STG ? SG - 1 : 0);
-        crossed = true;
-        if (r == STEP_ERR || ++P.steps >= STEP_GUARD) {
-            A.st->step_guard = 1;
-            ended = true;
-        } else if (r == STEP_END) {
-            ended = true;
-        }
-    }
-    if (STG) stage_group<STG ? SG : 1>(P, crossed, c_before, ended, nr, pos);
-    if (ended) finish_path<PREC, WM, uint32_t, STG>(A, ray, P);
-    return !ended;
-}
-
 // Batched walk over many grids in one persistent launch.  The device work
 // queue is a table of chunks (grid, path range); a wavefront takes one chunk
-// per atomic and keeps that grid's parameters uniform across its lanes,
-// refilling lanes from the chunk.  Before taking up a chunk of another grid it
-// lets its lanes finish their paths.  Octree and k-d grids mix freely: the
-// tree type is a wavefront-uniform branch.
+// per atomic and keeps that grid's parameters (and its level table)
+// uniform across its lanes, preparing the chunk's paths into its queue.
+// Before taking up a chunk of another grid it lets its lanes finish their
+// paths.  Octree and k-d grids mix freely: the tree type is a
+// wavefront-uniform branch.
 template <int PREC, int WM, int BT>
 __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                                              const BatchChunk *__restrict__ chunks, int n_chunks,
-                                             int refill_min, TraceStatus *st, char *lds_stage)
+                                             int refill_min, TraceStatus *st, LevelGeo *geo_all, Prep *ring_all,
+                                             uint32_t *stl, typename Lane<PREC, uint32_t>::DsT *stds)
 {
-    const int lane = threadIdx.x & 63;
-    // the record-filling walk stages its records in LDS (see flush_stage)
+    using R = uint32_t;
+    using DsT = typename Lane<PREC, R>::DsT;
     constexpr bool STG = WM == WM_FILL;
-    constexpr int SP = StageShape<BT>::SP;
-    using DsT = typename Path<PREC, uint32_t>::DsT;
-    uint32_t *stl = nullptr, *my_l = nullptr;
-    DsT *stds = nullptr, *my_d = nullptr;
-    if (STG) {
-        char *sb = lds_stage;
-        stl = reinterpret_cast<uint32_t *>(sb);
-        stds = reinterpret_cast<DsT *>(sb + size_t(BT) * SP * 4);
-        my_l = stl + threadIdx.x * SP;
-        my_d = stds + threadIdx.x * SP;
-    }
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    LevelGeo *geo = geo_all + wid * NLEV;
+    Prep *ring = ring_all + wid * RING;
+    uint32_t *my_l = STG ? stl + threadIdx.x * SP : nullptr;
+    DsT *my_d = STG ? stds + threadIdx.x * SP : nullptr;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    Path<PREC, uint32_t> P;
+    Lane<PREC, R> L;
     int64_t ray = -1;
     bool done = false;
-    int gi = -1, pc = -1;
+    int gi = -1, pc = -1;            // current grid, pending chunk
     int64_t cnext = 0, cend = 0;
     bool drained = false;
+    int rhead = 0, rn = 0;
+    int geo_tree = -1, geo_dm = -1;  // what the wavefront's level table was made for
+    double geo_side = 0.0;
     WalkGrid G;
     WalkArgs A;
     unsigned long long rechecks = 0;
-    uint32_t desc = 0;   // child levels descended
+    uint32_t desc = 0;
+    bool count_rechecks = false;
     for (;;) {
         const bool want = ray < 0 && !done;
         const uint64_t wmask = __ballot(want);
-        const uint64_t amask = __ballot(ray >= 0);
-        const int nwant = __popcll(wmask);
-        if (nwant && (nwant >= refill_min || !amask)) {
-            if (cnext >= cend) {
-                if (pc < 0 && !drained) {
-                    int c = 0;
-                    if (lane == 0) c = int(std::min<unsigned long long>(atomicAdd(&st->next_ray, 1ull), 0x7fffffffull));
-                    c = __builtin_amdgcn_readfirstlane(c);   // wavefront-uniform from here on
-                    if (c >= n_chunks) drained = true;
-                    else pc = c;
-                }
-                if (pc >= 0) {
-                    const int cg = __builtin_amdgcn_readfirstlane(chunks[pc].grid);
-                    if (cg == gi || !amask) {
+        if (wmask) {
+            const uint64_t amask = __ballot(ray >= 0);
+            const int nwant = __popcll(wmask);
+            if (nwant >= refill_min || !amask) {
+                while (rhead >= rn) {
+                    if (cnext >= cend) {
+                        if (pc < 0 && !drained) {
+                            int c = 0;
+                            if (lane == 0)
+                                c = int(std::min<unsigned long long>(atomicAdd(&st->next_ray, 1ull), 0x7fffffffull));
+                            c = __builtin_amdgcn_readfirstlane(c);
+                            if (c >= n_chunks) drained = true;
+                            else pc = c;
+                        }
+                        if (pc < 0) break;
+                        const int cg = __builtin_amdgcn_readfirstlane(chunks[pc].grid);
+                        if (cg != gi && amask) break;   // let this grid's paths finish first
                         if (cg != gi) {
                             gi = cg;
                             G = grids[gi];
                             A = args[gi];
+                            count_rechecks = count_rechecks || A.count_rechecks;
+                            if (G.tree != geo_tree || G.dm != geo_dm || G.side != geo_side) {
+                                fill_levels(geo, G, lane, 64);
+                                geo_tree = G.tree;
+                                geo_dm = G.dm;
+                                geo_side = G.side;
+                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                                __builtin_amdgcn_wave_barrier();
+                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                            }
                         }
                         cnext = chunks[pc].start;
                         cend = chunks[pc].end;
@@ -959,85 +1078,105 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
                             if (lane == 0) st->cap_overflow = 1;
                             cnext = cend;
                         }
+                        continue;
                     }
+                    rn = G.tree == KD ? fill_queue<KD, PREC, WM, R>(G, A, ring, cnext, cend, lane, below)
+                                      : fill_queue<OCT, PREC, WM, R>(G, A, ring, cnext, cend, lane, below);
+                    rhead = 0;
+                    cnext = std::min<int64_t>(cnext + 64, cend);
                 }
-            }
-            const int64_t avail = cend - cnext;
-            if (want) {
-                const int64_t rank = __popcll(wmask & below);
-                if (rank < avail) {
-                    const int64_t r = cnext + rank;
-                    const int why = G.tree == KD ? init_path<KD, PREC, WM, uint32_t>(G, A, r, P)
-                                                 : init_path<OCT, PREC, WM, uint32_t>(G, A, r, P);
-                    if (why == PATH_WALK) ray = r;
-                    else finish_unwalked<PREC, WM>(A, r, why);
-                } else if (drained && pc < 0) {
-                    done = true;
+                const int avail = rn - rhead;
+                if (want) {
+                    const int rank = __popcll(wmask & below);
+                    if (rank < avail) ray = take_path<WM, PREC, R>(G, A, ring[rhead + rank], L);
+                    else if (drained && pc < 0 && cnext >= cend) done = true;
                 }
+                rhead += std::min(avail, nwant);
             }
-            cnext += std::min<int64_t>(avail, nwant);
         }
-        if (!amask && !__ballot(ray >= 0)) {
+        if (!__ballot(ray >= 0)) {
             if (!__ballot(!done)) break;
             continue;
         }
-        constexpr int SGS = STG ? StageShape<BT>::SG : 0;
-        int nr = 0;
-        int64_t pos = 0;
-        if (ray >= 0) {
-            const bool alive =
-                G.tree == KD ? batched_step<KD, PREC, WM, SGS>(G, A, P, ray, rechecks, desc, my_l, my_d, nr, pos)
-                             : batched_step<OCT, PREC, WM, SGS>(G, A, P, ray, rechecks, desc, my_l, my_d, nr, pos);
-            if (!alive) ray = -1;
-        }
+        bool fin = false, crossed = false, bad = false;
+        int32_t c_before = 0;
+        if (ray >= 0)
+            fin = G.tree == KD ? walk_step<KD, PREC, WM, R, STG>(G, A, geo, L, ray, rechecks, desc, my_l, my_d,
+                                                                 crossed, c_before, bad)
+                               : walk_step<OCT, PREC, WM, R, STG>(G, A, geo, L, ray, rechecks, desc, my_l, my_d,
+                                                                  crossed, c_before, bad);
         // every lane holds the wavefront's current grid, so A is uniform here
-        if (STG) flush_stage<BT, DsT>(A, stl, stds, nr, pos, lane);
+        if (STG) {
+            int nr = 0;
+            int64_t pos = 0;
+            if (ray >= 0 && (crossed || bad)) stage_group<PREC, R>(L, crossed, c_before, fin, nr, pos);
+            flush_stage<DsT>(A, stl, stds, nr, pos, lane, wid * 64);
+        }
+        if (fin) {
+            if (bad) st->bad_ref = 1;
+            finish_path<PREC, WM, R, STG>(A, ray, L);
+            ray = -1;
+        }
     }
-    if (!(WM == WM_FILL) && A.count_rechecks) {
+    if (!(WM == WM_FILL) && count_rechecks) {
         if (rechecks) atomicAdd(&st->rechecks, rechecks);
         if (desc) atomicAdd(&st->descents, (unsigned long long)desc);
     }
 }
 
-// The batched walks as kernels: the counting walk at four wavefronts per SIMD,
-// the record-filling walk at three (it would otherwise take 170 VGPRs and run
-// two).
 template <int PREC, int BT>
-__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+__global__ void __launch_bounds__(BT)
     k_walk_batched_count(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                          const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min, TraceStatus *st)
 {
-    walk_batched<PREC, WM_COUNT, BT>(grids, args, chunks, n_chunks, refill_min, st, nullptr);
+    __shared__ LevelGeo geo_all[(BT / 64) * NLEV];
+    __shared__ Prep ring_all[(BT / 64) * RING];
+    walk_batched<PREC, WM_COUNT, BT>(grids, args, chunks, n_chunks, refill_min, st, geo_all, ring_all, nullptr,
+                                     nullptr);
 }
 
 template <int PREC, int BT>
-__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(BT)
     k_walk_batched_fill(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                         const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min, TraceStatus *st)
 {
-    extern __shared__ uint64_t lds_raw[];
-    walk_batched<PREC, WM_FILL, BT>(grids, args, chunks, n_chunks, refill_min, st,
-                                    reinterpret_cast<char *>(lds_raw));
+    using DsT = typename Lane<PREC, uint32_t>::DsT;
+    __shared__ LevelGeo geo_all[(BT / 64) * NLEV];
+    __shared__ Prep ring_all[(BT / 64) * RING];
+    __shared__ uint32_t stl[BT * SP];
+    __shared__ DsT stds[BT * SP];
+    walk_batched<PREC, WM_FILL, BT>(grids, args, chunks, n_chunks, refill_min, st, geo_all, ring_all, stl, stds);
 }
 
 template <int TREE, typename R>
 __global__ void __launch_bounds__(TB) k_locate(WalkGrid G, const double *__restrict__ X, int64_t n,
                                                int32_t *__restrict__ out)
 {
+    __shared__ LevelGeo geo[NLEV];
+    fill_levels(geo, G, threadIdx.x, TB);
+    __syncthreads();
     const int64_t i = int64_t(blockIdx.x) * TB + threadIdx.x;
     if (i >= n) return;
-    double x[3];
+    Lane<HG_FP64, R> L;
 #pragma unroll
-    for (int d = 0; d < 3; d++) x[d] = X[3 * i + d];
-    if (!inside_closed(G, x)) {
+    for (int d = 0; d < 3; d++) {
+        L.p[d] = X[3 * i + d];
+        L.k[d] = 0.0;
+    }
+    if (!inside_closed(G, L.p)) {
         out[i] = -1;
         return;
     }
-    double lo[3];
-    int lv = 0;
-    const R start = start_node<TREE, R>(G, x, 0, lv, lo);
-    const R r = descend<TREE, R>(G, nullptr, 0u, start, lv, lo, x, 0, TIE_NONE);
-    out[i] = r == Ref<R>::NUL ? -2 : int32_t(Ref<R>::id(r));
+    L.ref = start_node<TREE, R>(G, L.p, L.k, L.lv, L.X);
+    L.tie = 0;
+    while (!Ref<R>::leaf(L.ref)) {
+        if (!descend_ok<TREE, R>(G, L.ref, L.lv)) {
+            out[i] = -2;
+            return;
+        }
+        descend_step<TREE, HG_FP64, R>(G, geo, L);
+    }
+    out[i] = Ref<R>::id(L.ref) < G.n_leaves ? int32_t(Ref<R>::id(L.ref)) : -2;
 }
 
 __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0ull; }
@@ -1140,8 +1279,9 @@ __global__ void __launch_bounds__(TB)
     }
 }
 
-constexpr size_t LDS_BYTES = 16384;          // top-level child references per block
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
+constexpr uint32_t DEFAULT_CHUNK = 256;   // paths per work-queue atomic
+constexpr int DEFAULT_REFILL = 4;         // idle lanes that trigger a refill
 
 // Persistent grid size of a kernel: resident blocks per CU at this block size
 // and LDS use times the CU count of the current device.  Cached per (device,
@@ -1181,43 +1321,14 @@ int persistent_blocks(size_t lds, unsigned *blocks)
                             blocks);
 }
 
-// LDS a block may allocate on the current device (cached per device).
-inline size_t max_block_lds()
-{
-    constexpr int MAXDEV = 64;
-    static std::atomic<size_t> v[MAXDEV];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return 65536;
-    size_t r = v[dev].load(std::memory_order_relaxed);
-    if (!r) {
-        int b = 0;
-        r = hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && b > 0
-                ? size_t(b)
-                : 65536;
-        v[dev].store(r, std::memory_order_relaxed);
-    }
-    return r;
-}
-
 template <int TREE, int PREC, int WM, typename R, int BT>
 int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts *o, hipStream_t s)
 {
-    const int nc = TREE == OCT ? 8 : 2;
-    // record modes stage records in LDS behind the top-level child references
-    const size_t stage = WM == WM_COUNT ? 0
-                                        : size_t(BT) * StageShape<BT>::SP * (4 + (PREC == HG_FP64 ? 8 : 4));
-    const size_t cap = max_block_lds();
-    if (stage + 16 > cap) return HG_E_INVAL;
-    const size_t want = std::min(o->lds_bytes < 0 ? 0 : (o->lds_bytes == 0 ? LDS_BYTES : size_t(o->lds_bytes)),
-                                 cap - stage - 16);
-    const uint32_t lds_n = uint32_t(std::min<uint64_t>(G.n_internal, want / (sizeof(R) * size_t(nc))));
-    const uint32_t stage_off = uint32_t((size_t(lds_n) * nc * sizeof(R) + 15) & ~size_t(15));
-    const size_t lds = stage_off + stage;
     unsigned blocks = 0;
-    int rc = persistent_blocks<TREE, PREC, WM, R, BT>(lds, &blocks);
+    int rc = persistent_blocks<TREE, PREC, WM, R, BT>(0, &blocks);
     if (rc) return rc;
-    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : 128u;
-    const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : 16;
+    const uint32_t chunk = o->chunk > 0 ? uint32_t(o->chunk) : DEFAULT_CHUNK;
+    const int refill_min = o->refill_min > 0 ? std::min(o->refill_min, 64) : DEFAULT_REFILL;
     for (int64_t start = 0; start < A.n; start += PERSIST_CHUNK) {
         WalkArgs B = A;
         B.n = std::min(PERSIST_CHUNK, A.n - start);
@@ -1232,8 +1343,7 @@ int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts 
         }
         k_reset_counter<<<1, 1, 0, s>>>(A.st);
         HG_CHECK(hipGetLastError());
-        k_walk_persistent<TREE, PREC, WM, R, BT><<<dim3(blocks), dim3(BT), lds, s>>>(G, B, lds_n, chunk,
-                                                                                         refill_min, stage_off);
+        k_walk_persistent<TREE, PREC, WM, R, BT><<<dim3(blocks), dim3(BT), 0, s>>>(G, B, chunk, refill_min);
         HG_CHECK(hipGetLastError());
     }
     return HG_OK;
@@ -1280,8 +1390,7 @@ template <int PREC, int WM, int BT>
 int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
                      int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
 {
-    const size_t lds = WM == WM_FILL ? size_t(BT) * StageShape<BT>::SP * (4 + (PREC == HG_FP64 ? 8 : 4)) : 0;
-    if (lds > max_block_lds()) return HG_E_INVAL;
+    const size_t lds = 0;   // the batched walks use static LDS only
     const void *kern = WM == WM_FILL ? reinterpret_cast<const void *>(k_walk_batched_fill<PREC, BT>)
                                      : reinterpret_cast<const void *>(k_walk_batched_count<PREC, BT>);
     unsigned blocks = 0;
@@ -1292,7 +1401,7 @@ int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChu
     k_reset_counter<<<1, 1, 0, s>>>(st);
     HG_CHECK(hipGetLastError());
     if (WM == WM_FILL)
-        k_walk_batched_fill<PREC, BT><<<dim3(blocks), dim3(BT), lds, s>>>(grids, args, chunks, n_chunks,
+        k_walk_batched_fill<PREC, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
                                                                           refill_min, st);
     else
         k_walk_batched_count<PREC, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
@@ -1333,6 +1442,8 @@ WalkGrid walk_grid(const hg_grid *g, int precision)
     G.child = g->child;
     G.table = g->table;
     G.tdep = g->table ? g->tdep : 0;
+    G.dm = finest_depth(g->tree, g->max_level);
+    G.unit = ldexp(g->side, -G.dm);
     return G;
 }
 
@@ -1351,14 +1462,14 @@ int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *o
                    : dispatch_walk<OCT, uint32_t>(G, A, prec, wm, persistent, opts, s);
 }
 
-int launch_walk(const hg_grid *g, const double *o, const double *k, int64_t n,
+int launch_walk(const hg_grid *g, TraceStatus *st, const double *o, const double *k, int64_t n,
                 const hg_trace_opts *opts, hg_trace_out *out, int wm, hipStream_t s, float *ms)
 {
     (void)ms;
-    return launch_walk_args(g, walk_args(g, o, k, n, opts, out), opts, wm, s);
+    return launch_walk_args(g, walk_args(g, st, o, k, n, opts, out), opts, wm, s);
 }
 
-WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n,
+WalkArgs walk_args(const hg_grid *g, TraceStatus *st, const double *o, const double *k, int64_t n,
                    const hg_trace_opts *opts, hg_trace_out *out)
 {
     WalkArgs A;
@@ -1372,7 +1483,7 @@ WalkArgs walk_args(const hg_grid *g, const double *o, const double *k, int64_t n
     A.leaf = out->leaf;
     A.ds = out->ds;
     A.capacity = out->capacity;
-    A.st = g->status;
+    A.st = st;
     A.count_rechecks = (opts->flags & HG_FLAG_RECHECKS) ? 1 : 0;
     A.slab = 0;
     A.resume = nullptr;
@@ -1385,7 +1496,7 @@ int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk
                    int n_chunks, const hg_trace_opts *opts, bool fill, TraceStatus *st,
                    hipStream_t s)
 {
-    const int refill_min = opts->refill_min > 0 ? std::min(opts->refill_min, 64) : 16;
+    const int refill_min = opts->refill_min > 0 ? std::min(opts->refill_min, 64) : DEFAULT_REFILL;
     const int b = opts->block;
     if (opts->precision == HG_FP64)
         return fill ? launch_batched_b<HG_FP64, WM_FILL>(grids, args, chunks, n_chunks, b, refill_min, st, s)

@@ -1,9 +1,8 @@
 // Autotuner of the walk's launch shape.  The walk's results do not depend on
 // the launch shape (every path is walked by one lane with the same
-// arithmetic); its speed does: threads per block, the bytes of top-level
-// child references staged in LDS (more LDS per block means fewer resident
-// blocks), the number of paths a wavefront takes from the work queue per
-// atomic and the number of idle lanes that trigger a refill.  The tuner
+// arithmetic); its speed does: threads per block, the number of paths a
+// wavefront takes from the work queue per atomic and the number of idle
+// lanes that trigger a refill from its queue of prepared paths.  The tuner
 // times candidate shapes on a caller-supplied sample of the workload with HIP
 // events and keeps the fastest, by coordinate descent from the defaults.
 #include <math.h>
@@ -19,9 +18,9 @@ namespace hg {
 namespace {
 
 const int BLOCKS[] = {128, 256, 512};
-const int LDS[] = {-1, 4096, 16384, 32768, 65536};
-const int CHUNKS[] = {32, 64, 128, 256, 512, 1024};
-const int REFILLS[] = {4, 8, 16, 32};
+const int LDS[] = {0};   // lds_bytes: no longer used by the walk
+const int CHUNKS[] = {64, 128, 256, 512, 1024};
+const int REFILLS[] = {1, 2, 4, 8, 16};
 
 struct Events {
     hipEvent_t e[4] = {};
@@ -64,15 +63,10 @@ int time_candidate(Events &ev, bool records, int reps, hipStream_t s, RunCount c
     return HG_OK;
 }
 
-int status_error(hg_grid *g, hipStream_t s)
+int status_error(const TraceStatus *dst, hipStream_t s)
 {
     TraceStatus st;
-    HG_CHECK(hipMemcpyAsync(&st, g->status, sizeof st, hipMemcpyDeviceToHost, s));
-    HG_CHECK(hipStreamSynchronize(s));
-    if (st.bad_ref) return HG_E_FORMAT;
-    if (st.bad_dir) return HG_E_DIR;
-    if (st.step_guard) return HG_E_STEP;
-    return HG_OK;
+    return read_status(dst, &st, s);
 }
 
 // Coordinate descent over the parameter lists; eval(cand, &ms) times one.
@@ -123,13 +117,16 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     base.persistent = 3;
     base.flags = 0;
     base.block = 256;
-    base.lds_bytes = 16384;
-    base.chunk = 128;
-    base.refill_min = 16;
+    base.lds_bytes = 0;
+    base.chunk = 256;
+    base.refill_min = 4;
     hg_trace_out out;
     memset(&out, 0, sizeof out);
     int64_t *tmp = nullptr;
-    int rc = dalloc_n(&out.tau, size_t(n), s);
+    StatusSlot slot;
+    int rc = slot.acquire();
+    TraceStatus *const dst = slot.get();
+    if (!rc) rc = dalloc_n(&out.tau, size_t(n), s);
     if (!rc) rc = dalloc_n(&out.count, size_t(n), s);
     if (!rc) rc = dalloc_n(&out.offsets, size_t(n) + 1, s);
     if (!rc) rc = dalloc_n(&tmp, scan_tmp_elems(n), s);
@@ -153,11 +150,11 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
         }
     }
     if (!rc) {
-        hipError_t e = hipMemsetAsync(g->status, 0, sizeof(TraceStatus), s);
+        hipError_t e = hipMemsetAsync(dst, 0, sizeof(TraceStatus), s);
         if (e) rc = set_hip_error(e);
     }
-    if (!rc) rc = launch_walk(g, origins, dirs, n, &base, &out, WM_COUNT, s, nullptr);
-    if (!rc) rc = status_error(g, s);
+    if (!rc) rc = launch_walk(g, dst, origins, dirs, n, &base, &out, WM_COUNT, s, nullptr);
+    if (!rc) rc = status_error(dst, s);
     if (!rc && records && !slab_mode) {
         rc = scan_i32_to_i64(out.count, out.offsets, n, tmp, s);
         if (!rc) {
@@ -173,7 +170,7 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
     Events ev;
     if (!rc) rc = ev.create();
     if (!rc) {
-        WalkArgs SA = walk_args(g, origins, dirs, n, &base, &out);
+        WalkArgs SA = walk_args(g, dst, origins, dirs, n, &base, &out);
         SA.leaf = sleaf;
         SA.ds = sds;
         SA.slab = slab;
@@ -185,8 +182,8 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
                     [&]() { return HG_OK; }, ms);
             return time_candidate(
                 ev, records, 3, s,
-                [&]() { return launch_walk(g, origins, dirs, n, &c, &out, WM_COUNT, s, nullptr); },
-                [&]() { return launch_walk(g, origins, dirs, n, &c, &out, WM_FILL, s, nullptr); }, ms);
+                [&]() { return launch_walk(g, dst, origins, dirs, n, &c, &out, WM_COUNT, s, nullptr); },
+                [&]() { return launch_walk(g, dst, origins, dirs, n, &c, &out, WM_FILL, s, nullptr); }, ms);
         };
         const int *vals[] = {LDS, BLOCKS, CHUNKS, REFILLS};
         const int nvals[] = {int(sizeof LDS / sizeof *LDS), int(sizeof BLOCKS / sizeof *BLOCKS),
@@ -196,7 +193,7 @@ int grid_tune(hg_grid_t g, const double *origins, const double *dirs, int64_t n,
         float ms = 0.f;
         hg_trace_opts best = base;
         rc = descend_params(&best, 4, vals, nvals, field, eval, &ms);
-        if (!rc) rc = status_error(g, s);
+        if (!rc) rc = status_error(dst, s);
         if (!rc) {
             opts->block = best.block;
             opts->lds_bytes = best.lds_bytes;
