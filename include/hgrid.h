@@ -329,6 +329,36 @@ int grid_interact(hg_grid_t grid, const hg_trace_out *records, int precision, in
                   const double *tau_star, double kappa, int32_t *leaf_out, double *s_out,
                   void *stream);
 
+/* The same two consumers as walks that stop early and write no records: one
+ * persistent walk over the paths (exit decisions in opts->precision, tau
+ * summed in FP64 from the FP64 leaf densities in both precisions; the leaf
+ * sequence and ds are those of grid_trace).  s is the distance along the
+ * path from its origin (a part before the domain entry counts).
+ *
+ * grid_trace_segment (Sect. 3.2, second measure, grid side): tau_out[i] =
+ * kappa * sum of rho ds over path i up to length s_max[i] (the leaf holding
+ * s = s_max[i] adds its part up to there; the walk stops there), count_out[i]
+ * = the leaves with ds > 0 that this part enters.  A NaN s_max counts as 0.
+ *
+ * grid_trace_interact (Monte Carlo interaction point, Sect. 1 and 2.3):
+ * leaf_out[i] = the first leaf where the cumulative optical depth reaches
+ * tau_star[i] and s_out[i] the distance where it does (tau grows linearly in
+ * the leaf); -1 and the path's whole length when it stays below (paths that
+ * miss the domain: -1 and 0).
+ *
+ * origins, dirs: n x 3 doubles (device), as grid_trace; s_max / tau_star: n
+ * doubles (device); outputs: n values each (device, caller-owned).  Of opts
+ * only precision, kappa, block, chunk and refill_min are read (the walk is
+ * always persistent).  Synchronises the stream once.  Errors: HG_E_INVAL,
+ * HG_E_DIR (a direction that is not a unit vector: that path's tau_out or
+ * s_out is NaN), HG_E_STEP, HG_E_FORMAT, HG_E_HIP. */
+int grid_trace_segment(hg_grid_t grid, const double *origins, const double *dirs, const double *s_max,
+                       int64_t n, const hg_trace_opts *opts, double *tau_out, int32_t *count_out,
+                       void *stream);
+int grid_trace_interact(hg_grid_t grid, const double *origins, const double *dirs, const double *tau_star,
+                        int64_t n, const hg_trace_opts *opts, int32_t *leaf_out, double *s_out,
+                        void *stream);
+
 /* ---- the optical-depth recipe of Sect. 4.1 ---------------------------- */
 /* tau_out[l] (device, n_leaves) = the optical depth of leaf l by Eq. (2) with
  * its sampled mass M = S (V / n_samples) of Eq. (1) (n_samples as in the

@@ -143,6 +143,10 @@ _SIGS = [
                                 C.c_int, C.c_void_p, C.c_void_p]),
     ("grid_interact", C.c_int, [C.c_void_p, C.POINTER(TraceOut), C.c_int, C.c_int64, C.c_void_p,
                                 C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grid_trace_segment", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                     C.POINTER(TraceOpts), C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("grid_trace_interact", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                      C.POINTER(TraceOpts), C.c_void_p, C.c_void_p, C.c_void_p]),
     ("grid_leaf_tau", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_void_p, C.c_void_p]),
     ("grid_tau_percentile", C.c_int, [C.c_void_p, C.c_double, C.c_int, C.c_double,
                                       C.POINTER(C.c_double), C.c_void_p]),
@@ -497,6 +501,45 @@ class Grid:
         s = torch.empty(n, dtype=torch.float64, device=self.device)
         _check(lib().grid_interact(self._h, C.byref(to), prec, n, _ptr(ts), kappa, _ptr(leaf),
                                    _ptr(s), _stream(stream)), "grid_interact")
+        return leaf, s
+
+    def _early_opts(self, precision, kappa, tuned):
+        opts = TraceOpts()
+        opts.precision = precision
+        opts.kappa = kappa
+        if tuned is not None:
+            for key in ("block", "chunk", "refill_min"):
+                setattr(opts, key, int(tuned[key]))
+        return opts
+
+    def trace_segment(self, origins, dirs, s_max, precision: int = FP64, kappa: float = 1.0,
+                      stream=None, tuned: Optional[dict] = None):
+        """Early-exit walk (grid_trace_segment): (tau, count) of every path
+        up to length s_max, without records."""
+        o = _dev_f64x3(origins, self.device)
+        k = _dev_f64x3(dirs, self.device)
+        n = o.shape[0]
+        sm = torch.as_tensor(s_max, dtype=torch.float64).to(self.device).contiguous()
+        tau = torch.empty(n, dtype=torch.float64, device=self.device)
+        cnt = torch.empty(n, dtype=torch.int32, device=self.device)
+        opts = self._early_opts(precision, kappa, tuned)
+        _check(lib().grid_trace_segment(self._h, _ptr(o), _ptr(k), _ptr(sm), n, C.byref(opts), _ptr(tau),
+                                        _ptr(cnt), _stream(stream)), "grid_trace_segment")
+        return tau, cnt
+
+    def trace_interact(self, origins, dirs, tau_star, precision: int = FP64, kappa: float = 1.0,
+                       stream=None, tuned: Optional[dict] = None):
+        """Early-exit walk (grid_trace_interact): (leaf, s) of the interaction
+        point of every path, without records."""
+        o = _dev_f64x3(origins, self.device)
+        k = _dev_f64x3(dirs, self.device)
+        n = o.shape[0]
+        ts = torch.as_tensor(tau_star, dtype=torch.float64).to(self.device).contiguous()
+        leaf = torch.empty(n, dtype=torch.int32, device=self.device)
+        s = torch.empty(n, dtype=torch.float64, device=self.device)
+        opts = self._early_opts(precision, kappa, tuned)
+        _check(lib().grid_trace_interact(self._h, _ptr(o), _ptr(k), _ptr(ts), n, C.byref(opts), _ptr(leaf),
+                                         _ptr(s), _stream(stream)), "grid_trace_interact")
         return leaf, s
 
     # -- arrays ----------------------------------------------------------------

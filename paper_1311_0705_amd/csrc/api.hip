@@ -74,7 +74,7 @@ void free_grid_arrays(hg_grid *g)
     }
     void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
                     g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->recw,
-                    g->child, g->table};
+                    g->child, g->jump, g->table};
     for (void *p : ptrs) dfree(p, nullptr);
 }
 
@@ -797,6 +797,52 @@ int grid_trace(hg_grid_t g, const double *origins, const double *dirs, int64_t n
         for (int i = 0; i < 4; i++)
             if (ev[i]) (void)hipEventDestroy(ev[i]);
     return rc;
+}
+
+// The early-exit walks: one persistent walk, no records; dst_d / dst_i
+// take the per-path double and int32 results.
+static int trace_early_exit(hg_grid_t g, const double *origins, const double *dirs, const double *lim,
+                            int64_t n, const hg_trace_opts *opts, double *dst_d, int32_t *dst_i, int wm,
+                            void *stream)
+{
+    if (!g || !opts || n < 0) return HG_E_INVAL;
+    if (opts->precision != HG_FP64 && opts->precision != HG_FP32_RECHECK) return HG_E_INVAL;
+    if (!isfinite(opts->kappa)) return HG_E_INVAL;
+    if (opts->block != 0 && opts->block != 128 && opts->block != 256 && opts->block != 512)
+        return HG_E_INVAL;
+    if (opts->chunk < 0 || opts->chunk > HG_MAX_CHUNK || opts->refill_min < 0) return HG_E_INVAL;
+    if (n == 0) return HG_OK;
+    if (!origins || !dirs || !lim || !dst_d || !dst_i) return HG_E_INVAL;
+    hipStream_t s = (hipStream_t)stream;
+    StatusSlot slot;
+    int rc = slot.acquire();
+    if (rc) return rc;
+    TraceStatus *const st = slot.get();
+    HG_CHECK(hipMemsetAsync(st, 0, sizeof(TraceStatus), s));
+    hg_trace_out out;
+    memset(&out, 0, sizeof out);
+    out.tau = dst_d;
+    out.count = dst_i;
+    WalkArgs A = walk_args(g, st, origins, dirs, n, opts, &out);
+    A.lim = lim;
+    rc = launch_walk_args(g, A, opts, wm, s);
+    if (rc) return rc;
+    TraceStatus h;
+    return read_status(st, &h, s);
+}
+
+int grid_trace_segment(hg_grid_t g, const double *origins, const double *dirs, const double *s_max,
+                       int64_t n, const hg_trace_opts *opts, double *tau_out, int32_t *count_out,
+                       void *stream)
+{
+    return trace_early_exit(g, origins, dirs, s_max, n, opts, tau_out, count_out, WM_SEG, stream);
+}
+
+int grid_trace_interact(hg_grid_t g, const double *origins, const double *dirs, const double *tau_star,
+                        int64_t n, const hg_trace_opts *opts, int32_t *leaf_out, double *s_out,
+                        void *stream)
+{
+    return trace_early_exit(g, origins, dirs, tau_star, n, opts, s_out, leaf_out, WM_INT, stream);
 }
 
 // grid_trace_noalloc: the scan work space lives in a fixed device array,

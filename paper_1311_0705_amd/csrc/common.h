@@ -7,7 +7,9 @@
 //   walk arrays   per-leaf walk records holding the six encoded rope targets
 //                 and the leaf density, so one crossing reads one sector;
 //                 child: per internal node the encoded references of its
-//                 2 (k-d) or 8 (octree) children, read one per descent step.
+//                 2 (k-d) or 8 (octree) children, read one per descent step;
+//                 jump (k-d): per internal node the references three levels
+//                 down, one per side triple, read one per three levels.
 // An encoded reference packs  kind (top two bits) | level (6 bits) | id:
 // kind 2 = leaf (id = leaf rank), 0 = internal node (id = internal-node rank),
 // 1 = "twin", an internal node whose children are all leaves (id = the leaf
@@ -116,6 +118,8 @@ struct WalkGrid {
     uint64_t n_leaves, n_internal; // bounds every reference is checked against
     const void *rec;               // walk records of the precision in use
     const void *child;             // [n_internal][2 or 8] references
+    const void *jump;              // k-d: [n_internal][8] references three levels down
+                                   // (NULL: a descent reads one level at a time)
     const void *table;             // locate table (NULL: descents start at the root)
     int tdep;                      // its per-axis depth: 2^tdep cells per axis
     int dm;                        // finest per-axis depth of any node: every plane is
@@ -194,10 +198,11 @@ struct WalkArgs {
     unsigned long long *n_resume;  // slab walk: entries written to resume
     int pairs;                     // persistent slab walk, FP32 records: rows of (leaf, ds32)
                                    // pairs in leaf (ds unused)
+    const double *lim;             // WM_SEG: s_max per path; WM_INT: tau* per path
 };
 
 // Walk modes (see trace.hip).
-enum { WM_COUNT = 0, WM_FILL = 1, WM_SLAB = 2 };
+enum { WM_COUNT = 0, WM_FILL = 1, WM_SLAB = 2, WM_SEG = 3, WM_INT = 4 };
 
 // One entry of the batched walk's work queue: paths [start, end) of a grid.
 // One entry of the batched walk's work table: paths [start, end) of grid
@@ -235,6 +240,7 @@ struct hg_grid {
     hg::LeafRec64 *rec64;      // compact layout
     hg::LeafRecW *recw;        // wide layout
     void *child;               // uint32_t or uint64_t references
+    void *jump;                // k-d: three-level jump references (same type), or NULL
     uint64_t root_ref;
     void *table;               // locate table (uint32_t or uint64_t references), or NULL
     int tdep;                  // its per-axis depth

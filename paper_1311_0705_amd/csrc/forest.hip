@@ -52,6 +52,7 @@ struct ForestGrid {
     LeafRec32 *rec32;
     LeafRec64 *rec64;
     uint32_t *child;
+    uint32_t *jump;   // k-d jump references (8 per internal node), else NULL
     uint32_t *table;  // locate table, room for 2^(3 tmax) cells
     int tmax, pad2;
     int64_t *meta;  // [META]: level begins, then n_nodes, n_leaves, depth, error
@@ -378,6 +379,7 @@ __global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restri
         W.n_leaves = uint64_t(L);
         W.n_internal = uint64_t(I);
         W.child = G.child;
+        W.jump = G.jump;
         W.tdep = grid_tdep(G, L);
         W.table = W.tdep > 0 ? G.table : nullptr;
         W.dm = finest_depth(G.tree, G.C.max_level);
@@ -446,6 +448,10 @@ __global__ void __launch_bounds__(FT) k_f_child_refs(const ForestGrid *__restric
         const int64_t base = int64_t(G.int_of[n]) * G.nc;
         for (int k = 0; k < G.nc; k++)
             G.child[base + k] = encode<uint32_t>(f + k, G.nc, G.fc, G.level, G.leaf_of, G.int_of);
+        if (G.jump)
+            for (int c = 0; c < 8; c++)
+                G.jump[8 * int64_t(G.int_of[n]) + c] =
+                    jump_ref<uint32_t>(int32_t(n), c, G.fc, G.level, G.leaf_of, G.int_of);
     }
 }
 
@@ -668,6 +674,8 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
         cv.add(&G.rec32, cap);
         cv.add(&G.rec64, cap);
         cv.add(&G.child, cap);
+        // k-d: eight jump references per internal node (at most cap / 2 of them)
+        if (G.tree == HG_KDTREE) cv.add(&G.jump, 4 * cap);
         cv.add(&G.table, size_t(1) << (3 * G.tmax));
         void *blk = nullptr;
         rc = cv.alloc(&blk, &b->dev);
@@ -915,6 +923,7 @@ int batch_grid(hg_batch_t b, int i, hg_grid_t *out)
     g->rec32 = F.rec32;
     g->rec64 = F.rec64;
     g->child = F.child;
+    g->jump = F.jump;
     g->root_ref = Ref<uint32_t>::make(g->n_internal == 0 ? Ref<uint32_t>::LEAF : Ref<uint32_t>::INTERNAL, 0, 0);
     g->table = const_cast<void *>(W.table);
     g->tdep = W.tdep;

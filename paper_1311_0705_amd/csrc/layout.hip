@@ -1,5 +1,6 @@
 // Walk layout of a finished tree: face ropes, leaf / internal numbering, the
-// 32-byte per-leaf walk records and the encoded child references.
+// 32-byte per-leaf walk records, the encoded child references and, for a k-d
+// tree, the three-level jump references.
 //
 // Ropes stand in for the per-wall neighbor lists of Sect. 2.3: the leaves of
 // a rope target's subtree touching the face are exactly that face's neighbor
@@ -119,6 +120,20 @@ __global__ void __launch_bounds__(LT)
     child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, nc, fc, level, leaf_of, int_of);
 }
 
+// k-d jump references: one thread per (node, side triple) (see jump_ref).
+template <typename R>
+__global__ void __launch_bounds__(LT)
+    k_jump_refs(int64_t n, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+                const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of, R *__restrict__ jump)
+{
+    const int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
+    if (t >= n * 8) return;
+    const int64_t i = t >> 3;
+    const int c = int(t & 7);
+    if (fc[i] < 0) return;
+    jump[8 * int64_t(int_of[i]) + c] = jump_ref<R>(int32_t(i), c, fc, level, leaf_of, int_of);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(LT)
     k_locate_table(int tree, int tdep, int nc, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
@@ -181,6 +196,7 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     if (!arc && !g->wide) arc = dalloc_n(&g->rec32, size_t(L), s);
     if (!arc && !g->wide) arc = dalloc_n(&g->rec64, size_t(L), s);
     if (!arc) arc = dalloc(&g->child, size_t(I > 0 ? I : 1) * nc * rsz, s);
+    if (!arc && g->tree == KD && I > 0) arc = dalloc(&g->jump, size_t(I) * 8 * rsz, s);
     if (arc) {
         dfree(flag, s); dfree(rank, s); dfree(tmp, s);
         return arc;
@@ -205,6 +221,15 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
             k_child_refs<uint32_t><<<blocks_for(N * nc), LT, 0, s>>>(
                 N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->child);
         HG_CHECK(hipGetLastError());
+        if (g->jump) {
+            if (g->wide)
+                k_jump_refs<uint64_t><<<blocks_for(N * 8), LT, 0, s>>>(N, g->first_child, g->level, g->leaf_of,
+                                                                      g->int_of, (uint64_t *)g->jump);
+            else
+                k_jump_refs<uint32_t><<<blocks_for(N * 8), LT, 0, s>>>(N, g->first_child, g->level, g->leaf_of,
+                                                                      g->int_of, (uint32_t *)g->jump);
+            HG_CHECK(hipGetLastError());
+        }
     }
     g->root_ref = g->wide ? Ref<uint64_t>::make(I == 0 ? Ref<uint64_t>::LEAF : Ref<uint64_t>::INTERNAL, 0, 0)
                          : Ref<uint32_t>::make(I == 0 ? Ref<uint32_t>::LEAF : Ref<uint32_t>::INTERNAL, 0, 0);

@@ -150,6 +150,30 @@ __device__ inline R encode(int32_t n, int nc, const int32_t *__restrict__ fc, co
                : Ref<R>::make(Ref<R>::INTERNAL, level[n], uint64_t(uint32_t(int_of[n])));
 }
 
+// k-d jump reference from internal node i for the side triple c (s0 s1 s2 =
+// bits 2 1 0 of c; s_j is the side taken at level(i) + j): the node reached
+// by descending at most three levels with those sides: the first leaf met, a
+// twin's leaf child when a side is left for it, else the node three levels
+// down (internal or twin).
+template <typename R>
+__device__ inline R jump_ref(int32_t i, int c, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
+                             const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of)
+{
+    int32_t m = i;
+    R r = Ref<R>::NUL;
+    for (int j = 0; j < 3; j++) {
+        const int32_t ch = fc[m] + ((c >> (2 - j)) & 1);
+        r = encode<R>(ch, 2, fc, level, leaf_of, int_of);
+        if (Ref<R>::leaf(r)) break;
+        if (Ref<R>::twin(r)) {
+            if (j < 2) r = encode<R>(fc[ch] + ((c >> (1 - j)) & 1), 2, fc, level, leaf_of, int_of);
+            break;
+        }
+        m = ch;
+    }
+    return r;
+}
+
 // Grid density of a leaf = M/V = S/N (Sect. 3.2), or the imported value.
 __device__ inline double leaf_rho(int64_t l, int32_t n, const double *S, const double *rho_in,
                                   double n_samples)

@@ -84,15 +84,19 @@ __device__ __forceinline__ double max64(double a, double b)
 // Geometry of the nodes of one level: the widths per axis as doubles (exact
 // powers of two) and in units of WalkGrid::unit, the split axis and half
 // width a descent uses, and the FP32 recheck threshold (1e-5 of the smallest
-// width, which is axis 0's: no axis is finer).
+// width, which is axis 0's: no axis is finer).  For a k-d jump from this
+// level: per axis, the half width of the split among this level and the next
+// two that cuts it (jhw) and that split's level offset (byte d of jof).
 struct alignas(16) LevelGeo {
     double w[3];
     uint32_t W[3];
     uint32_t hw;
     float guard;
     int32_t axis;
+    uint32_t jhw[3];
+    uint32_t jof;
 };
-static_assert(sizeof(LevelGeo) == 48, "level record");
+static_assert(sizeof(LevelGeo) == 64, "level record");
 
 __device__ __forceinline__ LevelGeo make_level(int tree, int dm, double side, int lv)
 {
@@ -108,6 +112,19 @@ __device__ __forceinline__ LevelGeo make_level(int tree, int dm, double side, in
     const uint32_t W0 = in_reg(e.W[0]), W1 = in_reg(e.W[1]), W2 = in_reg(e.W[2]);
     e.hw = (e.axis == 0 ? W0 : (e.axis == 1 ? W1 : W2)) >> 1;
     e.guard = 1e-5f * float(e.w[0]);
+    e.jof = 0;
+    e.jhw[0] = e.jhw[1] = e.jhw[2] = 0;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        // k-d level lv + j splits axis (lv + j) mod 3, halving its width there
+        const int d = (lv + j) % 3;
+        const int sh = dm - axis_depth(tree, lv + j, d) - 1;
+        const uint32_t h = tree == KD && sh >= 0 && sh < 32 ? 1u << sh : 0u;
+        e.jhw[0] = d == 0 ? h : e.jhw[0];
+        e.jhw[1] = d == 1 ? h : e.jhw[1];
+        e.jhw[2] = d == 2 ? h : e.jhw[2];
+        e.jof |= uint32_t(j) << (8 * d);
+    }
     return e;
 }
 
@@ -144,6 +161,7 @@ struct Lane {
     int steps;
     double tau64;
     float tau32, comp32;
+    double lim;              // early-exit walks: s_max or tau* (after a hit: its s)
     bool force64;
     int64_t base, room;      // record slice of this path (record modes)
     uint32_t sl[4];          // one-thread walk: the last four records, staged
@@ -155,7 +173,11 @@ enum { STEP_GO = 0, STEP_END = 1, STEP_ERR = 2 };
 // Walk modes: WM_COUNT (tau and counts; also the tau-only mode), WM_FILL
 // (records into the slices given by the offsets of a counting walk),
 // WM_SLAB (tau, counts and the first A.slab records of every path into a
-// fixed-size row per path, for the one-pass records mode).
+// fixed-size row per path, for the one-pass records mode), and the
+// early-exit walks, which accumulate tau in FP64 from the FP64 records in
+// both precisions: WM_SEG (tau of the first s_max of the path, Sect. 3.2)
+// and WM_INT (the leaf and distance where tau reaches tau*, the Monte Carlo
+// interaction point of Sect. 1 and 2.3).
 
 __device__ __forceinline__ bool inside_closed(const WalkGrid &G, const double x[3])
 {
@@ -292,39 +314,89 @@ __device__ __forceinline__ bool descend_ok(const WalkGrid &G, R ref, int lv)
                        (kind == Ref<R>::TWIN && id + nc <= G.n_leaves));
 }
 
-// One descent level from the internal or twin node L.ref toward the point
-// L.p: the child holding it, with its corner and level.  A twin's children
-// are leaves whose ranks follow its own; an internal node's child reference is
-// read from the child array.  Returns true when the child is known to be a
-// leaf now (a twin's), so its record can be read at once.
-template <int TREE, int PREC, typename R>
-__device__ __forceinline__ bool descend_step(const WalkGrid &G, const LevelGeo *geo, Lane<PREC, R> &L)
+// The side of a k-d node's split plane that holds the point L.p (ties by
+// tie_upper), with the move of L.X to that child's corner.
+template <int PREC, typename R>
+__device__ __forceinline__ bool kd_side(const WalkGrid &G, const LevelGeo &g, Lane<PREC, R> &L)
+{
+    const uint32_t hw = g.hw;
+    const int b = g.axis;
+    const uint32_t X0 = in_reg(L.X[0]), X1 = in_reg(L.X[1]), X2 = in_reg(L.X[2]);
+    const double q0 = in_reg(L.p[0]), q1 = in_reg(L.p[1]), q2 = in_reg(L.p[2]);
+    const uint32_t Xb = b == 0 ? X0 : (b == 1 ? X1 : X2);
+    const double qb = b == 0 ? q0 : (b == 1 ? q1 : q2);
+    const double lob = b == 0 ? G.lo[0] : (b == 1 ? G.lo[1] : G.lo[2]);
+    const double c = fma(double(Xb + hw), G.unit, lob);
+    bool up = qb > c;
+    const bool eq = qb == c;
+    if (__ballot(eq)) {
+        const double k0 = in_reg(L.k[0]), k1 = in_reg(L.k[1]), k2 = in_reg(L.k[2]);
+        const double kb = b == 0 ? k0 : (b == 1 ? k1 : k2);
+        if (eq) up = tie_upper(L.tie, kb, b);
+    }
+    const uint32_t add = up ? hw : 0u;
+    L.X[0] = X0 + (b == 0 ? add : 0u);
+    L.X[1] = X1 + (b == 1 ? add : 0u);
+    L.X[2] = X2 + (b == 2 ? add : 0u);
+    return up;
+}
+
+// Up to three k-d levels at once through the jump references.  Levels lv,
+// lv+1 and lv+2 split the three axes once each, so the sides of all three
+// splits follow from the node's corner alone; the jump reference of those
+// sides is the node the descent reaches one to three levels down (it stops
+// early at a leaf, or at a twin's leaf child), and only the splits above that
+// node move the corner.  Returns the levels descended; a reference whose
+// level is not one to three below is replaced by the null reference.
+template <int PREC, typename R>
+__device__ __forceinline__ int kd_jump(const WalkGrid &G, const LevelGeo *geo, Lane<PREC, R> &L)
 {
     const uint64_t id = Ref<R>::id(L.ref);
+    const int lv = L.lv;
+    const LevelGeo &g = geo[lv];
+    const uint32_t jof = g.jof;
+    uint32_t idx = 0, jo[3], add[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const uint32_t h = g.jhw[d];
+        jo[d] = (jof >> (8 * d)) & 3u;
+        const double c = fma(double(L.X[d] + h), G.unit, G.lo[d]);
+        bool up = L.p[d] > c;
+        const bool eq = L.p[d] == c;
+        if (__ballot(eq)) {
+            if (eq) up = tie_upper(L.tie, L.k[d], d);
+        }
+        idx |= (up ? 4u : 0u) >> jo[d];
+        add[d] = up ? h : 0u;
+    }
+    R r = static_cast<const R *>(G.jump)[8 * id + idx];
+    int dl = Ref<R>::level(r) - lv;
+    const bool ok = (dl >= 1) & (dl <= 3);
+    r = ok ? r : Ref<R>::NUL;
+    dl = ok ? dl : 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) L.X[d] += int(jo[d]) < dl ? add[d] : 0u;
+    L.lv = lv + dl;
+    L.ref = r;
+    return dl;
+}
+
+// A descent from the internal or twin node L.ref toward the point L.p: the
+// child holding it, with its corner and level.  A twin's children are leaves
+// whose ranks follow its own; an internal node's child reference is read from
+// the child array, or a k-d node's reference up to three levels down from the
+// jump array when the grid has one.  Returns the levels descended.
+template <int TREE, int PREC, typename R>
+__device__ __forceinline__ int descend_step(const WalkGrid &G, const LevelGeo *geo, Lane<PREC, R> &L)
+{
     const bool tw = Ref<R>::twin(L.ref);
+    if (TREE == KD && G.jump != nullptr && !tw) return kd_jump<PREC, R>(G, geo, L);
+    const uint64_t id = Ref<R>::id(L.ref);
     const LevelGeo &g = geo[L.lv];
     const uint32_t hw = g.hw;
     uint32_t slot;
     if (TREE == KD) {
-        const int b = g.axis;
-        const uint32_t X0 = in_reg(L.X[0]), X1 = in_reg(L.X[1]), X2 = in_reg(L.X[2]);
-        const double q0 = in_reg(L.p[0]), q1 = in_reg(L.p[1]), q2 = in_reg(L.p[2]);
-        const uint32_t Xb = b == 0 ? X0 : (b == 1 ? X1 : X2);
-        const double qb = b == 0 ? q0 : (b == 1 ? q1 : q2);
-        const double lob = b == 0 ? G.lo[0] : (b == 1 ? G.lo[1] : G.lo[2]);
-        const double c = fma(double(Xb + hw), G.unit, lob);
-        bool up = qb > c;
-        const bool eq = qb == c;
-        if (__ballot(eq)) {
-            const double k0 = in_reg(L.k[0]), k1 = in_reg(L.k[1]), k2 = in_reg(L.k[2]);
-            const double kb = b == 0 ? k0 : (b == 1 ? k1 : k2);
-            if (eq) up = tie_upper(L.tie, kb, b);
-        }
-        slot = up ? 1u : 0u;
-        const uint32_t add = up ? hw : 0u;
-        L.X[0] = X0 + (b == 0 ? add : 0u);
-        L.X[1] = X1 + (b == 1 ? add : 0u);
-        L.X[2] = X2 + (b == 2 ? add : 0u);
+        slot = kd_side(G, g, L) ? 1u : 0u;
     } else {
         slot = 0;
 #pragma unroll
@@ -346,7 +418,7 @@ __device__ __forceinline__ bool descend_step(const WalkGrid &G, const LevelGeo *
         const uint64_t nc = TREE == OCT ? 8 : 2;
         L.ref = static_cast<const R *>(G.child)[nc * id + slot];
     }
-    return tw;
+    return 1;
 }
 
 // Records of the one-thread walk: staged four at a time and written as aligned
@@ -533,18 +605,42 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, const
                 save_resume<PREC, R>(A, path, L);
             }
         }
-        if (PREC != HG_FP64 && WM != WM_FILL) {
+        if (PREC != HG_FP64 && WM != WM_FILL && WM != WM_SEG && WM != WM_INT) {
             const float y = float(A.kappa) * rho32 * float(ds) - L.comp32;
             const float t = L.tau32 + y;
             L.comp32 = (t - L.tau32) - y;
             L.tau32 = t;
         }
-        L.cnt++;
+        if (WM != WM_SEG && WM != WM_INT) L.cnt++;
     }
     // FP64 tau: a zero-length step adds an exact zero
-    if (PREC == HG_FP64 && WM != WM_FILL) L.tau64 = L.tau64 + A.kappa * rho64 * ds;
+    if (PREC == HG_FP64 && WM != WM_FILL && WM != WM_SEG && WM != WM_INT)
+        L.tau64 = L.tau64 + A.kappa * rho64 * ds;
+    bool stop = false;
+    if (WM == WM_SEG) {
+        // the first lim of the path: a leaf entered at s >= lim adds nothing, the
+        // leaf holding s = lim adds its part up to there, and the walk stops there
+        if ((L.s < L.lim) & (ds > 0.0)) {
+            L.tau64 = L.tau64 + A.kappa * rho64 * min64(ds, L.lim - L.s);
+            L.cnt++;
+        }
+        stop = !(L.s + ds < L.lim);
+    } else if (WM == WM_INT) {
+        // the first leaf where the cumulative tau reaches tau* = lim; tau grows
+        // linearly inside it, which places the point
+        if (ds > 0.0) {
+            const double dt = A.kappa * rho64 * ds;
+            if ((L.tau64 + dt >= L.lim) & (dt > 0.0)) {
+                L.cnt = int32_t(id);
+                L.lim = L.s + (L.lim - L.tau64) / (A.kappa * rho64);
+                stop = true;
+            } else {
+                L.tau64 = L.tau64 + dt;
+            }
+        }
+    }
     // the exit face lies on the domain boundary: its rope is null and the path ends
-    const bool end = nref == Ref<R>::NUL;
+    const bool end = (nref == Ref<R>::NUL) | stop;
     // re-anchor the exit point on the crossed face
     L.s = L.s + ds;
     double q[3];
@@ -599,7 +695,8 @@ __device__ __forceinline__ void finish_path(const WalkArgs &A, int64_t i, const 
     }
     if (WM == WM_SLAB && !STG) flush_records<PREC, R>(A, L);
     A.count[i] = L.cnt;
-    if (PREC == HG_FP64) A.tau[i] = L.tau64;
+    if (WM == WM_INT) A.tau[i] = L.cnt >= 0 ? L.lim : L.s;
+    else if (PREC == HG_FP64 || WM == WM_SEG) A.tau[i] = L.tau64;
     else A.tau[i] = double(L.tau32) - double(L.comp32);
 }
 
@@ -607,7 +704,7 @@ template <int PREC, int WM>
 __device__ __forceinline__ void finish_unwalked(const WalkArgs &A, int64_t i, int why)
 {
     if (WM == WM_FILL) return;
-    A.count[i] = 0;
+    A.count[i] = WM == WM_INT ? -1 : 0;
     if (why == PATH_BAD_DIR) {
         A.tau[i] = __longlong_as_double(0x7ff8000000000000ll);
         A.st->bad_dir = 1;
@@ -719,10 +816,11 @@ __device__ __forceinline__ int64_t take_path(const WalkGrid &G, const WalkArgs &
         L.steps = 0;
     }
     L.tie = 0;
-    L.cnt = 0;
+    L.cnt = WM == WM_INT ? -1 : 0;
     L.tau64 = 0.0;
     L.tau32 = 0.f;
     L.comp32 = 0.f;
+    if (WM == WM_SEG || WM == WM_INT) L.lim = A.lim[i];
     if (WM == WM_FILL) {
         L.base = A.offsets[i] + (resumed ? A.slab : 0);
         L.room = A.offsets[i + 1] - L.base;
@@ -769,8 +867,7 @@ __global__ void __launch_bounds__(TB) k_walk(WalkGrid G, WalkArgs A)
                 A.st->bad_ref = 1;
                 break;
             }
-            descend_step<TREE, PREC, R>(G, geo, L);
-            desc++;
+            desc += descend_step<TREE, PREC, R>(G, geo, L);
         }
     }
     finish_path<PREC, WM, R, false>(A, i, L);
@@ -866,8 +963,7 @@ __device__ __forceinline__ bool walk_step(const WalkGrid &G, const WalkArgs &A, 
         if (!descend_ok<TREE, R>(G, L.ref, L.lv)) {
             bad = true;
         } else {
-            descend_step<TREE, PREC, R>(G, geo, L);
-            desc++;
+            desc += descend_step<TREE, PREC, R>(G, geo, L);
         }
     }
     return bad || r != STEP_GO;
@@ -919,7 +1015,7 @@ __global__ void __launch_bounds__(BT)
     k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t chunk, int refill_min)
 {
     using DsT = typename Lane<PREC, R>::DsT;
-    constexpr bool STG = WM != WM_COUNT;
+    constexpr bool STG = WM == WM_FILL || WM == WM_SLAB;   // record modes
     constexpr int NW = BT / 64;
     __shared__ LevelGeo geo[NLEV];
     __shared__ Prep ring_all[NW * RING];
@@ -1340,6 +1436,7 @@ int launch_persistent(const WalkGrid &G, const WalkArgs &A, const hg_trace_opts 
             B.tau = A.tau ? A.tau + start : nullptr;
             B.count = A.count ? A.count + start : nullptr;
             B.offsets = A.offsets ? A.offsets + start : nullptr;
+            B.lim = A.lim ? A.lim + start : nullptr;
         }
         k_reset_counter<<<1, 1, 0, s>>>(A.st);
         HG_CHECK(hipGetLastError());
@@ -1374,6 +1471,8 @@ int dispatch_mode(const WalkGrid &G, const WalkArgs &A, int wm, int persistent, 
     switch (wm) {
     case WM_FILL: return launch_t<TREE, PREC, WM_FILL, R>(G, A, persistent, o, s);
     case WM_SLAB: return launch_t<TREE, PREC, WM_SLAB, R>(G, A, persistent, o, s);
+    case WM_SEG: return launch_t<TREE, PREC, WM_SEG, R>(G, A, 1, o, s);
+    case WM_INT: return launch_t<TREE, PREC, WM_INT, R>(G, A, 1, o, s);
     default: return launch_t<TREE, PREC, WM_COUNT, R>(G, A, persistent, o, s);
     }
 }
@@ -1440,6 +1539,7 @@ WalkGrid walk_grid(const hg_grid *g, int precision)
                     : (precision == HG_FP64 ? static_cast<const void *>(g->rec64)
                                             : static_cast<const void *>(g->rec32));
     G.child = g->child;
+    G.jump = g->jump;
     G.table = g->table;
     G.tdep = g->table ? g->tdep : 0;
     G.dm = finest_depth(g->tree, g->max_level);
@@ -1453,7 +1553,8 @@ int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *o
     // bit 0: persistent counting / tau-only / slab walk, bit 1: persistent fill walk
     const int mode = opts->persistent < 0 ? 3 : opts->persistent;
     const int persistent = wm == WM_FILL ? (mode >> 1) & 1 : mode & 1;
-    const WalkGrid G = walk_grid(g, opts->precision);
+    // the early-exit walks read the FP64 records whatever the exit-decision precision
+    const WalkGrid G = walk_grid(g, wm == WM_SEG || wm == WM_INT ? HG_FP64 : opts->precision);
     const int prec = opts->precision;
     if (g->tree == KD)
         return g->wide ? dispatch_walk<KD, uint64_t>(G, A, prec, wm, persistent, opts, s)
@@ -1489,6 +1590,7 @@ WalkArgs walk_args(const hg_grid *g, TraceStatus *st, const double *o, const dou
     A.resume = nullptr;
     A.n_resume = nullptr;
     A.pairs = 0;
+    A.lim = nullptr;
     return A;
 }
 
