@@ -657,6 +657,20 @@ def run_c4(a):
                and torch.equal(res[i]["leaf"][:needed[i]], ref[i]["leaf"][:needed[i]])
                and torch.equal(res[i]["ds"][:needed[i]], ref[i]["ds"][:needed[i]])
                for i in range(64))
+    # the bound trace stage on its own (one walk into per-path rows, the row
+    # copy and the resume walk), timed with HIP events on its stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.run(hg.STAGE_TRACE, stream=side)
+    e0.record(side)
+    for _ in range(a.steps):
+        b.run(hg.STAGE_TRACE, stream=side)
+    e1.record(side)
+    b.result(side)
+    e1.synchronize()
+    trace_stage_ms = e0.elapsed_time(e1) / a.steps
+    same = same and all(torch.equal(res[i]["leaf"][:needed[i]], ref[i]["leaf"][:needed[i]])
+                        for i in range(64))
+    log(f"batch trace stage {trace_stage_ms:.3f} ms")
     # the batched walks on their own, timed with HIP events (eager, same grids)
     log("batched walk timing")
     grids = [b.grid(i) for i in range(64)]
@@ -684,11 +698,12 @@ def run_c4(a):
         "eager_batch_ms": round(eager_s * 1e3, 3),
         "graph_over_one_by_one": round(obo_s / step_s, 3),
         "batch_equals_one_by_one": bool(same),
-        "batched_walk_ms": {"count": round(kms[0], 3), "scan": round(kms[1], 3),
-                            "fill": round(kms[2], 3)},
+        "batch_trace_stage_ms": round(trace_stage_ms, 3),
+        "trace_batched_two_walks_ms": {"count": round(kms[0], 3), "scan": round(kms[1], 3),
+                                       "fill": round(kms[2], 3)},
         "tuned": tuned,
-        "roofline": roofline("k_walk_batched_fill<fp32_recheck>", kms[2],
-                             crossings * B_X_FILL32 + n * B_RAY_FILL, "w4_fill"),
+        "roofline": roofline("batch trace stage (one-pass batched walk, row copy, resume walk)",
+                             trace_stage_ms, crossings * B_X_FILL32 + n * B_RAY_SLAB, "w4_stage"),
     })
     if not a.no_cpu:
         import oracle as O

@@ -410,7 +410,8 @@ void grid_free(hg_grid_t grid);
  * allocates nor synchronises, and batch_capture records it into a HIP graph
  * that batch_replay launches again (the build-then-trace pass of a batch with
  * new contents of the bound input buffers, or simply again).  Grids use the
- * compact layout only (node capacity at most 2^24). */
+ * compact layout only (node capacity at most 2^24); a k-d grid's arrays
+ * include its jump references (about 16 more bytes per node). */
 typedef struct hg_batch *hg_batch_t;
 
 /* Reserve a batch: density dens[g] (copied; clumps binned here), criteria
@@ -425,9 +426,15 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit,
 /* Bind the path batches every later trace stage reads: origins[g] / dirs[g]
  * (device, n[g] paths) into outs[g] (caller-owned device buffers, as
  * grid_trace; the pointers are kept, the buffers must outlive their use).
- * opts as grid_trace_batched (chunk = paths per work-queue entry).  Replaces
- * an earlier binding and drops a captured graph.  Synchronises the device.
- * Errors: HG_E_INVAL, HG_E_LIMIT, HG_E_OOM, HG_E_HIP. */
+ * opts as grid_trace_batched (chunk = paths per work-queue entry).  Records
+ * mode walks the paths once unless opts->passes is 2: each path's first
+ * opts->slab records (0: as many as fit 8 GiB over all paths, at most 2048)
+ * go to a row of its own and a path past its row is saved where the row
+ * filled up; the rows are then copied into the CSR slices and the saved paths
+ * resume, all on the device.  When fewer than 16 rows per path fit, it walks
+ * twice (counting, then filling).  Replaces an earlier binding and drops a
+ * captured graph.  Synchronises the device.  Errors: HG_E_INVAL, HG_E_LIMIT,
+ * HG_E_OOM, HG_E_HIP. */
 int batch_bind(hg_batch_t batch, const double *const *origins, const double *const *dirs,
                const int64_t *n, const hg_trace_opts *opts, hg_trace_out *outs);
 
@@ -460,7 +467,7 @@ int batch_result(hg_batch_t batch, void *stream, int64_t *n_nodes, int64_t *n_le
  * HG_E_OOM, HG_E_HIP. */
 int batch_grid(hg_batch_t batch, int g, hg_grid_t *out);
 
-/* Autotune the bound trace of a built batch: times the batched walk for
+/* Autotune the bound trace of a built batch: times the bound trace stage for
  * candidate threads per block, paths per work-queue entry and refill
  * thresholds (coordinate descent, HIP events) and rebinds the batch with the
  * fastest (which drops a captured graph: tune before batch_capture).  The

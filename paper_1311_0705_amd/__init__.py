@@ -721,9 +721,12 @@ class Batch:
 
     def bind(self, origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
              kappa: float = 1.0, capacities=None, chunk: int = 0, refill_min: int = 0,
-             count_rechecks: bool = False, block: int = 0):
+             count_rechecks: bool = False, block: int = 0, passes: int = 0, slab: int = 0):
         """Bind path batches (one per grid) and allocate their outputs; the
-        returned result dicts are filled by each later run or replay."""
+        returned result dicts are filled by each later run or replay.
+        Records mode walks once into per-path rows of `slab` records (0: the
+        library's choice) unless passes=2 asks for a counting and a filling
+        walk."""
         dev = self.device
         os_ = [_dev_f64x3(o, dev) for o in origins]
         ks_ = [_dev_f64x3(k, dev) for k in dirs]
@@ -754,6 +757,8 @@ class Batch:
         opts.chunk = chunk
         opts.refill_min = refill_min
         opts.block = block
+        opts.passes = passes
+        opts.slab = slab
         op = (C.c_void_p * self.ng)(*[o.data_ptr() for o in os_])
         kp = (C.c_void_p * self.ng)(*[k.data_ptr() for k in ks_])
         np_ = (C.c_int64 * self.ng)(*ns)

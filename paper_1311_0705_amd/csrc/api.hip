@@ -519,13 +519,17 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         for (int t = 0; t < 4; t++) outs[i].kernel_ms[t] = 0.f;
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
+    const std::vector<int64_t> hP = chunk_prefix(hC, ng);
     WalkGrid *dG = nullptr;
     WalkArgs *dA = nullptr;
     BatchChunk *dC = nullptr;
-    int64_t *tmp = nullptr;
+    int64_t *tmp = nullptr, *dP = nullptr;
+    unsigned long long *dctr = nullptr;
     int rc = dalloc_n(&dG, size_t(ng), s);
     if (!rc) rc = dalloc_n(&dA, size_t(ng), s);
     if (!rc) rc = dalloc_n(&dC, std::max<size_t>(hC.size(), 1), s);
+    if (!rc) rc = dalloc_n(&dP, hP.size(), s);
+    if (!rc) rc = dalloc_n(&dctr, size_t(ng), s);
     // records: the chunk scan's work space, then one total per grid
     const size_t ctmp = scan_chunks_tmp_elems(int(hC.size()));
     if (!rc && records) rc = dalloc_n(&tmp, ctmp + size_t(ng), s);
@@ -538,12 +542,14 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     if (!rc && !e) e = hipMemcpyAsync(dA, hA.data(), sizeof(WalkArgs) * size_t(ng), hipMemcpyHostToDevice, s);
     if (!rc && !e && !hC.empty())
         e = hipMemcpyAsync(dC, hC.data(), sizeof(BatchChunk) * hC.size(), hipMemcpyHostToDevice, s);
+    if (!rc && !e) e = hipMemcpyAsync(dP, hP.data(), sizeof(int64_t) * hP.size(), hipMemcpyHostToDevice, s);
     if (!rc && e) rc = set_hip_error(e);
+    const BatchQueue Q{dC, dP, dctr, ng};
     TraceStatus st;
     if (!rc) {
         k_reset_status<<<1, 1, 0, s>>>(dst);
         if (timing) (void)hipEventRecord(ev[0], s);
-        rc = launch_batched(dG, dA, dC, int(hC.size()), opts, false, dst, s);
+        rc = launch_batched(dG, dA, Q, opts, WM_COUNT, dst, s);
         if (timing) (void)hipEventRecord(ev[1], s);
     }
     if (!rc) rc = read_status(dst, &st, s);
@@ -577,7 +583,7 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
         if (!rc && !fits) rc = HG_E_CAPACITY;
         if (!rc) {
             if (timing) (void)hipEventRecord(ev[2], s);
-            rc = launch_batched(dG, dA, dC, int(hC.size()), opts, true, dst, s);
+            rc = launch_batched(dG, dA, Q, opts, WM_FILL, dst, s);
             if (timing) (void)hipEventRecord(ev[3], s);
         }
         if (!rc) rc = read_status(dst, &st, s);
@@ -602,6 +608,8 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     dfree(dG, s);
     dfree(dA, s);
     dfree(dC, s);
+    dfree(dP, s);
+    dfree(dctr, s);
     dfree(tmp, s);
     return rc;
 }

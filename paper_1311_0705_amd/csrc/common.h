@@ -214,6 +214,25 @@ struct BatchChunk {
     int64_t start, end;
 };
 
+// Work queue of a batched walk: the chunk table (each grid's chunks together,
+// grids in order), per grid the prefix of its chunk counts (gpre[ng] = the
+// table's length) and a counter of its chunks taken (zeroed by the launch).
+struct BatchQueue {
+    const BatchChunk *chunks;
+    const int64_t *gpre;
+    unsigned long long *gctr;
+    int ng;
+};
+
+// gpre of a chunk table (each grid's chunks together, grids in order).
+inline std::vector<int64_t> chunk_prefix(const std::vector<BatchChunk> &table, int ng)
+{
+    std::vector<int64_t> p(size_t(ng) + 1, 0);
+    for (const BatchChunk &c : table) p[size_t(c.grid) + 1]++;
+    for (int g = 0; g < ng; g++) p[size_t(g) + 1] += p[size_t(g)];
+    return p;
+}
+
 }  // namespace hg
 
 // The library's grid object.
@@ -301,12 +320,17 @@ class Carve {
     {
         int rc = block_alloc(block, bytes_, dev);
         if (rc) return rc;
-        char *q = static_cast<char *>(*block);
+        assign(*block);
+        return HG_OK;
+    }
+    // the pieces of a block of at least bytes() that the caller allocated
+    void assign(void *block)
+    {
+        char *q = static_cast<char *>(block);
         for (const Part &pt : parts_) {
             *pt.p = q;
             q += pt.bytes;
         }
-        return HG_OK;
     }
 
   private:
@@ -407,8 +431,13 @@ int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int pr
                         hipStream_t s);
 WalkArgs walk_args(const hg_grid *g, TraceStatus *st, const double *o, const double *k, int64_t n,
                    const hg_trace_opts *opts, hg_trace_out *out);
-int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
-                   int n_chunks, const hg_trace_opts *opts, bool fill, TraceStatus *st,
-                   hipStream_t s);
+// The batched walk in mode wm (WM_COUNT, WM_SLAB or WM_FILL) over queue Q.
+int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchQueue &Q, const hg_trace_opts *opts,
+                   int wm, TraceStatus *st, hipStream_t s);
+// One-pass batched records: rows (slab_args[g].leaf / ds) into the CSR slices
+// (fill_args[g]) of every chunk's paths (Q's table has at most max_chunks
+// entries); grids over capacity are flagged.
+int launch_slab_compact_batch(const WalkArgs *slab_args, const WalkArgs *fill_args, const BatchQueue &Q,
+                              int max_chunks, int precision, int pairs, TraceStatus *st, hipStream_t s);
 
 }  // namespace hg

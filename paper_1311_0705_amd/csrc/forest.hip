@@ -508,9 +508,25 @@ struct hg_batch {
     std::vector<hg_trace_out> outs;
     WalkArgs *dA = nullptr;
     BatchChunk *dC = nullptr;
+    int64_t *gpre = nullptr;               // [ng + 1] chunks per grid, prefix
+    unsigned long long *gctr = nullptr;    // [ng] chunks taken per grid (walk queue counters)
     int n_chunks = 0;
     int64_t *ctmp = nullptr;
     int64_t *totals = nullptr;
+    // one-pass records (unless two walks are asked for): the slab walk writes
+    // each path's first `slab` records into a row and saves the state of a
+    // path past its row; the rows are copied into the CSR slices and the
+    // saved paths resume in a filling walk over a device-built chunk table
+    bool one_pass = false;
+    int64_t slab = 0;
+    int pairs = 0;
+    WalkArgs *dAs = nullptr;               // slab-walk arguments (rows, resume arrays)
+    WalkArgs *dAf = nullptr;               // resume-walk arguments (CSR slices, resume arrays)
+    void *op_block = nullptr;              // rows, resume entries, counters, resume chunk table
+    unsigned long long *n_res = nullptr;   // [ng] resume entries per grid
+    int64_t *rc_prefix = nullptr;          // [ng + 1] resume chunks per grid, prefix
+    BatchChunk *dRC = nullptr;             // resume chunk table
+    int rc_cap = 0;
     // captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -524,12 +540,23 @@ void free_bound(hg_batch *b)
 {
     dfree(b->dA, nullptr);
     dfree(b->dC, nullptr);
+    dfree(b->gpre, nullptr);
+    dfree(b->gctr, nullptr);
+    b->gpre = nullptr;
+    b->gctr = nullptr;
     dfree(b->ctmp, nullptr);
     dfree(b->totals, nullptr);
+    dfree(b->dAs, nullptr);
+    dfree(b->dAf, nullptr);
+    dfree(b->op_block, nullptr);
     b->dA = nullptr;
     b->dC = nullptr;
     b->ctmp = nullptr;
     b->totals = nullptr;
+    b->dAs = nullptr;
+    b->dAf = nullptr;
+    b->op_block = nullptr;
+    b->one_pass = false;
     b->bound = false;
 }
 
@@ -545,6 +572,49 @@ void free_batch(hg_batch *b)
     block_free(b->tmp_block, b->tmp_bytes, b->dev);
     (void)hipDeviceSynchronize();
     delete b;
+}
+
+__global__ void __launch_bounds__(FT) k_f_zero_u64(unsigned long long *__restrict__ p, int n)
+{
+    for (int i = int(blockIdx.x) * FT + threadIdx.x; i < n; i += int(gridDim.x) * FT) p[i] = 0ull;
+}
+
+// Chunk table of the resume walk: per grid, its resume entries (at most its
+// path count) in chunks of `per`, grids in order; P its per-grid prefix.
+__global__ void __launch_bounds__(FT) k_f_resume_chunks(const WalkArgs *__restrict__ A, int ng, int64_t per,
+                                                        int64_t *__restrict__ P, BatchChunk *__restrict__ out)
+{
+    auto entries = [&](int g) {
+        const unsigned long long r = *A[g].n_resume;
+        return int64_t(r < (unsigned long long)A[g].n ? r : (unsigned long long)A[g].n);
+    };
+    block_prefix(ng, P, [&](int g) { return (entries(g) + per - 1) / per; });
+    __syncthreads();
+    for (int g = threadIdx.x; g < ng; g += FT) {
+        const int64_t nr = entries(g), base = P[g];
+        for (int64_t j = 0; j * per < nr; j++)
+            out[base + j] = BatchChunk{int32_t(g), int32_t(base), j * per, min(nr, (j + 1) * per)};
+    }
+}
+
+constexpr int64_t RESUME_CHUNK = 64;                        // resume entries per chunk
+constexpr double BATCH_SLAB_BUDGET = double(int64_t(8) << 30);
+constexpr int64_t BATCH_SLAB_MIN = 16;
+
+// Rows per path of the one-pass batched records mode for n paths in all: the
+// caller's slab rounded up to a multiple of 4, else the most that fit the
+// budget (at most SLAB_MAX); 0 (two walks) when fewer than BATCH_SLAB_MIN fit.
+int64_t batch_slab_rows(const hg_trace_opts *opts, int64_t n)
+{
+    const double per = double(4 + (opts->precision == HG_FP64 ? 8 : 4));
+    if (n <= 0) return 0;
+    if (opts->slab > 0) {
+        const int64_t k = (int64_t(opts->slab) + 3) / 4 * 4;
+        return double(n) * (double(k) * per + double(sizeof(Resume))) <= BATCH_SLAB_BUDGET ? k : 0;
+    }
+    const double fit = (BATCH_SLAB_BUDGET / double(n) - double(sizeof(Resume))) / per;
+    if (fit < double(BATCH_SLAB_MIN)) return 0;
+    return std::min<int64_t>(SLAB_MAX, int64_t(fit) / 4 * 4);
 }
 
 std::vector<BatchChunk> chunk_table(const std::vector<int64_t> &n, int64_t chunk)
@@ -600,18 +670,41 @@ int enqueue_build(hg_batch *b, hipStream_t s)
     return HG_OK;
 }
 
-int enqueue_trace(hg_batch *b, hipStream_t s)
+// The bound trace over chunk table C (nc entries; ctmp: its scan work
+// space) with launch options o: one-pass records (slab walk, offsets, row
+// copy, resume walk), or the counting walk and, for records, the filling walk.
+int trace_pipeline(hg_batch *b, const BatchChunk *C, const int64_t *gpre, int nc, int64_t *ctmp,
+                   const hg_trace_opts *o, hipStream_t s)
 {
-    if (!b->bound) return HG_E_INVAL;
     const WalkGrid *G = b->opts.precision == HG_FP64 ? b->w64 : b->w32;
+    const int ng = b->ng;
+    const BatchQueue Q{C, gpre, b->gctr, ng};
     k_f_reset_status<<<1, 1, 0, s>>>(b->status);
     HG_CHECK(hipGetLastError());
     int rc = HG_OK;
-    if (b->n_chunks > 0) rc = launch_batched(G, b->dA, b->dC, b->n_chunks, &b->opts, false, b->status, s);
+    if (b->one_pass) {
+        k_f_zero_u64<<<unsigned((ng + FT - 1) / FT), FT, 0, s>>>(b->n_res, ng);
+        HG_CHECK(hipGetLastError());
+        if (nc > 0) rc = launch_batched(G, b->dAs, Q, o, WM_SLAB, b->status, s);
+        if (!rc) rc = scan_chunks(C, nc, b->dAf, ng, ctmp, s);
+        if (!rc) rc = launch_slab_compact_batch(b->dAs, b->dAf, Q, nc, b->opts.precision, b->pairs, b->status, s);
+        if (rc) return rc;
+        k_f_resume_chunks<<<1, FT, 0, s>>>(b->dAs, ng, RESUME_CHUNK, b->rc_prefix, b->dRC);
+        HG_CHECK(hipGetLastError());
+        const BatchQueue R{b->dRC, b->rc_prefix, b->gctr, ng};
+        return launch_batched(G, b->dAf, R, o, WM_FILL, b->status, s);
+    }
+    if (nc > 0) rc = launch_batched(G, b->dA, Q, o, WM_COUNT, b->status, s);
     if (rc || b->opts.mode != HG_RECORDS) return rc;
-    rc = scan_chunks(b->dC, b->n_chunks, b->dA, b->ng, b->ctmp, s);
-    if (rc || b->n_chunks == 0) return rc;
-    return launch_batched(G, b->dA, b->dC, b->n_chunks, &b->opts, true, b->status, s);
+    rc = scan_chunks(C, nc, b->dA, ng, ctmp, s);
+    if (rc || nc == 0) return rc;
+    return launch_batched(G, b->dA, Q, o, WM_FILL, b->status, s);
+}
+
+int enqueue_trace(hg_batch *b, hipStream_t s)
+{
+    if (!b->bound) return HG_E_INVAL;
+    return trace_pipeline(b, b->dC, b->gpre, b->n_chunks, b->ctmp, &b->opts, s);
 }
 
 }  // namespace
@@ -716,6 +809,84 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     return HG_OK;
 }
 
+}  // extern "C"
+
+namespace hg {
+namespace {
+
+// One-pass records of a bound batch: rows, resume entries and the argument
+// arrays of the slab and resume walks.  Leaves the batch in two-walk mode
+// (HG_OK) when the rows would not fit the budget or cannot be allocated.
+int bind_one_pass(hg_batch *b, const std::vector<WalkArgs> &hA, const hg_trace_opts *opts)
+{
+    const int ng = b->ng;
+    int64_t total = 0;
+    std::vector<int64_t> pre(size_t(ng) + 1, 0);
+    int64_t rc_cap = 0;
+    for (int g = 0; g < ng; g++) {
+        pre[size_t(g) + 1] = pre[size_t(g)] + hA[size_t(g)].n;
+        rc_cap += (hA[size_t(g)].n + RESUME_CHUNK - 1) / RESUME_CHUNK;
+    }
+    total = pre[size_t(ng)];
+    const int64_t slab = batch_slab_rows(opts, total);
+    if (slab == 0 || rc_cap > int64_t(0x7fffffff)) return HG_OK;
+    const int pairs = opts->precision != HG_FP64 ? 1 : 0;   // FP32 rows of (leaf, ds32) pairs
+    const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
+    const size_t rl = size_t(slab) * (pairs ? 8 : 4), rd = pairs ? 0 : size_t(slab) * dsz;
+    Carve cv;
+    char *rows_l = nullptr, *rows_d = nullptr;
+    Resume *res = nullptr;
+    cv.add(&rows_l, size_t(total) * rl);
+    if (!pairs) cv.add(&rows_d, size_t(total) * rd);
+    cv.add(&res, size_t(std::max<int64_t>(total, 1)));
+    cv.add(&b->n_res, size_t(ng));
+    cv.add(&b->rc_prefix, size_t(ng) + 1);
+    cv.add(&b->dRC, size_t(std::max<int64_t>(rc_cap, 1)));
+    if (dalloc(&b->op_block, cv.bytes(), nullptr)) {
+        b->n_res = nullptr;
+        b->rc_prefix = nullptr;
+        b->dRC = nullptr;
+        return HG_OK;   // two walks instead
+    }
+    cv.assign(b->op_block);
+    std::vector<WalkArgs> hs(hA), hf(hA);
+    for (int g = 0; g < ng; g++) {
+        WalkArgs &S = hs[size_t(g)], &F = hf[size_t(g)];
+        const int64_t p0 = pre[size_t(g)];
+        S.leaf = reinterpret_cast<int32_t *>(rows_l + size_t(p0) * rl);
+        S.ds = pairs ? nullptr : static_cast<void *>(rows_d + size_t(p0) * rd);
+        S.offsets = nullptr;
+        S.capacity = S.n * slab;
+        S.slab = slab;
+        S.resume = res + p0;
+        S.n_resume = b->n_res + g;
+        S.pairs = pairs;
+        F.slab = slab;
+        F.resume = res + p0;
+        F.n_resume = nullptr;
+        F.pairs = 0;
+    }
+    int rc = dalloc_n(&b->dAs, size_t(ng), nullptr);
+    if (!rc) rc = dalloc_n(&b->dAf, size_t(ng), nullptr);
+    if (!rc) {
+        hipError_t e = hipMemcpy(b->dAs, hs.data(), sizeof(WalkArgs) * hs.size(), hipMemcpyHostToDevice);
+        if (!e) e = hipMemcpy(b->dAf, hf.data(), sizeof(WalkArgs) * hf.size(), hipMemcpyHostToDevice);
+        if (!e) e = hipDeviceSynchronize();
+        if (e) rc = set_hip_error(e);
+    }
+    if (rc) return rc;
+    b->slab = slab;
+    b->pairs = pairs;
+    b->rc_cap = int(rc_cap);
+    b->one_pass = true;
+    return HG_OK;
+}
+
+}  // namespace
+}  // namespace hg
+
+extern "C" {
+
 int batch_bind(hg_batch_t b, const double *const *origins, const double *const *dirs, const int64_t *n,
                const hg_trace_opts *opts, hg_trace_out *outs)
 {
@@ -767,17 +938,22 @@ int batch_bind(hg_batch_t b, const double *const *origins, const double *const *
         A.pairs = 0;
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
+    const std::vector<int64_t> hP = chunk_prefix(hC, b->ng);
     int rc = dalloc_n(&b->dA, size_t(b->ng), nullptr);
     if (!rc) rc = dalloc_n(&b->dC, std::max<size_t>(hC.size(), 1), nullptr);
+    if (!rc) rc = dalloc_n(&b->gpre, hP.size(), nullptr);
+    if (!rc) rc = dalloc_n(&b->gctr, size_t(b->ng), nullptr);
     if (!rc) rc = dalloc_n(&b->ctmp, scan_chunks_tmp_elems(int(hC.size())), nullptr);
     if (!rc) rc = dalloc_n(&b->totals, size_t(b->ng), nullptr);
     if (!rc) {
         hipError_t e = hipMemcpy(b->dA, hA.data(), sizeof(WalkArgs) * hA.size(), hipMemcpyHostToDevice);
         if (!e && !hC.empty())
             e = hipMemcpy(b->dC, hC.data(), sizeof(BatchChunk) * hC.size(), hipMemcpyHostToDevice);
+        if (!e) e = hipMemcpy(b->gpre, hP.data(), sizeof(int64_t) * hP.size(), hipMemcpyHostToDevice);
         if (!e) e = hipDeviceSynchronize();
         if (e) rc = set_hip_error(e);
     }
+    if (!rc && records && opts->passes != 2) rc = bind_one_pass(b, hA, opts);
     if (rc) {
         free_bound(b);
         return rc;
@@ -935,8 +1111,6 @@ int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream
 {
     if (!b || !b->bound) return HG_E_INVAL;
     hipStream_t s = (hipStream_t)stream;
-    const bool records = b->opts.mode == HG_RECORDS;
-    const WalkGrid *G = b->opts.precision == HG_FP64 ? b->w64 : b->w32;
     const int nchunk = int(sizeof BATCH_CHUNKS / sizeof *BATCH_CHUNKS);
     std::vector<std::vector<BatchChunk>> tables;
     size_t most = 1;
@@ -946,14 +1120,19 @@ int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream
     }
     if (most > size_t(0x7fffffff)) return HG_E_LIMIT;
     BatchChunk *dC = nullptr;
-    int64_t *ctmp = nullptr;
+    int64_t *ctmp = nullptr, *dP = nullptr;
+    const size_t ng1 = size_t(b->ng) + 1;
+    std::vector<std::vector<int64_t>> prefixes;
+    for (int c = 0; c < nchunk; c++) prefixes.push_back(chunk_prefix(tables[size_t(c)], b->ng));
     int rc = dalloc_n(&dC, most * size_t(nchunk), s);
     if (!rc) rc = dalloc_n(&ctmp, scan_chunks_tmp_elems(int(most)), s);
+    if (!rc) rc = dalloc_n(&dP, ng1 * size_t(nchunk), s);
     for (int c = 0; c < nchunk && !rc; c++) {
-        if (tables[size_t(c)].empty()) continue;
-        hipError_t e = hipMemcpyAsync(dC + size_t(c) * most, tables[size_t(c)].data(),
-                                      sizeof(BatchChunk) * tables[size_t(c)].size(),
+        hipError_t e = hipMemcpyAsync(dP + size_t(c) * ng1, prefixes[size_t(c)].data(), sizeof(int64_t) * ng1,
                                       hipMemcpyHostToDevice, s);
+        if (!e && !tables[size_t(c)].empty())
+            e = hipMemcpyAsync(dC + size_t(c) * most, tables[size_t(c)].data(),
+                               sizeof(BatchChunk) * tables[size_t(c)].size(), hipMemcpyHostToDevice, s);
         if (e) rc = set_hip_error(e);
     }
     hipEvent_t ev[4] = {};
@@ -968,27 +1147,18 @@ int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream
         int ci = 0;
         while (ci < nchunk - 1 && BATCH_CHUNKS[ci] != c.chunk) ci++;
         const BatchChunk *C = dC + size_t(ci) * most;
+        const int64_t *P = dP + size_t(ci) * ng1;
         const int nc = int(tables[size_t(ci)].size());
         *ms = INFINITY;
         for (int r = 0; r <= 3; r++) {
             HG_CHECK(hipEventRecord(ev[0], s));
-            k_f_reset_status<<<1, 1, 0, s>>>(b->status);
-            int rc2 = nc ? launch_batched(G, b->dA, C, nc, &c, false, b->status, s) : HG_OK;
+            const int rc2 = trace_pipeline(b, C, P, nc, ctmp, &c, s);
             if (rc2) return rc2;
             HG_CHECK(hipEventRecord(ev[1], s));
-            float t1 = 0.f, t2 = 0.f;
-            if (records) {
-                rc2 = scan_chunks(C, nc, b->dA, b->ng, ctmp, s);
-                if (rc2) return rc2;
-                HG_CHECK(hipEventRecord(ev[2], s));
-                rc2 = nc ? launch_batched(G, b->dA, C, nc, &c, true, b->status, s) : HG_OK;
-                if (rc2) return rc2;
-                HG_CHECK(hipEventRecord(ev[3], s));
-            }
-            HG_CHECK(hipEventSynchronize(records ? ev[3] : ev[1]));
-            HG_CHECK(hipEventElapsedTime(&t1, ev[0], ev[1]));
-            if (records) HG_CHECK(hipEventElapsedTime(&t2, ev[2], ev[3]));
-            if (r > 0) *ms = std::min(*ms, t1 + t2);
+            HG_CHECK(hipEventSynchronize(ev[1]));
+            float t = 0.f;
+            HG_CHECK(hipEventElapsedTime(&t, ev[0], ev[1]));
+            if (r > 0) *ms = std::min(*ms, t);
         }
         return HG_OK;
     };
@@ -1019,6 +1189,7 @@ int batch_tune(hg_batch_t b, hg_trace_opts *chosen, float *best_ms, void *stream
     (void)hipStreamSynchronize(s);
     dfree(dC, s);
     dfree(ctmp, s);
+    dfree(dP, s);
     if (rc) return rc;
     // rebind the queue with the winner (a captured graph is dropped)
     std::vector<const double *> o(size_t(b->ng)), k(size_t(b->ng));

@@ -1095,21 +1095,24 @@ __global__ void __launch_bounds__(BT)
 }
 
 // Batched walk over many grids in one persistent launch.  The device work
-// queue is a table of chunks (grid, path range); a wavefront takes one chunk
-// per atomic and keeps that grid's parameters (and its level table)
+// queue is a table of chunks (grid, path range), each grid's chunks together
+// with a counter per grid; a wavefront takes one chunk per atomic from the
+// grid it is on, starting from a grid spread by its index and moving to the
+// next grid when that one has no chunk left, so it stays on one grid for
+// many chunks.  It keeps that grid's parameters (and its level table)
 // uniform across its lanes, preparing the chunk's paths into its queue.
 // Before taking up a chunk of another grid it lets its lanes finish their
 // paths.  Octree and k-d grids mix freely: the tree type is a
 // wavefront-uniform branch.
 template <int PREC, int WM, int BT>
 __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
-                                             const BatchChunk *__restrict__ chunks, int n_chunks,
-                                             int refill_min, TraceStatus *st, LevelGeo *geo_all, Prep *ring_all,
-                                             uint32_t *stl, typename Lane<PREC, uint32_t>::DsT *stds)
+                                             const BatchQueue Q, int refill_min, TraceStatus *st,
+                                             LevelGeo *geo_all, Prep *ring_all, uint32_t *stl,
+                                             typename Lane<PREC, uint32_t>::DsT *stds)
 {
     using R = uint32_t;
     using DsT = typename Lane<PREC, R>::DsT;
-    constexpr bool STG = WM == WM_FILL;
+    constexpr bool STG = WM == WM_FILL || WM == WM_SLAB;   // record modes
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     LevelGeo *geo = geo_all + wid * NLEV;
@@ -1126,11 +1129,15 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
     int rhead = 0, rn = 0;
     int geo_tree = -1, geo_dm = -1;  // what the wavefront's level table was made for
     double geo_side = 0.0;
-    WalkGrid G;
-    WalkArgs A;
+    // the current grid's parameters, read in place (wavefront-uniform addresses)
+    const WalkGrid *Gp = grids;
+    const WalkArgs *Ap = args;
     unsigned long long rechecks = 0;
     uint32_t desc = 0;
     bool count_rechecks = false;
+    const int64_t gw = int64_t(blockIdx.x) * (BT / 64) + wid, tw = int64_t(gridDim.x) * (BT / 64);
+    int qg = int(gw * Q.ng / tw);    // the grid whose chunks the wavefront takes
+    int tried = 0;                   // grids found empty since its last chunk
     for (;;) {
         const bool want = ray < 0 && !done;
         const uint64_t wmask = __ballot(want);
@@ -1140,51 +1147,57 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
             if (nwant >= refill_min || !amask) {
                 while (rhead >= rn) {
                     if (cnext >= cend) {
-                        if (pc < 0 && !drained) {
-                            int c = 0;
-                            if (lane == 0)
-                                c = int(std::min<unsigned long long>(atomicAdd(&st->next_ray, 1ull), 0x7fffffffull));
-                            c = __builtin_amdgcn_readfirstlane(c);
-                            if (c >= n_chunks) drained = true;
-                            else pc = c;
+                        while (pc < 0 && !drained) {
+                            unsigned long long t = 0;
+                            if (lane == 0) t = atomicAdd(&Q.gctr[qg], 1ull);
+                            t = readfirstlane64(t);
+                            const int64_t c0 = Q.gpre[qg], nq = Q.gpre[qg + 1] - c0;
+                            if (t < (unsigned long long)nq) {
+                                pc = int(c0 + int64_t(t));
+                                tried = 0;
+                            } else if (++tried >= Q.ng) {
+                                drained = true;
+                            } else {
+                                qg = qg + 1 == Q.ng ? 0 : qg + 1;
+                            }
                         }
                         if (pc < 0) break;
-                        const int cg = __builtin_amdgcn_readfirstlane(chunks[pc].grid);
+                        const int cg = __builtin_amdgcn_readfirstlane(Q.chunks[pc].grid);
                         if (cg != gi && amask) break;   // let this grid's paths finish first
                         if (cg != gi) {
                             gi = cg;
-                            G = grids[gi];
-                            A = args[gi];
-                            count_rechecks = count_rechecks || A.count_rechecks;
-                            if (G.tree != geo_tree || G.dm != geo_dm || G.side != geo_side) {
-                                fill_levels(geo, G, lane, 64);
-                                geo_tree = G.tree;
-                                geo_dm = G.dm;
-                                geo_side = G.side;
+                            Gp = grids + gi;
+                            Ap = args + gi;
+                            count_rechecks = count_rechecks || Ap->count_rechecks;
+                            if (Gp->tree != geo_tree || Gp->dm != geo_dm || Gp->side != geo_side) {
+                                fill_levels(geo, *Gp, lane, 64);
+                                geo_tree = Gp->tree;
+                                geo_dm = Gp->dm;
+                                geo_side = Gp->side;
                                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                                 __builtin_amdgcn_wave_barrier();
                                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                             }
                         }
-                        cnext = chunks[pc].start;
-                        cend = chunks[pc].end;
+                        cnext = Q.chunks[pc].start;
+                        cend = Q.chunks[pc].end;
                         pc = -1;
                         // records of a grid that does not fit are not written
-                        if ((WM == WM_FILL) && A.offsets[A.n] > A.capacity) {
+                        if ((WM == WM_FILL) && Ap->offsets[Ap->n] > Ap->capacity) {
                             if (lane == 0) st->cap_overflow = 1;
                             cnext = cend;
                         }
                         continue;
                     }
-                    rn = G.tree == KD ? fill_queue<KD, PREC, WM, R>(G, A, ring, cnext, cend, lane, below)
-                                      : fill_queue<OCT, PREC, WM, R>(G, A, ring, cnext, cend, lane, below);
+                    rn = Gp->tree == KD ? fill_queue<KD, PREC, WM, R>(*Gp, *Ap, ring, cnext, cend, lane, below)
+                                      : fill_queue<OCT, PREC, WM, R>(*Gp, *Ap, ring, cnext, cend, lane, below);
                     rhead = 0;
                     cnext = std::min<int64_t>(cnext + 64, cend);
                 }
                 const int avail = rn - rhead;
                 if (want) {
                     const int rank = __popcll(wmask & below);
-                    if (rank < avail) ray = take_path<WM, PREC, R>(G, A, ring[rhead + rank], L);
+                    if (rank < avail) ray = take_path<WM, PREC, R>(*Gp, *Ap, ring[rhead + rank], L);
                     else if (drained && pc < 0 && cnext >= cend) done = true;
                 }
                 rhead += std::min(avail, nwant);
@@ -1197,20 +1210,20 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
         bool fin = false, crossed = false, bad = false;
         int32_t c_before = 0;
         if (ray >= 0)
-            fin = G.tree == KD ? walk_step<KD, PREC, WM, R, STG>(G, A, geo, L, ray, rechecks, desc, my_l, my_d,
+            fin = Gp->tree == KD ? walk_step<KD, PREC, WM, R, STG>(*Gp, *Ap, geo, L, ray, rechecks, desc, my_l, my_d,
                                                                  crossed, c_before, bad)
-                               : walk_step<OCT, PREC, WM, R, STG>(G, A, geo, L, ray, rechecks, desc, my_l, my_d,
+                               : walk_step<OCT, PREC, WM, R, STG>(*Gp, *Ap, geo, L, ray, rechecks, desc, my_l, my_d,
                                                                   crossed, c_before, bad);
         // every lane holds the wavefront's current grid, so A is uniform here
         if (STG) {
             int nr = 0;
             int64_t pos = 0;
             if (ray >= 0 && (crossed || bad)) stage_group<PREC, R>(L, crossed, c_before, fin, nr, pos);
-            flush_stage<DsT>(A, stl, stds, nr, pos, lane, wid * 64);
+            flush_stage<DsT>(*Ap, stl, stds, nr, pos, lane, wid * 64);
         }
         if (fin) {
             if (bad) st->bad_ref = 1;
-            finish_path<PREC, WM, R, STG>(A, ray, L);
+            finish_path<PREC, WM, R, STG>(*Ap, ray, L);
             ray = -1;
         }
     }
@@ -1221,27 +1234,34 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
 }
 
 template <int PREC, int BT>
-__global__ void __launch_bounds__(BT)
-    k_walk_batched_count(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
-                         const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min, TraceStatus *st)
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
+    k_walk_batched_count(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args, const BatchQueue Q,
+                         int refill_min, TraceStatus *st)
 {
     __shared__ LevelGeo geo_all[(BT / 64) * NLEV];
     __shared__ Prep ring_all[(BT / 64) * RING];
-    walk_batched<PREC, WM_COUNT, BT>(grids, args, chunks, n_chunks, refill_min, st, geo_all, ring_all, nullptr,
-                                     nullptr);
+    walk_batched<PREC, WM_COUNT, BT>(grids, args, Q, refill_min, st, geo_all, ring_all, nullptr, nullptr);
 }
 
-template <int PREC, int BT>
-__global__ void __launch_bounds__(BT)
-    k_walk_batched_fill(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
-                        const BatchChunk *__restrict__ chunks, int n_chunks, int refill_min, TraceStatus *st)
+// Record modes of the batched walk: WM_FILL (the chunks' paths, or with
+// resume entries in the arguments the paths past their rows) and WM_SLAB
+// (the one-pass walk into per-path rows).
+template <int PREC, int WM, int BT>
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
+    k_walk_batched_rec(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args, const BatchQueue Q,
+                       int refill_min, TraceStatus *st)
 {
     using DsT = typename Lane<PREC, uint32_t>::DsT;
     __shared__ LevelGeo geo_all[(BT / 64) * NLEV];
     __shared__ Prep ring_all[(BT / 64) * RING];
     __shared__ uint32_t stl[BT * SP];
     __shared__ DsT stds[BT * SP];
-    walk_batched<PREC, WM_FILL, BT>(grids, args, chunks, n_chunks, refill_min, st, geo_all, ring_all, stl, stds);
+    walk_batched<PREC, WM, BT>(grids, args, Q, refill_min, st, geo_all, ring_all, stl, stds);
+}
+
+__global__ void k_zero_counters(unsigned long long *__restrict__ c, int n)
+{
+    for (int i = int(blockIdx.x) * TB + threadIdx.x; i < n; i += int(gridDim.x) * TB) c[i] = 0ull;
 }
 
 template <int TREE, typename R>
@@ -1288,17 +1308,14 @@ __global__ void k_reset_counter(TraceStatus *st) { st->next_ray = 0ull; }
 constexpr int CP = 256;
 constexpr int CU = 4;
 
-template <typename DsT>
-__global__ void __launch_bounds__(TB)
-    k_slab_compact(const int32_t *__restrict__ sleaf, const DsT *__restrict__ sds, int64_t slab,
-                   const int32_t *__restrict__ count, const int64_t *__restrict__ offsets, int64_t n,
-                   int32_t *__restrict__ leaf, DsT *__restrict__ ds)
+// The copy of the rows of paths [p0, p0 + np) into their CSR slices, by one
+// block; off holds offsets[p0 .. p0 + np] (in LDS).  PAIRS: rows of (leaf,
+// ds32) pairs in rl, else leaf rows in rl and ds rows in rd.
+template <typename DsT, bool PAIRS>
+__device__ __forceinline__ void compact_piece(const void *__restrict__ rl, const DsT *__restrict__ rd,
+                                              int64_t slab, const int64_t *off, int64_t p0, int np,
+                                              int32_t *__restrict__ leaf, DsT *__restrict__ ds)
 {
-    __shared__ int64_t off[CP + 1];
-    const int64_t p0 = int64_t(blockIdx.x) * CP;
-    const int np = int(n - p0 < CP ? n - p0 : CP);
-    for (int j = threadIdx.x; j <= np; j += TB) off[j] = offsets[p0 + j];
-    __syncthreads();
     const int64_t d0 = off[0], d1 = off[np];
     int lo = 0;   // the path of the thread's previous record: the search starts there
     for (int64_t db = d0 + threadIdx.x; db < d1; db += int64_t(CU) * TB) {
@@ -1318,10 +1335,21 @@ __global__ void __launch_bounds__(TB)
         }
         int32_t lf[CU];
         DsT dv[CU];
+        if (PAIRS) {
+            const uint2 *srow = static_cast<const uint2 *>(rl);
 #pragma unroll
-        for (int u = 0; u < CU; u++) {
-            lf[u] = ok[u] ? sleaf[src[u]] : 0;
-            dv[u] = ok[u] ? sds[src[u]] : DsT(0);
+            for (int u = 0; u < CU; u++) {
+                const uint2 v = ok[u] ? srow[src[u]] : make_uint2(0u, 0u);
+                lf[u] = int32_t(v.x);
+                dv[u] = DsT(__uint_as_float(v.y));
+            }
+        } else {
+            const int32_t *sleaf = static_cast<const int32_t *>(rl);
+#pragma unroll
+            for (int u = 0; u < CU; u++) {
+                lf[u] = ok[u] ? sleaf[src[u]] : 0;
+                dv[u] = ok[u] ? rd[src[u]] : DsT(0);
+            }
         }
 #pragma unroll
         for (int u = 0; u < CU; u++) {
@@ -1334,43 +1362,53 @@ __global__ void __launch_bounds__(TB)
     }
 }
 
-// As k_slab_compact for rows of (leaf, ds32) pairs: one 8-byte load per record.
+// One-pass records mode: copy the rows of the slab (each path's first `slab`
+// records) into the CSR slices.  A block takes CP consecutive paths, whose
+// slices form one contiguous range of the output, and its threads walk that
+// range in order (coalesced writes), each finding its path by a binary search
+// over the block's offsets in LDS.  Each thread moves CU records per round
+// (TB apart), issuing all their loads before any store.  A path with more
+// records than its row gets its first `slab` here, the rest from the fill
+// walk.
+template <typename DsT, bool PAIRS>
 __global__ void __launch_bounds__(TB)
-    k_slab_compact_pairs(const uint2 *__restrict__ srow, int64_t slab, const int64_t *__restrict__ offsets,
-                         int64_t n, int32_t *__restrict__ leaf, float *__restrict__ ds)
+    k_slab_compact(const void *__restrict__ rl, const DsT *__restrict__ rd, int64_t slab,
+                   const int64_t *__restrict__ offsets, int64_t n, int32_t *__restrict__ leaf,
+                   DsT *__restrict__ ds)
 {
     __shared__ int64_t off[CP + 1];
     const int64_t p0 = int64_t(blockIdx.x) * CP;
     const int np = int(n - p0 < CP ? n - p0 : CP);
     for (int j = threadIdx.x; j <= np; j += TB) off[j] = offsets[p0 + j];
     __syncthreads();
-    const int64_t d0 = off[0], d1 = off[np];
-    int lo = 0;
-    for (int64_t db = d0 + threadIdx.x; db < d1; db += int64_t(CU) * TB) {
-        int64_t src[CU];
-        bool ok[CU];
-#pragma unroll
-        for (int u = 0; u < CU; u++) {
-            const int64_t d = db + int64_t(u) * TB;
-            int hi = np;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (off[mid] <= d) lo = mid;
-                else hi = mid;
-            }
-            ok[u] = d < d1 && d - off[lo] < slab;
-            src[u] = (p0 + lo) * slab + (d - off[lo]);
+    compact_piece<DsT, PAIRS>(rl, rd, slab, off, p0, np, leaf, ds);
+}
+
+// The same over the chunks of a batch: grid g's rows are in slab_args[g]
+// (leaf / ds), its CSR slices in fill_args[g].  A grid whose records exceed
+// its capacity is skipped (and flagged).
+template <typename DsT, bool PAIRS>
+__global__ void __launch_bounds__(TB)
+    k_slab_compact_batch(const WalkArgs *__restrict__ slab_args, const WalkArgs *__restrict__ fill_args,
+                         const BatchQueue Q, TraceStatus *st)
+{
+    __shared__ int64_t off[CP + 1];
+    const int64_t n_chunks = Q.gpre[Q.ng];
+    for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
+        const BatchChunk ch = Q.chunks[c];
+        const WalkArgs &S = slab_args[ch.grid];
+        const WalkArgs &F = fill_args[ch.grid];
+        if (F.offsets[F.n] > F.capacity) {
+            if (threadIdx.x == 0) st->cap_overflow = 1;
+            continue;
         }
-        uint2 v[CU];
-#pragma unroll
-        for (int u = 0; u < CU; u++) v[u] = ok[u] ? srow[src[u]] : make_uint2(0u, 0u);
-#pragma unroll
-        for (int u = 0; u < CU; u++) {
-            const int64_t d = db + int64_t(u) * TB;
-            if (ok[u]) {
-                leaf[d] = int32_t(v[u].x);
-                ds[d] = __uint_as_float(v[u].y);
-            }
+        for (int64_t p0 = ch.start; p0 < ch.end; p0 += CP) {
+            const int np = int(ch.end - p0 < CP ? ch.end - p0 : CP);
+            __syncthreads();
+            for (int j = threadIdx.x; j <= np; j += TB) off[j] = F.offsets[p0 + j];
+            __syncthreads();
+            compact_piece<DsT, PAIRS>(S.leaf, static_cast<const DsT *>(S.ds), S.slab, off, p0, np, F.leaf,
+                                      static_cast<DsT *>(F.ds));
         }
     }
 }
@@ -1486,37 +1524,46 @@ int dispatch_walk(const WalkGrid &G, const WalkArgs &A, int prec, int wm, int pe
 }
 
 template <int PREC, int WM, int BT>
-int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
-                     int n_chunks, int refill_min, TraceStatus *st, hipStream_t s)
+int launch_batched_t(const WalkGrid *grids, const WalkArgs *args, const BatchQueue &Q, int refill_min,
+                     TraceStatus *st, hipStream_t s)
 {
     const size_t lds = 0;   // the batched walks use static LDS only
-    const void *kern = WM == WM_FILL ? reinterpret_cast<const void *>(k_walk_batched_fill<PREC, BT>)
-                                     : reinterpret_cast<const void *>(k_walk_batched_count<PREC, BT>);
+    const void *kern = WM == WM_COUNT ? reinterpret_cast<const void *>(k_walk_batched_count<PREC, BT>)
+                                      : reinterpret_cast<const void *>(k_walk_batched_rec<PREC, WM, BT>);
     unsigned blocks = 0;
     {
         const int rc = occupancy_blocks(kern, BT, lds, &blocks);
         if (rc) return rc;
     }
-    k_reset_counter<<<1, 1, 0, s>>>(st);
+    k_zero_counters<<<unsigned((Q.ng + TB - 1) / TB), TB, 0, s>>>(Q.gctr, Q.ng);
     HG_CHECK(hipGetLastError());
-    if (WM == WM_FILL)
-        k_walk_batched_fill<PREC, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
-                                                                          refill_min, st);
+    if (WM == WM_COUNT)
+        k_walk_batched_count<PREC, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, Q, refill_min, st);
     else
-        k_walk_batched_count<PREC, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, chunks, n_chunks,
-                                                                         refill_min, st);
+        k_walk_batched_rec<PREC, WM, BT><<<dim3(blocks), dim3(BT), 0, s>>>(grids, args, Q, refill_min, st);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }
 
 template <int PREC, int WM>
-int launch_batched_b(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
-                     int n_chunks, int block, int refill_min, TraceStatus *st, hipStream_t s)
+int launch_batched_b(const WalkGrid *grids, const WalkArgs *args, const BatchQueue &Q, int block, int refill_min,
+                     TraceStatus *st, hipStream_t s)
 {
     switch (block) {
-    case 128: return launch_batched_t<PREC, WM, 128>(grids, args, chunks, n_chunks, refill_min, st, s);
-    case 512: return launch_batched_t<PREC, WM, 512>(grids, args, chunks, n_chunks, refill_min, st, s);
-    default: return launch_batched_t<PREC, WM, 256>(grids, args, chunks, n_chunks, refill_min, st, s);
+    case 128: return launch_batched_t<PREC, WM, 128>(grids, args, Q, refill_min, st, s);
+    case 512: return launch_batched_t<PREC, WM, 512>(grids, args, Q, refill_min, st, s);
+    default: return launch_batched_t<PREC, WM, 256>(grids, args, Q, refill_min, st, s);
+    }
+}
+
+template <int PREC>
+int launch_batched_p(const WalkGrid *grids, const WalkArgs *args, const BatchQueue &Q, int wm, int block,
+                     int refill_min, TraceStatus *st, hipStream_t s)
+{
+    switch (wm) {
+    case WM_FILL: return launch_batched_b<PREC, WM_FILL>(grids, args, Q, block, refill_min, st, s);
+    case WM_SLAB: return launch_batched_b<PREC, WM_SLAB>(grids, args, Q, block, refill_min, st, s);
+    default: return launch_batched_b<PREC, WM_COUNT>(grids, args, Q, block, refill_min, st, s);
     }
 }
 
@@ -1594,17 +1641,29 @@ WalkArgs walk_args(const hg_grid *g, TraceStatus *st, const double *o, const dou
     return A;
 }
 
-int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchChunk *chunks,
-                   int n_chunks, const hg_trace_opts *opts, bool fill, TraceStatus *st,
-                   hipStream_t s)
+int launch_batched(const WalkGrid *grids, const WalkArgs *args, const BatchQueue &Q, const hg_trace_opts *opts,
+                   int wm, TraceStatus *st, hipStream_t s)
 {
+    if (Q.ng <= 0) return HG_OK;
     const int refill_min = opts->refill_min > 0 ? std::min(opts->refill_min, 64) : DEFAULT_REFILL;
-    const int b = opts->block;
     if (opts->precision == HG_FP64)
-        return fill ? launch_batched_b<HG_FP64, WM_FILL>(grids, args, chunks, n_chunks, b, refill_min, st, s)
-                    : launch_batched_b<HG_FP64, WM_COUNT>(grids, args, chunks, n_chunks, b, refill_min, st, s);
-    return fill ? launch_batched_b<HG_FP32_RECHECK, WM_FILL>(grids, args, chunks, n_chunks, b, refill_min, st, s)
-                : launch_batched_b<HG_FP32_RECHECK, WM_COUNT>(grids, args, chunks, n_chunks, b, refill_min, st, s);
+        return launch_batched_p<HG_FP64>(grids, args, Q, wm, opts->block, refill_min, st, s);
+    return launch_batched_p<HG_FP32_RECHECK>(grids, args, Q, wm, opts->block, refill_min, st, s);
+}
+
+int launch_slab_compact_batch(const WalkArgs *slab_args, const WalkArgs *fill_args, const BatchQueue &Q,
+                              int max_chunks, int precision, int pairs, TraceStatus *st, hipStream_t s)
+{
+    if (max_chunks <= 0) return HG_OK;
+    const unsigned blocks = unsigned(std::min(max_chunks, 4096));
+    if (pairs && precision != HG_FP64)
+        k_slab_compact_batch<float, true><<<blocks, TB, 0, s>>>(slab_args, fill_args, Q, st);
+    else if (precision == HG_FP64)
+        k_slab_compact_batch<double, false><<<blocks, TB, 0, s>>>(slab_args, fill_args, Q, st);
+    else
+        k_slab_compact_batch<float, false><<<blocks, TB, 0, s>>>(slab_args, fill_args, Q, st);
+    HG_CHECK(hipGetLastError());
+    return HG_OK;
 }
 
 int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int precision, int pairs,
@@ -1615,14 +1674,15 @@ int launch_slab_compact(const void *sleaf, const void *sds, int64_t slab, int pr
     const int64_t nb = (n + CP - 1) / CP;
     if (nb > 0x7fffffff) return HG_E_LIMIT;
     const unsigned blocks = unsigned(nb);
+    (void)count;
     if (pairs && precision != HG_FP64)
-        k_slab_compact_pairs<<<blocks, TB, 0, s>>>((const uint2 *)sleaf, slab, offsets, n, leaf, (float *)ds);
+        k_slab_compact<float, true><<<blocks, TB, 0, s>>>(sleaf, nullptr, slab, offsets, n, leaf, (float *)ds);
     else if (precision == HG_FP64)
-        k_slab_compact<double><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const double *)sds, slab,
-                                                     count, offsets, n, leaf, (double *)ds);
+        k_slab_compact<double, false><<<blocks, TB, 0, s>>>(sleaf, (const double *)sds, slab, offsets, n, leaf,
+                                                            (double *)ds);
     else
-        k_slab_compact<float><<<blocks, TB, 0, s>>>((const int32_t *)sleaf, (const float *)sds, slab,
-                                                    count, offsets, n, leaf, (float *)ds);
+        k_slab_compact<float, false><<<blocks, TB, 0, s>>>(sleaf, (const float *)sds, slab, offsets, n, leaf,
+                                                           (float *)ds);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }

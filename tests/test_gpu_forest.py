@@ -61,15 +61,21 @@ def test_batch_build_equals_grid_build(clumps):
     b.free()
 
 
+# records: one walk into rows of the library's size, one walk into rows of 4
+# (nearly every path resumes past its row), and a counting plus a filling walk
+WALKS = {"one-pass": dict(), "rows4": dict(slab=4), "two-pass": dict(passes=2)}
+
+
+@pytest.mark.parametrize("walk", list(WALKS))
 @pytest.mark.parametrize("prec", [hg.FP32_RECHECK, hg.FP64], ids=["fp32r", "fp64"])
-def test_batch_trace_and_graph_replays(clumps, prec):
+def test_batch_trace_and_graph_replays(clumps, prec, walk):
     ws, singles, os_, ks_ = clumps
     ref = [g.trace(os_[i], ks_[i], precision=prec, mode=hg.RECORDS)
            for i, g in enumerate(singles)]
     caps = [2 * g.n_nodes + 64 for g in singles]
     b = _batch(ws, caps)
     res = b.bind(os_, ks_, precision=prec, mode=hg.RECORDS,
-                 capacities=[r["needed"] for r in ref], chunk=700, count_rechecks=True)
+                 capacities=[r["needed"] for r in ref], chunk=700, count_rechecks=True, **WALKS[walk])
 
     def check():
         for i, r in enumerate(ref):
@@ -140,7 +146,8 @@ def test_node_capacity_overrun_is_reported(clumps):
     b.free()
 
 
-def test_record_capacity_overrun_and_empty_batch(clumps):
+@pytest.mark.parametrize("walk", list(WALKS))
+def test_record_capacity_overrun_and_empty_batch(clumps, walk):
     ws, singles, os_, ks_ = clumps
     sel = [4, 5, 6]
     ref = [singles[i].trace(os_[i], ks_[i], precision=hg.FP32_RECHECK, mode=hg.RECORDS)
@@ -149,7 +156,7 @@ def test_record_capacity_overrun_and_empty_batch(clumps):
     o = [os_[4], os_[5][:0], os_[6]]
     k = [ks_[4], ks_[5][:0], ks_[6]]
     caps = [ref[0]["needed"], 0, ref[2]["needed"] - 1]
-    res = b.bind(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, capacities=caps)
+    res = b.bind(o, k, precision=hg.FP32_RECHECK, mode=hg.RECORDS, capacities=caps, **WALKS[walk])
     b.run(hg.STAGE_ALL)
     with pytest.raises(hg.HGError) as ei:
         b.result()
