@@ -20,6 +20,7 @@ _LIB = os.path.join(_HERE, "libhgrid_oracle.so")
 
 OCTREE = 0
 KDTREE = 1
+KDGRAD = 2   # k-d tree split across the axis of strongest density gradient (Sect. 2.2)
 
 
 def build(force: bool = False) -> str:
@@ -71,6 +72,11 @@ def lib():
         L.or_build.argtypes = [P, P, C.c_int, P, C.c_double, C.c_int64]
         L.or_import.restype = P
         L.or_import.argtypes = [C.c_int, P, C.c_double, C.c_int64, P, P]
+        L.or_import_axes.restype = P
+        L.or_import_axes.argtypes = [C.c_int, P, C.c_double, C.c_int64, P, P, P]
+        L.or_get_axes.argtypes = [P, P, P]
+        L.or_equal_mass_plane.restype = C.c_double
+        L.or_equal_mass_plane.argtypes = [P, P, P, C.c_int, C.c_int, C.c_int]
         L.or_free.argtypes = [P]
         L.or_n_nodes.restype = C.c_int64
         L.or_n_nodes.argtypes = [P]
@@ -225,11 +231,14 @@ class Grid:
         return cls(g, tree, d.lo, d.side)
 
     @classmethod
-    def from_first_child(cls, tree, first_child, rho=None, lo=(-1.0, -1.0, -1.0), side=2.0):
+    def from_first_child(cls, tree, first_child, rho=None, lo=(-1.0, -1.0, -1.0), side=2.0, axis=None):
+        """The tree of a first-child array (and, for KDGRAD, the per-node
+        split axes)."""
         fc = np.ascontiguousarray(first_child, dtype=np.int32)
         r = None if rho is None else _f64(rho)
         lo_a = _f64(lo)
-        g = lib().or_import(tree, _ptr(lo_a), side, fc.shape[0], _ptr(fc), _ptr(r))
+        ax = None if axis is None else np.ascontiguousarray(axis, dtype=np.int8)
+        g = lib().or_import_axes(tree, _ptr(lo_a), side, fc.shape[0], _ptr(fc), _ptr(ax), _ptr(r))
         return cls(g, tree, lo, side)
 
     # -- arrays ---------------------------------------------------------------
@@ -244,7 +253,11 @@ class Grid:
         lf = np.empty(n, np.int32)
         lib().or_get_nodes(self._h, _ptr(fc), _ptr(lv), _ptr(co), _ptr(S), _ptr(mn), _ptr(mx),
                            _ptr(lf))
-        return dict(first_child=fc, level=lv, coord=co, S=S, rmin=mn, rmax=mx, leaf_of=lf)
+        ax = np.empty(n, np.int8)
+        dep = np.empty((n, 3), np.uint8)
+        lib().or_get_axes(self._h, _ptr(ax), _ptr(dep))
+        return dict(first_child=fc, level=lv, coord=co, S=S, rmin=mn, rmax=mx, leaf_of=lf, axis=ax,
+                    depth=dep)
 
     def leaves(self) -> dict:
         n = self.n_leaves
@@ -314,3 +327,11 @@ class Grid:
         out = np.empty(max(cap, 1), np.int32)
         nf = lib().or_neighbors_brute(self._h, int(leaf), int(face), _ptr(out), cap)
         return out[:nf].copy()
+
+
+def equal_mass_plane(d, lo, hi, axis, m=64, iters=50) -> float:
+    """The plane across `axis` that splits the cell [lo, hi] into two parts of
+    equal mass (midpoint-rule masses on m^3 points, bisection)."""
+    h = _DensityHolder(d)
+    lo_a, hi_a = _f64(lo), _f64(hi)
+    return float(lib().or_equal_mass_plane(h.ref, _ptr(lo_a), _ptr(hi_a), int(axis), int(m), int(iters)))

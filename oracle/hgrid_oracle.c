@@ -18,6 +18,12 @@
  *                 delta = M/M_tot (Sect. 2.2, 4.1), the optical-depth
  *                 criterion of Eq. (2) and the density-dispersion criterion
  *                 q of Eq. (3), plus a maximum subdivision level (Sect. 4.2).
+ *                 Trees: octree, k-d tree with cyclic split axes, and the
+ *                 k-d variant of Sect. 2.2 that splits each node across the
+ *                 axis of strongest density gradient (midpoint planes).
+ *   or_equal_mass_plane  the equal-mass split location of Sect. 2.2 for one
+ *                 cell and axis (a reading for the scope of that variant; the
+ *                 trees above split at the midpoint).
  *   or_locate     top-down search for the leaf containing a point (Sect. 2.3).
  *   or_trace      the ordered list of leaves a straight path crosses, the
  *                 length ds inside each and tau = sum kappa rho ds (Sect. 2.3);
@@ -39,6 +45,8 @@
 
 #define OR_OCTREE 0
 #define OR_KDTREE 1
+#define OR_KDGRAD 2   /* k-d tree, split axis of strongest density gradient */
+#define OR_MAX_DEPTH 19   /* per-axis halvings the 19-bit cell coordinates allow */
 
 /* ------------------------------------------------------------------------ */
 /* Counter-based random numbers: SplitMix64 (Steele, Lea & Flood 2014).      */
@@ -153,6 +161,8 @@ typedef struct {
     int32_t *first_child;     /* -1 for a leaf; children are contiguous */
     uint8_t *level;
     uint32_t *coord;          /* [n][3], cell index at the per-axis depth */
+    uint8_t *dep;             /* [n][3], per-axis depth (halvings along each axis) */
+    int8_t *axis;             /* split axis of an internal k-d node, else -1 */
     double *S, *rmin, *rmax;  /* sum, min, max of the sampled densities */
     int64_t n_leaves;
     int32_t *leaf_of;         /* node -> leaf id, -1 for internal nodes */
@@ -162,21 +172,22 @@ typedef struct {
 
 /* Number of halvings a node at this level has seen along axis d.  Octree:
  * every level halves every axis.  k-d tree: level l splits axis l mod 3
- * (x, y, z, x, ...; Sect. 2.2), so axis d was halved floor((l+2-d)/3) times. */
+ * (x, y, z, x, ...; Sect. 2.2), so axis d was halved floor((l+2-d)/3) times.
+ * (The gradient k-d tree keeps each node's depths in g->dep.) */
 static int axis_depth(int tree, int level, int d)
 {
     return tree == OR_OCTREE ? level : (level + 2 - d) / 3;
 }
 
-static double cell_width(const or_grid *g, int level, int d)
+static double cell_width(const or_grid *g, int64_t n, int d)
 {
-    return ldexp(g->side, -axis_depth(g->tree, level, d));
+    return ldexp(g->side, -(int)g->dep[3 * n + d]);
 }
 
 static void node_box(const or_grid *g, int64_t n, double lo[3], double hi[3])
 {
     for (int d = 0; d < 3; d++) {
-        double w = cell_width(g, g->level[n], d);
+        double w = cell_width(g, n, d);
         uint32_t c = g->coord[3 * n + d];
         lo[d] = g->lo[d] + (double)c * w;
         hi[d] = g->lo[d] + (double)(c + 1) * w;
@@ -196,6 +207,8 @@ static int grow(or_grid *g, int64_t need)
     RE(first_child, int32_t, 1)
     RE(level, uint8_t, 1)
     RE(coord, uint32_t, 3)
+    RE(dep, uint8_t, 3)
+    RE(axis, int8_t, 1)
     RE(S, double, 1)
     RE(rmin, double, 1)
     RE(rmax, double, 1)
@@ -207,7 +220,7 @@ static int grow(or_grid *g, int64_t need)
 void or_free(or_grid *g)
 {
     if (!g) return;
-    free(g->first_child); free(g->level); free(g->coord);
+    free(g->first_child); free(g->level); free(g->coord); free(g->dep); free(g->axis);
     free(g->S); free(g->rmin); free(g->rmax);
     free(g->leaf_of); free(g->node_of); free(g->rho);
     free(g);
@@ -230,18 +243,28 @@ static int number_leaves(or_grid *g)
     return 0;
 }
 
+/* Random-number key of a node.  A gradient k-d node's depths are mixed into
+ * its code: nodes of one level may share coordinates at different depths. */
+static uint64_t node_key(uint64_t seed, int tree, int level, const uint32_t c[3], const uint8_t dep[3])
+{
+    uint64_t code = node_code(level, c);
+    if (tree == OR_KDGRAD)
+        code ^= or_splitmix64((uint64_t)dep[0] | ((uint64_t)dep[1] << 8) | ((uint64_t)dep[2] << 16));
+    return or_splitmix64(seed ^ or_splitmix64(code));
+}
+
 /* Eq. (1) sampling of one node: S = sum of rho_t at n_samples positions drawn
  * uniformly in the node, summed in sample order; min and max of the samples. */
 static void sample_node(const or_density *m, uint64_t seed, int tree, const double dom_lo[3],
-                        double side, int n_samples, int level, const uint32_t c[3],
+                        double side, int n_samples, int level, const uint32_t c[3], const uint8_t dep[3],
                         double *S, double *mn, double *mx)
 {
     double lo[3], w[3];
     for (int d = 0; d < 3; d++) {
-        w[d] = ldexp(side, -axis_depth(tree, level, d));
+        w[d] = ldexp(side, -(int)dep[d]);
         lo[d] = dom_lo[d] + (double)c[d] * w[d];
     }
-    uint64_t key = or_splitmix64(seed ^ or_splitmix64(node_code(level, c)));
+    uint64_t key = node_key(seed, tree, level, c, dep);
     double s = 0.0, lo_r = INFINITY, hi_r = -INFINITY;
     for (int j = 0; j < n_samples; j++) {
         double x[3];
@@ -285,16 +308,48 @@ static int decide_split(const or_criteria *cr, int level, or_crit v)
     return v.delta > cr->delta_max || v.tau > cr->tau_max || v.q > cr->q_max;
 }
 
+/* Split axis of a gradient k-d node (Sect. 2.2, the strongest density
+ * gradient).  The gradient along axis d is taken as the central difference
+ * |rho_t(x_c + w_d/4 e_d) - rho_t(x_c - w_d/4 e_d)| / (w_d/2) between the
+ * centres of the node's two halves across d.  Axes already at
+ * OR_MAX_DEPTH are not eligible; ties (a uniform region has no gradient at
+ * all) go to the axis with the fewest halvings, then the lowest index, which
+ * makes a uniform medium's tree the cyclic one.  Returns -1 if no axis is
+ * eligible. */
+static int gradient_axis(const or_density *m, const double dom_lo[3], double side, const uint32_t c[3],
+                         const uint8_t dep[3])
+{
+    double xc[3], w[3];
+    for (int d = 0; d < 3; d++) {
+        w[d] = ldexp(side, -(int)dep[d]);
+        xc[d] = dom_lo[d] + (double)c[d] * w[d] + 0.5 * w[d];
+    }
+    int best = -1;
+    double gbest = 0.0;
+    for (int d = 0; d < 3; d++) {
+        if (dep[d] >= OR_MAX_DEPTH) continue;
+        double xp[3] = {xc[0], xc[1], xc[2]}, xm[3] = {xc[0], xc[1], xc[2]};
+        xp[d] = xc[d] + 0.25 * w[d];
+        xm[d] = xc[d] - 0.25 * w[d];
+        double gd = fabs(density_at(m, xp) - density_at(m, xm)) / (0.5 * w[d]);
+        if (best < 0 || gd > gbest || (gd == gbest && dep[d] < dep[best])) {
+            best = d;
+            gbest = gd;
+        }
+    }
+    return best;
+}
+
 /* The construction loop of Sect. 2.2: the list starts with the root; one pass
  * over the growing list decides each node and appends the children of every
  * node that is split.  Returns NULL on allocation failure or bad input. */
 or_grid *or_build(const or_density *m, const or_criteria *cr, int tree,
                   const double dom_lo[3], double side, int64_t max_nodes)
 {
-    if (tree != OR_OCTREE && tree != OR_KDTREE) return NULL;
+    if (tree != OR_OCTREE && tree != OR_KDTREE && tree != OR_KDGRAD) return NULL;
     if (cr->n_samples <= 0 || cr->max_level < 0) return NULL;
     if (tree == OR_OCTREE && cr->max_level > 19) return NULL;
-    if (tree == OR_KDTREE && cr->max_level > 57) return NULL;
+    if (tree != OR_OCTREE && cr->max_level > 57) return NULL;
     or_grid *g = (or_grid *)calloc(1, sizeof(or_grid));
     if (!g) return NULL;
     g->tree = tree;
@@ -305,37 +360,48 @@ or_grid *or_build(const or_density *m, const or_criteria *cr, int tree,
     g->n_nodes = 1;
     g->level[0] = 0;
     g->coord[0] = g->coord[1] = g->coord[2] = 0;
+    g->dep[0] = g->dep[1] = g->dep[2] = 0;
     int nchild = tree == OR_OCTREE ? 8 : 2;
     for (int64_t i = 0; i < g->n_nodes; i++) {
         int lv = g->level[i];
         uint32_t c[3] = {g->coord[3 * i], g->coord[3 * i + 1], g->coord[3 * i + 2]};
-        sample_node(m, cr->seed, tree, g->lo, side, cr->n_samples, lv, c,
+        uint8_t dp[3] = {g->dep[3 * i], g->dep[3 * i + 1], g->dep[3 * i + 2]};
+        sample_node(m, cr->seed, tree, g->lo, side, cr->n_samples, lv, c, dp,
                     &g->S[i], &g->rmin[i], &g->rmax[i]);
         double w[3];
-        for (int d = 0; d < 3; d++) w[d] = cell_width(g, lv, d);
+        for (int d = 0; d < 3; d++) w[d] = cell_width(g, i, d);
         or_crit v = node_criteria(g->S[i], g->rmin[i], g->rmax[i], w, cr->n_samples,
                                   cr->total_mass, cr->kappa);
-        if (!decide_split(cr, lv, v)) {
+        g->axis[i] = -1;
+        int a = tree == OR_KDTREE ? lv % 3 : -1;     /* cyclic orientation */
+        if (decide_split(cr, lv, v) && tree == OR_KDGRAD) a = gradient_axis(m, g->lo, side, c, dp);
+        if (!decide_split(cr, lv, v) || (tree == OR_KDGRAD && a < 0)) {
             g->first_child[i] = -1;
             continue;
         }
+        if (tree != OR_OCTREE) g->axis[i] = (int8_t)a;
         if (max_nodes > 0 && g->n_nodes + nchild > max_nodes) { or_free(g); return NULL; }
         if (grow(g, g->n_nodes + nchild)) { or_free(g); return NULL; }
         int64_t f = g->n_nodes;
         g->first_child[i] = (int32_t)f;
         for (int k = 0; k < nchild; k++) {
             uint32_t cc[3] = {c[0], c[1], c[2]};
-            if (tree == OR_KDTREE) {
-                int a = lv % 3;                  /* cyclic orientation */
+            uint8_t cd[3] = {dp[0], dp[1], dp[2]};
+            if (tree != OR_OCTREE) {
                 cc[a] = 2 * c[a] + (uint32_t)k;  /* lower half, then upper half */
+                cd[a] = (uint8_t)(dp[a] + 1);
             } else {
-                for (int d = 0; d < 3; d++)      /* octant k = bx + 2 by + 4 bz */
+                for (int d = 0; d < 3; d++) {    /* octant k = bx + 2 by + 4 bz */
                     cc[d] = 2 * c[d] + (uint32_t)((k >> d) & 1);
+                    cd[d] = (uint8_t)(dp[d] + 1);
+                }
             }
             g->level[f + k] = (uint8_t)(lv + 1);
-            g->coord[3 * (f + k) + 0] = cc[0];
-            g->coord[3 * (f + k) + 1] = cc[1];
-            g->coord[3 * (f + k) + 2] = cc[2];
+            for (int d = 0; d < 3; d++) {
+                g->coord[3 * (f + k) + d] = cc[d];
+                g->dep[3 * (f + k) + d] = cd[d];
+            }
+            g->axis[f + k] = -1;
             g->first_child[f + k] = -1;
         }
         g->n_nodes += nchild;
@@ -348,13 +414,15 @@ or_grid *or_build(const or_density *m, const or_criteria *cr, int tree,
 }
 
 /* Rebuild a grid from a first-child array in list (breadth-first) order; levels
- * and cell coordinates follow from the tree.  rho may be NULL (then 0).  The
- * sampled statistics are left at zero.  Returns NULL if the array is not a
- * valid tree in list order. */
-or_grid *or_import(int tree, const double dom_lo[3], double side, int64_t n_nodes,
-                   const int32_t *first_child, const double *rho)
+ * and cell coordinates follow from the tree (and, for the gradient k-d tree,
+ * from axis[]: the split axis of each internal node).  rho may be NULL (then
+ * 0).  The sampled statistics are left at zero.  Returns NULL if the arrays
+ * are not a valid tree in list order. */
+or_grid *or_import_axes(int tree, const double dom_lo[3], double side, int64_t n_nodes,
+                        const int32_t *first_child, const int8_t *axis, const double *rho)
 {
-    if (n_nodes < 1 || (tree != OR_OCTREE && tree != OR_KDTREE)) return NULL;
+    if (n_nodes < 1 || (tree != OR_OCTREE && tree != OR_KDTREE && tree != OR_KDGRAD)) return NULL;
+    if (tree == OR_KDGRAD && !axis) return NULL;
     or_grid *g = (or_grid *)calloc(1, sizeof(or_grid));
     if (!g) return NULL;
     g->tree = tree;
@@ -371,6 +439,8 @@ or_grid *or_import(int tree, const double dom_lo[3], double side, int64_t n_node
     int maxlv = tree == OR_OCTREE ? 19 : 57;
     g->level[0] = 0;
     g->coord[0] = g->coord[1] = g->coord[2] = 0;
+    g->dep[0] = g->dep[1] = g->dep[2] = 0;
+    for (int64_t i = 0; i < n_nodes; i++) g->axis[i] = -1;
     int64_t expect = 1; /* next child slot in list order */
     for (int64_t i = 0; i < n_nodes; i++) {
         int32_t f = first_child[i];
@@ -381,22 +451,41 @@ or_grid *or_import(int tree, const double dom_lo[3], double side, int64_t n_node
         }
         expect += nchild;
         int lv = g->level[i];
+        int a = tree == OR_KDTREE ? lv % 3 : (tree == OR_KDGRAD ? axis[i] : -1);
+        if (tree == OR_KDGRAD && (a < 0 || a > 2 || g->dep[3 * i + a] >= OR_MAX_DEPTH)) {
+            or_free(g);
+            return NULL;
+        }
+        if (tree != OR_OCTREE) g->axis[i] = (int8_t)a;
         for (int k = 0; k < nchild; k++) {
             uint32_t cc[3] = {g->coord[3 * i], g->coord[3 * i + 1], g->coord[3 * i + 2]};
-            if (tree == OR_KDTREE) {
-                int a = lv % 3;
+            uint8_t cd[3] = {g->dep[3 * i], g->dep[3 * i + 1], g->dep[3 * i + 2]};
+            if (tree != OR_OCTREE) {
                 cc[a] = 2 * cc[a] + (uint32_t)k;
+                cd[a] = (uint8_t)(cd[a] + 1);
             } else {
-                for (int d = 0; d < 3; d++) cc[d] = 2 * cc[d] + (uint32_t)((k >> d) & 1);
+                for (int d = 0; d < 3; d++) {
+                    cc[d] = 2 * cc[d] + (uint32_t)((k >> d) & 1);
+                    cd[d] = (uint8_t)(cd[d] + 1);
+                }
             }
             g->level[f + k] = (uint8_t)(lv + 1);
-            for (int d = 0; d < 3; d++) g->coord[3 * (f + k) + d] = cc[d];
+            for (int d = 0; d < 3; d++) {
+                g->coord[3 * (f + k) + d] = cc[d];
+                g->dep[3 * (f + k) + d] = cd[d];
+            }
         }
     }
     if (expect != n_nodes) { or_free(g); return NULL; }
     if (number_leaves(g)) { or_free(g); return NULL; }
     for (int64_t l = 0; l < g->n_leaves; l++) g->rho[l] = rho ? rho[l] : 0.0;
     return g;
+}
+
+or_grid *or_import(int tree, const double dom_lo[3], double side, int64_t n_nodes,
+                   const int32_t *first_child, const double *rho)
+{
+    return or_import_axes(tree, dom_lo, side, n_nodes, first_child, NULL, rho);
 }
 
 /* Accessors for the test harness. */
@@ -413,6 +502,13 @@ void or_get_nodes(const or_grid *g, int32_t *first_child, uint8_t *level, uint32
     if (rmin) memcpy(rmin, g->rmin, n * sizeof(double));
     if (rmax) memcpy(rmax, g->rmax, n * sizeof(double));
     if (leaf_of) memcpy(leaf_of, g->leaf_of, n * sizeof(int32_t));
+}
+/* Per-node split axes (-1 for leaves and octree nodes) and per-axis depths. */
+void or_get_axes(const or_grid *g, int8_t *axis, uint8_t *dep)
+{
+    size_t n = (size_t)g->n_nodes;
+    if (axis) memcpy(axis, g->axis, n);
+    if (dep) memcpy(dep, g->dep, 3 * n);
 }
 void or_get_leaves(const or_grid *g, int32_t *node_of, double *rho)
 {
@@ -431,13 +527,16 @@ void or_leaf_boxes(const or_grid *g, double *lo, double *hi)
 }
 
 /* Sampled statistics and criteria of one node given by level and coordinates,
- * without building a tree (for spot checks of large builds). */
+ * without building a tree (for spot checks of large builds; octree and cyclic
+ * k-d trees, whose per-axis depths follow from the level). */
 void or_sample_node(const or_density *m, const or_criteria *cr, int tree, const double dom_lo[3],
                     double side, int level, const uint32_t c[3], double out[7])
 {
     double S, mn, mx, w[3];
-    sample_node(m, cr->seed, tree, dom_lo, side, cr->n_samples, level, c, &S, &mn, &mx);
-    for (int d = 0; d < 3; d++) w[d] = ldexp(side, -axis_depth(tree, level, d));
+    uint8_t dep[3];
+    for (int d = 0; d < 3; d++) dep[d] = (uint8_t)axis_depth(tree, level, d);
+    sample_node(m, cr->seed, tree, dom_lo, side, cr->n_samples, level, c, dep, &S, &mn, &mx);
+    for (int d = 0; d < 3; d++) w[d] = ldexp(side, -(int)dep[d]);
     or_crit v = node_criteria(S, mn, mx, w, cr->n_samples, cr->total_mass, cr->kappa);
     out[0] = S; out[1] = mn; out[2] = mx;
     out[3] = v.delta; out[4] = v.tau; out[5] = v.q;
@@ -488,10 +587,10 @@ static int64_t descend(const or_grid *g, const double x[3], const tie_rule *t)
         double lo[3], hi[3];
         node_box(g, n, lo, hi);
         int64_t f = g->first_child[n];
-        if (g->tree == OR_KDTREE) {
-            int a = lv % 3;
+        if (g->tree != OR_OCTREE) {
+            int a = g->axis[n];
             double mid = g->lo[a] + (double)(2 * g->coord[3 * n + a] + 1) *
-                                        ldexp(g->side, -(axis_depth(g->tree, lv, a) + 1));
+                                        ldexp(g->side, -((int)g->dep[3 * n + a] + 1));
             n = f + upper_side(t, a, x[a], mid);
         } else {
             int k = 0;
@@ -771,7 +870,7 @@ int64_t or_neighbors_brute(const or_grid *g, int64_t l, int f, int32_t *out, int
     int64_t me = g->node_of[l];
     int64_t mlo[3], mhi[3];
     for (int d = 0; d < 3; d++) {
-        int sh = D - axis_depth(g->tree, g->level[me], d);
+        int sh = D - (int)g->dep[3 * me + d];
         mlo[d] = (int64_t)g->coord[3 * me + d] << sh;
         mhi[d] = (int64_t)(g->coord[3 * me + d] + 1) << sh;
     }
@@ -780,7 +879,7 @@ int64_t or_neighbors_brute(const or_grid *g, int64_t l, int f, int32_t *out, int
         int64_t n = g->node_of[o];
         int64_t lo[3], hi[3];
         for (int d = 0; d < 3; d++) {
-            int sh = D - axis_depth(g->tree, g->level[n], d);
+            int sh = D - (int)g->dep[3 * n + d];
             lo[d] = (int64_t)g->coord[3 * n + d] << sh;
             hi[d] = (int64_t)(g->coord[3 * n + d] + 1) << sh;
         }
@@ -798,4 +897,45 @@ int64_t or_neighbors_brute(const or_grid *g, int64_t l, int f, int32_t *out, int
         }
     }
     return nf;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Equal-mass split location (Sect. 2.2, the second location option)        */
+/* ------------------------------------------------------------------------ */
+
+/* Mass of the slab [lo[d], x] of a cell across axis d, by the midpoint rule
+ * on an m x m x m grid of the slab. */
+static double slab_mass(const or_density *den, const double lo[3], const double hi[3], int d, double x, int m)
+{
+    double a[3] = {lo[0], lo[1], lo[2]}, b[3] = {hi[0], hi[1], hi[2]};
+    b[d] = x;
+    double h[3];
+    for (int e = 0; e < 3; e++) h[e] = (b[e] - a[e]) / (double)m;
+    double acc = 0.0;
+    for (int i = 0; i < m; i++)
+        for (int j = 0; j < m; j++)
+            for (int k = 0; k < m; k++) {
+                double p[3] = {a[0] + ((double)i + 0.5) * h[0], a[1] + ((double)j + 0.5) * h[1],
+                               a[2] + ((double)k + 0.5) * h[2]};
+                acc = acc + density_at(den, p);
+            }
+    return acc * h[0] * h[1] * h[2];
+}
+
+/* The plane across axis d that splits the cell [lo, hi] into two parts of
+ * equal mass: the cell's mass by the midpoint rule on m^3 points, then
+ * bisection (iters halvings of [lo_d, hi_d]) on the mass of the lower slab,
+ * each slab integrated the same way.  Returns the midpoint of the final
+ * bracket. */
+double or_equal_mass_plane(const or_density *den, const double lo[3], const double hi[3], int d, int m,
+                           int iters)
+{
+    const double half = 0.5 * slab_mass(den, lo, hi, d, hi[d], m);
+    double a = lo[d], b = hi[d];
+    for (int it = 0; it < iters; it++) {
+        const double x = 0.5 * (a + b);
+        if (slab_mass(den, lo, hi, d, x, m) < half) a = x;
+        else b = x;
+    }
+    return 0.5 * (a + b);
 }
