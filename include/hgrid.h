@@ -53,6 +53,13 @@ extern "C" {
 /* ---- enums ------------------------------------------------------------- */
 #define HG_OCTREE 0        /* regular 8-way split at the node centre (Sect. 2.1) */
 #define HG_KDTREE 1        /* 2-way split at the midpoint, axis cycling x,y,z (Sect. 2.2) */
+#define HG_KDGRAD 2        /* 2-way split at the midpoint across the axis of strongest density
+                              gradient (the orientation option of Sect. 2.2): the gradient along
+                              axis d is |rho(x_c + w_d/4 e_d) - rho(x_c - w_d/4 e_d)| / (w_d/2)
+                              between the centres of the node's halves; ties (no gradient) go to
+                              the axis halved least often, then the lowest; an axis halved 19
+                              times is not split again.  Built by grid_build with max_nodes 0 and
+                              by grid_import (with split_axis); walked with 64-bit references. */
 
 #define HG_FP64         0  /* every step of the walk in FP64 */
 #define HG_FP32_RECHECK 1  /* FP32 exit decision with FP64 re-anchoring and near-tie recheck */
@@ -171,13 +178,18 @@ typedef struct {
  * root; the children of a split node are contiguous (2 for a k-d tree, lower
  * then upper half; 8 for an octree, octant index bx + 2 by + 4 bz) and appear
  * in the order their parents do.  coord[3] is the cell index of the node
- * along each axis at that axis' depth (octree: level; k-d: floor((level+2-d)/3)).
+ * along each axis at that axis' depth (octree: level; k-d: floor((level+2-d)/3);
+ * gradient k-d: the halvings in geom).
  * rope[6] per leaf, faces -x,+x,-y,+y,-z,+z: the node index of the smallest
  * node containing the whole region just across that face (-1 on the domain
  * boundary); its subtree holds the face's neighbor list of Sect. 2.3.
+ * geom per node: halvings along x, y, z in bytes 0-2 and the split axis in
+ * bits 24-25 (3: a leaf or an octree node).
  * For grid_import only tree_type, lo, side, n_nodes, first_child and rho are
- * read (device pointers); the rest is ignored.  For grid_export every pointer
- * is a borrowed device pointer into the grid, valid until grid_free. */
+ * read (device pointers), and for HG_KDGRAD geom (the split axes of the
+ * internal nodes; its halvings are recomputed); the rest is ignored.  For
+ * grid_export every pointer is a borrowed device pointer into the grid,
+ * valid until grid_free. */
 typedef struct {
     int32_t tree_type;
     int32_t max_level;
@@ -194,6 +206,7 @@ typedef struct {
     const int32_t *leaf_of;     /* [n_nodes] leaf id or -1 */
     const int32_t *node_of;     /* [n_leaves] */
     const int32_t *rope;        /* [n_nodes][6] rope target of each face (node index, -1: domain face) */
+    const uint32_t *geom;       /* [n_nodes] per-axis halvings and split axis (see above) */
 } hg_grid_arrays;
 
 typedef struct hg_grid *hg_grid_t;
@@ -418,7 +431,8 @@ typedef struct hg_batch *hg_batch_t;
  * crit[g] and tree type tree_types[g] of every grid.  crit[g].max_nodes >= 1
  * is grid g's node capacity: all its device arrays (about 160 bytes per node)
  * are allocated now.  Synchronises the device.  Errors: HG_E_INVAL (as
- * grid_build, or max_nodes < 1, or n_grids outside 1..HG_MAX_BATCH),
+ * grid_build, or max_nodes < 1, or n_grids outside 1..HG_MAX_BATCH, or a
+ * HG_KDGRAD tree),
  * HG_E_DOMAIN, HG_E_LIMIT (max_nodes > 2^24), HG_E_OOM, HG_E_HIP. */
 int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit,
                  const int *tree_types, hg_batch_t *out);

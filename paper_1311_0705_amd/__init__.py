@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("HGRID_LIB") or os.path.join(_HERE, "libhgrid.so")
 
 OCTREE = 0
 KDTREE = 1
+KDGRAD = 2   # k-d tree split across the axis of strongest density gradient
 FP64 = 0
 FP32_RECHECK = 1
 TAU_ONLY = 0
@@ -99,7 +100,7 @@ class GridArrays(C.Structure):
         ("first_child", C.c_void_p), ("rho", C.c_void_p), ("level", C.c_void_p),
         ("coord", C.c_void_p), ("S", C.c_void_p), ("rho_min", C.c_void_p),
         ("rho_max", C.c_void_p), ("leaf_of", C.c_void_p), ("node_of", C.c_void_p),
-        ("rope", C.c_void_p),
+        ("rope", C.c_void_p), ("geom", C.c_void_p),
     ]
 
 
@@ -323,9 +324,15 @@ class Grid:
 
     @classmethod
     def from_arrays(cls, tree_type: int, first_child, rho, lo=(-1.0, -1.0, -1.0), side=2.0,
-                    stream=None, device="cuda"):
+                    stream=None, device="cuda", axis=None):
+        """grid_import; axis (KDGRAD): the split axis of every node (-1 for leaves)."""
         fc = torch.as_tensor(first_child, dtype=torch.int32).to(device).contiguous()
         r = torch.as_tensor(rho, dtype=torch.float64).to(device).contiguous()
+        gm = None
+        if axis is not None:
+            ax = torch.as_tensor(axis, dtype=torch.int64)
+            gm = torch.where(ax < 0, torch.full_like(ax, 3), ax) << 24
+            gm = gm.to(torch.int32).to(device).contiguous()
         a = GridArrays()
         a.tree_type = tree_type
         for i in range(3):
@@ -335,6 +342,8 @@ class Grid:
         a.n_leaves = r.numel()
         a.first_child = fc.data_ptr()
         a.rho = r.data_ptr()
+        if gm is not None:
+            a.geom = gm.data_ptr()
         h = C.c_void_p()
         rc = lib().grid_import(C.byref(a), _stream(stream), C.byref(h))
         _check(rc, "grid_import")
@@ -572,7 +581,14 @@ class Grid:
             leaf_of=cp(a.leaf_of, (N,), torch.int32),
             node_of=cp(a.node_of, (L,), torch.int32),
             rope=cp(a.rope, (N, 6), torch.int32),
+            geom=cp(a.geom, (N,), torch.int32) if a.geom else None,
         )
+
+    @staticmethod
+    def split_axes(geom) -> torch.Tensor:
+        """Split axis of every node from exported geom (-1: not split)."""
+        ax = (geom.to(torch.int64) >> 24) & 3
+        return torch.where(ax == 3, torch.full_like(ax, -1), ax).to(torch.int8)
 
 
 def tune_cached(grid: "Grid", origins, dirs, precision: int = FP32_RECHECK, mode: int = RECORDS,
@@ -685,8 +701,8 @@ def build(density, criteria, tree_type, stream=None, device="cuda", max_nodes=0)
 
 
 def import_grid(tree_type, first_child, rho, lo=(-1.0, -1.0, -1.0), side=2.0, stream=None,
-                device="cuda") -> Grid:
-    return Grid.from_arrays(tree_type, first_child, rho, lo, side, stream, device)
+                device="cuda", axis=None) -> Grid:
+    return Grid.from_arrays(tree_type, first_child, rho, lo, side, stream, device, axis)
 
 
 class Batch:

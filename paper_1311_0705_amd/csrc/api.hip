@@ -16,7 +16,8 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
 int build_single_batched(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_t s,
                          hg_grid **out);
 int import_structure(int tree, const std::vector<int32_t> &fc, std::vector<uint8_t> &level,
-                     std::vector<uint32_t> &coord, int64_t level_begin[64], int *max_level);
+                     std::vector<uint32_t> &coord, std::vector<uint32_t> &geom, int64_t level_begin[64],
+                     int *max_level);
 
 static thread_local int g_last_hip = 0;
 
@@ -72,7 +73,7 @@ void free_grid_arrays(hg_grid *g)
         block_free(g->block, g->block_bytes, g->block_dev);
         return;
     }
-    void *ptrs[] = {g->first_child, g->level, g->coord, g->S, g->rmin, g->rmax, g->rope,
+    void *ptrs[] = {g->first_child, g->level, g->coord, g->geom, g->S, g->rmin, g->rmax, g->rope,
                     g->leaf_of, g->int_of, g->node_of, g->rho, g->rec32, g->rec64, g->recw,
                     g->child, g->jump, g->table};
     for (void *p : ptrs) dfree(p, nullptr);
@@ -120,7 +121,7 @@ bool finite_nonneg(double x) { return x >= 0.0 && !isnan(x); }
 
 int check_build_args(const hg_density *dn, const hg_criteria *cr, int tree_type)
 {
-    if (tree_type != HG_OCTREE && tree_type != HG_KDTREE) return HG_E_INVAL;
+    if (tree_type != HG_OCTREE && tree_type != HG_KDTREE && tree_type != HG_KDGRAD) return HG_E_INVAL;
     int rc = check_domain(dn->lo, dn->side);
     if (rc) return rc;
     const int maxlv = tree_type == HG_OCTREE ? 19 : 57;
@@ -327,7 +328,7 @@ int grid_build(const hg_density *dn, const hg_criteria *cr, int tree_type, void 
     int rc = check_build_args(dn, cr, tree_type);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if (cr->max_nodes > 0 && cr->max_nodes <= MAX_IDS) {
+    if (cr->max_nodes > 0 && cr->max_nodes <= MAX_IDS && tree_type != HG_KDGRAD) {
         // a known capacity: the construction without per-level synchronisation
         hg_grid *gb = nullptr;
         rc = build_single_batched(dn, cr, tree_type, s, &gb);
@@ -351,21 +352,25 @@ int grid_import(const hg_grid_arrays *a, void *stream, hg_grid_t *out)
 {
     if (!a || !out) return HG_E_INVAL;
     *out = nullptr;
-    if (a->tree_type != HG_OCTREE && a->tree_type != HG_KDTREE) return HG_E_INVAL;
+    if (a->tree_type != HG_OCTREE && a->tree_type != HG_KDTREE && a->tree_type != HG_KDGRAD) return HG_E_INVAL;
     if (a->n_nodes < 1 || a->n_nodes >= (int64_t(1) << 31) || !a->first_child || !a->rho)
         return HG_E_INVAL;
+    if (a->tree_type == HG_KDGRAD && !a->geom) return HG_E_INVAL;
     int rc = check_domain(a->lo, a->side);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = a->n_nodes;
     std::vector<int32_t> fc((size_t)n);
+    std::vector<uint32_t> geom((size_t)n, 0u);
     HG_CHECK(hipMemcpyAsync(fc.data(), a->first_child, size_t(n) * 4, hipMemcpyDeviceToHost, s));
+    if (a->tree_type == HG_KDGRAD)
+        HG_CHECK(hipMemcpyAsync(geom.data(), a->geom, size_t(n) * 4, hipMemcpyDeviceToHost, s));
     HG_CHECK(hipStreamSynchronize(s));
     std::vector<uint8_t> level;
     std::vector<uint32_t> coord;
     hg_grid *g = new_grid(a->tree_type, a->lo, a->side);
     if (!g) return HG_E_OOM;
-    rc = import_structure(a->tree_type, fc, level, coord, g->level_begin, &g->max_level);
+    rc = import_structure(a->tree_type, fc, level, coord, geom, g->level_begin, &g->max_level);
     int64_t nl = 0;
     for (int32_t f : fc) nl += f < 0;
     if (!rc && nl != a->n_leaves) rc = HG_E_FORMAT;
@@ -376,7 +381,8 @@ int grid_import(const hg_grid_arrays *a, void *stream, hg_grid_t *out)
     g->n_nodes = n;
     const size_t N = size_t(n);
     if (dalloc_n(&g->first_child, N, s) || dalloc_n(&g->level, N, s) ||
-        dalloc_n(&g->coord, N * 3, s) || dalloc_n(&g->S, N, s) || dalloc_n(&g->rmin, N, s) ||
+        dalloc_n(&g->coord, N * 3, s) || dalloc_n(&g->geom, N, s) || dalloc_n(&g->S, N, s) ||
+        dalloc_n(&g->rmin, N, s) ||
         dalloc_n(&g->rmax, N, s) || dalloc_n(&g->rope, N * 6, s)) {
         (void)hipStreamSynchronize(s);
         destroy(g);
@@ -386,6 +392,7 @@ int grid_import(const hg_grid_arrays *a, void *stream, hg_grid_t *out)
     if (!e) e = hipMemcpyAsync(g->first_child, fc.data(), N * 4, hipMemcpyHostToDevice, s);
     if (!e) e = hipMemcpyAsync(g->level, level.data(), N, hipMemcpyHostToDevice, s);
     if (!e) e = hipMemcpyAsync(g->coord, coord.data(), N * 12, hipMemcpyHostToDevice, s);
+    if (!e) e = hipMemcpyAsync(g->geom, geom.data(), N * 4, hipMemcpyHostToDevice, s);
     if (!e) e = hipMemsetAsync(g->S, 0, N * 8, s);
     if (!e) e = hipMemsetAsync(g->rmin, 0, N * 8, s);
     if (!e) e = hipMemsetAsync(g->rmax, 0, N * 8, s);
@@ -427,6 +434,7 @@ int grid_export(hg_grid_t g, hg_grid_arrays *out)
     out->leaf_of = g->leaf_of;
     out->node_of = g->node_of;
     out->rope = g->rope;
+    out->geom = g->geom;
     return HG_OK;
 }
 

@@ -117,50 +117,68 @@ __global__ void __launch_bounds__(BT) k_bin_recs(Dens D, int64_t items, ClumpRec
 // ---- per-level kernels ------------------------------------------------------
 
 // G lanes per node of the level slice [begin, begin+count).
+// The split decision of a node completed by its split axis: a gradient k-d
+// node that is split takes the axis of gradient_axis (written into its
+// geometry) and stays a leaf when no axis is eligible; other trees keep the
+// decision as it is.
+__device__ inline bool settle_axis(int tree, const Dens &D, int lv, const uint32_t *c, uint32_t *gm, bool split,
+                                   const int64_t *__restrict__ bin_start)
+{
+    if (tree != KDG || !split) return split;
+    const uint32_t g = *gm;
+    const uint32_t cc[3] = {c[0], c[1], c[2]};
+    double w[3], lo[3];
+    node_box(tree, D, lv, g, cc, w, lo);
+    const int a = gradient_axis(D, lo, w, g, bin_start);
+    if (a < 0) return false;
+    *gm = (g & 0xFFFFFFu) | (uint32_t(a) << 24);
+    return true;
+}
+
 template <int G>
 __global__ void __launch_bounds__(BT)
     k_sample_decide_group(int tree, Dens D, CritDev C, int64_t begin, int64_t count,
                           const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
-                          const int64_t *__restrict__ bin_start, double *__restrict__ S_out,
-                          double *__restrict__ mn_out, double *__restrict__ mx_out,
+                          uint32_t *__restrict__ geom, const int64_t *__restrict__ bin_start,
+                          double *__restrict__ S_out, double *__restrict__ mn_out, double *__restrict__ mx_out,
                           uint8_t *__restrict__ split)
 {
     const int64_t t = (int64_t(blockIdx.x) * BT + threadIdx.x) / G;
     if (t >= count) return;  // the whole group leaves together
     const int64_t i = begin + t;
-    const NodeSample r = sample_node_group<G>(tree, D, C, level[i], coord[3 * i], coord[3 * i + 1],
+    const NodeSample r = sample_node_group<G>(tree, D, C, level[i], geom[i], coord[3 * i], coord[3 * i + 1],
                                               coord[3 * i + 2], bin_start);
     if ((threadIdx.x & (G - 1)) != 0) return;
     S_out[i] = r.S;
     mn_out[i] = r.mn;
     mx_out[i] = r.mx;
-    split[t] = r.split ? 1 : 0;
+    split[t] = settle_axis(tree, D, level[i], coord + 3 * i, geom + i, r.split, bin_start) ? 1 : 0;
 }
 
 // One lane per node of the level slice [begin, begin+count).
 __global__ void __launch_bounds__(BT)
     k_sample_decide(int tree, Dens D, CritDev C, int64_t begin, int64_t count,
                     const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
-                    const int64_t *__restrict__ bin_start, double *__restrict__ S_out,
+                    uint32_t *__restrict__ geom, const int64_t *__restrict__ bin_start, double *__restrict__ S_out,
                     double *__restrict__ mn_out, double *__restrict__ mx_out,
                     uint8_t *__restrict__ split)
 {
     const int64_t t = int64_t(blockIdx.x) * BT + threadIdx.x;
     if (t >= count) return;
     const int64_t i = begin + t;
-    const NodeSample r = sample_node_lane(tree, D, C, level[i], coord[3 * i], coord[3 * i + 1],
+    const NodeSample r = sample_node_lane(tree, D, C, level[i], geom[i], coord[3 * i], coord[3 * i + 1],
                                           coord[3 * i + 2], bin_start);
     S_out[i] = r.S;
     mn_out[i] = r.mn;
     mx_out[i] = r.mx;
-    split[t] = r.split ? 1 : 0;
+    split[t] = settle_axis(tree, D, level[i], coord + 3 * i, geom + i, r.split, bin_start) ? 1 : 0;
 }
 
 // Children of the split nodes of the level slice, in list order.
 __global__ void __launch_bounds__(BT)
     k_append(int tree, int64_t begin, int64_t count, int64_t next, const uint8_t *__restrict__ split,
              const int64_t *__restrict__ off, int32_t *__restrict__ fc, uint8_t *__restrict__ level,
-             uint32_t *__restrict__ coord)
+             uint32_t *__restrict__ coord, uint32_t *__restrict__ geom)
 {
     int64_t t = int64_t(blockIdx.x) * BT + threadIdx.x;
     if (t >= count) return;
@@ -175,22 +193,24 @@ __global__ void __launch_bounds__(BT)
     int lv = level[i];
     uint32_t c[3] = {coord[3 * i], coord[3 * i + 1], coord[3 * i + 2]};
     for (int k = 0; k < nc; k++) {
-        uint32_t cc[3];
-        child_coord(tree, lv, c, k, cc);
+        uint32_t cc[3], cgm;
+        child_coord(tree, geom[i], c, k, cc, &cgm);
         int64_t ch = f + k;
         level[ch] = uint8_t(lv + 1);
         coord[3 * ch] = cc[0];
         coord[3 * ch + 1] = cc[1];
         coord[3 * ch + 2] = cc[2];
+        geom[ch] = tree == KDG ? cgm : level_geom(tree, lv + 1);
         fc[ch] = -1;
     }
 }
 
-__global__ void k_init_root(int32_t *fc, uint8_t *level, uint32_t *coord)
+__global__ void k_init_root(int tree, int32_t *fc, uint8_t *level, uint32_t *coord, uint32_t *geom)
 {
     fc[0] = -1;
     level[0] = 0;
     coord[0] = coord[1] = coord[2] = 0;
+    geom[0] = tree == KDG ? geom_make(0, 0, 0, 3) : level_geom(tree, 0);
 }
 
 inline unsigned nblocks(int64_t n, int per) { return unsigned((n + per - 1) / per); }
@@ -217,6 +237,7 @@ int grow_nodes(hg_grid *g, int64_t used, int64_t *cap, int64_t need, hipStream_t
     if ((rc = grow_array(&g->first_child, used, c, 1, s))) return rc;
     if ((rc = grow_array(&g->level, used, c, 1, s))) return rc;
     if ((rc = grow_array(&g->coord, used, c, 3, s))) return rc;
+    if ((rc = grow_array(&g->geom, used, c, 1, s))) return rc;
     if ((rc = grow_array(&g->S, used, c, 1, s))) return rc;
     if ((rc = grow_array(&g->rmin, used, c, 1, s))) return rc;
     if ((rc = grow_array(&g->rmax, used, c, 1, s))) return rc;
@@ -364,7 +385,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
     int64_t cap = 0;
     rc = grow_nodes(g, 0, &cap, 4096, s);
     if (rc) return rc;
-    k_init_root<<<1, 1, 0, s>>>(g->first_child, g->level, g->coord);
+    k_init_root<<<1, 1, 0, s>>>(tree, g->first_child, g->level, g->coord, g->geom);
     HG_CHECK(hipGetLastError());
     DevBuf split(s), off(s), tmp(s);
     int64_t scap = 0;
@@ -383,7 +404,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
             scap = c;
         }
         const int gs = sample_group(cnt, density_group_min(D.n_clumps, store.bin_load));
-#define HG_SAMPLE_ARGS tree, D, C, begin, cnt, g->level, g->coord, bin_start, g->S, g->rmin, g->rmax, \
+#define HG_SAMPLE_ARGS tree, D, C, begin, cnt, g->level, g->coord, g->geom, bin_start, g->S, g->rmin, g->rmax, \
                        (uint8_t *)split.p
         switch (gs) {
         case 1: k_sample_decide<<<nblocks(cnt, BT), BT, 0, s>>>(HG_SAMPLE_ARGS); break;
@@ -407,7 +428,7 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
         if ((rc = grow_nodes(g, end, &cap, end + n_next, s))) return rc;
         k_append<<<nblocks(cnt, BT), BT, 0, s>>>(tree, begin, cnt, end, (const uint8_t *)split.p,
                                                  (const int64_t *)off.p, g->first_child, g->level,
-                                                 g->coord);
+                                                 g->coord, g->geom);
         HG_CHECK(hipGetLastError());
         lv++;
         g->level_begin[lv] = end;
@@ -422,34 +443,44 @@ int build_grid(const hg_density *dn, const hg_criteria *cr, int tree, hipStream_
     return finalize_layout(g, nullptr, cr->n_samples, s);
 }
 
-// Levels and cell coordinates of an imported breadth-first tree, on the host,
-// with the structural checks the node list must satisfy.
+// Levels, cell coordinates and geometry of an imported breadth-first tree,
+// on the host, with the structural checks the node list must satisfy.  For
+// a gradient k-d tree geom holds the split axes of the internal nodes on
+// entry (bits 24-25); every node's geometry is rewritten.
 int import_structure(int tree, const std::vector<int32_t> &fc, std::vector<uint8_t> &level,
-                     std::vector<uint32_t> &coord, int64_t level_begin[64], int *max_level)
+                     std::vector<uint32_t> &coord, std::vector<uint32_t> &geom, int64_t level_begin[64],
+                     int *max_level)
 {
     const int64_t n = int64_t(fc.size());
     const int nc = tree == OCT ? 8 : 2;
     const int maxlv = tree == OCT ? 19 : 57;
     level.assign(size_t(n), 0);
     coord.assign(size_t(n) * 3, 0);
+    if (tree != KDG) geom.assign(size_t(n), 0u);
+    if (geom.size() != size_t(n)) return HG_E_FORMAT;
+    geom[0] = tree == KDG ? geom_make(0, 0, 0, geom_axis(geom[0])) : level_geom(tree, 0);
     int64_t expect = 1;
     for (int64_t i = 0; i < n; i++) {
         int32_t f = fc[size_t(i)];
-        if (f < 0) continue;
+        const uint32_t gm = geom[size_t(i)];
+        if (f < 0) {
+            geom[size_t(i)] = (gm & 0xFFFFFFu) | (3u << 24);
+            continue;
+        }
         if (f != expect || int64_t(f) + nc > n || level[size_t(i)] >= maxlv) return HG_E_FORMAT;
+        if (tree == KDG && (geom_axis(gm) > 2 || geom_depth(gm, geom_axis(gm)) >= KDG_MAX_DEPTH))
+            return HG_E_FORMAT;
         expect += nc;
         int lv = level[size_t(i)];
         for (int k = 0; k < nc; k++) {
             uint32_t c[3] = {coord[3 * size_t(i)], coord[3 * size_t(i) + 1], coord[3 * size_t(i) + 2]};
-            if (tree == KD) {
-                int a = lv % 3;
-                c[a] = 2u * c[a] + uint32_t(k);
-            } else {
-                for (int d = 0; d < 3; d++) c[d] = 2u * c[d] + uint32_t((k >> d) & 1);
-            }
+            uint32_t cc[3], cgm;
+            child_coord(tree, gm, c, k, cc, &cgm);
             size_t ch = size_t(f) + size_t(k);
             level[ch] = uint8_t(lv + 1);
-            for (int d = 0; d < 3; d++) coord[3 * ch + d] = c[d];
+            for (int d = 0; d < 3; d++) coord[3 * ch + d] = cc[d];
+            // a gradient node's entry keeps the child's own split axis
+            geom[ch] = tree == KDG ? (cgm & 0xFFFFFFu) | (geom[ch] & (3u << 24)) : level_geom(tree, lv + 1);
         }
     }
     if (expect != n) return HG_E_FORMAT;

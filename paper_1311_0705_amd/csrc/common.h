@@ -34,6 +34,8 @@ namespace hg {
 
 constexpr int OCT = HG_OCTREE;
 constexpr int KD = HG_KDTREE;
+constexpr int KDG = HG_KDGRAD;     // k-d tree with per-node split axes
+constexpr int KDG_MAX_DEPTH = 19;  // halvings along one axis the cell coordinates allow
 
 constexpr int64_t MAX_IDS = int64_t(1) << 24;       // compact-layout id limit
 constexpr int DEPTH_BITS = 20;  // integer box resolution: per-axis depth <= 19
@@ -43,24 +45,63 @@ __host__ __device__ inline int axis_depth(int tree, int level, int d)
     return tree == OCT ? level : (level + 2 - d) / 3;
 }
 
-// Reference encoding for R = uint32_t (compact) or uint64_t (wide).
+// Reference encoding for R = uint32_t (compact) or uint64_t (wide).  Wide
+// references of a gradient k-d tree also carry the node's halvings along x
+// and y (z: the level minus both) and, for internal and twin nodes, its split
+// axis (GEO_SHIFT: x in bits 0-5, y in 6-11, axis in 12-13); other trees
+// leave those bits zero.
 template <typename R>
 struct Ref {
     static constexpr int BITS = int(sizeof(R) * 8);
     static constexpr int KIND_SHIFT = BITS - 2;
     static constexpr int LEVEL_SHIFT = BITS == 32 ? 24 : 56;
+    static constexpr int ID_BITS = BITS == 32 ? 24 : 40;
+    static constexpr int GEO_SHIFT = 40;
     static constexpr R NUL = ~R(0);
     enum { INTERNAL = 0, TWIN = 1, LEAF = 2 };
     __host__ __device__ static R make(int kind, int level, uint64_t id)
     {
         return (R(kind) << KIND_SHIFT) | (R(level) << LEVEL_SHIFT) | R(id);
     }
+    // with the per-axis halvings dx, dy and split axis ax (wide references)
+    __host__ __device__ static R make_geo(int kind, int level, uint64_t id, int dx, int dy, int ax)
+    {
+        const uint64_t g = uint64_t(dx) | (uint64_t(dy) << 6) | (uint64_t(ax & 3) << 12);
+        return make(kind, level, id) | (BITS == 64 ? R(g << GEO_SHIFT) : R(0));
+    }
     __host__ __device__ static int kind(R r) { return int(r >> KIND_SHIFT); }
     __host__ __device__ static bool leaf(R r) { return kind(r) == LEAF; }
     __host__ __device__ static bool twin(R r) { return kind(r) == TWIN; }
     __host__ __device__ static int level(R r) { return int((r >> LEVEL_SHIFT) & R(63)); }
-    __host__ __device__ static uint64_t id(R r) { return uint64_t(r & ((R(1) << LEVEL_SHIFT) - R(1))); }
+    __host__ __device__ static uint64_t id(R r) { return uint64_t(r & ((R(1) << ID_BITS) - R(1))); }
+    // halvings along axis d and the split axis (wide references of a gradient k-d tree)
+    __host__ __device__ static int depth(R r, int d)
+    {
+        const uint64_t g = uint64_t(r) >> (BITS == 64 ? GEO_SHIFT : 0);
+        const int dx = int(g & 63u), dy = int((g >> 6) & 63u);
+        return d == 0 ? dx : (d == 1 ? dy : level(r) - dx - dy);
+    }
+    __host__ __device__ static int axis(R r) { return int((uint64_t(r) >> (BITS == 64 ? GEO_SHIFT + 12 : 0)) & 3u); }
 };
+
+// Packed geometry of a node (hg_grid::geom): halvings along x, y, z in bytes
+// 0-2, split axis in bits 24-25 (3: not split).  Filled for every tree.
+__host__ __device__ inline int geom_depth(uint32_t gm, int d) { return int((gm >> (8 * d)) & 255u); }
+__host__ __device__ inline int geom_axis(uint32_t gm) { return int((gm >> 24) & 3u); }
+__host__ __device__ inline uint32_t geom_make(int dx, int dy, int dz, int ax)
+{
+    return uint32_t(dx) | (uint32_t(dy) << 8) | (uint32_t(dz) << 16) | (uint32_t(ax & 3) << 24);
+}
+// Split axis and halvings of node n of a tree (level lv): from the level for
+// octrees and cyclic k-d trees, from geom for the gradient k-d tree.
+__host__ __device__ inline int node_axis(int tree, int lv, const uint32_t *geom, int64_t n)
+{
+    return tree == KDG ? geom_axis(geom[n]) : (tree == KD ? lv % 3 : -1);
+}
+__host__ __device__ inline int node_depth(int tree, int lv, const uint32_t *geom, int64_t n, int d)
+{
+    return tree == KDG ? geom_depth(geom[n], d) : axis_depth(tree, lv, d);
+}
 
 struct alignas(32) LeafRec32 {
     uint32_t rope[6];
@@ -130,7 +171,9 @@ struct WalkGrid {
 // Finest per-axis depth of a tree whose levels go up to max_level.
 __host__ __device__ inline int finest_depth(int tree, int max_level)
 {
-    return axis_depth(tree, max_level < 0 ? 0 : max_level, 0);
+    const int ml = max_level < 0 ? 0 : max_level;
+    if (tree == KDG) return ml < KDG_MAX_DEPTH ? ml : KDG_MAX_DEPTH;
+    return axis_depth(tree, ml, 0);
 }
 
 // Locate table: a uniform grid of 2^tdep cells per axis over the domain; cell
@@ -260,6 +303,7 @@ struct hg_grid {
     hg::LeafRecW *recw;        // wide layout
     void *child;               // uint32_t or uint64_t references
     void *jump;                // k-d: three-level jump references (same type), or NULL
+    uint32_t *geom;            // per node: halvings per axis and split axis (geom_make), or NULL
     uint64_t root_ref;
     void *table;               // locate table (uint32_t or uint64_t references), or NULL
     int tdep;                  // its per-axis depth

@@ -160,7 +160,7 @@ __device__ __forceinline__ void sample_level_group(const ForestGrid *__restrict_
         const int64_t k = (w - PW[i]) * (64 / G) + lane / G;   // rank of the group's node in the level
         if (k < P[i + 1] - P[i]) {
             const int64_t n = Gr.meta[lv] + k;
-            const NodeSample r = sample_node_group<G>(Gr.tree, D, C, lv, Gr.coord[3 * n],
+            const NodeSample r = sample_node_group<G>(Gr.tree, D, C, lv, 0u, Gr.coord[3 * n],
                                                       Gr.coord[3 * n + 1], Gr.coord[3 * n + 2], Gr.bin_start);
             if ((lane & (G - 1)) == 0) {
                 Gr.S[n] = r.S;
@@ -189,7 +189,7 @@ __device__ __forceinline__ void sample_level_lane(const ForestGrid *__restrict__
         const int64_t k = (w - PW[i]) * 64 + lane;   // rank of the lane's node in the level
         if (k < P[i + 1] - P[i]) {
             const int64_t n = G.meta[lv] + k;
-            const NodeSample r = sample_node_lane(G.tree, D, C, lv, G.coord[3 * n], G.coord[3 * n + 1],
+            const NodeSample r = sample_node_lane(G.tree, D, C, lv, 0u, G.coord[3 * n], G.coord[3 * n + 1],
                                                   G.coord[3 * n + 2], G.bin_start);
             G.S[n] = r.S;
             G.rmin[n] = r.mn;
@@ -261,7 +261,8 @@ __global__ void __launch_bounds__(FT) k_f_append(const ForestGrid *__restrict__ 
         const uint32_t c[3] = {G.coord[3 * n], G.coord[3 * n + 1], G.coord[3 * n + 2]};
         for (int k = 0; k < G.nc; k++) {
             uint32_t cc[3];
-            child_coord(G.tree, lv, c, k, cc);
+            uint32_t cgm;
+            child_coord(G.tree, level_geom(G.tree, lv), c, k, cc, &cgm);
             const int64_t ch = f + k;
             G.level[ch] = uint8_t(lv + 1);
             G.coord[3 * ch] = cc[0];
@@ -720,6 +721,7 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     int lmax = 0;
     int64_t total_cap = 0;
     for (int i = 0; i < n_grids; i++) {
+        if (tree_types[i] == HG_KDGRAD) return HG_E_INVAL;   // built by grid_build only
         int rc = check_build_args(&dens[i], &crit[i], tree_types[i]);
         if (rc) return rc;
         if (crit[i].max_nodes < 1) return HG_E_INVAL;

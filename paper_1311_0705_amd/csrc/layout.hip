@@ -21,12 +21,12 @@ constexpr int LT = 256;
 __global__ void __launch_bounds__(LT)
     k_child_ropes(int tree, int64_t begin, int64_t count, int nc, const int32_t *__restrict__ fc,
                   const uint8_t *__restrict__ level, const uint32_t *__restrict__ coord,
-                  int32_t *__restrict__ rope)
+                  const uint32_t *__restrict__ geom, int32_t *__restrict__ rope)
 {
     const int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (t >= count * nc * 6) return;
     const int64_t q = t / 6;   // one thread per (node, child, face)
-    child_rope(tree, begin + q / nc, int(q % nc), int(t % 6), fc, level, coord, rope);
+    child_rope(tree, begin + q / nc, int(q % nc), int(t % 6), fc, level, coord, rope, geom);
 }
 
 __global__ void __launch_bounds__(LT) k_flag_leaves(const int32_t *__restrict__ fc, int64_t n,
@@ -88,7 +88,8 @@ __global__ void __launch_bounds__(LT)
                         const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
                         const int32_t *__restrict__ rope, const double *__restrict__ S,
                         const double *__restrict__ rho_in, double n_samples,
-                        double *__restrict__ rho, LeafRecW *__restrict__ recw)
+                        double *__restrict__ rho, LeafRecW *__restrict__ recw,
+                        const uint32_t *__restrict__ geom)
 {
     int64_t l = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (l >= n_leaves) return;
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(LT)
     LeafRecW a;
 #pragma unroll
     for (int j = 0; j < 6; j++)
-        a.rope[j] = encode<uint64_t>(rope[6 * int64_t(n) + j], nc, fc, level, leaf_of, int_of);
+        a.rope[j] = encode<uint64_t>(rope[6 * int64_t(n) + j], nc, fc, level, leaf_of, int_of, geom);
     a.rho64 = r;
     a.rho32 = float(r);
     a.pad = 0;
@@ -109,7 +110,7 @@ template <typename R>
 __global__ void __launch_bounds__(LT)
     k_child_refs(int64_t n, int nc, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                  const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
-                 R *__restrict__ child)
+                 R *__restrict__ child, const uint32_t *__restrict__ geom)
 {
     int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (t >= n * nc) return;
@@ -117,7 +118,7 @@ __global__ void __launch_bounds__(LT)
     int k = int(t % nc);
     int32_t f = fc[i];
     if (f < 0) return;
-    child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, nc, fc, level, leaf_of, int_of);
+    child[int64_t(int_of[i]) * nc + k] = encode<R>(f + k, nc, fc, level, leaf_of, int_of, geom);
 }
 
 // k-d jump references: one thread per (node, side triple) (see jump_ref).
@@ -138,14 +139,15 @@ template <typename R>
 __global__ void __launch_bounds__(LT)
     k_locate_table(int tree, int tdep, int nc, const int32_t *__restrict__ fc, const uint8_t *__restrict__ level,
                    const int32_t *__restrict__ leaf_of, const int32_t *__restrict__ int_of,
-                   R *__restrict__ table)
+                   R *__restrict__ table, const uint32_t *__restrict__ geom)
 {
     const int64_t cells = int64_t(1) << (3 * tdep);
     const int64_t t = int64_t(blockIdx.x) * LT + threadIdx.x;
     if (t >= cells) return;
     const uint32_t m = (1u << tdep) - 1u;
     const uint32_t c[3] = {uint32_t(t >> (2 * tdep)) & m, uint32_t(t >> tdep) & m, uint32_t(t) & m};
-    table[t] = encode<R>(table_node(tree, tdep, c, fc, level), nc, fc, level, leaf_of, int_of);
+    table[t] = encode<R>(table_node(tree, tdep, c, fc, level, geom), nc, fc, level, leaf_of, int_of,
+                         tree == KDG ? geom : nullptr);
 }
 
 inline unsigned blocks_for(int64_t n) { return unsigned((n + LT - 1) / LT); }
@@ -162,7 +164,7 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
         int64_t b = g->level_begin[l], e = g->level_begin[l + 1];
         if (e <= b) continue;
         k_child_ropes<<<blocks_for((e - b) * nc * 6), LT, 0, s>>>(g->tree, b, e - b, nc, g->first_child,
-                                                              g->level, g->coord, g->rope);
+                                                              g->level, g->coord, g->geom, g->rope);
         HG_CHECK(hipGetLastError());
     }
     // numbering
@@ -185,7 +187,10 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     g->n_leaves = n_leaves;
     g->n_internal = N - n_leaves;
     const char *force = getenv("HGRID_WIDE_REFS");
-    g->wide = (n_leaves > MAX_IDS || g->n_internal > MAX_IDS || (force && force[0] == '1')) ? 1 : 0;
+    // the gradient k-d tree's references carry per-node geometry: wide only
+    g->wide = (n_leaves > MAX_IDS || g->n_internal > MAX_IDS || g->tree == KDG || (force && force[0] == '1')) ? 1
+                                                                                                              : 0;
+    const uint32_t *gk = g->tree == KDG ? g->geom : nullptr;   // geometry carried by references
     const int64_t L = n_leaves, I = g->n_internal;
     const size_t rsz = g->wide ? 8 : 4;
     int arc = dalloc_n(&g->leaf_of, size_t(N), s);
@@ -207,7 +212,7 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
         k_leaf_records_wide<<<blocks_for(L), LT, 0, s>>>(L, nc, g->node_of, g->first_child, g->level,
                                                          g->leaf_of, g->int_of, g->rope, g->S,
                                                          rho_leaf, double(n_samples), g->rho,
-                                                         g->recw);
+                                                         g->recw, gk);
     else
         k_leaf_records<<<blocks_for(L), LT, 0, s>>>(L, nc, g->node_of, g->first_child, g->level,
                                                     g->leaf_of, g->int_of, g->rope, g->S, rho_leaf,
@@ -216,10 +221,10 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
     if (I > 0) {
         if (g->wide)
             k_child_refs<uint64_t><<<blocks_for(N * nc), LT, 0, s>>>(
-                N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->child);
+                N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->child, gk);
         else
             k_child_refs<uint32_t><<<blocks_for(N * nc), LT, 0, s>>>(
-                N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->child);
+                N, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->child, nullptr);
         HG_CHECK(hipGetLastError());
         if (g->jump) {
             if (g->wide)
@@ -244,10 +249,12 @@ int finalize_layout(hg_grid *g, const double *rho_leaf, int n_samples, hipStream
         }
         if (g->wide)
             k_locate_table<uint64_t><<<blocks_for(cells), LT, 0, s>>>(
-                g->tree, g->tdep, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->table);
+                g->tree, g->tdep, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint64_t *)g->table,
+                g->geom);
         else
             k_locate_table<uint32_t><<<blocks_for(cells), LT, 0, s>>>(
-                g->tree, g->tdep, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->table);
+                g->tree, g->tdep, nc, g->first_child, g->level, g->leaf_of, g->int_of, (uint32_t *)g->table,
+                g->geom);
         HG_CHECK(hipGetLastError());
     }
     dfree(flag, s);

@@ -29,14 +29,15 @@ struct SelectState {
 
 __global__ void __launch_bounds__(RT)
     k_leaf_tau(int tree, double side, const int32_t *__restrict__ node_of, const uint8_t *__restrict__ level,
-               const double *__restrict__ S, double kappa, int n_samples, int64_t n, double *__restrict__ out)
+               const uint32_t *__restrict__ geom, const double *__restrict__ S, double kappa, int n_samples,
+               int64_t n, double *__restrict__ out)
 {
     const int64_t l = int64_t(blockIdx.x) * RT + threadIdx.x;
     if (l >= n) return;
     const int32_t nd = node_of[l];
     const int lv = level[nd];
     double w[3];
-    for (int d = 0; d < 3; d++) w[d] = ldexp(side, -axis_depth(tree, lv, d));
+    for (int d = 0; d < 3; d++) w[d] = ldexp(side, -node_depth(tree, lv, geom, nd, d));
     out[l] = node_tau(kappa, S[nd], w, n_samples);
 }
 
@@ -140,7 +141,7 @@ int grid_leaf_tau(hg_grid_t g, double kappa, int n_samples, double *tau_out, voi
     if (!g || !tau_out || n_samples < 1 || !(kappa >= 0.0) || !isfinite(kappa)) return HG_E_INVAL;
     if (g->n_leaves == 0) return HG_OK;
     k_leaf_tau<<<unsigned((g->n_leaves + RT - 1) / RT), RT, 0, (hipStream_t)stream>>>(
-        g->tree, g->side, g->node_of, g->level, g->S, kappa, n_samples, g->n_leaves, tau_out);
+        g->tree, g->side, g->node_of, g->level, g->geom, g->S, kappa, n_samples, g->n_leaves, tau_out);
     HG_CHECK(hipGetLastError());
     return HG_OK;
 }

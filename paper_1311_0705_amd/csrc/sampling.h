@@ -26,10 +26,14 @@ __device__ inline uint64_t splitmix64(uint64_t x)
     return z ^ (z >> 31);
 }
 
-// Node code: level in bits 57.., cell coordinates in 19-bit fields.
-__device__ inline uint64_t node_key(uint64_t seed, int level, uint32_t c0, uint32_t c1, uint32_t c2)
+// Node code: level in bits 57.., cell coordinates in 19-bit fields; a
+// gradient k-d node's halvings per axis are mixed in (nodes of one level may
+// share coordinates at different halvings).
+__device__ inline uint64_t node_key(uint64_t seed, int tree, int level, uint32_t gm, uint32_t c0, uint32_t c1,
+                                    uint32_t c2)
 {
     uint64_t code = (uint64_t(level) << 57) | (uint64_t(c0) << 38) | (uint64_t(c1) << 19) | uint64_t(c2);
+    if (tree == KDG) code ^= splitmix64(uint64_t(gm & 0xFFFFFFu));
     return splitmix64(seed ^ splitmix64(code));
 }
 
@@ -120,26 +124,59 @@ __device__ inline NodeSample decide_node(const CritDev &C, int lv, const double 
     return NodeSample{S, mn, mx, sp};
 }
 
-__device__ inline void node_box(int tree, const Dens &D, int lv, const uint32_t c[3], double w[3], double lo[3])
+__device__ inline void node_box(int tree, const Dens &D, int lv, uint32_t gm, const uint32_t c[3], double w[3],
+                                double lo[3])
 {
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        w[d] = ldexp(D.side, -axis_depth(tree, lv, d));
+        w[d] = ldexp(D.side, -(tree == KDG ? geom_depth(gm, d) : axis_depth(tree, lv, d)));
         lo[d] = D.lo[d] + double(c[d]) * w[d];
     }
+}
+
+// Split axis of a gradient k-d node with box lo + [0, w] and halvings dep[]
+// (the orientation option of Sect. 2.2): the axis of the largest central
+// difference |rho(x_c + w_d/4 e_d) - rho(x_c - w_d/4 e_d)| / (w_d/2) between
+// the centres of the node's halves; ties go to the axis halved least often,
+// then the lowest; axes halved KDG_MAX_DEPTH times are not eligible.  -1 if
+// none is.
+__device__ inline int gradient_axis(const Dens &D, const double lo[3], const double w[3], uint32_t gm,
+                                    const int64_t *__restrict__ bin_start)
+{
+    double xc[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) xc[d] = lo[d] + 0.5 * w[d];
+    int best = -1, dbest = 0;
+    double gbest = 0.0;
+    for (int d = 0; d < 3; d++) {
+        const int dd = geom_depth(gm, d);
+        if (dd >= KDG_MAX_DEPTH) continue;
+        double xp[3] = {xc[0], xc[1], xc[2]}, xm[3] = {xc[0], xc[1], xc[2]};
+        xp[d] = xc[d] + 0.25 * w[d];
+        xm[d] = xc[d] - 0.25 * w[d];
+        const double rp = density_at(D, xp[0], xp[1], xp[2], bin_start);
+        const double rm = density_at(D, xm[0], xm[1], xm[2], bin_start);
+        const double gd = fabs(rp - rm) / (0.5 * w[d]);
+        if (best < 0 || gd > gbest || (gd == gbest && dd < dbest)) {
+            best = d;
+            gbest = gd;
+            dbest = dd;
+        }
+    }
+    return best;
 }
 
 // One node per lane: samples j = 0 .. N-1 are drawn and summed in order, so
 // S is the sequential sum of Eq. (1) with no cross-lane reduction (the lanes
 // of a wavefront take different nodes).
-__device__ inline NodeSample sample_node_lane(int tree, const Dens &D, const CritDev &C, int lv,
+__device__ inline NodeSample sample_node_lane(int tree, const Dens &D, const CritDev &C, int lv, uint32_t gm,
                                               uint32_t c0, uint32_t c1, uint32_t c2,
                                               const int64_t *__restrict__ bin_start)
 {
     const uint32_t c[3] = {c0, c1, c2};
     double w[3], lo[3];
-    node_box(tree, D, lv, c, w, lo);
-    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
+    node_box(tree, D, lv, gm, c, w, lo);
+    const uint64_t key = node_key(C.seed, tree, lv, gm, c0, c1, c2);
     double S = 0.0, mn = INFINITY, mx = -INFINITY;
     for (int j = 0; j < C.n_samples; j++) {
         const double x0 = lo[0] + sample_unit(key, j, 0) * w[0];
@@ -177,15 +214,15 @@ __device__ inline double group_read_f64(double v, int j)
 // shorten the sequence of samples per lane on levels too small to fill the
 // chip.
 template <int G>
-__device__ inline NodeSample sample_node_group(int tree, const Dens &D, const CritDev &C, int lv,
+__device__ inline NodeSample sample_node_group(int tree, const Dens &D, const CritDev &C, int lv, uint32_t gm,
                                                uint32_t c0, uint32_t c1, uint32_t c2,
                                                const int64_t *__restrict__ bin_start)
 {
     const int l = threadIdx.x & (G - 1);
     const uint32_t c[3] = {c0, c1, c2};
     double w[3], lo[3];
-    node_box(tree, D, lv, c, w, lo);
-    const uint64_t key = node_key(C.seed, lv, c0, c1, c2);
+    node_box(tree, D, lv, gm, c, w, lo);
+    const uint64_t key = node_key(C.seed, tree, lv, gm, c0, c1, c2);
     double S = 0.0, mn = INFINITY, mx = -INFINITY;
     for (int base = 0; base < C.n_samples; base += G) {
         const int j = base + l;
@@ -240,19 +277,34 @@ __host__ __device__ inline int sample_group(int64_t n, int gmin)
     return g < gmin ? gmin : g;
 }
 
-// Level and cell coordinates of child k of a node (k-d: split axis level mod
-// 3, lower half first; octree: octant k = bx + 2 by + 4 bz).
-__host__ __device__ inline void child_coord(int tree, int lv, const uint32_t c[3], int k, uint32_t cc[3])
+// Cell coordinates and geometry of child k of a node with geometry gm (k-d:
+// across its split axis, lower half first; octree: octant k = bx + 2 by +
+// 4 bz).  The child's split axis is left open (3).
+__host__ __device__ inline void child_coord(int tree, uint32_t gm, const uint32_t c[3], int k, uint32_t cc[3],
+                                            uint32_t *cgm)
 {
     cc[0] = c[0];
     cc[1] = c[1];
     cc[2] = c[2];
-    if (tree == KD) {
-        const int a = lv % 3;
+    int dep[3] = {geom_depth(gm, 0), geom_depth(gm, 1), geom_depth(gm, 2)};
+    if (tree != OCT) {
+        const int a = geom_axis(gm);
         cc[a] = 2u * c[a] + uint32_t(k);
+        dep[a]++;
     } else {
-        for (int d = 0; d < 3; d++) cc[d] = 2u * c[d] + uint32_t((k >> d) & 1);
+        for (int d = 0; d < 3; d++) {
+            cc[d] = 2u * c[d] + uint32_t((k >> d) & 1);
+            dep[d]++;
+        }
     }
+    *cgm = geom_make(dep[0], dep[1], dep[2], 3);
+}
+
+// Geometry of a node of an octree or cyclic k-d tree at level lv.
+__host__ __device__ inline uint32_t level_geom(int tree, int lv)
+{
+    return geom_make(axis_depth(tree, lv, 0), axis_depth(tree, lv, 1), axis_depth(tree, lv, 2),
+                     tree == KD ? lv % 3 : 3);
 }
 
 }  // namespace hg

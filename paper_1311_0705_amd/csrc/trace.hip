@@ -134,6 +134,38 @@ __device__ __forceinline__ void fill_levels(LevelGeo *geo, const WalkGrid &G, in
     for (int j = t0; j < NLEV; j += nt) geo[j] = make_level(G.tree, G.dm, G.side, j);
 }
 
+// Geometry of a gradient k-d node from its (wide) reference, in the fields
+// of a level record: widths from the halvings the reference carries, the
+// FP32 recheck threshold from the smallest width, and the split axis with
+// its half width.
+template <typename R>
+__device__ __forceinline__ LevelGeo ref_geo(const WalkGrid &G, R ref)
+{
+    LevelGeo e;
+    double wmin = INFINITY;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        const int dep = Ref<R>::depth(ref, d);
+        const int sh = G.dm - dep;
+        e.W[d] = sh >= 0 && sh < 32 ? 1u << sh : 0u;
+        e.w[d] = ldexp(G.side, -dep);
+        wmin = e.w[d] < wmin ? e.w[d] : wmin;
+    }
+    e.guard = 1e-5f * float(wmin);
+    const int a = Ref<R>::axis(ref);
+    const int sa = G.dm - Ref<R>::depth(ref, a) - 1;
+    e.axis = a;
+    e.hw = sa >= 0 && sa < 32 ? 1u << sa : 0u;
+    return e;
+}
+
+// Halvings along axis d of the node of reference ref at level lv.
+template <int TREE, typename R>
+__device__ __forceinline__ int ref_depth(R ref, int lv, int d)
+{
+    return TREE == KDG ? Ref<R>::depth(ref, d) : axis_depth(TREE, lv, d);
+}
+
 // A path prepared by its wavefront, waiting in the LDS queue.
 struct alignas(16) Prep {
     double ainv[3];     // |1/k|
@@ -272,7 +304,7 @@ __device__ __forceinline__ R start_node(const WalkGrid &G, const double q[3], co
     lv = Ref<R>::level(ref);
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const int dep = axis_depth(TREE, lv, d);
+        const int dep = ref_depth<TREE, R>(ref, lv, d);
         X[d] = (uint32_t(c[d]) >> (G.tdep - dep)) << (G.dm - dep);
     }
     return ref;
@@ -392,10 +424,12 @@ __device__ __forceinline__ int descend_step(const WalkGrid &G, const LevelGeo *g
     const bool tw = Ref<R>::twin(L.ref);
     if (TREE == KD && G.jump != nullptr && !tw) return kd_jump<PREC, R>(G, geo, L);
     const uint64_t id = Ref<R>::id(L.ref);
-    const LevelGeo &g = geo[L.lv];
+    LevelGeo gk;
+    if (TREE == KDG) gk = ref_geo(G, L.ref);   // the node's own axis and half width
+    const LevelGeo &g = TREE == KDG ? gk : geo[L.lv];
     const uint32_t hw = g.hw;
     uint32_t slot;
-    if (TREE == KD) {
+    if (TREE != OCT) {
         slot = kd_side(G, g, L) ? 1u : 0u;
     } else {
         slot = 0;
@@ -412,7 +446,13 @@ __device__ __forceinline__ int descend_step(const WalkGrid &G, const LevelGeo *g
         }
     }
     L.lv = L.lv + 1;
-    if (tw) {
+    if (tw && TREE == KDG) {
+        // the leaf child's halvings: the twin's, one more across its split axis
+        const int a = g.axis;
+        const int dx = Ref<R>::depth(L.ref, 0) + (a == 0 ? 1 : 0);
+        const int dy = Ref<R>::depth(L.ref, 1) + (a == 1 ? 1 : 0);
+        L.ref = Ref<R>::make_geo(Ref<R>::LEAF, L.lv, id + slot, dx, dy, 3);
+    } else if (tw) {
         L.ref = Ref<R>::make(Ref<R>::LEAF, L.lv, id + slot);
     } else {
         const uint64_t nc = TREE == OCT ? 8 : 2;
@@ -512,7 +552,9 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, const
     // the record is read first: its load overlaps the exit decision
     uint32_t rec[8];
     if (sizeof(R) == 4) load_record(G, id, rec);
-    const LevelGeo &g = geo[L.lv];
+    LevelGeo gk;
+    if (TREE == KDG) gk = ref_geo(G, L.ref);   // the leaf's widths from its reference
+    const LevelGeo &g = TREE == KDG ? gk : geo[L.lv];
     double lo[3], hi[3], E[3];
     bool kp[3];
 #pragma unroll
@@ -670,7 +712,9 @@ __device__ __forceinline__ int cross(const WalkGrid &G, const WalkArgs &A, const
     // than the leaf across the face except along the exit axis, where it may
     // be the half of a same-size neighbour touching the face.
     const int nlv = Ref<R>::level(nref);
-    const LevelGeo &gn = geo[nlv];
+    LevelGeo gkn;
+    if (TREE == KDG) gkn = ref_geo(G, nref);
+    const LevelGeo &gn = TREE == KDG ? gkn : geo[nlv];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
         const bool isa = d == 0 ? a0 : (d == 1 ? a1 : a2);
@@ -1603,6 +1647,10 @@ int launch_walk_args(const hg_grid *g, const WalkArgs &A, const hg_trace_opts *o
     // the early-exit walks read the FP64 records whatever the exit-decision precision
     const WalkGrid G = walk_grid(g, wm == WM_SEG || wm == WM_INT ? HG_FP64 : opts->precision);
     const int prec = opts->precision;
+    if (g->tree == KDG) {
+        if (!g->wide) return HG_E_FORMAT;   // its references carry the node geometry
+        return dispatch_walk<KDG, uint64_t>(G, A, prec, wm, persistent, opts, s);
+    }
     if (g->tree == KD)
         return g->wide ? dispatch_walk<KD, uint64_t>(G, A, prec, wm, persistent, opts, s)
                        : dispatch_walk<KD, uint32_t>(G, A, prec, wm, persistent, opts, s);
@@ -1693,7 +1741,10 @@ int launch_locate(const hg_grid *g, const double *p, int64_t n, int32_t *leaf, h
     const int64_t nb = (n + TB - 1) / TB;
     if (nb == 0) return HG_OK;
     const dim3 grid{unsigned(nb), 1u, 1u}, block{unsigned(TB), 1u, 1u};
-    if (g->tree == KD) {
+    if (g->tree == KDG) {
+        if (!g->wide) return HG_E_FORMAT;
+        k_locate<KDG, uint64_t><<<grid, block, 0, s>>>(G, p, n, leaf);
+    } else if (g->tree == KD) {
         if (g->wide) k_locate<KD, uint64_t><<<grid, block, 0, s>>>(G, p, n, leaf);
         else k_locate<KD, uint32_t><<<grid, block, 0, s>>>(G, p, n, leaf);
     } else {
