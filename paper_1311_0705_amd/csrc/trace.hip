@@ -1054,8 +1054,12 @@ __device__ __forceinline__ unsigned long long readfirstlane64(unsigned long long
 // LDS queue; lanes take queued paths once at least refill_min lanes are idle
 // (or none is busy).  Each iteration a busy lane crosses its leaf and, if the
 // path goes on into a node that is not a leaf, descends one level.
+// Five wavefronts per SIMD for the walks without records (their registers
+// fit 96 without spilling: more paths in flight hide more load latency); the
+// record walks keep the compiler's choice.
 template <int TREE, int PREC, int WM, typename R, int BT>
 __global__ void __launch_bounds__(BT)
+    __attribute__((amdgpu_waves_per_eu(WM == WM_FILL || WM == WM_SLAB ? 1 : 5, 8)))
     k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t chunk, int refill_min)
 {
     using DsT = typename Lane<PREC, R>::DsT;
