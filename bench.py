@@ -76,10 +76,10 @@ TUNE_PATHS = 10_000_000
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_slab": {"trace_sha256": "058869655fe4a01471346ce14b61a33c736e0f7c72b34a07553ee59b941734a0",
-                "fetch_kib": 27463078.1, "write_kib": 5896542.4, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "058869655fe4a01471346ce14b61a33c736e0f7c72b34a07553ee59b941734a0",
-                 "fetch_kib": 93931542.2, "write_kib": 6928222.4, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "e8a75bc5cc4c83e94ae9ae3dd53dfc46501840557cc55030340e6323d9245a10",
+                "fetch_kib": 28232057.1, "write_kib": 5905403.9, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "e8a75bc5cc4c83e94ae9ae3dd53dfc46501840557cc55030340e6323d9245a10",
+                 "fetch_kib": 81690379.8, "write_kib": 6900512.3, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
