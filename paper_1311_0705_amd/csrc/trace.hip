@@ -1048,43 +1048,63 @@ __device__ __forceinline__ unsigned long long readfirstlane64(unsigned long long
            ((unsigned long long)__builtin_amdgcn_readfirstlane(uint32_t(v >> 32)) << 32);
 }
 
-// Persistent walk: each wavefront keeps its lanes busy by handing prepared
-// paths to lanes whose path ended.  A wavefront takes `chunk` paths per
-// atomic on the global path counter and prepares them 64 at a time into its
-// LDS queue; lanes take queued paths once at least refill_min lanes are idle
-// (or none is busy).  Each iteration a busy lane crosses its leaf and, if the
-// path goes on into a node that is not a leaf, descends one level.
-// Five wavefronts per SIMD for the walks without records (their registers
-// fit 96 without spilling: more paths in flight hide more load latency); the
-// record walks keep the compiler's choice.
-template <int TREE, int PREC, int WM, typename R, int BT>
-__global__ void __launch_bounds__(BT)
-    __attribute__((amdgpu_waves_per_eu(WM == WM_FILL || WM == WM_SLAB ? 1 : 5, 8)))
-    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t chunk, int refill_min)
+// Chunk sources of the persistent loop (wavefront-uniform; lane 0 takes the
+// atomic).  PathCounter: `chunk` paths per atomic on the launch's path counter.
+struct PathCounter {
+    uint32_t chunk;
+    __device__ __forceinline__ bool next(const WalkArgs &A, int lane, int64_t &b, int64_t &e) const
+    {
+        unsigned long long v = 0;
+        if (lane == 0) v = atomicAdd(&A.st->next_ray, (unsigned long long)chunk);
+        v = readfirstlane64(v);
+        if (v >= (unsigned long long)A.n) return false;
+        b = int64_t(v);
+        e = std::min<int64_t>(b + chunk, A.n);
+        return true;
+    }
+};
+
+// GridChunks: the chunks of one grid of a batched walk, one per atomic on
+// that grid's counter.
+struct GridChunks {
+    const BatchChunk *chunks;
+    unsigned long long *ctr;
+    int64_t c0, nq;
+    __device__ __forceinline__ bool next(const WalkArgs &, int lane, int64_t &b, int64_t &e) const
+    {
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(ctr, 1ull);
+        t = readfirstlane64(t);
+        if (t >= (unsigned long long)nq) return false;
+        b = chunks[c0 + int64_t(t)].start;
+        e = chunks[c0 + int64_t(t)].end;
+        return true;
+    }
+};
+
+// The persistent loop of one wavefront over one grid: it takes chunks of
+// paths from src (starting with [cnext, cend) if not empty), prepares them
+// 64 at a time into its LDS queue, and hands queued paths to lanes whose path
+// ended once at least refill_min lanes are idle (or none is busy).  Each
+// iteration a busy lane crosses its leaf and, if the path goes on into a node
+// that is not a leaf, descends.  Returns when src is exhausted and every lane
+// is idle.
+template <int TREE, int PREC, int WM, typename R, class Src>
+__device__ __forceinline__ void persistent_loop(const WalkGrid &G, const WalkArgs &A, const LevelGeo *geo,
+                                                Prep *ring, uint32_t *stl, typename Lane<PREC, R>::DsT *stds,
+                                                const Src &src, int64_t cnext, int64_t cend, int refill_min,
+                                                int lane, int wid, unsigned long long &rechecks, uint32_t &desc)
 {
     using DsT = typename Lane<PREC, R>::DsT;
     constexpr bool STG = WM == WM_FILL || WM == WM_SLAB;   // record modes
-    constexpr int NW = BT / 64;
-    __shared__ LevelGeo geo[NLEV];
-    __shared__ Prep ring_all[NW * RING];
-    __shared__ uint32_t stl[STG ? BT * SP : 1];
-    __shared__ DsT stds[STG ? BT * SP : 1];
-    fill_levels(geo, G, threadIdx.x, BT);
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    Prep *ring = ring_all + wid * RING;
-    uint32_t *my_l = stl + threadIdx.x * SP;
-    DsT *my_d = stds + threadIdx.x * SP;
+    uint32_t *my_l = STG ? stl + threadIdx.x * SP : nullptr;
+    DsT *my_d = STG ? stds + threadIdx.x * SP : nullptr;
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     Lane<PREC, R> L;
     int64_t ray = -1;
     bool done = false;
     int rhead = 0, rn = 0;           // the wavefront's queue [rhead, rn)
-    int64_t cnext = 0, cend = 0;     // its paths not yet prepared
-    bool drained = false;            // the global counter is exhausted
-    unsigned long long rechecks = 0;
-    uint32_t desc = 0;
+    bool drained = false;            // src is exhausted
     for (;;) {
         const bool want = ray < 0 && !done;
         const uint64_t wmask = __ballot(want);
@@ -1094,15 +1114,7 @@ __global__ void __launch_bounds__(BT)
             if (nwant >= refill_min || !amask) {
                 while (rhead >= rn && !(drained && cnext >= cend)) {
                     if (cnext >= cend) {
-                        unsigned long long b = 0;
-                        if (lane == 0) b = atomicAdd(&A.st->next_ray, (unsigned long long)chunk);
-                        b = readfirstlane64(b);
-                        if (b >= (unsigned long long)A.n) {
-                            drained = true;
-                        } else {
-                            cnext = int64_t(b);
-                            cend = std::min<int64_t>(int64_t(b) + chunk, A.n);
-                        }
+                        if (!src.next(A, lane, cnext, cend)) drained = true;
                         continue;
                     }
                     rn = fill_queue<TREE, PREC, WM, R>(G, A, ring, cnext, cend, lane, below);
@@ -1136,6 +1148,33 @@ __global__ void __launch_bounds__(BT)
             ray = -1;
         }
     }
+}
+
+// Persistent walk of one grid: every wavefront runs the persistent loop with
+// `chunk` paths per atomic on the launch's path counter.
+// Five wavefronts per SIMD for the walks without records (their registers
+// fit 96 without spilling: more paths in flight hide more load latency); the
+// record walks keep the compiler's choice.
+template <int TREE, int PREC, int WM, typename R, int BT>
+__global__ void __launch_bounds__(BT)
+    __attribute__((amdgpu_waves_per_eu(WM == WM_FILL || WM == WM_SLAB ? 1 : 5, 8)))
+    k_walk_persistent(WalkGrid G, WalkArgs A, uint32_t chunk, int refill_min)
+{
+    using DsT = typename Lane<PREC, R>::DsT;
+    constexpr bool STG = WM == WM_FILL || WM == WM_SLAB;   // record modes
+    constexpr int NW = BT / 64;
+    __shared__ LevelGeo geo[NLEV];
+    __shared__ Prep ring_all[NW * RING];
+    __shared__ uint32_t stl[STG ? BT * SP : 1];
+    __shared__ DsT stds[STG ? BT * SP : 1];
+    fill_levels(geo, G, threadIdx.x, BT);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned long long rechecks = 0;
+    uint32_t desc = 0;
+    persistent_loop<TREE, PREC, WM, R>(G, A, geo, ring_all + wid * RING, stl, stds, PathCounter{chunk}, 0, 0,
+                                       refill_min, lane, wid, rechecks, desc);
     if (!(WM == WM_FILL) && A.count_rechecks) {
         if (rechecks) atomicAdd(&A.st->rechecks, rechecks);
         if (desc) atomicAdd(&A.st->descents, (unsigned long long)desc);
@@ -1144,14 +1183,12 @@ __global__ void __launch_bounds__(BT)
 
 // Batched walk over many grids in one persistent launch.  The device work
 // queue is a table of chunks (grid, path range), each grid's chunks together
-// with a counter per grid; a wavefront takes one chunk per atomic from the
-// grid it is on, starting from a grid spread by its index and moving to the
-// next grid when that one has no chunk left, so it stays on one grid for
-// many chunks.  It keeps that grid's parameters (and its level table)
-// uniform across its lanes, preparing the chunk's paths into its queue.
-// Before taking up a chunk of another grid it lets its lanes finish their
-// paths.  Octree and k-d grids mix freely: the tree type is a
-// wavefront-uniform branch.
+// with a counter per grid.  A wavefront starts on a grid spread by its index
+// and runs the persistent loop over that grid's chunks; when the grid has
+// none left and its lanes are idle it moves on to the next grid with chunks
+// left.  While on a grid it holds the grid's parameters as wavefront-uniform
+// values and keeps a level table made for that grid's class.  Octree and k-d
+// grids mix freely: the tree type is a wavefront-uniform branch.
 template <int PREC, int WM, int BT>
 __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
                                              const BatchQueue Q, int refill_min, TraceStatus *st,
@@ -1159,121 +1196,57 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
                                              typename Lane<PREC, uint32_t>::DsT *stds)
 {
     using R = uint32_t;
-    using DsT = typename Lane<PREC, R>::DsT;
-    constexpr bool STG = WM == WM_FILL || WM == WM_SLAB;   // record modes
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     LevelGeo *geo = geo_all + wid * NLEV;
     Prep *ring = ring_all + wid * RING;
-    uint32_t *my_l = STG ? stl + threadIdx.x * SP : nullptr;
-    DsT *my_d = STG ? stds + threadIdx.x * SP : nullptr;
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    Lane<PREC, R> L;
-    int64_t ray = -1;
-    bool done = false;
-    int gi = -1, pc = -1;            // current grid, pending chunk
-    int64_t cnext = 0, cend = 0;
-    bool drained = false;
-    int rhead = 0, rn = 0;
     int geo_tree = -1, geo_dm = -1;  // what the wavefront's level table was made for
     double geo_side = 0.0;
-    // the current grid's parameters, read in place (wavefront-uniform addresses)
-    const WalkGrid *Gp = grids;
-    const WalkArgs *Ap = args;
     unsigned long long rechecks = 0;
     uint32_t desc = 0;
     bool count_rechecks = false;
     const int64_t gw = int64_t(blockIdx.x) * (BT / 64) + wid, tw = int64_t(gridDim.x) * (BT / 64);
-    int qg = int(gw * Q.ng / tw);    // the grid whose chunks the wavefront takes
+    int qg = __builtin_amdgcn_readfirstlane(int(gw * Q.ng / tw));   // the grid whose chunks it takes
     int tried = 0;                   // grids found empty since its last chunk
     for (;;) {
-        const bool want = ray < 0 && !done;
-        const uint64_t wmask = __ballot(want);
-        if (wmask) {
-            const uint64_t amask = __ballot(ray >= 0);
-            const int nwant = __popcll(wmask);
-            if (nwant >= refill_min || !amask) {
-                while (rhead >= rn) {
-                    if (cnext >= cend) {
-                        while (pc < 0 && !drained) {
-                            unsigned long long t = 0;
-                            if (lane == 0) t = atomicAdd(&Q.gctr[qg], 1ull);
-                            t = readfirstlane64(t);
-                            const int64_t c0 = Q.gpre[qg], nq = Q.gpre[qg + 1] - c0;
-                            if (t < (unsigned long long)nq) {
-                                pc = int(c0 + int64_t(t));
-                                tried = 0;
-                            } else if (++tried >= Q.ng) {
-                                drained = true;
-                            } else {
-                                qg = qg + 1 == Q.ng ? 0 : qg + 1;
-                            }
-                        }
-                        if (pc < 0) break;
-                        const int cg = __builtin_amdgcn_readfirstlane(Q.chunks[pc].grid);
-                        if (cg != gi && amask) break;   // let this grid's paths finish first
-                        if (cg != gi) {
-                            gi = cg;
-                            Gp = grids + gi;
-                            Ap = args + gi;
-                            count_rechecks = count_rechecks || Ap->count_rechecks;
-                            if (Gp->tree != geo_tree || Gp->dm != geo_dm || Gp->side != geo_side) {
-                                fill_levels(geo, *Gp, lane, 64);
-                                geo_tree = Gp->tree;
-                                geo_dm = Gp->dm;
-                                geo_side = Gp->side;
-                                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                                __builtin_amdgcn_wave_barrier();
-                                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                            }
-                        }
-                        cnext = Q.chunks[pc].start;
-                        cend = Q.chunks[pc].end;
-                        pc = -1;
-                        // records of a grid that does not fit are not written
-                        if ((WM == WM_FILL) && Ap->offsets[Ap->n] > Ap->capacity) {
-                            if (lane == 0) st->cap_overflow = 1;
-                            cnext = cend;
-                        }
-                        continue;
-                    }
-                    rn = Gp->tree == KD ? fill_queue<KD, PREC, WM, R>(*Gp, *Ap, ring, cnext, cend, lane, below)
-                                      : fill_queue<OCT, PREC, WM, R>(*Gp, *Ap, ring, cnext, cend, lane, below);
-                    rhead = 0;
-                    cnext = std::min<int64_t>(cnext + 64, cend);
-                }
-                const int avail = rn - rhead;
-                if (want) {
-                    const int rank = __popcll(wmask & below);
-                    if (rank < avail) ray = take_path<WM, PREC, R>(*Gp, *Ap, ring[rhead + rank], L);
-                    else if (drained && pc < 0 && cnext >= cend) done = true;
-                }
-                rhead += std::min(avail, nwant);
-            }
-        }
-        if (!__ballot(ray >= 0)) {
-            if (!__ballot(!done)) break;
+        unsigned long long t = 0;
+        if (lane == 0) t = atomicAdd(&Q.gctr[qg], 1ull);
+        t = readfirstlane64(t);
+        const int64_t c0 = Q.gpre[qg], nq = Q.gpre[qg + 1] - c0;
+        if (t >= (unsigned long long)nq) {
+            if (++tried >= Q.ng) break;
+            qg = qg + 1 == Q.ng ? 0 : qg + 1;
             continue;
         }
-        bool fin = false, crossed = false, bad = false;
-        int32_t c_before = 0;
-        if (ray >= 0)
-            fin = Gp->tree == KD ? walk_step<KD, PREC, WM, R, STG>(*Gp, *Ap, geo, L, ray, rechecks, desc, my_l, my_d,
-                                                                 crossed, c_before, bad)
-                               : walk_step<OCT, PREC, WM, R, STG>(*Gp, *Ap, geo, L, ray, rechecks, desc, my_l, my_d,
-                                                                  crossed, c_before, bad);
-        // every lane holds the wavefront's current grid, so A is uniform here
-        if (STG) {
-            int nr = 0;
-            int64_t pos = 0;
-            if (ray >= 0 && (crossed || bad)) stage_group<PREC, R>(L, crossed, c_before, fin, nr, pos);
-            flush_stage<DsT>(*Ap, stl, stds, nr, pos, lane, wid * 64);
+        tried = 0;
+        // read through the constant address space, as kernel arguments are:
+        // the loads are scalar and may be repeated where registers run short
+        const WalkGrid &G = *(const WalkGrid *)(const __attribute__((address_space(4))) WalkGrid *)(grids + qg);
+        const WalkArgs &A = *(const WalkArgs *)(const __attribute__((address_space(4))) WalkArgs *)(args + qg);
+        // records of a grid that does not fit are not written: its chunks are
+        // taken and dropped
+        if (WM == WM_FILL && A.offsets[A.n] > A.capacity) {
+            if (lane == 0) st->cap_overflow = 1;
+            continue;
         }
-        if (fin) {
-            if (bad) st->bad_ref = 1;
-            finish_path<PREC, WM, R, STG>(*Ap, ray, L);
-            ray = -1;
+        count_rechecks = count_rechecks || A.count_rechecks;
+        if (G.tree != geo_tree || G.dm != geo_dm || G.side != geo_side) {
+            fill_levels(geo, G, lane, 64);
+            geo_tree = G.tree;
+            geo_dm = G.dm;
+            geo_side = G.side;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        const GridChunks src{Q.chunks, Q.gctr + qg, c0, nq};
+        const int64_t b = Q.chunks[c0 + int64_t(t)].start, e = Q.chunks[c0 + int64_t(t)].end;
+        if (G.tree == KD)
+            persistent_loop<KD, PREC, WM, R>(G, A, geo, ring, stl, stds, src, b, e, refill_min, lane, wid, rechecks,
+                                             desc);
+        else
+            persistent_loop<OCT, PREC, WM, R>(G, A, geo, ring, stl, stds, src, b, e, refill_min, lane, wid,
+                                              rechecks, desc);
     }
     if (!(WM == WM_FILL) && count_rechecks) {
         if (rechecks) atomicAdd(&st->rechecks, rechecks);
