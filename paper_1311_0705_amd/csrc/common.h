@@ -241,6 +241,8 @@ struct WalkArgs {
     unsigned long long *n_resume;  // slab walk: entries written to resume
     int pairs;                     // persistent slab walk, FP32 records: rows of (leaf, ds32)
                                    // pairs in leaf (ds unused)
+    int resume_by_path;            // resume entry i is path i's (no counter): the slab walk
+                                   // saves there, the fill walk takes path i if count[i] > slab
     const double *lim;             // WM_SEG: s_max per path; WM_INT: tau* per path
 };
 

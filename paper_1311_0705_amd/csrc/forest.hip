@@ -524,10 +524,6 @@ struct hg_batch {
     WalkArgs *dAs = nullptr;               // slab-walk arguments (rows, resume arrays)
     WalkArgs *dAf = nullptr;               // resume-walk arguments (CSR slices, resume arrays)
     void *op_block = nullptr;              // rows, resume entries, counters, resume chunk table
-    unsigned long long *n_res = nullptr;   // [ng] resume entries per grid
-    int64_t *rc_prefix = nullptr;          // [ng + 1] resume chunks per grid, prefix
-    BatchChunk *dRC = nullptr;             // resume chunk table
-    int rc_cap = 0;
     // captured graph
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -575,30 +571,6 @@ void free_batch(hg_batch *b)
     delete b;
 }
 
-__global__ void __launch_bounds__(FT) k_f_zero_u64(unsigned long long *__restrict__ p, int n)
-{
-    for (int i = int(blockIdx.x) * FT + threadIdx.x; i < n; i += int(gridDim.x) * FT) p[i] = 0ull;
-}
-
-// Chunk table of the resume walk: per grid, its resume entries (at most its
-// path count) in chunks of `per`, grids in order; P its per-grid prefix.
-__global__ void __launch_bounds__(FT) k_f_resume_chunks(const WalkArgs *__restrict__ A, int ng, int64_t per,
-                                                        int64_t *__restrict__ P, BatchChunk *__restrict__ out)
-{
-    auto entries = [&](int g) {
-        const unsigned long long r = *A[g].n_resume;
-        return int64_t(r < (unsigned long long)A[g].n ? r : (unsigned long long)A[g].n);
-    };
-    block_prefix(ng, P, [&](int g) { return (entries(g) + per - 1) / per; });
-    __syncthreads();
-    for (int g = threadIdx.x; g < ng; g += FT) {
-        const int64_t nr = entries(g), base = P[g];
-        for (int64_t j = 0; j * per < nr; j++)
-            out[base + j] = BatchChunk{int32_t(g), int32_t(base), j * per, min(nr, (j + 1) * per)};
-    }
-}
-
-constexpr int64_t RESUME_CHUNK = 64;                        // resume entries per chunk
 constexpr double BATCH_SLAB_BUDGET = double(int64_t(8) << 30);
 constexpr int64_t BATCH_SLAB_MIN = 16;
 
@@ -684,16 +656,12 @@ int trace_pipeline(hg_batch *b, const BatchChunk *C, const int64_t *gpre, int nc
     HG_CHECK(hipGetLastError());
     int rc = HG_OK;
     if (b->one_pass) {
-        k_f_zero_u64<<<unsigned((ng + FT - 1) / FT), FT, 0, s>>>(b->n_res, ng);
-        HG_CHECK(hipGetLastError());
         if (nc > 0) rc = launch_batched(G, b->dAs, Q, o, WM_SLAB, b->status, s);
         if (!rc) rc = scan_chunks(C, nc, b->dAf, ng, ctmp, s);
         if (!rc) rc = launch_slab_compact_batch(b->dAs, b->dAf, Q, nc, b->opts.precision, b->pairs, b->status, s);
         if (rc) return rc;
-        k_f_resume_chunks<<<1, FT, 0, s>>>(b->dAs, ng, RESUME_CHUNK, b->rc_prefix, b->dRC);
-        HG_CHECK(hipGetLastError());
-        const BatchQueue R{b->dRC, b->rc_prefix, b->gctr, ng};
-        return launch_batched(G, b->dAf, R, o, WM_FILL, b->status, s);
+        // the paths past their row (count > slab) resume from their entries
+        return nc > 0 ? launch_batched(G, b->dAf, Q, o, WM_FILL, b->status, s) : HG_OK;
     }
     if (nc > 0) rc = launch_batched(G, b->dA, Q, o, WM_COUNT, b->status, s);
     if (rc || b->opts.mode != HG_RECORDS) return rc;
@@ -824,14 +792,10 @@ int bind_one_pass(hg_batch *b, const std::vector<WalkArgs> &hA, const hg_trace_o
     const int ng = b->ng;
     int64_t total = 0;
     std::vector<int64_t> pre(size_t(ng) + 1, 0);
-    int64_t rc_cap = 0;
-    for (int g = 0; g < ng; g++) {
-        pre[size_t(g) + 1] = pre[size_t(g)] + hA[size_t(g)].n;
-        rc_cap += (hA[size_t(g)].n + RESUME_CHUNK - 1) / RESUME_CHUNK;
-    }
+    for (int g = 0; g < ng; g++) pre[size_t(g) + 1] = pre[size_t(g)] + hA[size_t(g)].n;
     total = pre[size_t(ng)];
     const int64_t slab = batch_slab_rows(opts, total);
-    if (slab == 0 || rc_cap > int64_t(0x7fffffff)) return HG_OK;
+    if (slab == 0) return HG_OK;
     const int pairs = opts->precision != HG_FP64 ? 1 : 0;   // FP32 rows of (leaf, ds32) pairs
     const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;
     const size_t rl = size_t(slab) * (pairs ? 8 : 4), rd = pairs ? 0 : size_t(slab) * dsz;
@@ -841,15 +805,7 @@ int bind_one_pass(hg_batch *b, const std::vector<WalkArgs> &hA, const hg_trace_o
     cv.add(&rows_l, size_t(total) * rl);
     if (!pairs) cv.add(&rows_d, size_t(total) * rd);
     cv.add(&res, size_t(std::max<int64_t>(total, 1)));
-    cv.add(&b->n_res, size_t(ng));
-    cv.add(&b->rc_prefix, size_t(ng) + 1);
-    cv.add(&b->dRC, size_t(std::max<int64_t>(rc_cap, 1)));
-    if (dalloc(&b->op_block, cv.bytes(), nullptr)) {
-        b->n_res = nullptr;
-        b->rc_prefix = nullptr;
-        b->dRC = nullptr;
-        return HG_OK;   // two walks instead
-    }
+    if (dalloc(&b->op_block, cv.bytes(), nullptr)) return HG_OK;   // two walks instead
     cv.assign(b->op_block);
     std::vector<WalkArgs> hs(hA), hf(hA);
     for (int g = 0; g < ng; g++) {
@@ -861,11 +817,13 @@ int bind_one_pass(hg_batch *b, const std::vector<WalkArgs> &hA, const hg_trace_o
         S.capacity = S.n * slab;
         S.slab = slab;
         S.resume = res + p0;
-        S.n_resume = b->n_res + g;
+        S.n_resume = nullptr;
+        S.resume_by_path = 1;
         S.pairs = pairs;
         F.slab = slab;
         F.resume = res + p0;
         F.n_resume = nullptr;
+        F.resume_by_path = 1;
         F.pairs = 0;
     }
     int rc = dalloc_n(&b->dAs, size_t(ng), nullptr);
@@ -879,7 +837,6 @@ int bind_one_pass(hg_batch *b, const std::vector<WalkArgs> &hA, const hg_trace_o
     if (rc) return rc;
     b->slab = slab;
     b->pairs = pairs;
-    b->rc_cap = int(rc_cap);
     b->one_pass = true;
     return HG_OK;
 }

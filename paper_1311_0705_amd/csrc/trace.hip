@@ -517,12 +517,18 @@ __device__ __forceinline__ void flush_records(const WalkArgs &A, const Lane<PREC
 // Slab walk: the state on entry to the leaf of the path's first record beyond
 // its row, from which the record-filling walk resumes it.  The slab walk
 // reaches that point once per path, so the entries never exceed the paths.
+// Entries are taken from a counter, or (resume_by_path) entry i is path i's:
+// no atomic on one address per overflowing path, which serialises when many
+// paths overflow short rows.
 template <int PREC, typename R>
 __device__ __forceinline__ void save_resume(const WalkArgs &A, int64_t path, const Lane<PREC, R> &L)
 {
     if (!A.resume) return;   // a slab walk that only counts (the autotuner's)
-    const unsigned long long j = atomicAdd(A.n_resume, 1ull);
-    if (j >= (unsigned long long)A.n) return;
+    unsigned long long j = (unsigned long long)path;
+    if (!A.resume_by_path) {
+        j = atomicAdd(A.n_resume, 1ull);
+        if (j >= (unsigned long long)A.n) return;
+    }
     Resume &S = A.resume[j];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -1025,8 +1031,9 @@ __device__ __forceinline__ int fill_queue(const WalkGrid &G, const WalkArgs &A, 
     bool ok = false;
     if (i < cend) {
         if (WM == WM_FILL && A.resume) {
-            prep_resume(A, i, e);
-            ok = true;
+            // entries by path: only the paths past their row are resumed
+            ok = !A.resume_by_path || A.count[i] > A.slab;
+            if (ok) prep_resume(A, i, e);
         } else {
             const int why = prep_path<TREE, R>(G, A, i, e);
             ok = why == PATH_WALK;
@@ -1662,6 +1669,7 @@ WalkArgs walk_args(const hg_grid *g, TraceStatus *st, const double *o, const dou
     A.resume = nullptr;
     A.n_resume = nullptr;
     A.pairs = 0;
+    A.resume_by_path = 0;
     A.lim = nullptr;
     return A;
 }
