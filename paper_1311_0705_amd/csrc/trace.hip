@@ -323,6 +323,19 @@ __device__ __forceinline__ bool tie_upper(int tie, double kd, int d)
     return onhi ? false : (onlo ? true : !(kd < 0.0));
 }
 
+// The sides of three split planes for a point: up[d] from the comparison,
+// replaced by tie_upper where the point lies on the plane (eq[d]).  Such
+// points are rare, so the rule is applied behind one wavefront-wide test
+// instead of being evaluated for every axis of every descent.
+__device__ __forceinline__ void tie_sides(int tie, const double k[3], const bool eq[3], bool up[3])
+{
+    if (__ballot(eq[0] || eq[1] || eq[2])) {
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+            if (eq[d]) up[d] = tie_upper(tie, k[d], d);
+    }
+}
+
 // The 32-byte record of leaf id (compact layout): six encoded ropes, then the
 // density (f32, or the low and high words of the f64 record's density).  An id
 // out of range reads record 0: the crossing reports the error.
@@ -387,19 +400,21 @@ __device__ __forceinline__ int kd_jump(const WalkGrid &G, const LevelGeo *geo, L
     const int lv = L.lv;
     const LevelGeo &g = geo[lv];
     const uint32_t jof = g.jof;
-    uint32_t idx = 0, jo[3], add[3];
+    uint32_t idx = 0, jo[3], add[3], h[3];
+    bool up[3], eq[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        const uint32_t h = g.jhw[d];
+        h[d] = g.jhw[d];
         jo[d] = (jof >> (8 * d)) & 3u;
-        const double c = fma(double(L.X[d] + h), G.unit, G.lo[d]);
-        bool up = L.p[d] > c;
-        const bool eq = L.p[d] == c;
-        if (__ballot(eq)) {
-            if (eq) up = tie_upper(L.tie, L.k[d], d);
-        }
-        idx |= (up ? 4u : 0u) >> jo[d];
-        add[d] = up ? h : 0u;
+        const double c = fma(double(L.X[d] + h[d]), G.unit, G.lo[d]);
+        up[d] = L.p[d] > c;
+        eq[d] = L.p[d] == c;
+    }
+    tie_sides(L.tie, L.k, eq, up);
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        idx |= (up[d] ? 4u : 0u) >> jo[d];
+        add[d] = up[d] ? h[d] : 0u;
     }
     R r = static_cast<const R *>(G.jump)[8 * id + idx];
     int dl = Ref<R>::level(r) - lv;
@@ -433,16 +448,18 @@ __device__ __forceinline__ int descend_step(const WalkGrid &G, const LevelGeo *g
         slot = kd_side(G, g, L) ? 1u : 0u;
     } else {
         slot = 0;
+        bool up[3], eq[3];
 #pragma unroll
         for (int d = 0; d < 3; d++) {
             const double c = fma(double(L.X[d] + hw), G.unit, G.lo[d]);
-            bool up = L.p[d] > c;
-            const bool eq = L.p[d] == c;
-            if (__ballot(eq)) {
-                if (eq) up = tie_upper(L.tie, L.k[d], d);
-            }
-            slot |= (up ? 1u : 0u) << d;
-            L.X[d] += up ? hw : 0u;
+            up[d] = L.p[d] > c;
+            eq[d] = L.p[d] == c;
+        }
+        tie_sides(L.tie, L.k, eq, up);
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+            slot |= (up[d] ? 1u : 0u) << d;
+            L.X[d] += up[d] ? hw : 0u;
         }
     }
     L.lv = L.lv + 1;
