@@ -442,7 +442,8 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit,
  * grid_trace; the pointers are kept, the buffers must outlive their use).
  * opts as grid_trace_batched (chunk = paths per work-queue entry).  Records
  * mode walks the paths once unless opts->passes is 2: each path's first
- * opts->slab records (0: as many as fit 8 GiB over all paths, at most 2048)
+ * opts->slab records (0: as many as fit 32 GiB, or half the free device memory
+ * if less, over all paths, at most 2048)
  * go to a row of its own and a path past its row is saved where the row
  * filled up; the rows are then copied into the CSR slices and the saved paths
  * resume, all on the device.  When fewer than 16 rows per path fit, it walks

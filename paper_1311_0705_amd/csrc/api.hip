@@ -94,6 +94,7 @@ __global__ void k_reset_status(TraceStatus *st)
     st->step_guard = 0;
     st->bad_ref = 0;
     st->cap_overflow = 0;
+    st->resumed = 0;
     st->next_ray = 0;
     st->done_waves = 0;
 }

@@ -204,6 +204,8 @@ struct TraceStatus {
     int step_guard;
     int bad_ref;                   // a reference out of range: the layout is corrupt
     int cap_overflow;              // a grid's records did not fit (batched walk, device check)
+    int resumed;                   // a path has more records than its row (set by the batched
+                                   // row copy; without one the batched resume walk exits)
     unsigned long long next_ray;   // persistent-kernel work counter (64-bit: it grows by one
                                    // chunk per atomic, the drained wavefronts' included)
     unsigned long long done_waves;

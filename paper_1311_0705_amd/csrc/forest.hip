@@ -464,6 +464,7 @@ __global__ void k_f_reset_status(TraceStatus *st)
     st->step_guard = 0;
     st->bad_ref = 0;
     st->cap_overflow = 0;
+    st->resumed = 0;
     st->next_ray = 0;
     st->done_waves = 0;
 }
@@ -571,21 +572,29 @@ void free_batch(hg_batch *b)
     delete b;
 }
 
-constexpr double BATCH_SLAB_BUDGET = double(int64_t(8) << 30);
 constexpr int64_t BATCH_SLAB_MIN = 16;
+
+// Bytes the rows of a batch may take: the single-grid budget, at most half of
+// the device memory free at binding (the rows stay reserved while bound).
+double batch_slab_budget()
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0.0;
+    return std::min(SLAB_BUDGET, 0.5 * double(free_b));
+}
 
 // Rows per path of the one-pass batched records mode for n paths in all: the
 // caller's slab rounded up to a multiple of 4, else the most that fit the
 // budget (at most SLAB_MAX); 0 (two walks) when fewer than BATCH_SLAB_MIN fit.
-int64_t batch_slab_rows(const hg_trace_opts *opts, int64_t n)
+int64_t batch_slab_rows(const hg_trace_opts *opts, int64_t n, double budget)
 {
     const double per = double(4 + (opts->precision == HG_FP64 ? 8 : 4));
     if (n <= 0) return 0;
     if (opts->slab > 0) {
         const int64_t k = (int64_t(opts->slab) + 3) / 4 * 4;
-        return double(n) * (double(k) * per + double(sizeof(Resume))) <= BATCH_SLAB_BUDGET ? k : 0;
+        return double(n) * (double(k) * per + double(sizeof(Resume))) <= budget ? k : 0;
     }
-    const double fit = (BATCH_SLAB_BUDGET / double(n) - double(sizeof(Resume))) / per;
+    const double fit = (budget / double(n) - double(sizeof(Resume))) / per;
     if (fit < double(BATCH_SLAB_MIN)) return 0;
     return std::min<int64_t>(SLAB_MAX, int64_t(fit) / 4 * 4);
 }
@@ -794,7 +803,7 @@ int bind_one_pass(hg_batch *b, const std::vector<WalkArgs> &hA, const hg_trace_o
     std::vector<int64_t> pre(size_t(ng) + 1, 0);
     for (int g = 0; g < ng; g++) pre[size_t(g) + 1] = pre[size_t(g)] + hA[size_t(g)].n;
     total = pre[size_t(ng)];
-    const int64_t slab = batch_slab_rows(opts, total);
+    const int64_t slab = batch_slab_rows(opts, total, batch_slab_budget());
     if (slab == 0) return HG_OK;
     const int pairs = opts->precision != HG_FP64 ? 1 : 0;   // FP32 rows of (leaf, ds32) pairs
     const size_t dsz = opts->precision == HG_FP64 ? 8 : 4;

@@ -1220,6 +1220,8 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
                                              typename Lane<PREC, uint32_t>::DsT *stds)
 {
     using R = uint32_t;
+    // a resume walk with no path saved past its row has nothing to do
+    if (WM == WM_FILL && args[0].resume && args[0].resume_by_path && !st->resumed) return;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     LevelGeo *geo = geo_all + wid * NLEV;
@@ -1439,6 +1441,7 @@ __global__ void __launch_bounds__(TB)
 {
     __shared__ int64_t off[CP + 1];
     const int64_t n_chunks = Q.gpre[Q.ng];
+    bool past = false;   // a path with more records than its row: the resume walk has work
     for (int64_t c = blockIdx.x; c < n_chunks; c += gridDim.x) {
         const BatchChunk ch = Q.chunks[c];
         const WalkArgs &S = slab_args[ch.grid];
@@ -1452,10 +1455,12 @@ __global__ void __launch_bounds__(TB)
             __syncthreads();
             for (int j = threadIdx.x; j <= np; j += TB) off[j] = F.offsets[p0 + j];
             __syncthreads();
+            for (int j = threadIdx.x; j < np; j += TB) past = past || off[j + 1] - off[j] > S.slab;
             compact_piece<DsT, PAIRS>(S.leaf, static_cast<const DsT *>(S.ds), S.slab, off, p0, np, F.leaf,
                                       static_cast<DsT *>(F.ds));
         }
     }
+    if (__syncthreads_or(past) && threadIdx.x == 0) st->resumed = 1;
 }
 
 constexpr int64_t PERSIST_CHUNK = int64_t(1) << 30;
