@@ -529,6 +529,18 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     }
     if (hC.size() > size_t(0x7fffffff)) return HG_E_LIMIT;
     const std::vector<int64_t> hP = chunk_prefix(hC, ng);
+    std::vector<int32_t> hcg, hcp;
+    {
+        std::vector<int> tr((size_t)ng), dm((size_t)ng);
+        std::vector<double> sd((size_t)ng);
+        for (int i = 0; i < ng; i++) {
+            tr[size_t(i)] = hG[size_t(i)].tree;
+            dm[size_t(i)] = hG[size_t(i)].dm;
+            sd[size_t(i)] = hG[size_t(i)].side;
+        }
+        grid_classes(tr, dm, sd, hcg, hcp);
+    }
+    int32_t *dcg = nullptr, *dcp = nullptr;
     WalkGrid *dG = nullptr;
     WalkArgs *dA = nullptr;
     BatchChunk *dC = nullptr;
@@ -539,6 +551,8 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     if (!rc) rc = dalloc_n(&dC, std::max<size_t>(hC.size(), 1), s);
     if (!rc) rc = dalloc_n(&dP, hP.size(), s);
     if (!rc) rc = dalloc_n(&dctr, size_t(ng), s);
+    if (!rc) rc = dalloc_n(&dcg, hcg.size(), s);
+    if (!rc) rc = dalloc_n(&dcp, hcp.size(), s);
     // records: the chunk scan's work space, then one total per grid
     const size_t ctmp = scan_chunks_tmp_elems(int(hC.size()));
     if (!rc && records) rc = dalloc_n(&tmp, ctmp + size_t(ng), s);
@@ -552,8 +566,10 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     if (!rc && !e && !hC.empty())
         e = hipMemcpyAsync(dC, hC.data(), sizeof(BatchChunk) * hC.size(), hipMemcpyHostToDevice, s);
     if (!rc && !e) e = hipMemcpyAsync(dP, hP.data(), sizeof(int64_t) * hP.size(), hipMemcpyHostToDevice, s);
+    if (!rc && !e) e = hipMemcpyAsync(dcg, hcg.data(), sizeof(int32_t) * hcg.size(), hipMemcpyHostToDevice, s);
+    if (!rc && !e) e = hipMemcpyAsync(dcp, hcp.data(), sizeof(int32_t) * hcp.size(), hipMemcpyHostToDevice, s);
     if (!rc && e) rc = set_hip_error(e);
-    const BatchQueue Q{dC, dP, dctr, ng};
+    const BatchQueue Q{dC, dP, dctr, ng, dcg, dcp, int(hcp.size()) - 1};
     TraceStatus st;
     if (!rc) {
         k_reset_status<<<1, 1, 0, s>>>(dst);
@@ -619,6 +635,8 @@ int grid_trace_batched(int ng, const hg_grid_t *grids, const double *const *orig
     dfree(dC, s);
     dfree(dP, s);
     dfree(dctr, s);
+    dfree(dcg, s);
+    dfree(dcp, s);
     dfree(tmp, s);
     return rc;
 }

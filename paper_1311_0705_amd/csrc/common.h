@@ -269,7 +269,34 @@ struct BatchQueue {
     const int64_t *gpre;
     unsigned long long *gctr;
     int ng;
+    const int32_t *cgrid;          // the grids class by class (grid_classes)
+    const int32_t *cpre;           // [ncls + 1]: class c's grids are cgrid[cpre[c] .. cpre[c+1])
+    int ncls;
 };
+
+// Classes of a batch's grids: grids of one class (tree type, finest per-axis
+// depth, domain side) have the same per-level table.  cgrid lists the grids
+// class by class, each class's grids in index order; cpre is the prefix of
+// the class sizes.
+inline void grid_classes(const std::vector<int> &tree, const std::vector<int> &dm, const std::vector<double> &side,
+                         std::vector<int32_t> &cgrid, std::vector<int32_t> &cpre)
+{
+    const size_t ng = tree.size();
+    std::vector<int32_t> cls(ng, -1);
+    cgrid.clear();
+    cpre.assign(1, 0);
+    for (size_t i = 0; i < ng; i++) {
+        if (cls[i] >= 0) continue;
+        const int32_t c = int32_t(cpre.size()) - 1;
+        for (size_t j = i; j < ng; j++) {
+            if (cls[j] < 0 && tree[j] == tree[i] && dm[j] == dm[i] && side[j] == side[i]) {
+                cls[j] = c;
+                cgrid.push_back(int32_t(j));
+            }
+        }
+        cpre.push_back(int32_t(cgrid.size()));
+    }
+}
 
 // gpre of a chunk table (each grid's chunks together, grids in order).
 inline std::vector<int64_t> chunk_prefix(const std::vector<BatchChunk> &table, int ng)

@@ -496,6 +496,8 @@ struct hg_batch {
     int64_t *off = nullptr;         // [sum of capacities + 1]
     int64_t *stmp = nullptr;
     WalkGrid *w32 = nullptr, *w64 = nullptr;
+    int32_t *cgrid = nullptr, *cpre = nullptr;   // the grids by level-table class (grid_classes)
+    int ncls = 0;
     TraceStatus *status = nullptr;
     void *tmp_block = nullptr;      // the batch-wide arrays above, carved from one block
     size_t tmp_bytes = 0;
@@ -660,7 +662,7 @@ int trace_pipeline(hg_batch *b, const BatchChunk *C, const int64_t *gpre, int nc
 {
     const WalkGrid *G = b->opts.precision == HG_FP64 ? b->w64 : b->w32;
     const int ng = b->ng;
-    const BatchQueue Q{C, gpre, b->gctr, ng};
+    const BatchQueue Q{C, gpre, b->gctr, ng, b->cgrid, b->cpre, b->ncls};
     k_f_reset_status<<<1, 1, 0, s>>>(b->status);
     HG_CHECK(hipGetLastError());
     int rc = HG_OK;
@@ -771,12 +773,28 @@ int batch_create(int n_grids, const hg_density *dens, const hg_criteria *crit, c
     ct.add(&b->w32, size_t(n_grids));
     ct.add(&b->w64, size_t(n_grids));
     ct.add(&b->status, 1);
+    std::vector<int32_t> hcg, hcp;
+    {
+        std::vector<int> tr((size_t)n_grids), dm((size_t)n_grids);
+        std::vector<double> sd((size_t)n_grids);
+        for (int i = 0; i < n_grids; i++) {
+            tr[size_t(i)] = tree_types[i];
+            dm[size_t(i)] = finest_depth(tree_types[i], crit[i].max_level);
+            sd[size_t(i)] = dens[i].side;
+        }
+        grid_classes(tr, dm, sd, hcg, hcp);
+    }
+    ct.add(&b->cgrid, hcg.size());
+    ct.add(&b->cpre, hcp.size());
+    b->ncls = int(hcp.size()) - 1;
     if (!rc) rc = ct.alloc(&b->tmp_block, &b->dev);
     if (!rc) b->tmp_bytes = ct.bytes();
     for (int i = 0; i < n_grids && !rc; i++) b->hF[size_t(i)].meta = b->meta + size_t(i) * META;
     if (!rc) {
         hipError_t e = hipMemcpy(b->dF, b->hF.data(), sizeof(ForestGrid) * size_t(n_grids),
                                  hipMemcpyHostToDevice);
+        if (!e) e = hipMemcpy(b->cgrid, hcg.data(), sizeof(int32_t) * hcg.size(), hipMemcpyHostToDevice);
+        if (!e) e = hipMemcpy(b->cpre, hcp.data(), sizeof(int32_t) * hcp.size(), hipMemcpyHostToDevice);
         if (!e) e = hipDeviceSynchronize();
         if (e) rc = set_hip_error(e);
     }

@@ -1207,16 +1207,18 @@ __global__ void __launch_bounds__(BT)
 
 // Batched walk over many grids in one persistent launch.  The device work
 // queue is a table of chunks (grid, path range), each grid's chunks together
-// with a counter per grid.  A wavefront starts on a grid spread by its index
-// and runs the persistent loop over that grid's chunks; when the grid has
-// none left and its lanes are idle it moves on to the next grid with chunks
-// left.  While on a grid it holds the grid's parameters as wavefront-uniform
-// values and keeps a level table made for that grid's class.  Octree and k-d
-// grids mix freely: the tree type is a wavefront-uniform branch.
+// with a counter per grid, and the grids grouped in classes that share a
+// per-level table.  A block works through the classes one at a time (in an
+// order rotated by its index) with one level table in LDS: for each class it
+// makes the table, then each wavefront starts on a grid of the class spread
+// by its index and runs the persistent loop over that grid's chunks, moving
+// on to the class's next grid with chunks left once its lanes are idle; the
+// block meets at a barrier before the next class's table.  While on a grid a
+// wavefront holds the grid's parameters as wavefront-uniform values.
 template <int PREC, int WM, int BT>
 __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args,
-                                             const BatchQueue Q, int refill_min, TraceStatus *st,
-                                             LevelGeo *geo_all, Prep *ring_all, uint32_t *stl,
+                                             const BatchQueue Q, int refill_min, TraceStatus *st, LevelGeo *geo,
+                                             Prep *ring_all, uint32_t *stl,
                                              typename Lane<PREC, uint32_t>::DsT *stds)
 {
     using R = uint32_t;
@@ -1224,55 +1226,51 @@ __device__ __forceinline__ void walk_batched(const WalkGrid *__restrict__ grids,
     if (WM == WM_FILL && args[0].resume && args[0].resume_by_path && !st->resumed) return;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    LevelGeo *geo = geo_all + wid * NLEV;
     Prep *ring = ring_all + wid * RING;
-    int geo_tree = -1, geo_dm = -1;  // what the wavefront's level table was made for
-    double geo_side = 0.0;
     unsigned long long rechecks = 0;
     uint32_t desc = 0;
     bool count_rechecks = false;
     const int64_t gw = int64_t(blockIdx.x) * (BT / 64) + wid, tw = int64_t(gridDim.x) * (BT / 64);
-    int qg = __builtin_amdgcn_readfirstlane(int(gw * Q.ng / tw));   // the grid whose chunks it takes
-    int tried = 0;                   // grids found empty since its last chunk
-    for (;;) {
-        unsigned long long t = 0;
-        if (lane == 0) t = atomicAdd(&Q.gctr[qg], 1ull);
-        t = readfirstlane64(t);
-        const int64_t c0 = Q.gpre[qg], nq = Q.gpre[qg + 1] - c0;
-        if (t >= (unsigned long long)nq) {
-            if (++tried >= Q.ng) break;
-            qg = qg + 1 == Q.ng ? 0 : qg + 1;
-            continue;
+    for (int k = 0; k < Q.ncls; k++) {
+        const int c = int((blockIdx.x + unsigned(k)) % unsigned(Q.ncls));
+        const int c0g = Q.cpre[c], ncg = Q.cpre[c + 1] - c0g;
+        __syncthreads();   // the previous class's walks no longer read the table
+        fill_levels(geo, grids[Q.cgrid[c0g]], threadIdx.x, BT);
+        __syncthreads();
+        int qi = __builtin_amdgcn_readfirstlane(int(gw * ncg / tw));   // the class's grid it takes chunks of
+        int tried = 0;   // grids of the class found empty since its last chunk
+        for (;;) {
+            const int qg = __builtin_amdgcn_readfirstlane(Q.cgrid[c0g + qi]);
+            unsigned long long t = 0;
+            if (lane == 0) t = atomicAdd(&Q.gctr[qg], 1ull);
+            t = readfirstlane64(t);
+            const int64_t c0 = Q.gpre[qg], nq = Q.gpre[qg + 1] - c0;
+            if (t >= (unsigned long long)nq) {
+                if (++tried >= ncg) break;
+                qi = qi + 1 == ncg ? 0 : qi + 1;
+                continue;
+            }
+            tried = 0;
+            // read through the constant address space, as kernel arguments are:
+            // the loads are scalar and may be repeated where registers run short
+            const WalkGrid &G = *(const WalkGrid *)(const __attribute__((address_space(4))) WalkGrid *)(grids + qg);
+            const WalkArgs &A = *(const WalkArgs *)(const __attribute__((address_space(4))) WalkArgs *)(args + qg);
+            // records of a grid that does not fit are not written: its chunks
+            // are taken and dropped
+            if (WM == WM_FILL && A.offsets[A.n] > A.capacity) {
+                if (lane == 0) st->cap_overflow = 1;
+                continue;
+            }
+            count_rechecks = count_rechecks || A.count_rechecks;
+            const GridChunks src{Q.chunks, Q.gctr + qg, c0, nq};
+            const int64_t b = Q.chunks[c0 + int64_t(t)].start, e = Q.chunks[c0 + int64_t(t)].end;
+            if (G.tree == KD)
+                persistent_loop<KD, PREC, WM, R>(G, A, geo, ring, stl, stds, src, b, e, refill_min, lane, wid,
+                                                 rechecks, desc);
+            else
+                persistent_loop<OCT, PREC, WM, R>(G, A, geo, ring, stl, stds, src, b, e, refill_min, lane, wid,
+                                                  rechecks, desc);
         }
-        tried = 0;
-        // read through the constant address space, as kernel arguments are:
-        // the loads are scalar and may be repeated where registers run short
-        const WalkGrid &G = *(const WalkGrid *)(const __attribute__((address_space(4))) WalkGrid *)(grids + qg);
-        const WalkArgs &A = *(const WalkArgs *)(const __attribute__((address_space(4))) WalkArgs *)(args + qg);
-        // records of a grid that does not fit are not written: its chunks are
-        // taken and dropped
-        if (WM == WM_FILL && A.offsets[A.n] > A.capacity) {
-            if (lane == 0) st->cap_overflow = 1;
-            continue;
-        }
-        count_rechecks = count_rechecks || A.count_rechecks;
-        if (G.tree != geo_tree || G.dm != geo_dm || G.side != geo_side) {
-            fill_levels(geo, G, lane, 64);
-            geo_tree = G.tree;
-            geo_dm = G.dm;
-            geo_side = G.side;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-        const GridChunks src{Q.chunks, Q.gctr + qg, c0, nq};
-        const int64_t b = Q.chunks[c0 + int64_t(t)].start, e = Q.chunks[c0 + int64_t(t)].end;
-        if (G.tree == KD)
-            persistent_loop<KD, PREC, WM, R>(G, A, geo, ring, stl, stds, src, b, e, refill_min, lane, wid, rechecks,
-                                             desc);
-        else
-            persistent_loop<OCT, PREC, WM, R>(G, A, geo, ring, stl, stds, src, b, e, refill_min, lane, wid,
-                                              rechecks, desc);
     }
     if (!(WM == WM_FILL) && count_rechecks) {
         if (rechecks) atomicAdd(&st->rechecks, rechecks);
@@ -1285,9 +1283,9 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
     k_walk_batched_count(const WalkGrid *__restrict__ grids, const WalkArgs *__restrict__ args, const BatchQueue Q,
                          int refill_min, TraceStatus *st)
 {
-    __shared__ LevelGeo geo_all[(BT / 64) * NLEV];
+    __shared__ LevelGeo geo[NLEV];
     __shared__ Prep ring_all[(BT / 64) * RING];
-    walk_batched<PREC, WM_COUNT, BT>(grids, args, Q, refill_min, st, geo_all, ring_all, nullptr, nullptr);
+    walk_batched<PREC, WM_COUNT, BT>(grids, args, Q, refill_min, st, geo, ring_all, nullptr, nullptr);
 }
 
 // Record modes of the batched walk: WM_FILL (the chunks' paths, or with
@@ -1299,11 +1297,11 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4)))
                        int refill_min, TraceStatus *st)
 {
     using DsT = typename Lane<PREC, uint32_t>::DsT;
-    __shared__ LevelGeo geo_all[(BT / 64) * NLEV];
+    __shared__ LevelGeo geo[NLEV];
     __shared__ Prep ring_all[(BT / 64) * RING];
     __shared__ uint32_t stl[BT * SP];
     __shared__ DsT stds[BT * SP];
-    walk_batched<PREC, WM, BT>(grids, args, Q, refill_min, st, geo_all, ring_all, stl, stds);
+    walk_batched<PREC, WM, BT>(grids, args, Q, refill_min, st, geo, ring_all, stl, stds);
 }
 
 __global__ void k_zero_counters(unsigned long long *__restrict__ c, int n)
