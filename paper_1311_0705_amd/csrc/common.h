@@ -166,6 +166,7 @@ struct WalkGrid {
     int dm;                        // finest per-axis depth of any node: every plane is
                                    // lo + i unit with unit = side 2^-dm, i an integer
     double unit;
+    double tw, tscale;             // locate-table cell width and 2^tdep / side
 };
 
 // Finest per-axis depth of a tree whose levels go up to max_level.

@@ -382,6 +382,8 @@ __global__ void __launch_bounds__(FT) k_f_leaf_prefix(const ForestGrid *__restri
         W.child = G.child;
         W.jump = G.jump;
         W.tdep = grid_tdep(G, L);
+        W.tw = ldexp(G.D.side, -W.tdep);
+        W.tscale = ldexp(1.0, W.tdep) / G.D.side;
         W.table = W.tdep > 0 ? G.table : nullptr;
         W.dm = finest_depth(G.tree, G.C.max_level);
         W.unit = ldexp(G.D.side, -W.dm);

@@ -287,8 +287,7 @@ __device__ __forceinline__ R start_node(const WalkGrid &G, const double q[3], co
         return R(G.root);
     }
     const int T = 1 << G.tdep;
-    const double wc = ldexp(G.side, -G.tdep);
-    const double scale = ldexp(1.0, G.tdep) / G.side;
+    const double wc = G.tw, scale = G.tscale;
     int c[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -1637,6 +1636,8 @@ WalkGrid walk_grid(const hg_grid *g, int precision)
     G.jump = g->jump;
     G.table = g->table;
     G.tdep = g->table ? g->tdep : 0;
+    G.tw = ldexp(g->side, -G.tdep);
+    G.tscale = ldexp(1.0, G.tdep) / g->side;
     G.dm = finest_depth(g->tree, g->max_level);
     G.unit = ldexp(g->side, -G.dm);
     return G;
