@@ -76,10 +76,10 @@ TUNE_PATHS = 10_000_000
 # Valid only for the walk source it was measured on (sha256 of trace.hip) and
 # the workload it was measured on.
 TRAFFIC = {
-    "w2_slab": {"trace_sha256": "e8a75bc5cc4c83e94ae9ae3dd53dfc46501840557cc55030340e6323d9245a10",
-                "fetch_kib": 28232057.1, "write_kib": 5905403.9, "fetch_scale": 2.0, "write_scale": 1.0},
-    "w3kd_tau": {"trace_sha256": "e8a75bc5cc4c83e94ae9ae3dd53dfc46501840557cc55030340e6323d9245a10",
-                 "fetch_kib": 81690379.8, "write_kib": 6900512.3, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w2_slab": {"trace_sha256": "c18f1b6b3d9b6ab484e9bd7258dd9233c3d93c3f6a2c4c7f222613edf8ed5a77",
+                "fetch_kib": 28233007.0, "write_kib": 5905506.9, "fetch_scale": 2.0, "write_scale": 1.0},
+    "w3kd_tau": {"trace_sha256": "c18f1b6b3d9b6ab484e9bd7258dd9233c3d93c3f6a2c4c7f222613edf8ed5a77",
+                 "fetch_kib": 81700626.0, "write_kib": 6899754.9, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
