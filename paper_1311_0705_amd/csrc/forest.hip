@@ -30,7 +30,7 @@ constexpr int FT = 256;
 constexpr int LB_N = 66;         // level-begin slots per grid
 constexpr int META = LB_N + 4;   // + n_nodes, n_leaves, depth, error
 constexpr int M_NODES = LB_N, M_LEAVES = LB_N + 1, M_DEPTH = LB_N + 2, M_ERR = LB_N + 3;
-constexpr unsigned FLAT_BLOCKS = 1024;    // grid-stride launches over device-sized ranges
+constexpr unsigned FLAT_BLOCKS = 4096;    // grid-stride launches over device-sized ranges
 constexpr unsigned SAMPLE_BLOCKS = 2048;  // node sampling: 4 wavefronts of 64 nodes per block
 // launch shapes the batch tuner tries
 const int BLOCKS[] = {128, 256, 512};
