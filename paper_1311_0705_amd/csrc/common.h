@@ -363,7 +363,7 @@ void destroy(hg_grid *g);
 void free_grid_arrays(hg_grid *g);
 
 // Stream-ordered device memory from the device's default pool (kept by the
-// pool between calls, so repeated builds do not go back to the driver).
+// pool between calls, so repeated builds do not go back to the HIP allocator).
 int dalloc(void **p, size_t bytes, hipStream_t s);
 void dfree(void *p, hipStream_t s);
 template <typename T>
