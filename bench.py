@@ -67,8 +67,11 @@ B_X_COUNT64 = 28
 B_RAY_SLAB = 48 + 12
 
 # Paths the launch-shape autotuner times each candidate on (a sample large
-# enough that the walk's tail does not dominate the timing).
+# enough that the walk's tail does not dominate the timing); the tau-only
+# walks over 1e8 paths take a larger one, on which the candidates' order
+# matches the full run's more often.
 TUNE_PATHS = 10_000_000
+TUNE_PATHS_TAU = 30_000_000
 
 # HBM traffic of the dominant kernel from rocprofv3 --pmc runs (FETCH_SIZE and
 # WRITE_SIZE in KiB per dispatch), scaled by what the same counters read for a
@@ -463,10 +466,9 @@ def run_c3(a, w):
     n_leaves, n_nodes = g.n_leaves, g.n_nodes
     tuned = {}
     if not a.no_tune:
-        for mode in (hg.TAU_ONLY, hg.RECORDS):
-            tuned[mode] = hg.tune_cached(g, o[:TUNE_PATHS], k[:TUNE_PATHS], precision=hg.FP32_RECHECK,
-                                         mode=mode)
-        tuned["fp64_tau"] = hg.tune_cached(g, o[:TUNE_PATHS], k[:TUNE_PATHS], precision=hg.FP64,
+        for mode, m in ((hg.TAU_ONLY, TUNE_PATHS_TAU), (hg.RECORDS, TUNE_PATHS)):
+            tuned[mode] = hg.tune_cached(g, o[:m], k[:m], precision=hg.FP32_RECHECK, mode=mode)
+        tuned["fp64_tau"] = hg.tune_cached(g, o[:TUNE_PATHS_TAU], k[:TUNE_PATHS_TAU], precision=hg.FP64,
                                            mode=hg.TAU_ONLY)
         log(f"tuned launch shapes: {tuned}")
     tt = tuned.get(hg.TAU_ONLY)
@@ -751,7 +753,7 @@ def run_c5(a, w):
     log(f"build {build_s:.2f} s: {g.n_leaves} leaves")
     tt = None
     if not a.no_tune:
-        tt = hg.tune_cached(g, o[:TUNE_PATHS], k0[:TUNE_PATHS], precision=hg.FP32_RECHECK,
+        tt = hg.tune_cached(g, o[:TUNE_PATHS_TAU], k0[:TUNE_PATHS_TAU], precision=hg.FP32_RECHECK,
                             mode=hg.TAU_ONLY)
         log(f"tuned {tt}")
     res = g.trace(o, k0, precision=hg.FP32_RECHECK, mode=hg.TAU_ONLY, tuned=tt)
